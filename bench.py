@@ -1,0 +1,268 @@
+#!/usr/bin/env python3
+"""Field-synthesis throughput of the HIP CWT library on one MI355X.
+
+A step is one complete synthesis of the 3-component E field on the output
+grid from a solved problem whose inputs are resident in HBM: phase tables,
+modal sums P_l (alpha o g(z)) for every interior plane, exterior plane waves,
+and the separable inverse transform to the pixel grid. The FP64 setup
+(spectra, eigensolves, boundary solve) runs once before timing and is reported
+separately.
+
+Default workload: 64x64x32 voxels of a smoothed random index field, 21x21
+spatial frequencies (M = 441), NA 0.9 focused x-polarised incident image,
+256x256x128 output grid, complex64 synthesis.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "field voxels/s (3-comp E) plain FP32 vs BF16+comp/batched at stated rel-L2"
+HBM_PEAK = 8.0e12          # bytes/s
+FP32_PEAK = 157.3e12       # flop/s (vector and matrix)
+FP64_PEAK = 78.6e12
+GOLDEN = os.path.join(ROOT, "tests", "golden", "working_samples.npz")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def stage_model(sol_info, plan, prec):
+    """Algorithmic bytes and flops of each synthesis stage for one call."""
+    M, L = plan["M"], plan["L"]
+    fx, fy, fz = plan["fx"], plan["fy"], plan["fz"]
+    U, V = plan["U"], plan["V"]
+    eb = 16 if prec == "fp64" else 8
+    n2, n3 = 2 * M, 3 * M
+    layers = plan["layers_touched"]
+    ntask, zt = plan["ntasks"], plan["zt"]
+    interior = plan["interior_planes"]
+    return {
+        "phase": {"bytes": ntask * 2 * zt * n2 * eb + 3 * layers * n2 * 16,
+                  "flops": ntask * zt * n2 * 40},
+        "modal_sum": {"bytes": layers * n3 * n2 * eb + ntask * 2 * zt * n2 * eb
+                      + interior * n3 * eb,
+                      "flops": 8 * n3 * n2 * interior},
+        "exterior": {"bytes": (fz - interior) * n3 * eb, "flops": (fz - interior) * n3 * 40},
+        "idft_x": {"bytes": fz * n3 * eb + fz * 3 * V * fx * eb,
+                   "flops": 8 * fz * 3 * V * U * fx},
+        "idft_y": {"bytes": fz * 3 * V * fx * eb + 3 * fx * fy * fz * eb,
+                   "flops": 8 * fz * 3 * V * fx * fy},
+    }
+
+
+def plan_summary(prob, grid):
+    """Plane classification mirroring the library's plan (for the model)."""
+    L, d = prob.nz, prob.pz
+    zs = grid.z_planes()
+    per = {}
+    for z in zs:
+        if 0.0 <= z < L * d:
+            l = min(int(np.floor(z / d)), L - 1)
+            per[l] = per.get(l, 0) + 1
+    maxc = max(per.values()) if per else 0
+    zt = 1
+    while zt < min(maxc, 8):
+        zt *= 2
+    ntasks = sum((c + zt - 1) // zt for c in per.values())
+    return {"M": prob.U * prob.V, "L": L, "U": prob.U, "V": prob.V, "fx": grid.fx,
+            "fy": grid.fy, "fz": grid.fz, "layers_touched": len(per), "ntasks": ntasks,
+            "zt": zt, "interior_planes": sum(per.values())}
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in ("kernels_synth.hip", "kernels_mfma.hip"):
+        p = os.path.join(ROOT, "paper_2404_07293_amd", "csrc", f)
+        if os.path.exists(p):
+            h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_stage, precision, workload):
+    """HBM bytes per launch from the committed PMC summary, if it was taken on
+    the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s_%s.json" % (kernel_stage, workload,
+                                                                     precision))
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("source_hash") != source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(prob_full, grid_full, n_layers=2):
+    """The FP64 oracle on a bounded sample of the same workload: the first
+    `n_layers` layers of the sample (same lateral size, truncation and
+    incident field) and the output planes inside them."""
+    import workloads as W
+    from oracle import cwt
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    prob = W.Problem(n=prob_full.n[:n_layers].copy(), px=prob_full.px, py=prob_full.py,
+                     pz=prob_full.pz, lam=prob_full.lam, U=prob_full.U, V=prob_full.V,
+                     n_top=prob_full.n_top, n_bot=prob_full.n_bot, inc_ex=prob_full.inc_ex,
+                     inc_ey=prob_full.inc_ey, plane_wave=prob_full.plane_wave)
+    ppl = grid_full.fz // prob_full.nz
+    grid = W.Grid(fx=grid_full.fx, fy=grid_full.fy, fz=ppl * n_layers, z_begin=0.0,
+                  z_end=prob.thickness)
+    t0 = time.perf_counter()
+    st = cwt.setup(prob)
+    sol = cwt.solve(st, "reduced")
+    t1 = time.perf_counter()
+    E = cwt.synthesize(st, sol, grid)
+    t2 = time.perf_counter()
+    vox = grid.fx * grid.fy * grid.fz
+    assert E.shape == (3, grid.fz, grid.fy, grid.fx)
+    return {"value": vox / (t2 - t1), "unit": "voxels/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": "first %d of %d layers, %d planes of %dx%d, M=%d; synthesis %.2f s, "
+                      "setup+solve %.1f s (not in value)" % (
+                          n_layers, prob_full.nz, grid.fz, grid.fx, grid.fy,
+                          prob.U * prob.V, t2 - t1, t1 - t0)}
+
+
+def golden_error(E, prob, grid):
+    """rel-L2 of the synthesised field at the stored oracle sample voxels."""
+    if not os.path.exists(GOLDEN):
+        return None
+    g = np.load(GOLDEN, allow_pickle=False)
+    if int(g["fx"]) != grid.fx or int(g["fz"]) != grid.fz or int(g["M"]) != prob.U * prob.V:
+        return None
+    j, gg, f = g["j"], g["g"], g["f"]
+    import torch
+    idx = torch.as_tensor(np.stack([j, gg, f]), device=E.device)
+    got = E[:, idx[0], idx[1], idx[2]].cpu().numpy()
+    want = g["E"]
+    return float(np.linalg.norm(got - want) / np.linalg.norm(want))
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16x3", "fp16x3"])
+    ap.add_argument("--workload", default="working", choices=["working", "large"])
+    ap.add_argument("--layers", type=int, default=None, help="keep only the first N layers")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="also run N plain 256 MiB device copies (PMC scale reference)")
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(requested --gpus %d)" % args.gpus, file=sys.stderr)
+        return 2
+
+    import torch
+    import paper_2404_07293_amd as P
+    import workloads as W
+
+    prob, grid = W.random_field_config(args.workload, nz=args.layers)
+    log("workload %s: sample %s, U=V=%d, grid %dx%dx%d, precision %s" % (
+        args.workload, prob.n.shape, prob.U, grid.fx, grid.fy, grid.fz, args.precision))
+    ctx = P.Context(0)
+    t0 = time.perf_counter()
+    sol = ctx.solve(prob)
+    info = sol.info()
+    log("setup %.1f s (eig %.1f s), growth exponent %.1f" % (
+        time.perf_counter() - t0, info["eig_seconds"], info["growth_exponent"]))
+
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream(dev)
+    dt = torch.complex128 if args.precision == "fp64" else torch.complex64
+    E = torch.empty((3, grid.fz, grid.fy, grid.fx), dtype=dt, device=dev)
+    for _ in range(args.warmup):
+        sol.synthesize(grid, args.precision, out=E, stream=stream)
+    torch.cuda.synchronize()
+    lib = ctx.lib
+    import ctypes
+    P._native.check(lib.scw_profile_begin(ctx.handle, args.steps))
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for _ in range(args.steps):
+        sol.synthesize(grid, args.precision, out=E, stream=stream)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / args.steps
+    nst = 5
+    stage_ms = (ctypes.c_double * nst)()
+    calls = ctypes.c_int()
+    P._native.check(lib.scw_profile_end(ctx.handle, stage_ms, nst, ctypes.byref(calls)))
+    names = [lib.scw_stage_name(i).decode() for i in range(nst)]
+    stages = {n: float(stage_ms[i]) for i, n in enumerate(names)}
+    log("ms/step %.4f; stages %s" % (ms, {k: round(v, 4) for k, v in stages.items()}))
+
+    voxels = grid.fx * grid.fy * grid.fz
+    value = voxels / (ms * 1e-3)
+    err = golden_error(E, prob, grid)
+    log("rel-L2 vs oracle samples: %s" % err)
+
+    model = stage_model(info, plan_summary(prob, grid), args.precision)
+    dom = max(stages, key=lambda k: stages[k])
+    t = stages[dom] * 1e-3
+    by, fl = model[dom]["bytes"], model[dom]["flops"]
+    fpeak = FP64_PEAK if args.precision == "fp64" else FP32_PEAK
+    if by / HBM_PEAK >= fl / fpeak:
+        roof = {"bound": "hbm", "achieved": by / t / 1e9, "peak": HBM_PEAK / 1e9,
+                "unit": "GB/s"}
+    else:
+        roof = {"bound": "alu", "achieved": fl / t / 1e12, "peak": fpeak / 1e12,
+                "unit": "TFLOP/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["kernel"] = dom
+    roof["traffic"] = measured_traffic(dom, args.precision, args.workload)
+    roof["algorithmic_bytes"] = by
+    roof["algorithmic_flops"] = fl
+
+    if args.copy_calibration:
+        a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(args.copy_calibration):
+            b.copy_(a)
+        torch.cuda.synchronize()
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "voxels/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp32": "f32", "fp64": "f64", "bf16x3": "bf16x3+f32acc",
+                  "fp16x3": "fp16x3+f32acc"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": "%s: %dx%dx%d random-field sample, M=%d, %dx%dx%d grid" % (
+            args.workload, prob.nx, prob.ny, prob.nz, prob.U * prob.V, grid.fx, grid.fy,
+            grid.fz), "precision": args.precision, "voxels_per_step": voxels},
+        "rel_l2_vs_oracle": err,
+        "stages_ms": stages,
+        "setup_s": info["setup_seconds"],
+        "assembly_device_ms": info["assembly_device_ms"],
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        log("timing the oracle on a bounded sample ...")
+        out["cpu_baseline"] = cpu_baseline(prob, grid)
+    print(json.dumps(out), flush=True)
+    sol.free()
+    ctx.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,200 @@
+/*
+ * scw.h -- C ABI of the MI355X coupled-wave-theory (CWT) field-synthesis
+ * library.
+ *
+ * The library takes a sample of complex refractive index on a voxel grid and
+ * an incident field (a 2D image at the top surface, or one plane wave), solves
+ * the coupled-wave boundary-value problem in FP64, and synthesises the 3D
+ * electric field on a regular grid on the GPU (gfx950).
+ *
+ * Section and equation numbers refer to Sun, Reddy and Mayerich, "sCWatter:
+ * Open source coupled wave scattering simulation for spectroscopy and
+ * microscopy".
+ *
+ * Conventions shared by every entry point
+ *   - Complex numbers are interleaved (re, im) pairs of double (complex128) or
+ *     float (complex64).
+ *   - Host arrays passed in are read-only and owned by the caller; they may be
+ *     freed as soon as the call returns.
+ *   - Device buffers passed in are owned by the caller and must be allocated
+ *     on the context's device. The library never frees them.
+ *   - Handles (scw_ctx, scw_solution) are owned by the library and freed with
+ *     their destroy call.
+ *   - Every int-returning call returns SCW_OK (0) or a negative scw_status;
+ *     scw_last_error() then describes the failure. No C++ exception crosses
+ *     this boundary.
+ *   - A context may be used from one host thread at a time.
+ */
+#ifndef SCW_H
+#define SCW_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SCW_OK = 0,
+    SCW_EINVAL = -1,      /* bad shape, even truncation, null pointer, bad enum */
+    SCW_ENOMEM = -2,      /* host or device allocation failed */
+    SCW_EHIP = -3,        /* HIP runtime error (message keeps the HIP code) */
+    SCW_ELAPACK = -4,     /* LAPACK returned info != 0, or no LAPACK found */
+    SCW_EGRAZING = -5,    /* |s_z| < 1e-9 in a half-space (Eq. 2 at grazing) */
+    SCW_EDEFECTIVE = -6,  /* |gamma| < 1e-9 max|gamma| in a layer: D defective */
+    SCW_EILLCOND = -7     /* connection route chosen explicitly and its system
+                             is numerically singular */
+} scw_status;
+
+typedef enum {
+    SCW_FP64 = 0,         /* complex128 synthesis, complex128 output */
+    SCW_FP32 = 1,         /* complex64 synthesis, complex64 output */
+    SCW_BF16X3 = 2,       /* bf16 hi/lo split products, FP32 accumulate, complex64 out */
+    SCW_FP16X3 = 3        /* fp16 hi/lo split products, FP32 accumulate, complex64 out */
+} scw_precision;
+
+typedef enum {
+    /* Layer-by-layer elimination from the bottom up that only ever forms
+       decaying exponentials; the default. Same solution as the full
+       boundary-value system of Eqs. 24-26. */
+    SCW_ROUTE_STABLE = 0,
+    /* The paper's connection equations (Sec. 2.5.4, Eqs. 27-29): the product
+       K of per-layer transfer matrices and a 6M x 6M solve. Loses accuracy
+       when K contains large growing evanescent exponentials. */
+    SCW_ROUTE_CONNECTION = 1
+} scw_route;
+
+typedef struct scw_ctx scw_ctx;
+typedef struct scw_solution scw_solution;
+
+/* Problem description (Sec. 2.3, Sec. 3). All lengths use the unit of lambda.
+ *
+ *   nx, ny, nz   sample voxels; layer l covers z in [l*pz, (l+1)*pz], the top
+ *                surface is z0 = 0 and the field propagates towards +z.
+ *   px, py, pz   voxel pitch; the lateral period is X = nx*px, Y = ny*py and
+ *                voxel (i, j) sits at (i*px, j*py).
+ *   n            host complex128 [nz][ny][nx]: complex refractive index
+ *                n + i*kappa (kappa > 0 absorbs).
+ *   lambda       vacuum wavelength.
+ *   n_top        real index of the upper half-space.
+ *   n_bot_re/im  complex index of the lower half-space.
+ *   U, V         odd numbers of spatial frequencies along x and y (Sec. 2.2);
+ *                M = U*V.
+ *   inc_ex, inc_ey
+ *                host complex128 [inc_ny][inc_nx] images of the incident E_x
+ *                and E_y at the top surface, spanning one lateral period
+ *                (either may be NULL for zero). When both are NULL the
+ *                incident field is the plane wave below.
+ *   pw_u, pw_v   integer spatial frequency of the incident plane wave; must
+ *                lie inside the U x V band.
+ *   pw_ex, pw_ey complex (re, im) transverse amplitudes of the plane wave.
+ *   route        scw_route of the boundary solve.
+ */
+typedef struct {
+    int nx, ny, nz;
+    double px, py, pz;
+    const double* n;
+    double lambda;
+    double n_top;
+    double n_bot_re, n_bot_im;
+    int U, V;
+    const double* inc_ex;
+    const double* inc_ey;
+    int inc_nx, inc_ny;
+    int pw_u, pw_v;
+    double pw_ex[2];
+    double pw_ey[2];
+    int route;
+} scw_problem;
+
+/* Output grid: fx*fy points per plane spanning one lateral period,
+ * x_f = f*X/fx, y_g = g*Y/fy, and fz cell-centred planes
+ * z_j = z_begin + (j + 1/2)(z_end - z_begin)/fz. Planes above the sample get
+ * incident + reflected waves, planes below get the transmitted waves (Eq. 9),
+ * planes inside get the modal field of their layer (Eqs. 30-34); a plane on
+ * an interface belongs to the layer below. */
+typedef struct {
+    int fx, fy, fz;
+    double z_begin, z_end;
+} scw_grid;
+
+/* Diagnostics of one solution. */
+typedef struct {
+    int M, L;
+    double min_abs_sz;         /* min |s_z| over both half-spaces */
+    double min_abs_gamma_rel;  /* min |gamma| / max |gamma| over layers */
+    double growth_exponent;    /* k * d * sum_l max_j Im(gamma_lj): largest
+                                  exponent a transfer-matrix product holds */
+    double connection_rcond;   /* reciprocal condition (1-norm) of the 6M x 6M
+                                  system for SCW_ROUTE_CONNECTION, else 0 */
+    double setup_seconds;      /* wall time of scw_solve */
+    double eig_seconds;        /* part spent in the eigensolves */
+    double assembly_device_ms; /* GPU time of the band DFT + assembly kernels */
+} scw_solution_info;
+
+/* Thread-local description of the last failure on the calling thread. */
+const char* scw_last_error(void);
+
+/* Create a context on HIP device `hip_device`. It owns device workspaces and
+ * a host thread pool of `host_threads` workers (<= 0: all hardware threads). */
+int scw_create(scw_ctx** out, int hip_device, int host_threads);
+void scw_destroy(scw_ctx* ctx);
+
+/* FP64 setup (Sec. 3.1-3.4 and Sec. 3.6's alpha recovery):
+ *   device  band Fourier coefficients of n^2 and 1/n^2 per layer (Eqs. 11-12)
+ *           and the blocks of the property matrix D (Eq. 21);
+ *   host    per-layer eigendecomposition (LAPACK zgeev on the 2M x 2M product
+ *           of D's off-diagonal blocks, since D^2 is block diagonal),
+ *           boundary solve by `route`, and the mode coefficients alpha of
+ *           every layer;
+ *   device  the per-layer synthesis matrix P = [Q_x; Q_y; Psi (S_y Q_bx -
+ *           S_x Q_by)] of Sec. 4.1 (Eq. 34), its z rows by a band
+ *           convolution with psi.
+ * Blocks until done. On success *out is a library-owned solution. */
+int scw_solve(scw_ctx* ctx, const scw_problem* prob, scw_solution** out);
+void scw_solution_free(scw_solution* sol);
+int scw_solution_info_get(const scw_solution* sol, scw_solution_info* info);
+
+/* Copy the exterior coefficients (host complex128 [3][M] each, component
+ * major p_x, p_y, p_z, mode order m of Sec. 2.2) into caller buffers; any
+ * pointer may be NULL. p_inc is at z0, p_ref at z0, p_trn at the bottom
+ * surface (Eq. 9). */
+int scw_solution_exterior(const scw_solution* sol, double* p_inc, double* p_ref,
+                          double* p_trn);
+
+/* Field synthesis, the hot path (Eqs. 9, 10, 30-34):
+ *   for every plane, p(m, z) = P_l (alpha_l o g(z)) inside layer l, or the
+ *   exterior plane waves outside; then E(x, y, z) = sum_m p(m, z)
+ *   exp(i k s_m . r) on the grid by a separable inverse transform.
+ * E_dev: caller-owned device buffer [3][fz][fy][fx], complex128 for SCW_FP64,
+ * complex64 otherwise. `hip_stream` is a hipStream_t (NULL = default stream).
+ * The call enqueues work and returns; the first call for a new grid or
+ * precision builds a plan (device tables) synchronously. */
+int scw_synthesize(scw_ctx* ctx, scw_solution* sol, const scw_grid* grid,
+                   int precision, void* E_dev, void* hip_stream);
+
+/* Convenience: scw_solve + scw_synthesize + scw_solution_free. */
+int scw_field(scw_ctx* ctx, const scw_problem* prob, const scw_grid* grid,
+              int precision, void* E_dev, void* hip_stream);
+
+/* Per-stage timing of scw_synthesize with HIP events recorded on the
+ * synthesis stream between its kernels. scw_profile_begin enables recording
+ * for up to `max_calls` following scw_synthesize calls on this context;
+ * scw_profile_end waits for those events and writes the mean duration of each
+ * stage in milliseconds to stage_ms[0 .. n_stages-1] (n_stages <= 8) and the
+ * number of calls recorded to *calls; it then disables recording. Stage names
+ * come from scw_stage_name. */
+int scw_profile_begin(scw_ctx* ctx, int max_calls);
+int scw_profile_end(scw_ctx* ctx, double* stage_ms, int n_stages, int* calls);
+const char* scw_stage_name(int stage);
+
+/* Bytes of HBM the synthesis of `grid` must move at `precision`: the
+ * per-layer synthesis matrices of the layers the grid touches, once each, plus
+ * the output field. Used for roofline reporting. */
+double scw_synthesis_bytes(const scw_solution* sol, const scw_grid* grid,
+                           int precision);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SCW_H */

@@ -1,0 +1,110 @@
+"""ctypes declarations of the C ABI in include/scw.h.
+
+Loading fails loudly (ImportError) when libscw.so has not been built: there is
+no fallback implementation.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libscw.so")
+
+SCW_OK = 0
+STATUS = {0: "SCW_OK", -1: "SCW_EINVAL", -2: "SCW_ENOMEM", -3: "SCW_EHIP",
+          -4: "SCW_ELAPACK", -5: "SCW_EGRAZING", -6: "SCW_EDEFECTIVE",
+          -7: "SCW_EILLCOND"}
+PRECISION = {"fp64": 0, "fp32": 1, "bf16x3": 2, "fp16x3": 3}
+ROUTE = {"stable": 0, "connection": 1}
+
+c_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class ScwProblem(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+        ("px", ctypes.c_double), ("py", ctypes.c_double), ("pz", ctypes.c_double),
+        ("n", c_dp),
+        ("lam", ctypes.c_double),
+        ("n_top", ctypes.c_double),
+        ("n_bot_re", ctypes.c_double), ("n_bot_im", ctypes.c_double),
+        ("U", ctypes.c_int), ("V", ctypes.c_int),
+        ("inc_ex", c_dp), ("inc_ey", c_dp),
+        ("inc_nx", ctypes.c_int), ("inc_ny", ctypes.c_int),
+        ("pw_u", ctypes.c_int), ("pw_v", ctypes.c_int),
+        ("pw_ex", ctypes.c_double * 2), ("pw_ey", ctypes.c_double * 2),
+        ("route", ctypes.c_int),
+    ]
+
+
+class ScwGrid(ctypes.Structure):
+    _fields_ = [("fx", ctypes.c_int), ("fy", ctypes.c_int), ("fz", ctypes.c_int),
+                ("z_begin", ctypes.c_double), ("z_end", ctypes.c_double)]
+
+
+class ScwSolutionInfo(ctypes.Structure):
+    _fields_ = [
+        ("M", ctypes.c_int), ("L", ctypes.c_int),
+        ("min_abs_sz", ctypes.c_double),
+        ("min_abs_gamma_rel", ctypes.c_double),
+        ("growth_exponent", ctypes.c_double),
+        ("connection_rcond", ctypes.c_double),
+        ("setup_seconds", ctypes.c_double),
+        ("eig_seconds", ctypes.c_double),
+        ("assembly_device_ms", ctypes.c_double),
+    ]
+
+
+# name -> (restype, argtypes); every entry point of include/scw.h
+SIGNATURES = {
+    "scw_last_error": (ctypes.c_char_p, []),
+    "scw_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_int]),
+    "scw_destroy": (None, [ctypes.c_void_p]),
+    "scw_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ScwProblem),
+                                 ctypes.POINTER(ctypes.c_void_p)]),
+    "scw_solution_free": (None, [ctypes.c_void_p]),
+    "scw_solution_info_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ScwSolutionInfo)]),
+    "scw_solution_exterior": (ctypes.c_int, [ctypes.c_void_p, c_dp, c_dp, c_dp]),
+    "scw_synthesize": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ScwGrid),
+                                      ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
+    "scw_field": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ScwProblem),
+                                 ctypes.POINTER(ScwGrid), ctypes.c_int, ctypes.c_void_p,
+                                 ctypes.c_void_p]),
+    "scw_synthesis_bytes": (ctypes.c_double, [ctypes.c_void_p, ctypes.POINTER(ScwGrid),
+                                              ctypes.c_int]),
+    "scw_profile_begin": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "scw_profile_end": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                       ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
+    "scw_stage_name": (ctypes.c_char_p, [ctypes.c_int]),
+}
+
+_lib = None
+
+
+def load(path=LIB_PATH):
+    """Load libscw.so and declare its signatures (cached)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError("libscw.so is not built (%s); run python -m "
+                          "paper_2404_07293_amd.build" % path)
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class ScwError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (STATUS.get(code, "?"), code, msg))
+        self.code = code
+
+
+def check(rc):
+    if rc != SCW_OK:
+        msg = _lib.scw_last_error()
+        raise ScwError(rc, msg.decode() if msg else "")
+    return rc

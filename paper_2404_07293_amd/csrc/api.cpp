@@ -1,0 +1,383 @@
+// C ABI of the library (declared in include/scw.h): contexts, the FP64 solve,
+// synthesis plans and the synthesis launch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <new>
+#include <thread>
+
+#include "scw_internal.h"
+
+struct scw_ctx {
+  scw::Context c;
+};
+struct scw_solution {
+  scw::Solution s;
+};
+
+namespace scw {
+
+namespace {
+thread_local std::string g_err;
+}
+
+void set_error(int code, const std::string& msg) {
+  g_err = "scw error " + std::to_string(code) + ": " + msg;
+}
+
+int fail(int code, const std::string& msg) {
+  set_error(code, msg);
+  return code;
+}
+
+namespace {
+
+int elem_bytes(int precision) { return precision == SCW_FP64 ? 16 : 8; }
+
+// exp(2 pi i * idx / n) with idx reduced modulo n in integers.
+zc twiddle_inv(long long idx, int n) {
+  long long r = idx % n;
+  if (r < 0) r += n;
+  const double ang = 2.0 * M_PI * (double)r / (double)n;
+  return zc(std::cos(ang), std::sin(ang));
+}
+
+template <typename T>
+void pack(const std::vector<zc>& in, std::vector<T>& out) {
+  out.resize(2 * in.size());
+  for (size_t i = 0; i < in.size(); ++i) {
+    out[2 * i] = (T)in[i].real();
+    out[2 * i + 1] = (T)in[i].imag();
+  }
+}
+
+int upload(DevBuf& buf, const void* src, size_t bytes) {
+  int rc = buf.reserve(std::max<size_t>(bytes, 16));
+  if (rc) return rc;
+  if (bytes) SCW_HIP(hipMemcpy(buf.p, src, bytes, hipMemcpyHostToDevice));
+  return SCW_OK;
+}
+
+// Plane classification, task grouping and device tables for one grid.
+int build_plan(Solution& s, const scw_grid& g, int precision) {
+  Plan& pl = s.plan;
+  pl.valid = false;
+  pl.grid = g;
+  pl.precision = precision;
+  pl.planes.assign(g.fz, PlaneInfo{});
+  const double zL = s.L * s.d;
+  const double dz = (g.z_end - g.z_begin) / g.fz;
+  std::vector<int> per_layer(s.L, 0);
+  std::vector<ExtPlane> ext;
+  for (int j = 0; j < g.fz; ++j) {
+    const double z = g.z_begin + (j + 0.5) * dz;
+    PlaneInfo& pi = pl.planes[j];
+    if (z < 0.0) {
+      pi = {0, -1, z, 0.0};
+      ext.push_back({j, 0, z});
+    } else if (z >= zL) {
+      pi = {2, s.L, z - zL, 0.0};
+      ext.push_back({j, 2, z - zL});
+    } else {
+      int l = std::min((int)std::floor(z / s.d), s.L - 1);
+      pi = {1, l, z - l * s.d, z - (l + 1) * s.d};
+      per_layer[l]++;
+    }
+  }
+  int maxc = 0;
+  for (int c : per_layer) maxc = std::max(maxc, c);
+  int zt = 1;
+  while (zt < std::min(maxc, 8)) zt *= 2;
+  pl.zt = zt;
+  pl.tasks.clear();
+  std::vector<double> tdz;
+  for (int j = 0; j < g.fz;) {
+    if (pl.planes[j].kind != 1) {
+      ++j;
+      continue;
+    }
+    const int l = pl.planes[j].layer;
+    Task t{l, j, 0, 0};
+    while (j < g.fz && t.count < zt && pl.planes[j].kind == 1 && pl.planes[j].layer == l) {
+      tdz.push_back(pl.planes[j].dz_top);
+      tdz.push_back(pl.planes[j].dz_bot);
+      ++t.count;
+      ++j;
+    }
+    for (int p = t.count; p < zt; ++p) {
+      tdz.push_back(0.0);
+      tdz.push_back(0.0);
+    }
+    pl.tasks.push_back(t);
+  }
+  pl.n_exterior = (int)ext.size();
+  int rc;
+  if ((rc = upload(pl.d_tasks, pl.tasks.data(), pl.tasks.size() * sizeof(Task))) ||
+      (rc = upload(pl.d_task_dz, tdz.data(), tdz.size() * sizeof(double))) ||
+      (rc = upload(pl.d_ext, ext.data(), ext.size() * sizeof(ExtPlane))))
+    return rc;
+  const int eb = elem_bytes(precision);
+  const size_t n2 = 2 * (size_t)s.M;
+  if ((rc = pl.d_w.reserve(std::max<size_t>(16, pl.tasks.size() * 2 * zt * n2 * eb))) ||
+      (rc = pl.d_spec.reserve((size_t)g.fz * 3 * s.M * eb)) ||
+      (rc = pl.d_t1.reserve((size_t)g.fz * 3 * s.V * g.fx * eb)))
+    return rc;
+  // inverse-transform twiddles W_x[u][f] = exp(2 pi i u f / fx), W_y[v][g]
+  std::vector<zc> twx((size_t)s.U * g.fx), twy((size_t)s.V * g.fy);
+  for (int ui = 0; ui < s.U; ++ui)
+    for (int f = 0; f < g.fx; ++f)
+      twx[(size_t)ui * g.fx + f] = twiddle_inv((long long)(ui - s.U / 2) * f, g.fx);
+  for (int vi = 0; vi < s.V; ++vi)
+    for (int gg = 0; gg < g.fy; ++gg)
+      twy[(size_t)vi * g.fy + gg] = twiddle_inv((long long)(vi - s.V / 2) * gg, g.fy);
+  if (precision == SCW_FP64) {
+    std::vector<double> a, b;
+    pack(twx, a);
+    pack(twy, b);
+    if ((rc = upload(pl.d_twx, a.data(), a.size() * 8)) ||
+        (rc = upload(pl.d_twy, b.data(), b.size() * 8)))
+      return rc;
+  } else {
+    std::vector<float> a, b;
+    pack(twx, a);
+    pack(twy, b);
+    if ((rc = upload(pl.d_twx, a.data(), a.size() * 4)) ||
+        (rc = upload(pl.d_twy, b.data(), b.size() * 4)))
+      return rc;
+  }
+  pl.valid = true;
+  return SCW_OK;
+}
+
+bool same_grid(const scw_grid& a, const scw_grid& b) {
+  return a.fx == b.fx && a.fy == b.fy && a.fz == b.fz && a.z_begin == b.z_begin &&
+         a.z_end == b.z_end;
+}
+
+int check_grid(const scw_grid* g) {
+  if (!g) return fail(SCW_EINVAL, "grid is null");
+  if (g->fx < 1 || g->fy < 1 || g->fz < 1)
+    return fail(SCW_EINVAL, "grid sizes must be positive");
+  if ((long long)g->fz * 3 > 65535) return fail(SCW_EINVAL, "fz above 21845");
+  if ((long long)g->fy > 65535 * 8LL) return fail(SCW_EINVAL, "fy too large");
+  if (!(g->z_end > g->z_begin)) return fail(SCW_EINVAL, "z_end must exceed z_begin");
+  return SCW_OK;
+}
+
+}  // namespace
+}  // namespace scw
+
+using namespace scw;
+
+extern "C" {
+
+const char* scw_last_error(void) { return g_err.c_str(); }
+
+int scw_create(scw_ctx** out, int hip_device, int host_threads) {
+  if (!out) return fail(SCW_EINVAL, "out is null");
+  *out = nullptr;
+  int ndev = 0;
+  SCW_HIP(hipGetDeviceCount(&ndev));
+  if (hip_device < 0 || hip_device >= ndev)
+    return fail(SCW_EINVAL, "no HIP device " + std::to_string(hip_device));
+  scw_ctx* c = new (std::nothrow) scw_ctx();
+  if (!c) return fail(SCW_ENOMEM, "context allocation failed");
+  c->c.device = hip_device;
+  unsigned hw = std::thread::hardware_concurrency();
+  c->c.host_threads = host_threads > 0 ? host_threads : (int)std::max(1u, hw);
+  if (hipSetDevice(hip_device) != hipSuccess ||
+      hipStreamCreateWithFlags(&c->c.setup_stream, hipStreamNonBlocking) != hipSuccess) {
+    delete c;
+    return fail(SCW_EHIP, "could not create the setup stream");
+  }
+  *out = c;
+  return SCW_OK;
+}
+
+static void profile_free(scw::Context& c);
+
+void scw_destroy(scw_ctx* ctx) {
+  if (!ctx) return;
+  profile_free(ctx->c);
+  if (ctx->c.setup_stream) (void)hipStreamDestroy(ctx->c.setup_stream);
+  delete ctx;
+}
+
+int scw_solve(scw_ctx* ctx, const scw_problem* prob, scw_solution** out) {
+  if (!ctx || !prob || !out) return fail(SCW_EINVAL, "null argument");
+  *out = nullptr;
+  scw_solution* sol = new (std::nothrow) scw_solution();
+  if (!sol) return fail(SCW_ENOMEM, "solution allocation failed");
+  int rc;
+  try {
+    rc = solve_problem(ctx->c, *prob, sol->s);
+  } catch (const std::bad_alloc&) {
+    rc = fail(SCW_ENOMEM, "host allocation failed during setup");
+  } catch (const std::exception& e) {
+    rc = fail(SCW_EINVAL, std::string("setup failed: ") + e.what());
+  }
+  if (rc) {
+    delete sol;
+    return rc;
+  }
+  *out = sol;
+  return SCW_OK;
+}
+
+void scw_solution_free(scw_solution* sol) { delete sol; }
+
+int scw_solution_info_get(const scw_solution* sol, scw_solution_info* info) {
+  if (!sol || !info) return fail(SCW_EINVAL, "null argument");
+  *info = sol->s.info;
+  return SCW_OK;
+}
+
+int scw_solution_exterior(const scw_solution* sol, double* p_inc, double* p_ref,
+                          double* p_trn) {
+  if (!sol) return fail(SCW_EINVAL, "null solution");
+  const Solution& s = sol->s;
+  const size_t n = 3 * (size_t)s.M;
+  if (p_inc) std::copy(s.p_inc.begin(), s.p_inc.end(), reinterpret_cast<zc*>(p_inc));
+  if (p_ref) std::copy(s.p_ref.begin(), s.p_ref.end(), reinterpret_cast<zc*>(p_ref));
+  if (p_trn) std::copy(s.p_trn.begin(), s.p_trn.end(), reinterpret_cast<zc*>(p_trn));
+  (void)n;
+  return SCW_OK;
+}
+
+int scw_synthesize(scw_ctx* ctx, scw_solution* sol, const scw_grid* grid, int precision,
+                   void* E_dev, void* hip_stream) {
+  if (!ctx || !sol || !E_dev) return fail(SCW_EINVAL, "null argument");
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  if (precision != SCW_FP64 && precision != SCW_FP32)
+    return fail(SCW_EINVAL, "precision " + std::to_string(precision) + " is not available");
+  Solution& s = sol->s;
+  if (s.device != ctx->c.device) return fail(SCW_EINVAL, "solution belongs to another device");
+  SCW_HIP(hipSetDevice(ctx->c.device));
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  const size_t pl_elems = (size_t)s.L * 3 * s.M * 2 * s.M;
+  if (precision == SCW_FP32 && s.d_P32.bytes < pl_elems * 8) {
+    if ((rc = s.d_P32.reserve(pl_elems * 8))) return rc;
+    SCW_HIP(launch_p_to_fp32(s.d_P64.as<double>(), s.d_P32.as<float>(), pl_elems, st));
+  }
+  if (!s.plan.valid || s.plan.precision != precision || !same_grid(s.plan.grid, *grid)) {
+    SCW_HIP(hipStreamSynchronize(st));
+    if ((rc = build_plan(s, *grid, precision))) return rc;
+  }
+  Plan& pl = s.plan;
+  SynthArgs a{};
+  a.M = s.M;
+  a.U = s.U;
+  a.V = s.V;
+  a.L = s.L;
+  a.fx = grid->fx;
+  a.fy = grid->fy;
+  a.fz = grid->fz;
+  a.zt = pl.zt;
+  a.ntasks = (int)pl.tasks.size();
+  a.n_ext = pl.n_exterior;
+  a.P = precision == SCW_FP64 ? s.d_P64.p : s.d_P32.p;
+  a.kg = s.d_kg.as<double>();
+  a.a = s.d_a.as<double>();
+  a.b = s.d_b.as<double>();
+  a.ext = s.d_ext.as<double>();
+  a.ksz = s.d_ksz.as<double>();
+  a.tasks = pl.d_tasks.as<Task>();
+  a.task_dz = pl.d_task_dz.as<double>();
+  a.ext_planes = pl.d_ext.p;
+  a.w = pl.d_w.p;
+  a.spec = pl.d_spec.p;
+  a.t1 = pl.d_t1.p;
+  a.twx = pl.d_twx.p;
+  a.twy = pl.d_twy.p;
+  a.E = E_dev;
+  hipEvent_t* ev = nullptr;
+  Context& c = ctx->c;
+  if (c.prof_used < c.prof_max) ev = c.prof_events.data() + (size_t)c.prof_used++ * (kNumStages + 1);
+  SCW_HIP(precision == SCW_FP64 ? launch_synthesis_fp64(a, st, ev)
+                                : launch_synthesis_fp32(a, st, ev));
+  return SCW_OK;
+}
+
+static void profile_free(Context& c) {
+  for (hipEvent_t e : c.prof_events) (void)hipEventDestroy(e);
+  c.prof_events.clear();
+  c.prof_max = c.prof_used = 0;
+}
+
+int scw_profile_begin(scw_ctx* ctx, int max_calls) {
+  if (!ctx || max_calls < 1 || max_calls > 100000) return fail(SCW_EINVAL, "bad profile request");
+  Context& c = ctx->c;
+  SCW_HIP(hipSetDevice(c.device));
+  profile_free(c);
+  c.prof_events.resize((size_t)max_calls * (kNumStages + 1));
+  for (auto& e : c.prof_events) {
+    if (hipEventCreate(&e) != hipSuccess) {
+      e = nullptr;
+      profile_free(c);
+      return fail(SCW_EHIP, "hipEventCreate failed");
+    }
+  }
+  c.prof_max = max_calls;
+  c.prof_used = 0;
+  return SCW_OK;
+}
+
+int scw_profile_end(scw_ctx* ctx, double* stage_ms, int n_stages, int* calls) {
+  if (!ctx || !stage_ms || n_stages < 1 || n_stages > 8) return fail(SCW_EINVAL, "bad profile query");
+  Context& c = ctx->c;
+  SCW_HIP(hipSetDevice(c.device));
+  std::vector<double> acc(kNumStages, 0.0);
+  for (int k = 0; k < c.prof_used; ++k) {
+    hipEvent_t* ev = c.prof_events.data() + (size_t)k * (kNumStages + 1);
+    SCW_HIP(hipEventSynchronize(ev[kNumStages]));
+    for (int i = 0; i < kNumStages; ++i) {
+      float ms = 0;
+      SCW_HIP(hipEventElapsedTime(&ms, ev[i], ev[i + 1]));
+      acc[i] += ms;
+    }
+  }
+  for (int i = 0; i < n_stages; ++i)
+    stage_ms[i] = (i < kNumStages && c.prof_used) ? acc[i] / c.prof_used : 0.0;
+  if (calls) *calls = c.prof_used;
+  profile_free(c);
+  return SCW_OK;
+}
+
+const char* scw_stage_name(int stage) {
+  static const char* names[kNumStages] = {"phase", "modal_sum", "exterior", "idft_x", "idft_y"};
+  return (stage >= 0 && stage < kNumStages) ? names[stage] : "";
+}
+
+int scw_field(scw_ctx* ctx, const scw_problem* prob, const scw_grid* grid, int precision,
+              void* E_dev, void* hip_stream) {
+  scw_solution* sol = nullptr;
+  int rc = scw_solve(ctx, prob, &sol);
+  if (rc) return rc;
+  rc = scw_synthesize(ctx, sol, grid, precision, E_dev, hip_stream);
+  if (rc == SCW_OK && hipStreamSynchronize(reinterpret_cast<hipStream_t>(hip_stream)) != hipSuccess)
+    rc = fail(SCW_EHIP, "stream synchronize failed");
+  scw_solution_free(sol);
+  return rc;
+}
+
+double scw_synthesis_bytes(const scw_solution* sol, const scw_grid* grid, int precision) {
+  if (!sol || !grid || grid->fz < 1) return 0.0;
+  const Solution& s = sol->s;
+  const double eb = precision == SCW_FP64 ? 16.0 : 8.0;
+  const double zL = s.L * s.d;
+  const double dz = (grid->z_end - grid->z_begin) / grid->fz;
+  std::vector<char> touched(s.L, 0);
+  for (int j = 0; j < grid->fz; ++j) {
+    const double z = grid->z_begin + (j + 0.5) * dz;
+    if (z >= 0.0 && z < zL) touched[std::min((int)std::floor(z / s.d), s.L - 1)] = 1;
+  }
+  double layers = 0;
+  for (char t : touched) layers += t;
+  const double pbytes = layers * 3.0 * s.M * 2.0 * s.M * eb;
+  const double ebytes = 3.0 * grid->fx * grid->fy * grid->fz * eb;
+  return pbytes + ebytes;
+}
+
+}  // extern "C"

@@ -1,0 +1,185 @@
+// Internal types shared by the host setup, the kernel launchers and the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <complex>
+#include <cstdint>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/scw.h"
+
+namespace scw {
+
+using zc = std::complex<double>;
+
+// ------------------------------------------------------------------ errors
+struct Error {
+  int code;
+  std::string msg;
+};
+void set_error(int code, const std::string& msg);
+int fail(int code, const std::string& msg);
+
+#define SCW_HIP(call)                                                          \
+  do {                                                                         \
+    hipError_t e_ = (call);                                                    \
+    if (e_ != hipSuccess)                                                      \
+      return ::scw::fail(SCW_EHIP, std::string(#call) + ": " +                 \
+                                       hipGetErrorString(e_) + " (" +          \
+                                       std::to_string((int)e_) + ")");         \
+  } while (0)
+
+// ------------------------------------------------------------------ device memory
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  // Grows (never shrinks); contents are not preserved.
+  int reserve(size_t n) {
+    if (n <= bytes) return SCW_OK;
+    release();
+    if (n == 0) return SCW_OK;
+    if (hipMalloc(&p, n) != hipSuccess) {
+      p = nullptr;
+      return fail(SCW_ENOMEM, "hipMalloc of " + std::to_string(n) + " bytes failed");
+    }
+    bytes = n;
+    return SCW_OK;
+  }
+  template <typename T>
+  T* as() const { return reinterpret_cast<T*>(p); }
+};
+
+// ------------------------------------------------------------------ synthesis plan
+// One interior task = one layer and up to `zt` consecutive planes inside it.
+struct Task {
+  int layer;
+  int plane0;   // first output plane index
+  int count;    // planes in this task (<= zt)
+  int pad;
+};
+
+// Exterior plane entry of a plan (device table).
+struct ExtPlane {
+  int plane;
+  int kind;   // 0 above, 2 below
+  double dz;  // z - z0 (above) or z - zL (below)
+};
+
+struct PlaneInfo {
+  int kind;     // 0 above, 1 inside, 2 below
+  int layer;
+  double dz_top;  // z - z_top(layer) inside; z - z0 above; z - zL below
+  double dz_bot;  // z - z_bot(layer) inside
+};
+
+struct Plan {
+  scw_grid grid{};
+  int precision = -1;
+  int zt = 0;                       // planes per task (1, 2, 4 or 8)
+  std::vector<Task> tasks;
+  std::vector<PlaneInfo> planes;
+  int n_exterior = 0;
+  DevBuf d_tasks;                   // Task[ntasks]
+  DevBuf d_task_dz;                 // double2 [ntasks][zt] (dz_top, dz_bot)
+  DevBuf d_ext;                     // int2 + double: exterior plane table
+  DevBuf d_w;                       // W  [ntasks][2][zt][2M] complex<T>
+  DevBuf d_spec;                    // [fz][3M] complex<T>
+  DevBuf d_t1;                      // [fz][3][V][fx] complex<T>
+  DevBuf d_twx;                     // [U][fx] complex<T>
+  DevBuf d_twy;                     // [V][fy] complex<T>
+  DevBuf d_twy_split;               // split-precision copies for MFMA paths
+  DevBuf d_p_lo;                    // unused placeholder for split P
+  bool valid = false;
+};
+
+// ------------------------------------------------------------------ solution
+struct Solution {
+  int U = 0, V = 0, M = 0, L = 0;
+  double lam = 0, k = 0, X = 0, Y = 0, d = 0;
+  std::vector<int> u, v;
+  std::vector<double> sx, sy;
+  std::vector<zc> sz_top, sz_bot;
+  std::vector<zc> p_inc, p_ref, p_trn;   // [3M]
+  // per layer, forward-branch eigenvalues and mode coefficients
+  std::vector<zc> gamma;                 // [L][2M]
+  std::vector<zc> a, b;                  // [L][2M]
+  scw_solution_info info{};
+
+  // device copies
+  DevBuf d_P64;      // [L][3M][2M] complex128, row-major
+  DevBuf d_P32;      // [L][3M][2M] complex64 (lazy)
+  DevBuf d_kg;       // [L][2M] complex128: k * gamma
+  DevBuf d_a, d_b;   // [L][2M] complex128
+  DevBuf d_ext;      // [3][3M] complex128: p_inc, p_ref, p_trn
+  DevBuf d_ksz;      // [2][M] complex128: k*sz_top, k*sz_bot
+  Plan plan;
+  int device = 0;
+};
+
+// ------------------------------------------------------------------ context
+constexpr int kNumStages = 5;  // phase, modal, exterior, idft_x, idft_y
+
+struct Context {
+  int device = 0;
+  int host_threads = 1;
+  hipStream_t setup_stream = nullptr;
+  // profiling: (kNumStages + 1) events per recorded call
+  std::vector<hipEvent_t> prof_events;
+  int prof_max = 0;
+  int prof_used = 0;
+};
+
+// ------------------------------------------------------------------ setup
+int solve_problem(Context& ctx, const scw_problem& prob, Solution& sol);
+
+// ------------------------------------------------------------------ kernels
+// All launchers enqueue on `s` and return a HIP status code.
+hipError_t launch_band_dft(const double* n, int L, int ny, int nx, int hu, int hv,
+                           bool inverse_eps_too, bool square, double* rowbuf,
+                           double* out_eps, double* out_inv, hipStream_t s);
+hipError_t launch_assemble_ac(const double* phi, const double* psi,
+                              const int* u, const int* v, const double* sx,
+                              const double* sy, int U, int V, int L,
+                              double* A, double* C, hipStream_t s);
+hipError_t launch_build_p(const double* X, const double* Y, const double* psi,
+                          const int* u, const int* v, const double* sx,
+                          const double* sy, int U, int V, int nlayers,
+                          double* P, hipStream_t s);
+hipError_t launch_p_to_fp32(const double* P64, float* P32, size_t n_complex,
+                            hipStream_t s);
+
+struct SynthArgs {
+  int M, U, V, L, fx, fy, fz, zt, ntasks, n_ext;
+  const void* P;           // [L][3M][2M] complex<T>
+  const double* kg;        // [L][2M] complex128
+  const double* a;         // [L][2M]
+  const double* b;         // [L][2M]
+  const double* ext;       // [3][3M]
+  const double* ksz;       // [2][M]
+  const Task* tasks;
+  const double* task_dz;   // [ntasks][zt][2]
+  const void* ext_planes;  // exterior plane table
+  void* w;                 // [ntasks][2][zt][2M] complex<T>
+  void* spec;              // [fz][3M]
+  void* t1;                // [fz][3][V][fx]
+  const void* twx;         // [U][fx]
+  const void* twy;         // [V][fy]
+  void* E;                 // [3][fz][fy][fx]
+};
+// `ev`, when non-null, holds kNumStages + 1 events recorded around the stages.
+hipError_t launch_synthesis_fp64(const SynthArgs& a, hipStream_t s, hipEvent_t* ev);
+hipError_t launch_synthesis_fp32(const SynthArgs& a, hipStream_t s, hipEvent_t* ev);
+
+}  // namespace scw

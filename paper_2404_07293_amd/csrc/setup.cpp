@@ -1,0 +1,629 @@
+// FP64 setup of one CWT problem (Sec. 3.1-3.4, Sec. 3.6): layer spectra and
+// property-matrix blocks on the device, eigendecompositions and the boundary
+// solve on the host (LAPACK), then the per-layer synthesis matrices on the
+// device.
+//
+// Eigenproblem. D = [[0, A], [C, 0]] (Eq. 21) gives D^2 = diag(A C, C A), so
+// the 4M eigenpairs of D come in pairs +-gamma_j with gamma_j^2 an eigenvalue
+// of the 2M x 2M product A C. With A C x_j = gamma_j^2 x_j and y_j = C x_j /
+// gamma_j, the forward eigenvector is [x_j; y_j] and the backward one
+// [x_j; -y_j]. So Q = W = [[X, X], [Y, -Y]] with forward columns first.
+//
+// Boundary solve. Field at the top / bottom of layer l (Eqs. 24-26 in the
+// top/bottom reading): W_l [a_l; E_l b_l] and W_l [E_l a_l; b_l], with
+// E_l = diag(exp(i k gamma d)) (|E| <= 1), a_l forward amplitudes referenced at
+// the top and b_l backward amplitudes referenced at the bottom.
+//   SCW_ROUTE_STABLE: eliminate from the bottom up. Below layer l the field at
+//   its bottom is F_{l+1} x_{l+1} (x = downward amplitudes of the region
+//   below, F_{L+1} = transmitted plane waves). Solving W_l [E a_l; b_l] =
+//   F_{l+1} x_{l+1} gives x_{l+1} = t_l E a_l and b_l = r_l E a_l, hence the
+//   field at the top of layer l is F_l a_l with F_l = W_l [I; E r_l E]. At the
+//   top surface, incident + reflected = F_1 a_1. Only E (never E^-1) appears.
+//   SCW_ROUTE_CONNECTION: the paper's K = prod B_l T_l^-1 and the 6M x 6M
+//   system C_t p_trn - K C_r p_ref = K C_i p_inc plus Gauss rows (Eq. 29).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <functional>
+#include <mutex>
+#include <thread>
+
+#include "lapack.h"
+#include "scw_internal.h"
+
+namespace scw {
+
+namespace {
+
+using Mat = std::vector<zc>;  // column-major
+
+double now_s() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+// Runs fn(i) for i in [0, n) on up to `threads` host threads. Each worker
+// pins MKL to one thread. Returns the first nonzero status.
+int parallel_for(int n, int threads, const std::function<int(int)>& fn) {
+  const Lapack& lp = lapack();
+  std::atomic<int> next(0), status(0);
+  std::mutex mu;
+  std::string msg;
+  auto worker = [&]() {
+    if (lp.set_threads_local) lp.set_threads_local(1);
+    for (;;) {
+      int i = next.fetch_add(1);
+      if (i >= n || status.load() != 0) break;
+      int rc = fn(i);
+      if (rc != 0) {
+        int zero = 0;
+        if (status.compare_exchange_strong(zero, rc)) {
+          std::lock_guard<std::mutex> g(mu);
+          msg = scw_last_error();
+        }
+      }
+    }
+    if (lp.set_threads_local) lp.set_threads_local(0);
+  };
+  int nt = std::max(1, std::min(threads, n));
+  std::vector<std::thread> pool;
+  for (int t = 1; t < nt; ++t) pool.emplace_back(worker);
+  worker();
+  for (auto& th : pool) th.join();
+  // a worker's message lives in that worker's thread-local slot; copy it here
+  if (status.load() != 0) set_error(status.load(), msg);
+  return status.load();
+}
+
+struct Lin {
+  const Lapack& lp;
+  void gemm(char ta, char tb, int m, int n, int k, zc alpha, const zc* A, int lda,
+            const zc* B, int ldb, zc beta, zc* C, int ldc) const {
+    lp.zgemm(&ta, &tb, &m, &n, &k, &alpha, A, &lda, B, &ldb, &beta, C, &ldc);
+  }
+  int lu(int n, zc* A, std::vector<int>& piv) const {
+    piv.resize(n);
+    int info = 0;
+    lp.zgetrf(&n, &n, A, &n, piv.data(), &info);
+    return info;
+  }
+  int lu_solve(int n, int nrhs, const zc* LU, const std::vector<int>& piv, zc* B) const {
+    int info = 0;
+    char t = 'N';
+    lp.zgetrs(&t, &n, &nrhs, LU, &n, piv.data(), B, &n, &info);
+    return info;
+  }
+};
+
+Mat identity(int n) {
+  Mat I((size_t)n * n, zc(0));
+  for (int i = 0; i < n; ++i) I[(size_t)i * n + i] = 1.0;
+  return I;
+}
+
+// Transverse plane-wave field map for a half-space wave with s = (sx, sy, sigma):
+// [px, py] -> [px, py, bx, by] with pz = -(sx px + sy py)/sigma (Eq. 14) and
+// b = s x p. Returns the 2M x 2M H block (the E block is the identity).
+Mat half_space_h(const Solution& s, const std::vector<zc>& sigma) {
+  const int M = s.M, n2 = 2 * M;
+  Mat H((size_t)n2 * n2, zc(0));
+  for (int m = 0; m < M; ++m) {
+    const zc sg = sigma[m];
+    const double sx = s.sx[m], sy = s.sy[m];
+    // bx = -(sx sy / sg) px - (sy^2/sg + sg) py ; by = (sg + sx^2/sg) px + (sx sy/sg) py
+    H[(size_t)m * n2 + m] = -(sx * sy) / sg;
+    H[(size_t)(M + m) * n2 + m] = -(sy * sy / sg + sg);
+    H[(size_t)m * n2 + M + m] = sg + sx * sx / sg;
+    H[(size_t)(M + m) * n2 + M + m] = (sx * sy) / sg;
+  }
+  return H;
+}
+
+// Full 4M x 3M map C(sigma) of Eq. 28 with the corrected sign of b_x:
+// [px, py, pz] -> [px, py, sy pz - sigma py, sigma px - sx pz].
+Mat c_map(const Solution& s, const std::vector<zc>& sigma) {
+  const int M = s.M, n4 = 4 * M;
+  Mat C((size_t)n4 * 3 * M, zc(0));
+  auto at = [&](int r, int c) -> zc& { return C[(size_t)c * n4 + r]; };
+  for (int m = 0; m < M; ++m) {
+    at(m, m) = 1.0;
+    at(M + m, M + m) = 1.0;
+    at(2 * M + m, M + m) = -sigma[m];
+    at(2 * M + m, 2 * M + m) = s.sy[m];
+    at(3 * M + m, m) = sigma[m];
+    at(3 * M + m, 2 * M + m) = -s.sx[m];
+  }
+  return C;
+}
+
+zc principal_sqrt_branch(zc lam, double tol_abs) {
+  zc g = std::sqrt(lam);  // Re >= 0
+  if (g.imag() < -tol_abs) g = -g;
+  return g;
+}
+
+struct LayerHost {
+  Mat A, C;           // property blocks (freed after use)
+  Mat X, Y;           // E and H parts of the forward eigenvectors
+  Mat Xlu, Ylu;       // LU factors (stable route)
+  std::vector<int> Xpiv, Ypiv;
+  std::vector<zc> gamma;   // forward branch, [2M]
+  std::vector<zc> E;       // exp(i k gamma d)
+};
+
+int layer_eig(const Lin& lin, Solution& s, LayerHost& h) {
+  const int n2 = 2 * s.M;
+  Mat AC((size_t)n2 * n2);
+  lin.gemm('N', 'N', n2, n2, n2, 1.0, h.A.data(), n2, h.C.data(), n2, 0.0, AC.data(), n2);
+  std::vector<zc> lam(n2), work(1);
+  std::vector<double> rwork(2 * n2);
+  h.X.assign((size_t)n2 * n2, zc(0));
+  int lwork = -1, info = 0, one = 1;
+  zc dummy;
+  char jl = 'N', jr = 'V';
+  lin.lp.zgeev(&jl, &jr, &n2, AC.data(), &n2, lam.data(), &dummy, &one, h.X.data(), &n2,
+               work.data(), &lwork, rwork.data(), &info);
+  lwork = std::max(1, (int)work[0].real());
+  work.resize(lwork);
+  lin.lp.zgeev(&jl, &jr, &n2, AC.data(), &n2, lam.data(), &dummy, &one, h.X.data(), &n2,
+               work.data(), &lwork, rwork.data(), &info);
+  if (info != 0) return fail(SCW_ELAPACK, "zgeev info=" + std::to_string(info));
+  double gmax = 0;
+  h.gamma.resize(n2);
+  for (int j = 0; j < n2; ++j) gmax = std::max(gmax, std::sqrt(std::abs(lam[j])));
+  // forward iff Im(gamma) > tol, or |Im| <= tol and Re > 0 (tol = 1e-12 max|gamma|)
+  for (int j = 0; j < n2; ++j) h.gamma[j] = principal_sqrt_branch(lam[j], 1e-12 * gmax);
+  double gmin = gmax;
+  for (int j = 0; j < n2; ++j) gmin = std::min(gmin, std::abs(h.gamma[j]));
+  if (gmin < 1e-9 * gmax)
+    return fail(SCW_EDEFECTIVE, "near-defective property matrix: |gamma| ~ 0");
+  // Y = C X diag(1/gamma)
+  h.Y.assign((size_t)n2 * n2, zc(0));
+  lin.gemm('N', 'N', n2, n2, n2, 1.0, h.C.data(), n2, h.X.data(), n2, 0.0, h.Y.data(), n2);
+  for (int j = 0; j < n2; ++j) {
+    const zc ig = 1.0 / h.gamma[j];
+    zc* col = h.Y.data() + (size_t)j * n2;
+    for (int r = 0; r < n2; ++r) col[r] *= ig;
+  }
+  h.E.resize(n2);
+  for (int j = 0; j < n2; ++j)
+    h.E[j] = std::exp(zc(0, 1) * s.k * h.gamma[j] * s.d);
+  Mat().swap(h.A);
+  Mat().swap(h.C);
+  return SCW_OK;
+}
+
+// ---------------------------------------------------------------- stable route
+int solve_stable(const Lin& lin, Solution& s, std::vector<LayerHost>& layers) {
+  const int M = s.M, n2 = 2 * M, n4 = 4 * M, L = s.L;
+  std::vector<Mat> t(L), r(L);
+  // F_{L+1}: transmitted waves
+  Mat Fe = identity(n2);
+  Mat Fh = half_space_h(s, s.sz_bot);
+  for (int l = L - 1; l >= 0; --l) {
+    LayerHost& h = layers[l];
+    Mat A1 = Fe, A2 = Fh;
+    if (lin.lu_solve(n2, n2, h.Xlu.data(), h.Xpiv, A1.data()) != 0 ||
+        lin.lu_solve(n2, n2, h.Ylu.data(), h.Ypiv, A2.data()) != 0)
+      return fail(SCW_ELAPACK, "zgetrs failed in the stable route");
+    Mat Gt((size_t)n2 * n2), Gb((size_t)n2 * n2);
+    for (size_t i = 0; i < Gt.size(); ++i) {
+      Gt[i] = 0.5 * (A1[i] + A2[i]);
+      Gb[i] = 0.5 * (A1[i] - A2[i]);
+    }
+    std::vector<int> piv;
+    if (lin.lu(n2, Gt.data(), piv) != 0)
+      return fail(SCW_EILLCOND, "singular interface matrix in the stable route");
+    t[l] = identity(n2);
+    lin.lu_solve(n2, n2, Gt.data(), piv, t[l].data());
+    r[l].assign((size_t)n2 * n2, zc(0));
+    lin.gemm('N', 'N', n2, n2, n2, 1.0, Gb.data(), n2, t[l].data(), n2, 0.0, r[l].data(), n2);
+    // F_l = [X (I + E r E); Y (I - E r E)]
+    Mat P1((size_t)n2 * n2), P2((size_t)n2 * n2);
+    for (int c = 0; c < n2; ++c)
+      for (int rr = 0; rr < n2; ++rr) {
+        const zc ere = h.E[rr] * r[l][(size_t)c * n2 + rr] * h.E[c];
+        const zc id = (rr == c) ? zc(1) : zc(0);
+        P1[(size_t)c * n2 + rr] = id + ere;
+        P2[(size_t)c * n2 + rr] = id - ere;
+      }
+    Fe.assign((size_t)n2 * n2, zc(0));
+    Fh.assign((size_t)n2 * n2, zc(0));
+    lin.gemm('N', 'N', n2, n2, n2, 1.0, h.X.data(), n2, P1.data(), n2, 0.0, Fe.data(), n2);
+    lin.gemm('N', 'N', n2, n2, n2, 1.0, h.Y.data(), n2, P2.data(), n2, 0.0, Fh.data(), n2);
+  }
+  // top surface: F(-sz_top) rho - F_1 a_1 = -C_i p_inc
+  std::vector<zc> msz(M);
+  for (int m = 0; m < M; ++m) msz[m] = -s.sz_top[m];
+  Mat Hr = half_space_h(s, msz);
+  Mat S((size_t)n4 * n4, zc(0));
+  for (int c = 0; c < n2; ++c) {
+    S[(size_t)c * n4 + c] = 1.0;
+    for (int rr = 0; rr < n2; ++rr) S[(size_t)c * n4 + n2 + rr] = Hr[(size_t)c * n2 + rr];
+    for (int rr = 0; rr < n2; ++rr) {
+      S[(size_t)(n2 + c) * n4 + rr] = -Fe[(size_t)c * n2 + rr];
+      S[(size_t)(n2 + c) * n4 + n2 + rr] = -Fh[(size_t)c * n2 + rr];
+    }
+  }
+  Mat Ci = c_map(s, s.sz_top);
+  std::vector<zc> rhs(n4, zc(0));
+  for (int c = 0; c < 3 * M; ++c)
+    for (int rr = 0; rr < n4; ++rr) rhs[rr] -= Ci[(size_t)c * n4 + rr] * s.p_inc[c];
+  std::vector<int> piv;
+  if (lin.lu(n4, S.data(), piv) != 0)
+    return fail(SCW_EILLCOND, "singular top-surface system in the stable route");
+  lin.lu_solve(n4, 1, S.data(), piv, rhs.data());
+  s.p_ref.assign(3 * M, zc(0));
+  for (int m = 0; m < M; ++m) {
+    const zc px = rhs[m], py = rhs[M + m];
+    s.p_ref[m] = px;
+    s.p_ref[M + m] = py;
+    s.p_ref[2 * M + m] = (s.sx[m] * px + s.sy[m] * py) / s.sz_top[m];
+  }
+  std::vector<zc> a(rhs.begin() + n2, rhs.end()), ea(n2), nxt(n2);
+  s.a.assign((size_t)L * n2, zc(0));
+  s.b.assign((size_t)L * n2, zc(0));
+  for (int l = 0; l < L; ++l) {
+    std::copy(a.begin(), a.end(), s.a.begin() + (size_t)l * n2);
+    for (int j = 0; j < n2; ++j) ea[j] = layers[l].E[j] * a[j];
+    lin.gemm('N', 'N', n2, 1, n2, 1.0, r[l].data(), n2, ea.data(), n2, 0.0,
+             s.b.data() + (size_t)l * n2, n2);
+    lin.gemm('N', 'N', n2, 1, n2, 1.0, t[l].data(), n2, ea.data(), n2, 0.0, nxt.data(), n2);
+    a = nxt;
+  }
+  s.p_trn.assign(3 * M, zc(0));
+  for (int m = 0; m < M; ++m) {
+    const zc px = a[m], py = a[M + m];
+    s.p_trn[m] = px;
+    s.p_trn[M + m] = py;
+    s.p_trn[2 * M + m] = -(s.sx[m] * px + s.sy[m] * py) / s.sz_bot[m];
+  }
+  return SCW_OK;
+}
+
+// ---------------------------------------------------------------- connection route
+int solve_connection(const Lin& lin, Solution& s, std::vector<LayerHost>& layers, int threads) {
+  const int M = s.M, n2 = 2 * M, n4 = 4 * M, n6 = 6 * M, L = s.L;
+  std::vector<Mat> Tlu(L), Bm(L), Mk(L);
+  std::vector<std::vector<int>> Tpiv(L);
+  // T_l = W diag(I, E), B_l = W diag(E, I), M_l = B_l T_l^-1 (Eq. 27)
+  int rc = parallel_for(L, threads, [&](int l) -> int {
+    LayerHost& h = layers[l];
+    Mat T((size_t)n4 * n4), B((size_t)n4 * n4);
+    for (int c = 0; c < n2; ++c)
+      for (int rr = 0; rr < n2; ++rr) {
+        const zc x = h.X[(size_t)c * n2 + rr], y = h.Y[(size_t)c * n2 + rr];
+        const zc e = h.E[c];
+        // forward column c, backward column n2 + c
+        T[(size_t)c * n4 + rr] = x;
+        T[(size_t)c * n4 + n2 + rr] = y;
+        T[(size_t)(n2 + c) * n4 + rr] = x * e;
+        T[(size_t)(n2 + c) * n4 + n2 + rr] = -y * e;
+        B[(size_t)c * n4 + rr] = x * e;
+        B[(size_t)c * n4 + n2 + rr] = y * e;
+        B[(size_t)(n2 + c) * n4 + rr] = x;
+        B[(size_t)(n2 + c) * n4 + n2 + rr] = -y;
+      }
+    if (lin.lu(n4, T.data(), Tpiv[l]) != 0)
+      return fail(SCW_EILLCOND, "singular layer matrix T in the connection route");
+    Mat Ti = identity(n4);
+    lin.lu_solve(n4, n4, T.data(), Tpiv[l], Ti.data());
+    Mk[l].assign((size_t)n4 * n4, zc(0));
+    lin.gemm('N', 'N', n4, n4, n4, 1.0, B.data(), n4, Ti.data(), n4, 0.0, Mk[l].data(), n4);
+    Tlu[l] = std::move(T);
+    Bm[l] = std::move(B);
+    return 0;
+  });
+  if (rc) return rc;
+  Mat K = identity(n4), tmp((size_t)n4 * n4);
+  for (int l = 0; l < L; ++l) {
+    lin.gemm('N', 'N', n4, n4, n4, 1.0, Mk[l].data(), n4, K.data(), n4, 0.0, tmp.data(), n4);
+    K.swap(tmp);
+    Mat().swap(Mk[l]);
+  }
+  std::vector<zc> msz(M);
+  for (int m = 0; m < M; ++m) msz[m] = -s.sz_top[m];
+  Mat Ci = c_map(s, s.sz_top), Cr = c_map(s, msz), Ct = c_map(s, s.sz_bot);
+  Mat KCr((size_t)n4 * 3 * M);
+  lin.gemm('N', 'N', n4, 3 * M, n4, 1.0, K.data(), n4, Cr.data(), n4, 0.0, KCr.data(), n4);
+  std::vector<zc> cip(n4, zc(0)), rhs(n6, zc(0));
+  for (int c = 0; c < 3 * M; ++c)
+    for (int rr = 0; rr < n4; ++rr) cip[rr] += Ci[(size_t)c * n4 + rr] * s.p_inc[c];
+  lin.gemm('N', 'N', n4, 1, n4, 1.0, K.data(), n4, cip.data(), n4, 0.0, rhs.data(), n6);
+  Mat A((size_t)n6 * n6, zc(0));
+  for (int c = 0; c < 3 * M; ++c)
+    for (int rr = 0; rr < n4; ++rr) {
+      A[(size_t)c * n6 + rr] = -KCr[(size_t)c * n4 + rr];
+      A[(size_t)(3 * M + c) * n6 + rr] = Ct[(size_t)c * n4 + rr];
+    }
+  for (int m = 0; m < M; ++m) {  // Gauss rows (Eq. 14)
+    A[(size_t)m * n6 + n4 + m] = s.sx[m];
+    A[(size_t)(M + m) * n6 + n4 + m] = s.sy[m];
+    A[(size_t)(2 * M + m) * n6 + n4 + m] = -s.sz_top[m];
+    A[(size_t)(3 * M + m) * n6 + n4 + M + m] = s.sx[m];
+    A[(size_t)(4 * M + m) * n6 + n4 + M + m] = s.sy[m];
+    A[(size_t)(5 * M + m) * n6 + n4 + M + m] = s.sz_bot[m];
+  }
+  char one = '1';
+  std::vector<double> rw(2 * n6);
+  const double anorm = lin.lp.zlange(&one, &n6, &n6, A.data(), &n6, rw.data());
+  std::vector<int> piv;
+  if (lin.lu(n6, A.data(), piv) != 0)
+    return fail(SCW_EILLCOND, "singular 6M x 6M connection system");
+  double rcond = 0;
+  int info = 0;
+  std::vector<zc> cw(2 * n6);
+  lin.lp.zgecon(&one, &n6, A.data(), &n6, &anorm, &rcond, cw.data(), rw.data(), &info);
+  s.info.connection_rcond = rcond;
+  if (!(rcond > 1e-15))
+    return fail(SCW_EILLCOND, "connection system is numerically singular (rcond " +
+                                  std::to_string(rcond) + ")");
+  lin.lu_solve(n6, 1, A.data(), piv, rhs.data());
+  s.p_ref.assign(rhs.begin(), rhs.begin() + 3 * M);
+  s.p_trn.assign(rhs.begin() + 3 * M, rhs.end());
+  // alpha_1 = T_1^-1 (C_i p_inc + C_r p_ref); alpha_l = T_l^-1 B_{l-1} alpha_{l-1}
+  std::vector<zc> alpha(cip);
+  for (int c = 0; c < 3 * M; ++c)
+    for (int rr = 0; rr < n4; ++rr) alpha[rr] += Cr[(size_t)c * n4 + rr] * s.p_ref[c];
+  s.a.assign((size_t)L * n2, zc(0));
+  s.b.assign((size_t)L * n2, zc(0));
+  std::vector<zc> nxt(n4);
+  for (int l = 0; l < L; ++l) {
+    if (l > 0) {
+      lin.gemm('N', 'N', n4, 1, n4, 1.0, Bm[l - 1].data(), n4, alpha.data(), n4, 0.0,
+               nxt.data(), n4);
+      alpha = nxt;
+    }
+    lin.lu_solve(n4, 1, Tlu[l].data(), Tpiv[l], alpha.data());
+    std::copy(alpha.begin(), alpha.begin() + n2, s.a.begin() + (size_t)l * n2);
+    std::copy(alpha.begin() + n2, alpha.end(), s.b.begin() + (size_t)l * n2);
+  }
+  return SCW_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- driver
+int solve_problem(Context& ctx, const scw_problem& p, Solution& s) {
+  const double t_start = now_s();
+  if (p.nx < 1 || p.ny < 1 || p.nz < 1 || !p.n)
+    return fail(SCW_EINVAL, "sample shape must be positive and n non-null");
+  if (p.U < 1 || p.V < 1 || p.U % 2 == 0 || p.V % 2 == 0)
+    return fail(SCW_EINVAL, "U and V must be odd and positive");
+  if (!(p.px > 0) || !(p.py > 0) || !(p.pz > 0) || !(p.lambda > 0))
+    return fail(SCW_EINVAL, "pitches and wavelength must be positive");
+  if (!(p.n_top > 0)) return fail(SCW_EINVAL, "n_top must be positive");
+  if (p.route != SCW_ROUTE_STABLE && p.route != SCW_ROUTE_CONNECTION)
+    return fail(SCW_EINVAL, "unknown route");
+  const bool image = p.inc_ex || p.inc_ey;
+  if (image && (p.inc_nx < 1 || p.inc_ny < 1))
+    return fail(SCW_EINVAL, "incident image shape must be positive");
+  if ((long long)p.U * p.V > 8192) return fail(SCW_EINVAL, "U*V above 8192");
+  const Lapack& lp = lapack();
+  if (!lp.ok) return fail(SCW_ELAPACK, "LAPACK unavailable: " + lp.error);
+  const Lin lin{lp};
+
+  s.U = p.U;
+  s.V = p.V;
+  s.M = p.U * p.V;
+  s.L = p.nz;
+  s.lam = p.lambda;
+  s.k = 2.0 * M_PI / p.lambda;
+  s.X = p.nx * p.px;
+  s.Y = p.ny * p.py;
+  s.d = p.pz;
+  const int M = s.M, n2 = 2 * M, L = s.L, U = s.U, V = s.V;
+  // Sec. 2.2 mode table and Eq. 6 spatial frequencies
+  s.u.resize(M);
+  s.v.resize(M);
+  s.sx.resize(M);
+  s.sy.resize(M);
+  s.sz_top.resize(M);
+  s.sz_bot.resize(M);
+  const zc nbot(p.n_bot_re, p.n_bot_im);
+  double min_sz = 1e300;
+  for (int m = 0; m < M; ++m) {
+    const int vv = m / U - V / 2;
+    const int uu = m - (vv + V / 2) * U - U / 2;
+    s.u[m] = uu;
+    s.v[m] = vv;
+    s.sx[m] = p.lambda * uu / s.X;
+    s.sy[m] = p.lambda * vv / s.Y;
+    const double st2 = s.sx[m] * s.sx[m] + s.sy[m] * s.sy[m];
+    // Eq. 2 with the branch Im >= 0
+    zc a = std::sqrt(zc(p.n_top * p.n_top - st2, 0.0));
+    zc b = std::sqrt(nbot * nbot - st2);
+    if (a.imag() < 0) a = -a;
+    if (b.imag() < 0 || (b.imag() == 0 && b.real() < 0)) b = -b;
+    s.sz_top[m] = a;
+    s.sz_bot[m] = b;
+    min_sz = std::min(min_sz, std::min(std::abs(a), std::abs(b)));
+  }
+  s.info.M = M;
+  s.info.L = L;
+  s.info.min_abs_sz = min_sz;
+  if (min_sz < 1e-9) return fail(SCW_EGRAZING, "grazing spatial frequency in a half-space");
+
+  SCW_HIP(hipSetDevice(ctx.device));
+  hipStream_t st = ctx.setup_stream;
+  hipEvent_t ev0, ev1;
+  SCW_HIP(hipEventCreate(&ev0));
+  SCW_HIP(hipEventCreate(&ev1));
+
+  // ---- device: band coefficients of n^2 and 1/n^2 (Eqs. 11-12)
+  const int nbu = 2 * U - 1, nbv = 2 * V - 1;
+  const size_t nvox = (size_t)p.nx * p.ny * p.nz;
+  DevBuf d_n, d_row, d_phi, d_psi, d_u, d_v, d_sx, d_sy;
+  int rc;
+  if ((rc = d_n.reserve(nvox * 16))) return rc;
+  if ((rc = d_row.reserve((size_t)2 * L * p.ny * nbu * 16))) return rc;
+  if ((rc = d_phi.reserve((size_t)L * nbv * nbu * 16))) return rc;
+  if ((rc = d_psi.reserve((size_t)L * nbv * nbu * 16))) return rc;
+  if ((rc = d_u.reserve(M * sizeof(int))) || (rc = d_v.reserve(M * sizeof(int))) ||
+      (rc = d_sx.reserve(M * 8)) || (rc = d_sy.reserve(M * 8)))
+    return rc;
+  SCW_HIP(hipMemcpyAsync(d_n.p, p.n, nvox * 16, hipMemcpyHostToDevice, st));
+  SCW_HIP(hipMemcpyAsync(d_u.p, s.u.data(), M * sizeof(int), hipMemcpyHostToDevice, st));
+  SCW_HIP(hipMemcpyAsync(d_v.p, s.v.data(), M * sizeof(int), hipMemcpyHostToDevice, st));
+  SCW_HIP(hipMemcpyAsync(d_sx.p, s.sx.data(), M * 8, hipMemcpyHostToDevice, st));
+  SCW_HIP(hipMemcpyAsync(d_sy.p, s.sy.data(), M * 8, hipMemcpyHostToDevice, st));
+  SCW_HIP(hipEventRecord(ev0, st));
+  SCW_HIP(launch_band_dft(d_n.as<double>(), L, p.ny, p.nx, U - 1, V - 1, true, true,
+                          d_row.as<double>(), d_phi.as<double>(), d_psi.as<double>(), st));
+
+  // ---- device: property blocks A, C per layer chunk, copied to the host
+  std::vector<LayerHost> layers(L);
+  const size_t blk = (size_t)n2 * n2;
+  const int chunk = (int)std::max<size_t>(1, std::min<size_t>(L, (size_t)(1u << 30) / (blk * 32)));
+  DevBuf d_A, d_C;
+  if ((rc = d_A.reserve(blk * 16 * chunk)) || (rc = d_C.reserve(blk * 16 * chunk))) return rc;
+  float asm_ms = 0;
+  for (int l0 = 0; l0 < L; l0 += chunk) {
+    const int nl = std::min(chunk, L - l0);
+    SCW_HIP(launch_assemble_ac(d_phi.as<double>() + (size_t)l0 * nbv * nbu * 2,
+                               d_psi.as<double>() + (size_t)l0 * nbv * nbu * 2, d_u.as<int>(),
+                               d_v.as<int>(), d_sx.as<double>(), d_sy.as<double>(), U, V, nl,
+                               d_A.as<double>(), d_C.as<double>(), st));
+    if (l0 == 0) {
+      SCW_HIP(hipEventRecord(ev1, st));
+      SCW_HIP(hipEventSynchronize(ev1));
+      SCW_HIP(hipEventElapsedTime(&asm_ms, ev0, ev1));
+    }
+    for (int l = l0; l < l0 + nl; ++l) {
+      layers[l].A.resize(blk);
+      layers[l].C.resize(blk);
+      SCW_HIP(hipMemcpyAsync(layers[l].A.data(), d_A.as<char>() + (size_t)(l - l0) * blk * 16,
+                             blk * 16, hipMemcpyDeviceToHost, st));
+      SCW_HIP(hipMemcpyAsync(layers[l].C.data(), d_C.as<char>() + (size_t)(l - l0) * blk * 16,
+                             blk * 16, hipMemcpyDeviceToHost, st));
+    }
+    SCW_HIP(hipStreamSynchronize(st));
+  }
+  s.info.assembly_device_ms = asm_ms * ((double)L / std::min(chunk, L));
+  d_A.release();
+  d_C.release();
+
+  // ---- incident coefficients (Sec. 2.3): in-band DFT of the images / plane wave
+  s.p_inc.assign(3 * M, zc(0));
+  if (image) {
+    const int hu = U / 2, hv = V / 2;
+    const size_t npx = (size_t)p.inc_nx * p.inc_ny;
+    DevBuf d_img, d_irow, d_ic;
+    if ((rc = d_img.reserve(npx * 16)) || (rc = d_irow.reserve((size_t)p.inc_ny * U * 16)) ||
+        (rc = d_ic.reserve((size_t)M * 16)))
+      return rc;
+    std::vector<zc> coef(M);
+    for (int comp = 0; comp < 2; ++comp) {
+      const double* img = comp == 0 ? p.inc_ex : p.inc_ey;
+      if (!img) continue;
+      SCW_HIP(hipMemcpyAsync(d_img.p, img, npx * 16, hipMemcpyHostToDevice, st));
+      SCW_HIP(launch_band_dft(d_img.as<double>(), 1, p.inc_ny, p.inc_nx, hu, hv, false, false,
+                              d_irow.as<double>(), d_ic.as<double>(), nullptr, st));
+      SCW_HIP(hipMemcpyAsync(coef.data(), d_ic.p, (size_t)M * 16, hipMemcpyDeviceToHost, st));
+      SCW_HIP(hipStreamSynchronize(st));
+      // the band is laid out [v + hv][u + hu], which is the mode order m
+      for (int m = 0; m < M; ++m) s.p_inc[comp * M + m] = coef[m];
+    }
+  } else {
+    int hit = -1;
+    for (int m = 0; m < M; ++m)
+      if (s.u[m] == p.pw_u && s.v[m] == p.pw_v) hit = m;
+    if (hit < 0) return fail(SCW_EINVAL, "plane-wave frequency outside the U x V band");
+    s.p_inc[hit] = zc(p.pw_ex[0], p.pw_ex[1]);
+    s.p_inc[M + hit] = zc(p.pw_ey[0], p.pw_ey[1]);
+  }
+  for (int m = 0; m < M; ++m)  // Gauss (Eq. 14)
+    s.p_inc[2 * M + m] = -(s.sx[m] * s.p_inc[m] + s.sy[m] * s.p_inc[M + m]) / s.sz_top[m];
+
+  // ---- host: eigendecompositions, one layer per worker (Sec. 3.2, Sec. 4.2)
+  const double t_eig = now_s();
+  const bool stable = p.route == SCW_ROUTE_STABLE;
+  rc = parallel_for(L, ctx.host_threads, [&](int l) -> int {
+    int r = layer_eig(lin, s, layers[l]);
+    if (r) return r;
+    if (stable) {
+      layers[l].Xlu = layers[l].X;
+      layers[l].Ylu = layers[l].Y;
+      if (lin.lu(n2, layers[l].Xlu.data(), layers[l].Xpiv) != 0 ||
+          lin.lu(n2, layers[l].Ylu.data(), layers[l].Ypiv) != 0)
+        return fail(SCW_EDEFECTIVE, "eigenvector matrix is singular");
+    }
+    return 0;
+  });
+  if (rc) return rc;
+  s.info.eig_seconds = now_s() - t_eig;
+  double gmin_rel = 1e300, growth = 0;
+  s.gamma.resize((size_t)L * n2);
+  for (int l = 0; l < L; ++l) {
+    double gmax = 0, gmin = 1e300, imax = 0;
+    for (int j = 0; j < n2; ++j) {
+      const zc g = layers[l].gamma[j];
+      s.gamma[(size_t)l * n2 + j] = g;
+      gmax = std::max(gmax, std::abs(g));
+      gmin = std::min(gmin, std::abs(g));
+      imax = std::max(imax, g.imag());
+    }
+    gmin_rel = std::min(gmin_rel, gmin / gmax);
+    growth += s.k * s.d * imax;
+  }
+  s.info.min_abs_gamma_rel = gmin_rel;
+  s.info.growth_exponent = growth;
+
+  // ---- host: boundary solve (Sec. 2.5.4, Sec. 3.3-3.4)
+  if (lp.set_threads) lp.set_threads(ctx.host_threads);
+  rc = stable ? solve_stable(lin, s, layers) : solve_connection(lin, s, layers, ctx.host_threads);
+  if (rc) return rc;
+
+  // ---- device: synthesis matrices P_l = [X; Psi (S_y Y_x - S_x Y_y)] (Sec. 4.1)
+  const size_t pl = (size_t)3 * M * n2;
+  if ((rc = s.d_P64.reserve(pl * 16 * L))) return rc;
+  DevBuf d_X, d_Y;
+  const int pchunk = std::max(1, std::min(L, (int)((size_t)(1u << 30) / (blk * 32))));
+  if ((rc = d_X.reserve(blk * 16 * pchunk)) || (rc = d_Y.reserve(blk * 16 * pchunk))) return rc;
+  for (int l0 = 0; l0 < L; l0 += pchunk) {
+    const int nl = std::min(pchunk, L - l0);
+    for (int l = l0; l < l0 + nl; ++l) {
+      SCW_HIP(hipMemcpyAsync(d_X.as<char>() + (size_t)(l - l0) * blk * 16, layers[l].X.data(),
+                             blk * 16, hipMemcpyHostToDevice, st));
+      SCW_HIP(hipMemcpyAsync(d_Y.as<char>() + (size_t)(l - l0) * blk * 16, layers[l].Y.data(),
+                             blk * 16, hipMemcpyHostToDevice, st));
+    }
+    SCW_HIP(launch_build_p(d_X.as<double>(), d_Y.as<double>(),
+                           d_psi.as<double>() + (size_t)l0 * nbv * nbu * 2, d_u.as<int>(),
+                           d_v.as<int>(), d_sx.as<double>(), d_sy.as<double>(), U, V, nl,
+                           s.d_P64.as<double>() + (size_t)l0 * pl * 2, st));
+    SCW_HIP(hipStreamSynchronize(st));
+  }
+  // per-layer k*gamma, a, b and the exterior coefficients
+  std::vector<zc> kg((size_t)L * n2), ext(9 * (size_t)M), ksz(2 * (size_t)M);
+  for (size_t i = 0; i < kg.size(); ++i) kg[i] = s.k * s.gamma[i];
+  for (int i = 0; i < 3 * M; ++i) {
+    ext[i] = s.p_inc[i];
+    ext[3 * M + i] = s.p_ref[i];
+    ext[6 * M + i] = s.p_trn[i];
+  }
+  for (int m = 0; m < M; ++m) {
+    ksz[m] = s.k * s.sz_top[m];
+    ksz[M + m] = s.k * s.sz_bot[m];
+  }
+  if ((rc = s.d_kg.reserve(kg.size() * 16)) || (rc = s.d_a.reserve(kg.size() * 16)) ||
+      (rc = s.d_b.reserve(kg.size() * 16)) || (rc = s.d_ext.reserve(ext.size() * 16)) ||
+      (rc = s.d_ksz.reserve(ksz.size() * 16)))
+    return rc;
+  SCW_HIP(hipMemcpyAsync(s.d_kg.p, kg.data(), kg.size() * 16, hipMemcpyHostToDevice, st));
+  SCW_HIP(hipMemcpyAsync(s.d_a.p, s.a.data(), kg.size() * 16, hipMemcpyHostToDevice, st));
+  SCW_HIP(hipMemcpyAsync(s.d_b.p, s.b.data(), kg.size() * 16, hipMemcpyHostToDevice, st));
+  SCW_HIP(hipMemcpyAsync(s.d_ext.p, ext.data(), ext.size() * 16, hipMemcpyHostToDevice, st));
+  SCW_HIP(hipMemcpyAsync(s.d_ksz.p, ksz.data(), ksz.size() * 16, hipMemcpyHostToDevice, st));
+  SCW_HIP(hipStreamSynchronize(st));
+  (void)hipEventDestroy(ev0);
+  (void)hipEventDestroy(ev1);
+  s.device = ctx.device;
+  s.info.setup_seconds = now_s() - t_start;
+  return SCW_OK;
+}
+
+}  // namespace scw

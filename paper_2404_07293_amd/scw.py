@@ -1,0 +1,133 @@
+"""Python binding of the HIP CWT library: argument marshalling only.
+
+Every computation runs in libscw.so (HIP kernels on the GPU and the library's
+own host FP64 setup). PyTorch supplies device memory for outputs and the
+stream the synthesis is enqueued on.
+"""
+import ctypes
+
+import numpy as np
+
+from . import _native as N
+
+
+def _ptr(a):
+    return a.ctypes.data_as(N.c_dp) if a is not None else None
+
+
+class Context:
+    """A library context on one HIP device (``scw_create``)."""
+
+    def __init__(self, device=0, host_threads=0):
+        self.lib = N.load()
+        h = ctypes.c_void_p()
+        N.check(self.lib.scw_create(ctypes.byref(h), int(device), int(host_threads)))
+        self.handle = h
+        self.device = int(device)
+
+    def close(self):
+        if self.handle:
+            self.lib.scw_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, prob, route="stable"):
+        """Run ``scw_solve`` on a ``workloads.Problem``; returns a Solution."""
+        n = np.ascontiguousarray(prob.n, dtype=np.complex128)
+        keep = [n]
+        p = N.ScwProblem()
+        p.nz, p.ny, p.nx = n.shape
+        p.px, p.py, p.pz = float(prob.px), float(prob.py), float(prob.pz)
+        p.n = _ptr(n)
+        p.lam = float(prob.lam)
+        p.n_top = float(prob.n_top)
+        nb = complex(prob.n_bot)
+        p.n_bot_re, p.n_bot_im = nb.real, nb.imag
+        p.U, p.V = int(prob.U), int(prob.V)
+        if prob.inc_ex is not None or prob.inc_ey is not None:
+            ref = prob.inc_ex if prob.inc_ex is not None else prob.inc_ey
+            p.inc_ny, p.inc_nx = ref.shape
+            for name in ("inc_ex", "inc_ey"):
+                img = getattr(prob, name)
+                if img is not None:
+                    img = np.ascontiguousarray(img, dtype=np.complex128)
+                    keep.append(img)
+                    setattr(p, name, _ptr(img))
+        pw = prob.plane_wave
+        p.pw_u, p.pw_v = int(pw.u), int(pw.v)
+        ex, ey = complex(pw.ex), complex(pw.ey)
+        p.pw_ex[0], p.pw_ex[1] = ex.real, ex.imag
+        p.pw_ey[0], p.pw_ey[1] = ey.real, ey.imag
+        p.route = N.ROUTE[route]
+        h = ctypes.c_void_p()
+        N.check(self.lib.scw_solve(self.handle, ctypes.byref(p), ctypes.byref(h)))
+        return Solution(self, h, prob)
+
+
+def _grid(grid):
+    g = N.ScwGrid()
+    g.fx, g.fy, g.fz = int(grid.fx), int(grid.fy), int(grid.fz)
+    g.z_begin, g.z_end = float(grid.z_begin), float(grid.z_end)
+    return g
+
+
+class Solution:
+    """A solved problem (``scw_solution``) living on the context's device."""
+
+    def __init__(self, ctx, handle, prob):
+        self.ctx = ctx
+        self.lib = ctx.lib
+        self.handle = handle
+        self.M = int(prob.U) * int(prob.V)
+
+    def free(self):
+        if self.handle:
+            self.lib.scw_solution_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def info(self):
+        inf = N.ScwSolutionInfo()
+        N.check(self.lib.scw_solution_info_get(self.handle, ctypes.byref(inf)))
+        return {f: getattr(inf, f) for f, _ in N.ScwSolutionInfo._fields_}
+
+    def exterior(self):
+        """(p_inc, p_ref, p_trn), each complex128 [3, M]."""
+        out = [np.zeros(3 * self.M, np.complex128) for _ in range(3)]
+        N.check(self.lib.scw_solution_exterior(self.handle, *[_ptr(a) for a in out]))
+        return tuple(a.reshape(3, self.M) for a in out)
+
+    def synthesis_bytes(self, grid, precision="fp32"):
+        return self.lib.scw_synthesis_bytes(self.handle, ctypes.byref(_grid(grid)),
+                                            N.PRECISION[precision])
+
+    def synthesize(self, grid, precision="fp32", out=None, stream=None):
+        """Enqueue ``scw_synthesize`` into ``out`` (a CUDA tensor
+        [3, fz, fy, fx]); allocates it when None. Returns the tensor."""
+        import torch
+        dt = torch.complex128 if precision == "fp64" else torch.complex64
+        shape = (3, int(grid.fz), int(grid.fy), int(grid.fx))
+        dev = torch.device("cuda", self.ctx.device)
+        if out is None:
+            out = torch.empty(shape, dtype=dt, device=dev)
+        if tuple(out.shape) != shape or out.dtype != dt or not out.is_contiguous() \
+                or out.device != dev:
+            raise ValueError("out must be a contiguous %s tensor of shape %s on %s"
+                             % (dt, shape, dev))
+        if stream is None:
+            stream = torch.cuda.current_stream(dev)
+        N.check(self.lib.scw_synthesize(self.ctx.handle, self.handle,
+                                        ctypes.byref(_grid(grid)), N.PRECISION[precision],
+                                        ctypes.c_void_p(out.data_ptr()),
+                                        ctypes.c_void_p(stream.cuda_stream)))
+        return out

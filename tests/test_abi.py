@@ -1,0 +1,92 @@
+"""CPU checks of the C ABI: the library loads, exports every entry point that
+include/scw.h declares, and the ctypes structures have the C layout."""
+import ctypes
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+from paper_2404_07293_amd import _native as N
+
+HEADER = os.path.join(os.path.dirname(__file__), "..", "include", "scw.h")
+
+
+def _declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(scw_[a-z_]+)\s*\(", src)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_function():
+    lib = N.load()
+    declared = _declared_functions()
+    assert len(declared) >= 10
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert set(declared) == set(N.SIGNATURES), "binding and header disagree"
+
+
+def _c_layout():
+    prog = r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "scw.h"
+#define F(T, f) printf("%s %s %zu\n", #T, #f, offsetof(T, f));
+int main(void) {
+  F(scw_problem, nx) F(scw_problem, px) F(scw_problem, n) F(scw_problem, lambda)
+  F(scw_problem, n_top) F(scw_problem, n_bot_im) F(scw_problem, U) F(scw_problem, inc_ex)
+  F(scw_problem, inc_ey) F(scw_problem, inc_nx) F(scw_problem, pw_u) F(scw_problem, pw_ex)
+  F(scw_problem, pw_ey) F(scw_problem, route)
+  F(scw_grid, fx) F(scw_grid, z_begin) F(scw_grid, z_end)
+  F(scw_solution_info, M) F(scw_solution_info, min_abs_sz)
+  F(scw_solution_info, connection_rcond) F(scw_solution_info, assembly_device_ms)
+  printf("size scw_problem %zu\nsize scw_grid %zu\nsize scw_solution_info %zu\n",
+         sizeof(scw_problem), sizeof(scw_grid), sizeof(scw_solution_info));
+  return 0;
+}
+'''
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "layout.c")
+        exe = os.path.join(d, "layout")
+        open(c, "w").write(prog)
+        subprocess.run(["gcc", "-I", os.path.dirname(HEADER), c, "-o", exe], check=True)
+        out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout
+    return out.split("\n")
+
+
+def test_ctypes_structures_match_c_layout():
+    rename = {"lambda": "lam"}
+    types = {"scw_problem": N.ScwProblem, "scw_grid": N.ScwGrid,
+             "scw_solution_info": N.ScwSolutionInfo}
+    for line in _c_layout():
+        if not line:
+            continue
+        a, b, c = line.split()
+        if a == "size":
+            assert ctypes.sizeof(types[b]) == int(c), line
+        else:
+            field = getattr(types[a], rename.get(b, b))
+            assert field.offset == int(c), line
+
+
+def test_create_without_gpu_reports_hip_error():
+    import torch
+    if torch.cuda.device_count() > 0:
+        pytest.skip("a GPU is present")
+    lib = N.load()
+    h = ctypes.c_void_p()
+    rc = lib.scw_create(ctypes.byref(h), 0, 0)
+    assert rc == -3
+    assert b"hipGetDeviceCount" in lib.scw_last_error()
+    assert lib.scw_create(None, 0, 0) == -1
+
+
+def test_null_arguments_rejected_without_touching_the_gpu():
+    lib = N.load()
+    assert lib.scw_solve(None, None, None) == -1
+    assert lib.scw_synthesize(None, None, None, 1, None, None) == -1
+    assert lib.scw_solution_info_get(None, None) == -1
+    assert lib.scw_synthesis_bytes(None, None, 1) == 0.0

@@ -1,0 +1,181 @@
+"""GPU parity of the HIP library against the FP64 oracle, through the C ABI.
+
+Tolerances (relative L2 over all voxels and components):
+  FP64 synthesis  <= 1e-10  (both sides are FP64; the setups differ in
+                             formulation: 2M product eigenproblem and stable
+                             elimination vs. 4M geev and the full system)
+  FP32 synthesis  <= 1e-4   (complex64 storage of P and outputs; expected error
+                             ~1e-6, sum lengths up to 2M terms)
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import cwt
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+FP32_TOL = 1e-4
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    _torch()
+    import paper_2404_07293_amd as P
+    return P.Context(0)
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def run(ctx, prob, grid, precision="fp64", route="stable"):
+    torch = _torch()
+    sol = ctx.solve(prob, route)
+    E = sol.synthesize(grid, precision)
+    torch.cuda.synchronize()
+    return sol, E.cpu().numpy()
+
+
+def ragged_problem(seed=1, nx=8, ny=6, nz=3, U=5, V=3, lossy=True, pw=(1, -1)):
+    rng = np.random.default_rng(seed)
+    n = 1.3 + 0.3 * rng.random((nz, ny, nx))
+    if lossy:
+        n = n + 0.04j * rng.random((nz, ny, nx))
+    return W.Problem(n=n.astype(complex), px=0.31, py=0.27, pz=0.19, lam=1.0, U=U, V=V,
+                     n_top=1.0, n_bot=1.45 + 0.01j,
+                     plane_wave=W.PlaneWave(pw[0], pw[1], 0.8, 0.3 - 0.2j))
+
+
+def test_sphere_fp64_matches_oracle(ctx):
+    prob, grid = W.sphere_config()
+    _, _, want = cwt.simulate(prob, grid)
+    _, got = run(ctx, prob, grid, "fp64")
+    assert got.shape == want.shape
+    err = rel_l2(got, want)
+    print("sphere fp64 rel-L2 %.3e" % err)
+    assert err <= FP64_TOL
+    for c in range(3):
+        assert rel_l2(got[c], want[c]) <= 10 * FP64_TOL
+
+
+def test_sphere_fp32_matches_oracle(ctx):
+    prob, grid = W.sphere_config()
+    _, _, want = cwt.simulate(prob, grid)
+    _, got = run(ctx, prob, grid, "fp32")
+    err = rel_l2(got, want)
+    print("sphere fp32 rel-L2 %.3e" % err)
+    assert err <= FP32_TOL
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("fp32", FP32_TOL)])
+def test_planes_above_inside_below_ragged_grid(ctx, precision, tol):
+    prob = ragged_problem()
+    T = prob.thickness
+    grid = W.Grid(fx=13, fy=7, fz=11, z_begin=-0.4, z_end=T + 0.4)
+    _, _, want = cwt.simulate(prob, grid)
+    _, got = run(ctx, prob, grid, precision)
+    err = rel_l2(got, want)
+    print("ragged %s rel-L2 %.3e" % (precision, err))
+    assert err <= tol
+
+
+def test_connection_route_matches_oracle(ctx):
+    prob = ragged_problem(seed=2)
+    grid = W.Grid(fx=9, fy=10, fz=6, z_begin=-0.2, z_end=prob.thickness + 0.2)
+    _, _, want = cwt.simulate(prob, grid)
+    sol, got = run(ctx, prob, grid, "fp64", route="connection")
+    assert rel_l2(got, want) <= FP64_TOL
+    assert sol.info()["connection_rcond"] > 0
+
+
+def test_exterior_coefficients_match_oracle(ctx):
+    prob = ragged_problem(seed=3, U=3, V=5)
+    st = cwt.setup(prob)
+    ref = cwt.solve(st)
+    sol = ctx.solve(prob)
+    p_inc, p_ref, p_trn = sol.exterior()
+    M = st.M
+    np.testing.assert_allclose(p_inc.ravel(), st.p_inc, atol=1e-13)
+    assert rel_l2(p_ref.ravel(), ref.p_ref) < 1e-11
+    assert rel_l2(p_trn.ravel(), ref.p_trn) < 1e-11
+    assert p_ref.shape == (3, M)
+
+
+def test_image_incidence_matches_oracle(ctx):
+    prob = ragged_problem(seed=4)
+    rng = np.random.default_rng(9)
+    prob.inc_ex = rng.standard_normal((5, 9)) + 1j * rng.standard_normal((5, 9))
+    prob.inc_ey = rng.standard_normal((5, 9)) + 1j * rng.standard_normal((5, 9))
+    grid = W.Grid(fx=16, fy=12, fz=5, z_begin=0.0, z_end=prob.thickness)
+    _, _, want = cwt.simulate(prob, grid)
+    _, got = run(ctx, prob, grid, "fp64")
+    assert rel_l2(got, want) <= FP64_TOL
+
+
+def test_many_planes_per_layer(ctx):
+    # 23 planes over 2 layers: tasks of 8 planes plus ragged remainders
+    prob = ragged_problem(seed=5, nz=2)
+    grid = W.Grid(fx=8, fy=8, fz=23, z_begin=0.0, z_end=prob.thickness)
+    _, _, want = cwt.simulate(prob, grid)
+    for precision, tol in (("fp64", FP64_TOL), ("fp32", FP32_TOL)):
+        _, got = run(ctx, prob, grid, precision)
+        assert rel_l2(got, want) <= tol
+
+
+def test_single_frequency(ctx):
+    prob = ragged_problem(seed=6, U=1, V=1, pw=(0, 0))
+    grid = W.Grid(fx=4, fy=4, fz=6, z_begin=-0.1, z_end=prob.thickness + 0.1)
+    _, _, want = cwt.simulate(prob, grid)
+    _, got = run(ctx, prob, grid, "fp64")
+    assert rel_l2(got, want) <= FP64_TOL
+
+
+def test_lossless_energy_balance_from_library(ctx):
+    prob = ragged_problem(seed=7, lossy=False)
+    prob.n_bot = 1.5 + 0j
+    sol = ctx.solve(prob)
+    st = cwt.setup(prob)   # only for s_x, s_y, s_z of the modes
+    p_inc, p_ref, p_trn = sol.exterior()
+    fi = cwt.z_flux(p_inc, cwt.h_coefficients(p_inc, st.sx, st.sy, st.sz_top))
+    fr = -cwt.z_flux(p_ref, cwt.h_coefficients(p_ref, st.sx, st.sy, -st.sz_top))
+    ft = cwt.z_flux(p_trn, cwt.h_coefficients(p_trn, st.sx, st.sy, st.sz_bot))
+    assert abs(fi - fr - ft) < 1e-11 * fi
+
+
+def test_fp32_is_deterministic(ctx):
+    torch = _torch()
+    prob, grid = W.sphere_config()
+    sol = ctx.solve(prob)
+    a = sol.synthesize(grid, "fp32").clone()
+    b = sol.synthesize(grid, "fp32")
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+def test_error_codes(ctx):
+    import paper_2404_07293_amd as P
+    prob = ragged_problem()
+    prob.U = 4
+    with pytest.raises(P.ScwError) as e:
+        ctx.solve(prob)
+    assert e.value.code == -1
+    # X = 2 wavelengths puts (u, v) = (2, 0) at |s| = 1 = n_top: grazing
+    n = np.full((1, 4, 4), 1.5 + 0j)
+    prob = W.Problem(n=n, px=0.5, py=0.5, pz=0.2, lam=1.0, U=5, V=1)
+    with pytest.raises(P.ScwError) as e:
+        ctx.solve(prob)
+    assert e.value.code == -5
+    sol = ctx.solve(ragged_problem())
+    with pytest.raises(P.ScwError):
+        sol.synthesize(W.Grid(fx=0, fy=4, fz=4, z_begin=0, z_end=1), "fp32")
+    with pytest.raises(P.ScwError):
+        sol.synthesize(W.Grid(fx=4, fy=4, fz=4, z_begin=1, z_end=0), "fp32")
