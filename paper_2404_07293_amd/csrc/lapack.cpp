@@ -49,7 +49,8 @@ void load() {
   ok &= bind(h, "zgemm_", g_lapack.zgemm, err);
   ok &= bind(h, "zgecon_", g_lapack.zgecon, err);
   ok &= bind(h, "zlange_", g_lapack.zlange, err);
-  ok &= bind(h, "mkl_set_num_threads_local", g_lapack.set_threads_local, err);
+  // C entry points (by-value int); the lower-case exports take a pointer.
+  ok &= bind(h, "MKL_Set_Num_Threads_Local", g_lapack.set_threads_local, err);
   ok &= bind(h, "MKL_Set_Num_Threads", g_lapack.set_threads, err);
   g_lapack.ok = ok;
   g_lapack.error = err;

@@ -21,7 +21,7 @@ struct Lapack {
                  double*, zc*, double*, int*) = nullptr;
   double (*zlange)(const char*, const int*, const int*, const zc*, const int*,
                    double*) = nullptr;
-  void (*set_threads_local)(int) = nullptr;   // per calling thread
+  int (*set_threads_local)(int) = nullptr;    // per calling thread
   void (*set_threads)(int) = nullptr;         // process default
   bool ok = false;
   std::string error;
