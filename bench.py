@@ -51,16 +51,15 @@ def stage_model(sol_info, plan, prec):
     return {
         "phase": {"bytes": ntask * 2 * zt * n2 * eb + 3 * layers * n2 * 16,
                   "flops": ntask * zt * n2 * 40},
-        "modal_sum": {"bytes": layers * n3 * n2 * eb + ntask * 2 * zt * n2 * eb
+        # P_l streamed once per task, the phase inputs and the spectra written
+        "modal_sum": {"bytes": ntask * n3 * n2 * eb + 3 * layers * n2 * eb
                       + interior * n3 * eb,
                       "flops": 8 * n3 * n2 * interior},
         "exterior": {"bytes": (fz - interior) * n3 * eb, "flops": (fz - interior) * n3 * 40},
-        "idft_x": {"bytes": fz * n3 * eb + fz * 3 * V * fx * eb,
-                   "flops": 8 * fz * 3 * V * U * fx},
-        "idft_y": {"bytes": fz * 3 * V * fx * eb + 3 * fx * fy * fz * eb,
-                   "flops": 8 * fz * 3 * V * fx * fy},
+        # spectra read, field written; x pass U and y pass V complex MACs
+        "idft": {"bytes": fz * n3 * eb + 3 * fx * fy * fz * eb,
+                 "flops": 8 * fz * 3 * (V * U * fx + V * fx * fy)},
     }
-
 
 def plan_summary(prob, grid):
     """Plane classification mirroring the library's plan (for the model)."""
@@ -202,7 +201,7 @@ def main(argv=None):
     stop.record(stream)
     torch.cuda.synchronize()
     ms = start.elapsed_time(stop) / args.steps
-    nst = 5
+    nst = 4
     stage_ms = (ctypes.c_double * nst)()
     calls = ctypes.c_int()
     P._native.check(lib.scw_profile_end(ctx.handle, stage_ms, nst, ctypes.byref(calls)))

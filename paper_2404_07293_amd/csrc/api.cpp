@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <new>
 #include <thread>
 
@@ -105,7 +106,7 @@ int build_plan(Solution& s, const scw_grid& g, int precision) {
       ++t.count;
       ++j;
     }
-    for (int p = t.count; p < zt; ++p) {
+    for (int p = t.count; p < zt; ++p) {  // padding planes: zero offsets
       tdz.push_back(0.0);
       tdz.push_back(0.0);
     }
@@ -113,24 +114,27 @@ int build_plan(Solution& s, const scw_grid& g, int precision) {
   }
   pl.n_exterior = (int)ext.size();
   int rc;
+  std::vector<float> tdz32(tdz.begin(), tdz.end());
   if ((rc = upload(pl.d_tasks, pl.tasks.data(), pl.tasks.size() * sizeof(Task))) ||
       (rc = upload(pl.d_task_dz, tdz.data(), tdz.size() * sizeof(double))) ||
+      (rc = upload(pl.d_task_dz32, tdz32.data(), tdz32.size() * sizeof(float))) ||
       (rc = upload(pl.d_ext, ext.data(), ext.size() * sizeof(ExtPlane))))
     return rc;
   const int eb = elem_bytes(precision);
   const size_t n2 = 2 * (size_t)s.M;
   if ((rc = pl.d_w.reserve(std::max<size_t>(16, pl.tasks.size() * 2 * zt * n2 * eb))) ||
-      (rc = pl.d_spec.reserve((size_t)g.fz * 3 * s.M * eb)) ||
-      (rc = pl.d_t1.reserve((size_t)g.fz * 3 * s.V * g.fx * eb)))
+      (rc = pl.d_spec.reserve((size_t)g.fz * 3 * s.M * eb)))
     return rc;
-  // inverse-transform twiddles W_x[u][f] = exp(2 pi i u f / fx), W_y[v][g]
-  std::vector<zc> twx((size_t)s.U * g.fx), twy((size_t)s.V * g.fy);
-  for (int ui = 0; ui < s.U; ++ui)
-    for (int f = 0; f < g.fx; ++f)
-      twx[(size_t)ui * g.fx + f] = twiddle_inv((long long)(ui - s.U / 2) * f, g.fx);
-  for (int vi = 0; vi < s.V; ++vi)
-    for (int gg = 0; gg < g.fy; ++gg)
-      twy[(size_t)vi * g.fy + gg] = twiddle_inv((long long)(vi - s.V / 2) * gg, g.fy);
+  // inverse-transform factors: wx[0][f] = e^{2 pi i f/fx}, wx[1][f] = e^{-2 pi i (U/2) f/fx}
+  std::vector<zc> twx(2 * (size_t)g.fx), twy(2 * (size_t)g.fy);
+  for (int f = 0; f < g.fx; ++f) {
+    twx[f] = twiddle_inv(f, g.fx);
+    twx[g.fx + f] = twiddle_inv(-(long long)(s.U / 2) * f, g.fx);
+  }
+  for (int gg = 0; gg < g.fy; ++gg) {
+    twy[gg] = twiddle_inv(gg, g.fy);
+    twy[g.fy + gg] = twiddle_inv(-(long long)(s.V / 2) * gg, g.fy);
+  }
   if (precision == SCW_FP64) {
     std::vector<double> a, b;
     pack(twx, a);
@@ -288,10 +292,15 @@ int scw_synthesize(scw_ctx* ctx, scw_solution* sol, const scw_grid* grid, int pr
   a.ext_planes = pl.d_ext.p;
   a.w = pl.d_w.p;
   a.spec = pl.d_spec.p;
-  a.t1 = pl.d_t1.p;
   a.twx = pl.d_twx.p;
   a.twy = pl.d_twy.p;
   a.E = E_dev;
+  a.kgab32 = s.d_kgab32.p;
+  a.task_dz32 = pl.d_task_dz32.p;
+  {
+    const char* env = getenv("SCW_IDFT_GTILES");
+    a.idft_gtiles = env ? atoi(env) : 0;
+  }
   hipEvent_t* ev = nullptr;
   Context& c = ctx->c;
   if (c.prof_used < c.prof_max) ev = c.prof_events.data() + (size_t)c.prof_used++ * (kNumStages + 1);
@@ -346,7 +355,7 @@ int scw_profile_end(scw_ctx* ctx, double* stage_ms, int n_stages, int* calls) {
 }
 
 const char* scw_stage_name(int stage) {
-  static const char* names[kNumStages] = {"phase", "modal_sum", "exterior", "idft_x", "idft_y"};
+  static const char* names[kNumStages] = {"phase", "modal_sum", "exterior", "idft"};
   return (stage >= 0 && stage < kNumStages) ? names[stage] : "";
 }
 

@@ -11,6 +11,8 @@
 //             exp(2 pi i (u f / fx + v g / fy)), as two passes (x, then y).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "scw_internal.h"
 
 namespace scw {
@@ -149,6 +151,140 @@ __global__ void __launch_bounds__(256) modal_kernel(
   }
 }
 
+// ---------------------------------------------------------------- modal sum, FP32
+// Phase factors are generated in the block: W(sign)[p][j] = a_j g_f(z_p) +-
+// b_j g_b(z_p) for the block's rows' sign, written straight into LDS. Lanes
+// read P two complex at a time (16-byte loads); every lane accumulates
+// RW rows x ZT planes, and a recursive-halving butterfly leaves the complete
+// sum of value index i in lane i (NV = 2 RW ZT values, NV - 1 shuffles).
+template <int N>
+__device__ __forceinline__ void halve(float* v, int lane) {
+  if constexpr (N > 1) {
+    constexpr int H = N / 2;
+    const bool up = (lane & H) != 0;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+      const float send = up ? v[i] : v[i + H];
+      const float keep = up ? v[i + H] : v[i];
+      v[i] = keep + __shfl_xor(send, H, 64);
+    }
+    halve<H>(v, lane);
+  }
+}
+
+__device__ __forceinline__ float2 cexpi_f(float re, float im) {  // exp(i (re + i im))
+  float sn, cs;
+  sincosf(re, &sn, &cs);
+  const float m = expf(-im);
+  return make_float2(m * cs, m * sn);
+}
+
+template <int ZT, int RW>
+__global__ void __launch_bounds__(256) modal_f32_kernel(
+    const float4* __restrict__ P, const float2* __restrict__ kgab, const Task* __restrict__ tasks,
+    const float2* __restrict__ tdz, int M, int L, int nb_xy, int nb_z, int jc,
+    float2* __restrict__ spec) {
+  constexpr int NV = 2 * RW * ZT;
+  static_assert(NV <= 64 && (NV & (NV - 1)) == 0, "value count must be a power of two <= 64");
+  extern __shared__ float4 sw4[];  // [ZT][jc / 2]
+  float2* sw = reinterpret_cast<float2*>(sw4);
+  const int n2 = 2 * M, n3 = 3 * M, h2 = M;  // h2 = float4 per row
+  const int nb = nb_xy + nb_z;
+  const int task = blockIdx.x / nb;
+  const int rb = blockIdx.x % nb;
+  const Task tk = tasks[task];
+  const bool zrows = rb >= nb_xy;
+  const int rows_per_block = 4 * RW;
+  const int row_begin = zrows ? n2 + (rb - nb_xy) * rows_per_block : rb * rows_per_block;
+  const int row_end = zrows ? n3 : n2;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r0 = row_begin + wave * RW;
+  const float4* Pl = P + (long long)tk.layer * n3 * h2;
+  const float2* kg = kgab + (long long)tk.layer * n2;
+  const float2* av = kgab + ((long long)L + tk.layer) * n2;
+  const float2* bv = kgab + (2LL * L + tk.layer) * n2;
+  const float sgn = zrows ? -1.f : 1.f;
+  const float4* prow[RW];
+#pragma unroll
+  for (int r = 0; r < RW; ++r) prow[r] = Pl + (long long)min(r0 + r, row_end - 1) * h2;
+  float2 dzp[ZT];
+#pragma unroll
+  for (int p = 0; p < ZT; ++p) dzp[p] = tdz[task * ZT + p];
+
+  float acc[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) acc[i] = 0.f;
+
+  for (int j0 = 0; j0 < n2; j0 += jc) {
+    const int jn = min(jc, n2 - j0);
+    __syncthreads();
+    for (int jj = threadIdx.x; jj < jn; jj += 256) {
+      const float2 g = kg[j0 + jj], a = av[j0 + jj], b = bv[j0 + jj];
+#pragma unroll
+      for (int p = 0; p < ZT; ++p) {
+        const float2 gf = cexpi_f(g.x * dzp[p].x, g.y * dzp[p].x);
+        const float2 gb = cexpi_f(-g.x * dzp[p].y, -g.y * dzp[p].y);
+        const float fx = a.x * gf.x - a.y * gf.y, fy = a.x * gf.y + a.y * gf.x;
+        const float bx = b.x * gb.x - b.y * gb.y, by = b.x * gb.y + b.y * gb.x;
+        sw[p * jc + jj] = make_float2(fx + sgn * bx, fy + sgn * by);
+      }
+    }
+    __syncthreads();
+    const int q0 = j0 / 2, qn = jn / 2;
+    for (int q = lane; q < qn; q += 64) {
+      float4 pv[RW];
+#pragma unroll
+      for (int r = 0; r < RW; ++r) pv[r] = prow[r][q0 + q];
+#pragma unroll
+      for (int p = 0; p < ZT; ++p) {
+        const float4 w = sw4[p * (jc / 2) + q];
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+          float& re = acc[(r * ZT + p) * 2];
+          float& im = acc[(r * ZT + p) * 2 + 1];
+          re = fmaf(pv[r].x, w.x, re);
+          re = fmaf(-pv[r].y, w.y, re);
+          im = fmaf(pv[r].x, w.y, im);
+          im = fmaf(pv[r].y, w.x, im);
+          re = fmaf(pv[r].z, w.z, re);
+          re = fmaf(-pv[r].w, w.w, re);
+          im = fmaf(pv[r].z, w.w, im);
+          im = fmaf(pv[r].w, w.z, im);
+        }
+      }
+    }
+  }
+  halve<NV>(acc, lane);
+#pragma unroll
+  for (int off = NV; off < 64; off <<= 1) acc[0] += __shfl_xor(acc[0], off, 64);
+  if (lane < NV) {
+    const int comp = lane & 1, p = (lane >> 1) % ZT, r = (lane >> 1) / ZT;
+    const int row = r0 + r;
+    if (row < row_end && p < tk.count)
+      reinterpret_cast<float*>(spec)[((long long)(tk.plane0 + p) * n3 + row) * 2 + comp] = acc[0];
+  }
+}
+
+template <int ZT>
+hipError_t launch_modal_f32(const SynthArgs& a, hipStream_t s) {
+  constexpr int RW = ZT >= 8 ? 4 : (ZT == 4 ? 8 : 16);
+  const int n2 = 2 * a.M;
+  const int rows_per_block = 4 * RW;
+  const int nb_xy = (n2 + rows_per_block - 1) / rows_per_block;
+  const int nb_z = (a.M + rows_per_block - 1) / rows_per_block;
+  const size_t max_lds = 64 * 1024;
+  int jc = (int)(max_lds / (ZT * sizeof(float2)));
+  jc = jc >= n2 ? n2 : (jc / 128) * 128;
+  const size_t lds = (size_t)ZT * jc * sizeof(float2);
+  const long long nblocks = (long long)a.ntasks * (nb_xy + nb_z);
+  if (nblocks == 0) return hipSuccess;
+  modal_f32_kernel<ZT, RW><<<(unsigned)nblocks, 256, lds, s>>>(
+      reinterpret_cast<const float4*>(a.P), reinterpret_cast<const float2*>(a.kgab32), a.tasks,
+      reinterpret_cast<const float2*>(a.task_dz32), a.M, a.L, nb_xy, nb_z, jc,
+      reinterpret_cast<float2*>(a.spec));
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- exterior
 template <typename T>
 __global__ void exterior_kernel(const ExtPlane* __restrict__ ext, int n_ext, int M,
@@ -175,48 +311,109 @@ __global__ void exterior_kernel(const ExtPlane* __restrict__ ext, int n_ext, int
 }
 
 // ---------------------------------------------------------------- inverse DFT
-// Pass 1: t1[plane][c][v][f] = sum_u spec[plane][c][v][u] twx[u][f].
+// One block per (plane, component, f tile, g tile). The spectrum S[v][u] of the
+// plane/component is staged in LDS; each thread owns one output column f:
+//   pass x:  T[v][f] = sum_u S[v][u] exp(2 pi i u f / fx)
+//            = e^{-2 pi i (U/2) f/fx} * Horner_u(S[v][.], w_f),  w_f = e^{2 pi i f/fx}
+//            kept in LDS as T[v][thread];
+//   pass y:  E[g][f] = e^{-2 pi i (V/2) g/fy} * Horner_v(T[.][f], w_g)
+//            for the block's rows g, four rows at a time sharing each LDS read.
+// wx[0][f] = w_f, wx[1][f] = e^{-2 pi i (U/2) f/fx}; wy likewise for g.
 template <typename T>
-__global__ void idft_x_kernel(const cx<T>* __restrict__ spec, const cx<T>* __restrict__ twx,
-                              int U, int V, int fx, int fz, cx<T>* __restrict__ t1) {
-  const int M = U * V;
-  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (long long)fz * 3 * V * fx) return;
-  const int f = (int)(t % fx);
-  long long q = t / fx;
-  const int vi = (int)(q % V);
-  q /= V;  // plane * 3 + c
-  const cx<T>* s = spec + q * M + (long long)vi * U;  // spec[plane][c*M + vi*U + u]
-  cx<T> acc = {0, 0};
-  for (int u = 0; u < U; ++u) cfma(acc, s[u], twx[(long long)u * fx + f]);
-  t1[t] = acc;
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> cmuladd(cx<T> a, cx<T> w, cx<T> c) {  // a*w + c
+  cx<T> r;
+  r.x = fma(a.x, w.x, fma(-a.y, w.y, c.x));
+  r.y = fma(a.x, w.y, fma(a.y, w.x, c.y));
+  return r;
 }
 
-// Pass 2: E[c][plane][g][f] = sum_v twy[v][g] t1[plane][c][v][f]; each thread
-// computes GT consecutive g for one f.
-template <typename T, int GT>
-__global__ void idft_y_kernel(const cx<T>* __restrict__ t1, const cx<T>* __restrict__ twy,
-                              int V, int fx, int fy, int fz, cx<T>* __restrict__ E) {
-  const int f = blockIdx.x * blockDim.x + threadIdx.x;
-  const int g0 = blockIdx.y * GT;
-  const int pc = blockIdx.z;  // plane * 3 + c
-  if (f >= fx) return;
-  const int plane = pc / 3, c = pc % 3;
-  const cx<T>* src = t1 + (long long)pc * V * fx + f;
-  cx<T> acc[GT];
-#pragma unroll
-  for (int i = 0; i < GT; ++i) acc[i] = {0, 0};
-  for (int vi = 0; vi < V; ++vi) {
-    const cx<T> tv = src[(long long)vi * fx];
-    const cx<T>* wy = twy + (long long)vi * fy + g0;
-#pragma unroll
-    for (int i = 0; i < GT; ++i)
-      if (g0 + i < fy) cfma(acc[i], wy[i], tv);
+template <typename T, int FT>
+__global__ void __launch_bounds__(FT) idft_kernel(
+    const cx<T>* __restrict__ spec, const cx<T>* __restrict__ wx, const cx<T>* __restrict__ wy,
+    int U, int V, int fx, int fy, int fz, int grows, cx<T>* __restrict__ E) {
+  extern __shared__ unsigned char smem_raw[];
+  cx<T>* S = reinterpret_cast<cx<T>*>(smem_raw);  // [V*U]
+  cx<T>* Tt = S + U * V;                          // [V][FT]
+  const int M = U * V;
+  const int pc = blockIdx.z;
+  const int plane = pc / 3, comp = pc % 3;
+  const int t = threadIdx.x;
+  const int f = blockIdx.x * FT + t;
+  const int g0 = blockIdx.y * grows;
+  const int g1 = min(fy, g0 + grows);
+  const cx<T>* src = spec + ((long long)plane * 3 + comp) * M;
+  for (int i = t; i < M; i += FT) S[i] = src[i];
+  __syncthreads();
+  const bool live = f < fx;
+  if (live) {
+    const cx<T> w = wx[f], sh = wx[fx + f];
+    for (int v = 0; v < V; ++v) {
+      const cx<T>* row = S + v * U;
+      cx<T> acc = row[U - 1];
+      for (int u = U - 2; u >= 0; --u) acc = cmuladd(acc, w, row[u]);
+      Tt[v * FT + t] = cmul(acc, sh);
+    }
   }
-  cx<T>* dst = E + (((long long)c * fz + plane) * fy + g0) * fx + f;
+  // each thread reads only its own column of Tt: no barrier needed
+  if (!live) return;
+  cx<T>* dst = E + (((long long)comp * fz + plane) * fy) * fx + f;
+  int g = g0;
+  for (; g + 4 <= g1; g += 4) {
+    cx<T> w[4], acc[4];
+    const cx<T> top = Tt[(V - 1) * FT + t];
 #pragma unroll
-  for (int i = 0; i < GT; ++i)
-    if (g0 + i < fy) dst[(long long)i * fx] = acc[i];
+    for (int k = 0; k < 4; ++k) {
+      w[k] = wy[g + k];
+      acc[k] = top;
+    }
+    for (int v = V - 2; v >= 0; --v) {
+      const cx<T> c = Tt[v * FT + t];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) acc[k] = cmuladd(acc[k], w[k], c);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const cx<T> o = cmul(acc[k], wy[fy + g + k]);
+      __builtin_nontemporal_store(o.x, &dst[(long long)(g + k) * fx].x);
+      __builtin_nontemporal_store(o.y, &dst[(long long)(g + k) * fx].y);
+    }
+  }
+  for (; g < g1; ++g) {
+    const cx<T> w = wy[g];
+    cx<T> acc = Tt[(V - 1) * FT + t];
+    for (int v = V - 2; v >= 0; --v) acc = cmuladd(acc, w, Tt[v * FT + t]);
+    const cx<T> o = cmul(acc, wy[fy + g]);
+    __builtin_nontemporal_store(o.x, &dst[(long long)g * fx].x);
+    __builtin_nontemporal_store(o.y, &dst[(long long)g * fx].y);
+  }
+}
+
+template <typename T>
+hipError_t launch_idft(const SynthArgs& a, hipStream_t s) {
+  const int n_pc = a.fz * 3;
+  auto go = [&](auto ft_tag) -> hipError_t {
+    constexpr int FT = decltype(ft_tag)::value;
+    const int nft = (a.fx + FT - 1) / FT;
+    // enough g tiles for ~2 blocks per CU, but at least 64 rows per tile
+    int ng = 1;
+    while ((long long)n_pc * nft * ng < 512 && a.fy / (ng * 2) >= 64) ng *= 2;
+    if (a.idft_gtiles > 0) ng = a.idft_gtiles;
+    const int grows = (a.fy + ng - 1) / ng;
+    const size_t lds = ((size_t)a.U * a.V + (size_t)a.V * FT) * sizeof(cx<T>);
+    dim3 grid(nft, (a.fy + grows - 1) / grows, n_pc);
+    idft_kernel<T, FT><<<grid, FT, lds, s>>>(
+        reinterpret_cast<const cx<T>*>(a.spec), reinterpret_cast<const cx<T>*>(a.twx),
+        reinterpret_cast<const cx<T>*>(a.twy), a.U, a.V, a.fx, a.fy, a.fz, grows,
+        reinterpret_cast<cx<T>*>(a.E));
+    return hipGetLastError();
+  };
+  if (a.fx <= 64) return go(std::integral_constant<int, 64>());
+  if (a.fx <= 128) return go(std::integral_constant<int, 128>());
+  return go(std::integral_constant<int, 256>());
 }
 
 inline unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
@@ -246,7 +443,7 @@ hipError_t launch_synthesis(const SynthArgs& a, hipStream_t s, hipEvent_t* ev) {
   const int n2 = 2 * a.M;
   auto mark = [&](int i) -> hipError_t { return ev ? hipEventRecord(ev[i], s) : hipSuccess; };
   if ((e = mark(0)) != hipSuccess) return e;
-  if (a.ntasks > 0) {
+  if (a.ntasks > 0 && sizeof(T) == 8) {
     phase_kernel<T><<<blocks_for((long long)a.ntasks * n2, 256), 256, 0, s>>>(
         a.tasks, a.task_dz, reinterpret_cast<const zd*>(a.kg),
         reinterpret_cast<const zd*>(a.a), reinterpret_cast<const zd*>(a.b), n2, a.zt,
@@ -258,6 +455,16 @@ hipError_t launch_synthesis(const SynthArgs& a, hipStream_t s, hipEvent_t* ev) {
       case 2: e = launch_modal<T, 2>(a, s); break;
       case 4: e = launch_modal<T, 4>(a, s); break;
       case 8: e = launch_modal<T, 8>(a, s); break;
+      default: return hipErrorInvalidValue;
+    }
+    if (e != hipSuccess) return e;
+  } else if (a.ntasks > 0) {
+    if ((e = mark(1)) != hipSuccess) return e;
+    switch (a.zt) {
+      case 1: e = launch_modal_f32<1>(a, s); break;
+      case 2: e = launch_modal_f32<2>(a, s); break;
+      case 4: e = launch_modal_f32<4>(a, s); break;
+      case 8: e = launch_modal_f32<8>(a, s); break;
       default: return hipErrorInvalidValue;
     }
     if (e != hipSuccess) return e;
@@ -273,19 +480,8 @@ hipError_t launch_synthesis(const SynthArgs& a, hipStream_t s, hipEvent_t* ev) {
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if ((e = mark(3)) != hipSuccess) return e;
-  idft_x_kernel<T><<<blocks_for((long long)a.fz * 3 * a.V * a.fx, 256), 256, 0, s>>>(
-      reinterpret_cast<const cx<T>*>(a.spec), reinterpret_cast<const cx<T>*>(a.twx), a.U,
-      a.V, a.fx, a.fz, reinterpret_cast<cx<T>*>(a.t1));
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  if ((e = mark(4)) != hipSuccess) return e;
-  constexpr int GT = 8;
-  const int bx = a.fx >= 256 ? 256 : ((a.fx + 63) / 64) * 64;
-  dim3 grid((a.fx + bx - 1) / bx, (a.fy + GT - 1) / GT, a.fz * 3);
-  idft_y_kernel<T, GT><<<grid, bx, 0, s>>>(reinterpret_cast<const cx<T>*>(a.t1),
-                                          reinterpret_cast<const cx<T>*>(a.twy), a.V, a.fx,
-                                          a.fy, a.fz, reinterpret_cast<cx<T>*>(a.E));
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  return mark(5);
+  if ((e = launch_idft<T>(a, s)) != hipSuccess) return e;
+  return mark(4);
 }
 
 }  // namespace

@@ -93,14 +93,12 @@ struct Plan {
   int n_exterior = 0;
   DevBuf d_tasks;                   // Task[ntasks]
   DevBuf d_task_dz;                 // double2 [ntasks][zt] (dz_top, dz_bot)
+  DevBuf d_task_dz32;               // float2 [ntasks][zt]
   DevBuf d_ext;                     // int2 + double: exterior plane table
   DevBuf d_w;                       // W  [ntasks][2][zt][2M] complex<T>
   DevBuf d_spec;                    // [fz][3M] complex<T>
-  DevBuf d_t1;                      // [fz][3][V][fx] complex<T>
-  DevBuf d_twx;                     // [U][fx] complex<T>
-  DevBuf d_twy;                     // [V][fy] complex<T>
-  DevBuf d_twy_split;               // split-precision copies for MFMA paths
-  DevBuf d_p_lo;                    // unused placeholder for split P
+  DevBuf d_twx;                     // [2][fx] complex<T>: e^{2 pi i f/fx}, e^{-2 pi i (U/2) f/fx}
+  DevBuf d_twy;                     // [2][fy] complex<T>: same for g, V
   bool valid = false;
 };
 
@@ -122,6 +120,7 @@ struct Solution {
   DevBuf d_P32;      // [L][3M][2M] complex64 (lazy)
   DevBuf d_kg;       // [L][2M] complex128: k * gamma
   DevBuf d_a, d_b;   // [L][2M] complex128
+  DevBuf d_kgab32;   // [3][L][2M] complex64: k*gamma, a, b
   DevBuf d_ext;      // [3][3M] complex128: p_inc, p_ref, p_trn
   DevBuf d_ksz;      // [2][M] complex128: k*sz_top, k*sz_bot
   Plan plan;
@@ -129,7 +128,7 @@ struct Solution {
 };
 
 // ------------------------------------------------------------------ context
-constexpr int kNumStages = 5;  // phase, modal, exterior, idft_x, idft_y
+constexpr int kNumStages = 4;  // phase (FP64 path), modal sum, exterior, inverse DFT
 
 struct Context {
   int device = 0;
@@ -173,10 +172,12 @@ struct SynthArgs {
   const void* ext_planes;  // exterior plane table
   void* w;                 // [ntasks][2][zt][2M] complex<T>
   void* spec;              // [fz][3M]
-  void* t1;                // [fz][3][V][fx]
-  const void* twx;         // [U][fx]
-  const void* twy;         // [V][fy]
+  const void* twx;         // [2][fx]: e^{2 pi i f/fx}, e^{-2 pi i (U/2) f/fx}
+  const void* twy;         // [2][fy]: e^{2 pi i g/fy}, e^{-2 pi i (V/2) g/fy}
   void* E;                 // [3][fz][fy][fx]
+  const void* kgab32;      // complex64 [3][L][2M]: k*gamma, a, b
+  const void* task_dz32;   // float2 [ntasks][zt]
+  int idft_gtiles;         // 0 = automatic
 };
 // `ev`, when non-null, holds kNumStages + 1 events recorded around the stages.
 hipError_t launch_synthesis_fp64(const SynthArgs& a, hipStream_t s, hipEvent_t* ev);

@@ -609,6 +609,17 @@ int solve_problem(Context& ctx, const scw_problem& p, Solution& s) {
     ksz[m] = s.k * s.sz_top[m];
     ksz[M + m] = s.k * s.sz_bot[m];
   }
+  std::vector<float> kgab32(6 * kg.size());
+  for (size_t i = 0; i < kg.size(); ++i) {
+    kgab32[2 * i] = (float)kg[i].real();
+    kgab32[2 * i + 1] = (float)kg[i].imag();
+    kgab32[2 * (kg.size() + i)] = (float)s.a[i].real();
+    kgab32[2 * (kg.size() + i) + 1] = (float)s.a[i].imag();
+    kgab32[2 * (2 * kg.size() + i)] = (float)s.b[i].real();
+    kgab32[2 * (2 * kg.size() + i) + 1] = (float)s.b[i].imag();
+  }
+  if ((rc = s.d_kgab32.reserve(kgab32.size() * 4))) return rc;
+  SCW_HIP(hipMemcpyAsync(s.d_kgab32.p, kgab32.data(), kgab32.size() * 4, hipMemcpyHostToDevice, st));
   if ((rc = s.d_kg.reserve(kg.size() * 16)) || (rc = s.d_a.reserve(kg.size() * 16)) ||
       (rc = s.d_b.reserve(kg.size() * 16)) || (rc = s.d_ext.reserve(ext.size() * 16)) ||
       (rc = s.d_ksz.reserve(ksz.size() * 16)))
