@@ -136,7 +136,7 @@ def cpu_baseline(prob_full, grid_full, n_layers=2):
                           prob.U * prob.V, t2 - t1, t1 - t0)}
 
 
-def golden_error(E, prob, grid):
+def golden_error(E, prob, grid, per_component=False):
     """rel-L2 of the synthesised field at the stored oracle sample voxels."""
     if not os.path.exists(GOLDEN):
         return None
@@ -148,6 +148,9 @@ def golden_error(E, prob, grid):
     idx = torch.as_tensor(np.stack([j, gg, f]), device=E.device)
     got = E[:, idx[0], idx[1], idx[2]].cpu().numpy()
     want = g["E"]
+    if per_component:
+        return [float(np.linalg.norm(got[c] - want[c]) / np.linalg.norm(want[c]))
+                for c in range(3)]
     return float(np.linalg.norm(got - want) / np.linalg.norm(want))
 
 
@@ -160,6 +163,8 @@ def main(argv=None):
     ap.add_argument("--workload", default="working", choices=["working", "large"])
     ap.add_argument("--layers", type=int, default=None, help="keep only the first N layers")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--variants", default="bf16x3,fp16x3",
+                    help="other precisions timed in the same run ('' for none)")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="also run N plain 256 MiB device copies (PMC scale reference)")
     args = ap.parse_args(argv)
@@ -254,6 +259,25 @@ def main(argv=None):
         "assembly_device_ms": info["assembly_device_ms"],
         "roofline": roof,
     }
+    if args.variants:
+        variants = {}
+        for prec in args.variants.split(","):
+            Ev = torch.empty((3, grid.fz, grid.fy, grid.fx), dtype=torch.complex64, device=dev)
+            for _ in range(max(2, args.warmup)):
+                sol.synthesize(grid, prec, out=Ev, stream=stream)
+            torch.cuda.synchronize()
+            start.record(stream)
+            for _ in range(args.steps):
+                sol.synthesize(grid, prec, out=Ev, stream=stream)
+            stop.record(stream)
+            torch.cuda.synchronize()
+            vms = start.elapsed_time(stop) / args.steps
+            variants[prec] = {"value": voxels / (vms * 1e-3), "ms_per_step": vms,
+                              "rel_l2_vs_oracle": golden_error(Ev, prob, grid),
+                              "rel_l2_per_component": golden_error(Ev, prob, grid, True)}
+            log("%s: ms/step %.4f rel-L2 %s" % (prec, vms, variants[prec]["rel_l2_vs_oracle"]))
+            del Ev
+        out["variants"] = variants
     if not args.no_cpu_baseline:
         log("timing the oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(prob, grid)

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <cstring>
 #include <new>
 #include <thread>
 
@@ -58,6 +59,69 @@ int upload(DevBuf& buf, const void* src, size_t bytes) {
   if (rc) return rc;
   if (bytes) SCW_HIP(hipMemcpy(buf.p, src, bytes, hipMemcpyHostToDevice));
   return SCW_OK;
+}
+
+// Round-to-nearest-even conversions to the 16-bit MFMA operand formats.
+uint16_t f32_to_bf16(float x) {
+  uint32_t u;
+  memcpy(&u, &x, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+float bf16_to_f32(uint16_t h) {
+  uint32_t u = (uint32_t)h << 16;
+  float x;
+  memcpy(&x, &u, 4);
+  return x;
+}
+uint16_t f32_to_f16(float x) {
+  _Float16 h = (_Float16)x;
+  uint16_t b;
+  memcpy(&b, &h, 2);
+  return b;
+}
+float f16_to_f32(uint16_t b) {
+  _Float16 h;
+  memcpy(&h, &b, 2);
+  return (float)h;
+}
+
+// Twiddle operand of the MFMA y pass: A_re = [Re W, -Im W], A_im = [Im W, Re W]
+// with W[g][v] = exp(2 pi i (v - V/2) g / fy), K padded to kp with zeros.
+int build_amat(Solution& s, const scw_grid& g, int precision, Plan& pl) {
+  const int V = s.V, kp = pl.kp, fy = g.fy;
+  std::vector<float> are((size_t)fy * kp, 0.f), aim((size_t)fy * kp, 0.f);
+  for (int gg = 0; gg < fy; ++gg)
+    for (int v = 0; v < V; ++v) {
+      const zc w = twiddle_inv((long long)(v - V / 2) * gg, fy);
+      are[(size_t)gg * kp + v] = (float)w.real();
+      are[(size_t)gg * kp + V + v] = (float)-w.imag();
+      aim[(size_t)gg * kp + v] = (float)w.imag();
+      aim[(size_t)gg * kp + V + v] = (float)w.real();
+    }
+  if (precision == SCW_FP32) {
+    std::vector<float> kmaj(2 * (size_t)fy * kp);
+    for (int gg = 0; gg < fy; ++gg)
+      for (int k = 0; k < kp; ++k) {
+        kmaj[(size_t)k * fy + gg] = are[(size_t)gg * kp + k];
+        kmaj[((size_t)kp + k) * fy + gg] = aim[(size_t)gg * kp + k];
+      }
+    return upload(pl.d_amat, kmaj.data(), kmaj.size() * 4);
+  }
+  const bool bf = precision == SCW_BF16X3;
+  std::vector<uint16_t> out(4 * (size_t)fy * kp);
+  const std::vector<float>* src[2] = {&are, &aim};
+  for (int q = 0; q < 2; ++q)
+    for (int gg = 0; gg < fy; ++gg)
+      for (int k = 0; k < kp; ++k) {
+        const float x = (*src[q])[(size_t)gg * kp + k];
+        const uint16_t hi = bf ? f32_to_bf16(x) : f32_to_f16(x);
+        const float r = x - (bf ? bf16_to_f32(hi) : f16_to_f32(hi));
+        const size_t o = ((size_t)(k / 8) * fy + gg) * 8 + k % 8;
+        out[(size_t)(2 * q) * fy * kp + o] = hi;
+        out[(size_t)(2 * q + 1) * fy * kp + o] = bf ? f32_to_bf16(r) : f32_to_f16(r);
+      }
+  return upload(pl.d_amat, out.data(), out.size() * 2);
 }
 
 // Plane classification, task grouping and device tables for one grid.
@@ -148,6 +212,45 @@ int build_plan(Solution& s, const scw_grid& g, int precision) {
     pack(twy, b);
     if ((rc = upload(pl.d_twx, a.data(), a.size() * 4)) ||
         (rc = upload(pl.d_twy, b.data(), b.size() * 4)))
+      return rc;
+  }
+  // factored y pass for FP64 / FP32 when fy = R * P (P <= 32 a power of two)
+  pl.fft_p = 0;
+  const char* idft_mode = getenv("SCW_IDFT");
+  const bool want_fft = (precision == SCW_FP64 || precision == SCW_FP32) && s.V <= 32 &&
+                        !(idft_mode && (strcmp(idft_mode, "valu") == 0 ||
+                                        strcmp(idft_mode, "mfma") == 0));
+  if (want_fft && g.fy >= 2 && (g.fy & (g.fy - 1)) == 0) {
+    const int P = std::min(32, std::max(2, g.fy / 16));
+    const int R = g.fy / P;
+    pl.fft_p = P;
+    std::vector<zc> tw(32 * (size_t)R + P);
+    for (int sl = 0; sl < 32; ++sl)
+      for (int g1 = 0; g1 < R; ++g1)
+        tw[(size_t)sl * R + g1] = twiddle_inv((long long)(sl - 16) * g1, g.fy);
+    for (int k = 0; k < P; ++k) tw[32 * (size_t)R + k] = twiddle_inv(k, P);
+    if (precision == SCW_FP64) {
+      std::vector<double> b;
+      pack(tw, b);
+      if ((rc = upload(pl.d_fft_tw, b.data(), b.size() * 8))) return rc;
+    } else {
+      std::vector<float> b;
+      pack(tw, b);
+      if ((rc = upload(pl.d_fft_tw, b.data(), b.size() * 4))) return rc;
+    }
+  }
+  // matrix-core inverse transform for the single-precision modes
+  const char* idft_env = getenv("SCW_IDFT");
+  pl.mfma = precision != SCW_FP64 && s.V <= 32 && pl.fft_p == 0 &&
+            !(idft_env && strcmp(idft_env, "valu") == 0);
+  if (precision == SCW_BF16X3 || precision == SCW_FP16X3) pl.mfma = s.V <= 32;
+  if (pl.mfma) {
+    const int ks = mfma_kstep(precision);
+    pl.kp = ((2 * s.V + ks - 1) / ks) * ks;
+    if ((rc = build_amat(s, g, precision, pl))) return rc;
+    const size_t ebyte = precision == SCW_FP32 ? 4 : 4;  // f32, or hi + lo 16-bit
+    if ((rc = pl.d_bmat.reserve((size_t)g.fz * 3 * pl.kp * g.fx * ebyte)) ||
+        (rc = pl.d_bscale.reserve((size_t)g.fz * 3 * sizeof(float))))
       return rc;
   }
   pl.valid = true;
@@ -254,14 +357,16 @@ int scw_synthesize(scw_ctx* ctx, scw_solution* sol, const scw_grid* grid, int pr
   if (!ctx || !sol || !E_dev) return fail(SCW_EINVAL, "null argument");
   int rc = check_grid(grid);
   if (rc) return rc;
-  if (precision != SCW_FP64 && precision != SCW_FP32)
-    return fail(SCW_EINVAL, "precision " + std::to_string(precision) + " is not available");
+  if (precision < SCW_FP64 || precision > SCW_FP16X3)
+    return fail(SCW_EINVAL, "unknown precision " + std::to_string(precision));
+  if ((precision == SCW_BF16X3 || precision == SCW_FP16X3) && sol->s.V > 32)
+    return fail(SCW_EINVAL, "split-precision transform needs V <= 32");
   Solution& s = sol->s;
   if (s.device != ctx->c.device) return fail(SCW_EINVAL, "solution belongs to another device");
   SCW_HIP(hipSetDevice(ctx->c.device));
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
   const size_t pl_elems = (size_t)s.L * 3 * s.M * 2 * s.M;
-  if (precision == SCW_FP32 && s.d_P32.bytes < pl_elems * 8) {
+  if (precision != SCW_FP64 && s.d_P32.bytes < pl_elems * 8) {
     if ((rc = s.d_P32.reserve(pl_elems * 8))) return rc;
     SCW_HIP(launch_p_to_fp32(s.d_P64.as<double>(), s.d_P32.as<float>(), pl_elems, st));
   }
@@ -297,6 +402,14 @@ int scw_synthesize(scw_ctx* ctx, scw_solution* sol, const scw_grid* grid, int pr
   a.E = E_dev;
   a.kgab32 = s.d_kgab32.p;
   a.task_dz32 = pl.d_task_dz32.p;
+  a.precision = precision;
+  a.mfma = pl.mfma;
+  a.kp = pl.kp;
+  a.fft_p = pl.fft_p;
+  a.fft_tw = pl.d_fft_tw.p;
+  a.bmat = pl.d_bmat.p;
+  a.bscale = pl.d_bscale.as<float>();
+  a.amat = pl.d_amat.p;
   {
     const char* env = getenv("SCW_IDFT_GTILES");
     a.idft_gtiles = env ? atoi(env) : 0;

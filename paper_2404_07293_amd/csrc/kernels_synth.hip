@@ -392,6 +392,134 @@ __global__ void __launch_bounds__(FT) idft_kernel(
   }
 }
 
+// ---------------------------------------------------------------- inverse DFT, factored
+// For fy = R * P with P in {2, 4, 8, 16, 32} and V <= 32. One block per
+// (plane/component, 64 columns f); threads are 64 columns x 4 groups.
+//   x pass: T[v][f] by Horner (as above) into 32 zero-padded slots s = v + 16.
+//   y pass: write g = g1 + R g2. With w = exp(2 pi i / fy), w^R = exp(2 pi i / P):
+//     E[g1 + R g2] = sum_r A[r] exp(2 pi i r g2 / P),
+//     A[r] = sum_{v = r mod P} T[v] w^(v g1),
+//   so each (column, g1) costs 32 twiddle MACs plus one P-point FFT held in
+//   registers, and writes P outputs; each store writes 64 consecutive columns.
+template <typename T, int P>
+__device__ __forceinline__ void small_fft(cx<T>* a, const cx<T>* tw) {  // tw[k] = e^{2 pi i k/P}
+  // bit-reversal permutation
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    int r = 0;
+#pragma unroll
+    for (int b = 1, x = i; b < P; b <<= 1, x >>= 1) r = (r << 1) | (x & 1);
+    if (r > i) {
+      const cx<T> tmp = a[i];
+      a[i] = a[r];
+      a[r] = tmp;
+    }
+  }
+#pragma unroll
+  for (int len = 2; len <= P; len <<= 1) {
+#pragma unroll
+    for (int i = 0; i < P; i += len) {
+#pragma unroll
+      for (int j = 0; j < len / 2; ++j) {
+        const cx<T> w = tw[j * (P / len)];
+        const cx<T> u = a[i + j], v = a[i + j + len / 2];
+        const cx<T> t = {v.x * w.x - v.y * w.y, v.x * w.y + v.y * w.x};
+        a[i + j] = {u.x + t.x, u.y + t.y};
+        a[i + j + len / 2] = {u.x - t.x, u.y - t.y};
+      }
+    }
+  }
+}
+
+constexpr int FFT_COLS = 64;
+
+template <typename T, int P>
+__global__ void __launch_bounds__(256) idft_fft_kernel(
+    const cx<T>* __restrict__ spec, const cx<T>* __restrict__ wx, const cx<T>* __restrict__ tw1g,
+    const cx<T>* __restrict__ tw2g, int U, int V, int fx, int fy, int fz, cx<T>* __restrict__ E) {
+  extern __shared__ unsigned char smem_raw[];
+  const int R = fy / P;
+  cx<T>* S = reinterpret_cast<cx<T>*>(smem_raw);  // [V*U]
+  cx<T>* Ts = S + U * V;                          // [32][FFT_COLS]
+  cx<T>* tw1 = Ts + 32 * FFT_COLS;                // [32][R]: w^((s-16) g1)
+  cx<T>* tw2 = tw1 + 32 * R;                      // [P]: e^{2 pi i k / P}
+  const int M = U * V;
+  const int pc = blockIdx.y;
+  const int plane = pc / 3, comp = pc % 3;
+  const int t = threadIdx.x, col = t % FFT_COLS, q = t / FFT_COLS;
+  const int f = blockIdx.x * FFT_COLS + col;
+  const bool live = f < fx;
+  const cx<T>* src = spec + (long long)pc * M;
+  for (int i = t; i < M; i += 256) S[i] = src[i];
+  for (int i = t; i < 32 * FFT_COLS; i += 256) Ts[i] = {0, 0};
+  for (int i = t; i < 32 * R; i += 256) tw1[i] = tw1g[i];
+  for (int i = t; i < P; i += 256) tw2[i] = tw2g[i];
+  __syncthreads();
+  if (live) {
+    const cx<T> w = wx[f], sh = wx[fx + f];
+    for (int vi = q; vi < V; vi += 4) {
+      const cx<T>* row = S + vi * U;
+      cx<T> acc = row[U - 1];
+      for (int u = U - 2; u >= 0; --u) acc = cmuladd(acc, w, row[u]);
+      Ts[(vi - V / 2 + 16) * FFT_COLS + col] = cmul(acc, sh);
+    }
+  }
+  __syncthreads();
+  if (!live) return;
+  cx<T> tcol[32];
+#pragma unroll
+  for (int sl = 0; sl < 32; ++sl) tcol[sl] = Ts[sl * FFT_COLS + col];
+  cx<T> twr[P];
+#pragma unroll
+  for (int k = 0; k < P; ++k) twr[k] = tw2[k];
+  cx<T>* dst = E + (((long long)comp * fz + plane) * fy) * fx + f;
+  for (int g1 = q; g1 < R; g1 += 4) {
+    cx<T> a[P];
+#pragma unroll
+    for (int r = 0; r < P; ++r) a[r] = {0, 0};
+#pragma unroll
+    for (int sl = 0; sl < 32; ++sl) {
+      constexpr int dummy = 0;
+      (void)dummy;
+      const int r = ((sl - 16) % P + P) % P;
+      const cx<T> w1 = tw1[sl * R + g1];
+      a[r].x = fma(tcol[sl].x, w1.x, fma(-tcol[sl].y, w1.y, a[r].x));
+      a[r].y = fma(tcol[sl].x, w1.y, fma(tcol[sl].y, w1.x, a[r].y));
+    }
+    small_fft<T, P>(a, twr);
+#pragma unroll
+    for (int g2 = 0; g2 < P; ++g2) {
+      cx<T>* d = dst + (long long)(g1 + R * g2) * fx;
+      __builtin_nontemporal_store(a[g2].x, &d->x);
+      __builtin_nontemporal_store(a[g2].y, &d->y);
+    }
+  }
+}
+
+template <typename T>
+hipError_t launch_idft_fft(const SynthArgs& a, hipStream_t s) {
+  const int P = a.fft_p, R = a.fy / P;
+  const size_t lds =
+      ((size_t)a.U * a.V + 32 * FFT_COLS + 32 * (size_t)R + (size_t)P) * sizeof(cx<T>);
+  dim3 grid((a.fx + FFT_COLS - 1) / FFT_COLS, a.fz * 3);
+  const cx<T>* tw1 = reinterpret_cast<const cx<T>*>(a.fft_tw);
+  const cx<T>* tw2 = tw1 + 32 * (size_t)R;
+  auto go = [&](auto kern) {
+    kern<<<grid, 256, lds, s>>>(reinterpret_cast<const cx<T>*>(a.spec),
+                                reinterpret_cast<const cx<T>*>(a.twx), tw1, tw2, a.U, a.V, a.fx,
+                                a.fy, a.fz, reinterpret_cast<cx<T>*>(a.E));
+  };
+  switch (P) {
+    case 2: go(idft_fft_kernel<T, 2>); break;
+    case 4: go(idft_fft_kernel<T, 4>); break;
+    case 8: go(idft_fft_kernel<T, 8>); break;
+    case 16: go(idft_fft_kernel<T, 16>); break;
+    case 32: go(idft_fft_kernel<T, 32>); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_idft(const SynthArgs& a, hipStream_t s) {
   const int n_pc = a.fz * 3;
@@ -480,7 +608,14 @@ hipError_t launch_synthesis(const SynthArgs& a, hipStream_t s, hipEvent_t* ev) {
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if ((e = mark(3)) != hipSuccess) return e;
-  if ((e = launch_idft<T>(a, s)) != hipSuccess) return e;
+  if (a.fft_p > 0) {
+    if ((e = launch_idft_fft<T>(a, s)) != hipSuccess) return e;
+  } else if (sizeof(T) == 4 && a.mfma) {
+    MfmaArgs m{a.U, a.V, a.fx, a.fy, a.fz, a.kp, a.idft_gtiles, a.spec, a.twx, a.bmat, a.bscale, a.amat, a.E};
+    if ((e = launch_idft_mfma(m, a.precision, s)) != hipSuccess) return e;
+  } else if ((e = launch_idft<T>(a, s)) != hipSuccess) {
+    return e;
+  }
   return mark(4);
 }
 

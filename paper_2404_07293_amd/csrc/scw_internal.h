@@ -97,6 +97,13 @@ struct Plan {
   DevBuf d_ext;                     // int2 + double: exterior plane table
   DevBuf d_w;                       // W  [ntasks][2][zt][2M] complex<T>
   DevBuf d_spec;                    // [fz][3M] complex<T>
+  DevBuf d_amat;                    // MFMA twiddle operand of the y pass
+  DevBuf d_bmat;                    // MFMA T operand written by the x pass
+  DevBuf d_bscale;                  // float [fz*3] power-of-two operand scales
+  int kp = 0;                       // padded K of the y-pass GEMM
+  int fft_p = 0;                    // factored y pass (fy = R * P) when > 0
+  DevBuf d_fft_tw;                  // its twiddles
+  bool mfma = false;                // inverse transform on the matrix cores
   DevBuf d_twx;                     // [2][fx] complex<T>: e^{2 pi i f/fx}, e^{-2 pi i (U/2) f/fx}
   DevBuf d_twy;                     // [2][fy] complex<T>: same for g, V
   bool valid = false;
@@ -178,7 +185,28 @@ struct SynthArgs {
   const void* kgab32;      // complex64 [3][L][2M]: k*gamma, a, b
   const void* task_dz32;   // float2 [ntasks][zt]
   int idft_gtiles;         // 0 = automatic
+  int precision;           // scw_precision
+  bool mfma;               // inverse transform on the matrix cores
+  int kp;
+  int fft_p;               // > 0: factored transform with this P (fy = R * P)
+  const void* fft_tw;      // [32][R] then [P] twiddles of the factored transform
+  void* bmat;
+  float* bscale;
+  const void* amat;
 };
+
+struct MfmaArgs {
+  int U, V, fx, fy, fz, Kp;
+  int pcb;            // plane/components per y-pass block (0 = automatic)
+  const void* spec;   // [fz*3][M] complex64
+  const void* wx;     // [2][fx] complex64
+  void* bmat;
+  float* bscale;
+  const void* amat;
+  void* E;
+};
+int mfma_kstep(int precision);
+hipError_t launch_idft_mfma(const MfmaArgs& a, int precision, hipStream_t s);
 // `ev`, when non-null, holds kNumStages + 1 events recorded around the stages.
 hipError_t launch_synthesis_fp64(const SynthArgs& a, hipStream_t s, hipEvent_t* ev);
 hipError_t launch_synthesis_fp32(const SynthArgs& a, hipStream_t s, hipEvent_t* ev);

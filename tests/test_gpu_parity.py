@@ -179,3 +179,48 @@ def test_error_codes(ctx):
         sol.synthesize(W.Grid(fx=0, fy=4, fz=4, z_begin=0, z_end=1), "fp32")
     with pytest.raises(P.ScwError):
         sol.synthesize(W.Grid(fx=4, fy=4, fz=4, z_begin=1, z_end=0), "fp32")
+
+
+# Split-precision inverse transform on the matrix cores. Each operand is split
+# x = hi + lo and three products are accumulated in FP32; the dropped lo*lo
+# term and the rounding of lo leave a relative error per product of about
+# 2^-16 (bf16) or 2^-22 (fp16) of the operand magnitudes. Over the K <= 2V
+# terms of one output and the spread of magnitudes in a field, the bounds are:
+BF16X3_TOL = 1e-4
+FP16X3_TOL = 1e-5
+
+
+@pytest.mark.parametrize("precision,tol", [("bf16x3", BF16X3_TOL), ("fp16x3", FP16X3_TOL),
+                                           ("fp32", FP32_TOL)])
+def test_split_precision_matches_oracle(ctx, precision, tol):
+    for prob, grid in (W.sphere_config(),
+                       (ragged_problem(seed=11),
+                        W.Grid(fx=13, fy=7, fz=9, z_begin=-0.3, z_end=0.9))):
+        _, _, want = cwt.simulate(prob, grid)
+        _, got = run(ctx, prob, grid, precision)
+        err = rel_l2(got, want)
+        per = [rel_l2(got[c], want[c]) for c in range(3)]
+        print("%s rel-L2 %.3e per component %s" % (precision, err,
+                                                   ["%.2e" % x for x in per]))
+        assert err <= tol
+
+
+@pytest.mark.parametrize("mode", ["valu", "mfma", "fft"])
+def test_fp32_transform_variants_match_oracle(ctx, monkeypatch, mode):
+    # the FP32 inverse transform has three kernels: direct Horner sums on the
+    # VALU, MFMA GEMM, and the factored y pass (default when fy = R * P)
+    torch = _torch()
+    if mode != "fft":
+        monkeypatch.setenv("SCW_IDFT", mode)
+    for prob, grid in (W.sphere_config(),
+                       (ragged_problem(seed=12),
+                        W.Grid(fx=24, fy=64, fz=7, z_begin=-0.2, z_end=0.8)),
+                       (ragged_problem(seed=13, U=7, V=5),
+                        W.Grid(fx=70, fy=512, fz=3, z_begin=0.1, z_end=0.5))):
+        _, _, want = cwt.simulate(prob, grid)
+        sol = ctx.solve(prob)
+        got = sol.synthesize(grid, "fp32").cpu().numpy()
+        torch.cuda.synchronize()
+        err = rel_l2(got, want)
+        print("fp32 %s fy=%d rel-L2 %.3e" % (mode, grid.fy, err))
+        assert err <= FP32_TOL
