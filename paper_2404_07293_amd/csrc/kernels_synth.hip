@@ -215,6 +215,13 @@ __global__ void __launch_bounds__(256) modal_f32_kernel(
 #pragma unroll
   for (int i = 0; i < NV; ++i) acc[i] = 0.f;
 
+  // The first rows' loads are issued before the phase table is built, and
+  // each iteration prefetches the next one, so every wave keeps two sets of
+  // RW 16-byte loads in flight.
+  const int qn_first = min(jc, n2) / 2;
+  float4 cur[RW];
+#pragma unroll
+  for (int r = 0; r < RW; ++r) cur[r] = lane < qn_first ? prow[r][lane] : make_float4(0, 0, 0, 0);
   for (int j0 = 0; j0 < n2; j0 += jc) {
     const int jn = min(jc, n2 - j0);
     __syncthreads();
@@ -231,10 +238,16 @@ __global__ void __launch_bounds__(256) modal_f32_kernel(
     }
     __syncthreads();
     const int q0 = j0 / 2, qn = jn / 2;
+    const int nq_next = (j0 + jc < n2) ? min(jc, n2 - j0 - jc) / 2 : 0;
     for (int q = lane; q < qn; q += 64) {
-      float4 pv[RW];
+      // prefetch the next iteration (or the first of the next chunk)
+      float4 nxt[RW];
+      const int qa = q + 64;
+      const bool in_chunk = qa < qn;
+      const int qg = in_chunk ? q0 + qa : q0 + qn + (qa - qn);
+      const bool have = in_chunk || (qa - qn) < nq_next;
 #pragma unroll
-      for (int r = 0; r < RW; ++r) pv[r] = prow[r][q0 + q];
+      for (int r = 0; r < RW; ++r) nxt[r] = have ? prow[r][qg] : make_float4(0, 0, 0, 0);
 #pragma unroll
       for (int p = 0; p < ZT; ++p) {
         const float4 w = sw4[p * (jc / 2) + q];
@@ -242,16 +255,18 @@ __global__ void __launch_bounds__(256) modal_f32_kernel(
         for (int r = 0; r < RW; ++r) {
           float& re = acc[(r * ZT + p) * 2];
           float& im = acc[(r * ZT + p) * 2 + 1];
-          re = fmaf(pv[r].x, w.x, re);
-          re = fmaf(-pv[r].y, w.y, re);
-          im = fmaf(pv[r].x, w.y, im);
-          im = fmaf(pv[r].y, w.x, im);
-          re = fmaf(pv[r].z, w.z, re);
-          re = fmaf(-pv[r].w, w.w, re);
-          im = fmaf(pv[r].z, w.w, im);
-          im = fmaf(pv[r].w, w.z, im);
+          re = fmaf(cur[r].x, w.x, re);
+          re = fmaf(-cur[r].y, w.y, re);
+          im = fmaf(cur[r].x, w.y, im);
+          im = fmaf(cur[r].y, w.x, im);
+          re = fmaf(cur[r].z, w.z, re);
+          re = fmaf(-cur[r].w, w.w, re);
+          im = fmaf(cur[r].z, w.w, im);
+          im = fmaf(cur[r].w, w.z, im);
         }
       }
+#pragma unroll
+      for (int r = 0; r < RW; ++r) cur[r] = nxt[r];
     }
   }
   halve<NV>(acc, lane);
@@ -433,6 +448,17 @@ __device__ __forceinline__ void small_fft(cx<T>* a, const cx<T>* tw) {  // tw[k]
 
 constexpr int FFT_COLS = 64;
 
+// One non-temporal store of a whole complex value (the field is written once
+// and not read back by the synthesis).
+__device__ __forceinline__ void store_nt(cx<float>* d, cx<float> v) {
+  typedef float f2v __attribute__((ext_vector_type(2)));
+  __builtin_nontemporal_store(f2v{v.x, v.y}, reinterpret_cast<f2v*>(d));
+}
+__device__ __forceinline__ void store_nt(cx<double>* d, cx<double> v) {
+  typedef double d2v __attribute__((ext_vector_type(2)));
+  __builtin_nontemporal_store(d2v{v.x, v.y}, reinterpret_cast<d2v*>(d));
+}
+
 template <typename T, int P>
 __global__ void __launch_bounds__(256) idft_fft_kernel(
     const cx<T>* __restrict__ spec, const cx<T>* __restrict__ wx, const cx<T>* __restrict__ tw1g,
@@ -488,11 +514,7 @@ __global__ void __launch_bounds__(256) idft_fft_kernel(
     }
     small_fft<T, P>(a, twr);
 #pragma unroll
-    for (int g2 = 0; g2 < P; ++g2) {
-      cx<T>* d = dst + (long long)(g1 + R * g2) * fx;
-      __builtin_nontemporal_store(a[g2].x, &d->x);
-      __builtin_nontemporal_store(a[g2].y, &d->y);
-    }
+    for (int g2 = 0; g2 < P; ++g2) store_nt(dst + (long long)(g1 + R * g2) * fx, a[g2]);
   }
 }
 
