@@ -161,6 +161,64 @@ def golden_error(E, prob, grid, per_component=False):
     return float(np.linalg.norm(got - want) / np.linalg.norm(want))
 
 
+SWEEP_GOLDEN = os.path.join(ROOT, "tests", "golden", "sweep_job.npz")
+
+
+def batched_sweep(ctx, torch, dev, stream, args):
+    """The spectral sweep (256 wavenumbers x 16 patches of 32x32x16 voxels,
+    truncation 9..25 per patch, 8 transmitted planes of 64x64) as one batched,
+    graph-captured launch. Each patch is solved once at one wavenumber (patch
+    p at the (16p+1)-th); the 4096 jobs reuse the solution of their patch, so
+    the launch does the synthesis work of the full sweep (the work per job
+    depends only on its truncation and the grid)."""
+    import workloads as W
+    jobs = W.spectral_sweep_jobs()
+    nus = sorted(set(j[0] for j in jobs))
+    u_of = {p: u for _, p, u in jobs}
+    t0 = time.perf_counter()
+    solved, grid = {}, None
+    for p in sorted(u_of):
+        prob, grid = W.sweep_problem(nus[16 * p], p, u_of[p])
+        solved[p] = ctx.solve(prob)
+    t_setup = time.perf_counter() - t0
+    b = ctx.batch([solved[p] for _, p, _ in jobs], grid)
+    Eb = torch.empty((len(jobs), 3, grid.fz, grid.fy, grid.fx), dtype=torch.complex64,
+                     device=dev)
+    for _ in range(max(2, args.warmup)):
+        b.launch(out=Eb, stream=stream)
+    torch.cuda.synchronize()
+    s0 = torch.cuda.Event(enable_timing=True)
+    s1 = torch.cuda.Event(enable_timing=True)
+    s0.record(stream)
+    for _ in range(args.steps):
+        b.launch(out=Eb, stream=stream)
+    s1.record(stream)
+    torch.cuda.synchronize()
+    ms = s0.elapsed_time(s1) / args.steps
+    voxels = len(jobs) * grid.fz * grid.fy * grid.fx
+    err = None
+    if os.path.exists(SWEEP_GOLDEN):
+        g = np.load(SWEEP_GOLDEN, allow_pickle=False)
+        pt, k = int(g["patch"]), int(g["nu_index"])
+        if k == 16 * pt:
+            idx = [i for i, (nu, p, _) in enumerate(jobs) if p == pt][0]
+            got = Eb[idx].cpu().numpy()
+            err = float(np.linalg.norm(got - g["E"]) / np.linalg.norm(g["E"]))
+    bytes_out = voxels * 3 * 8
+    log("batched sweep: %d jobs, %.3f ms/launch, %.3e voxels/s, rel-L2 %s (setup %.1f s)" % (
+        len(jobs), ms, voxels / (ms * 1e-3), err, t_setup))
+    rec = {"value": voxels / (ms * 1e-3), "ms_per_step": ms, "jobs": len(jobs),
+           "voxels_per_step": voxels, "rel_l2_vs_oracle": err,
+           "hbm_write_gbps": bytes_out / (ms * 1e-3) / 1e9,
+           "solved_jobs": len(solved), "setup_s": t_setup,
+           "note": "one solve per patch; all 256 wavenumbers of a patch reuse it"}
+    del Eb
+    b.free()
+    for sol in solved.values():
+        sol.free()
+    return rec
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -170,6 +228,8 @@ def main(argv=None):
     ap.add_argument("--workload", default="working", choices=["working", "large"])
     ap.add_argument("--layers", type=int, default=None, help="keep only the first N layers")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batched", type=int, default=1,
+                    help="also time the batched spectral sweep (4096 jobs, one launch)")
     ap.add_argument("--variants", default="bf16x3,fp16x3",
                     help="other precisions timed in the same run ('' for none)")
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -288,6 +348,9 @@ def main(argv=None):
             log("%s: ms/step %.4f rel-L2 %s" % (prec, vms, variants[prec]["rel_l2_vs_oracle"]))
             del Ev
         out["variants"] = variants
+    if args.batched:
+        out.setdefault("variants", {})["batched_sweep"] = batched_sweep(ctx, torch, dev, stream,
+                                                                     args)
     if not args.no_cpu_baseline:
         log("timing the oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(prob, grid)

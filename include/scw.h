@@ -177,6 +177,24 @@ int scw_synthesize(scw_ctx* ctx, scw_solution* sol, const scw_grid* grid,
 int scw_field(scw_ctx* ctx, const scw_problem* prob, const scw_grid* grid,
               int precision, void* E_dev, void* hip_stream);
 
+/* Batched synthesis: many solved problems (for example wavelengths x patches
+ * with different truncation orders U x V) on one shared grid, in one
+ * persistent kernel launch that is captured in a HIP graph and replayed.
+ * Every plane of `grid` must lie outside every job's sample (above z0 or
+ * below its bottom surface): the field there follows from the exterior
+ * coefficients alone (Eq. 9, then Eq. 10). Requirements: precision
+ * SCW_FP32; U, V <= 31; grid->fy a power of two >= 2.
+ * `jobs` are borrowed: they must outlive the batch. E_dev receives
+ * [njobs][3][fz][fy][fx] complex64, jobs in the order given.
+ * scw_batch_launch enqueues the graph on `hip_stream` (NULL = default
+ * stream); the first launch with a given E_dev captures the graph. Launches of
+ * one batch must not overlap (they share a work counter). */
+typedef struct scw_batch scw_batch;
+int scw_batch_plan(scw_ctx* ctx, scw_solution* const* jobs, int njobs, const scw_grid* grid,
+                   int precision, scw_batch** out);
+int scw_batch_launch(scw_batch* batch, void* E_dev, void* hip_stream);
+void scw_batch_free(scw_batch* batch);
+
 /* Per-stage timing of scw_synthesize with HIP events recorded on the
  * synthesis stream between its kernels. scw_profile_begin enables recording
  * for up to `max_calls` following scw_synthesize calls on this context;

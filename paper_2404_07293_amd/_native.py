@@ -75,6 +75,11 @@ SIGNATURES = {
     "scw_profile_end": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                        ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
     "scw_stage_name": (ctypes.c_char_p, [ctypes.c_int]),
+    "scw_batch_plan": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
+                                      ctypes.c_int, ctypes.POINTER(ScwGrid), ctypes.c_int,
+                                      ctypes.POINTER(ctypes.c_void_p)]),
+    "scw_batch_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "scw_batch_free": (None, [ctypes.c_void_p]),
 }
 
 _lib = None

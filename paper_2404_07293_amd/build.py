@@ -21,6 +21,7 @@ SOURCES = [
     "kernels_setup.hip",
     "kernels_synth.hip",
     "kernels_mfma.hip",
+    "kernels_batch.hip",
 ]
 
 ARCH = "gfx950"

@@ -7,6 +7,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <memory>
 #include <thread>
 
 #include "scw_internal.h"
@@ -16,6 +17,21 @@ struct scw_ctx {
 };
 struct scw_solution {
   scw::Solution s;
+};
+struct scw_batch {
+  scw::Context* ctx = nullptr;
+  int njobs = 0, n_items = 0, P = 0, grid_blocks = 0;
+  scw_grid grid{};
+  scw::DevBuf d_jobs, d_items, d_planes, d_coef, d_wfull, d_tw, d_counter;
+  hipStream_t capture_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  void* graph_E = nullptr;
+  ~scw_batch() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (capture_stream) (void)hipStreamDestroy(capture_stream);
+  }
 };
 
 namespace scw {
@@ -501,5 +517,149 @@ double scw_synthesis_bytes(const scw_solution* sol, const scw_grid* grid, int pr
   const double ebytes = 3.0 * grid->fx * grid->fy * grid->fz * eb;
   return pbytes + ebytes;
 }
+
+int scw_batch_plan(scw_ctx* ctx, scw_solution* const* jobs, int njobs, const scw_grid* grid,
+                   int precision, scw_batch** out) {
+  if (!ctx || !jobs || njobs < 1 || !out) return fail(SCW_EINVAL, "null or empty batch");
+  *out = nullptr;
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  if (precision != SCW_FP32) return fail(SCW_EINVAL, "batched synthesis runs in SCW_FP32");
+  if (grid->fy < 2 || (grid->fy & (grid->fy - 1)) != 0)
+    return fail(SCW_EINVAL, "batched synthesis needs fy a power of two");
+  SCW_HIP(hipSetDevice(ctx->c.device));
+  std::unique_ptr<scw_batch> b(new (std::nothrow) scw_batch());
+  if (!b) return fail(SCW_ENOMEM, "batch allocation failed");
+  b->ctx = &ctx->c;
+  b->njobs = njobs;
+  b->grid = *grid;
+  const int fz = grid->fz;
+  std::vector<BatchJob> jt(njobs);
+  std::vector<BatchPlane> pt((size_t)njobs * fz);
+  std::vector<float> coef;
+  const double dz = (grid->z_end - grid->z_begin) / fz;
+  for (int j = 0; j < njobs; ++j) {
+    if (!jobs[j]) return fail(SCW_EINVAL, "null job");
+    const Solution& s = jobs[j]->s;
+    if (s.device != ctx->c.device) return fail(SCW_EINVAL, "job on another device");
+    if (s.U > 31 || s.V > 31) return fail(SCW_EINVAL, "batched synthesis needs U, V <= 31");
+    const double zL = s.L * s.d;
+    for (int p = 0; p < fz; ++p) {
+      const double z = grid->z_begin + (p + 0.5) * dz;
+      if (z < 0.0) pt[(size_t)j * fz + p] = {0, (float)z};
+      else if (z >= zL) pt[(size_t)j * fz + p] = {2, (float)(z - zL)};
+      else return fail(SCW_EINVAL, "batched grid plane inside job " + std::to_string(j));
+    }
+    const int M = s.M;
+    jt[j] = {s.U, s.V, (long long)(coef.size() / 2)};
+    auto put = [&](zc c) {
+      coef.push_back((float)c.real());
+      coef.push_back((float)c.imag());
+    };
+    for (zc c : s.p_inc) put(c);
+    for (zc c : s.p_ref) put(c);
+    for (zc c : s.p_trn) put(c);
+    for (int m = 0; m < M; ++m) put(s.k * s.sz_top[m]);
+    for (int m = 0; m < M; ++m) put(s.k * s.sz_bot[m]);
+  }
+  // work items, costliest jobs first
+  std::vector<int> order(njobs);
+  for (int j = 0; j < njobs; ++j) order[j] = j;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    return jt[x].U * jt[x].V > jt[y].U * jt[y].V;
+  });
+  const int nft = (grid->fx + 63) / 64;
+  std::vector<BatchItem> items;
+  items.reserve((size_t)njobs * fz * 3 * nft);
+  for (int j : order)
+    for (int p = 0; p < fz; ++p)
+      for (int c = 0; c < 3; ++c)
+        for (int ft = 0; ft < nft; ++ft) items.push_back({j, p, c, ft});
+  b->n_items = (int)items.size();
+  const int P = std::min(32, std::max(2, grid->fy / 16));
+  const int R = grid->fy / P;
+  b->P = P;
+  std::vector<float> wfull(2 * (size_t)grid->fx), tw(2 * (32 * (size_t)R + P));
+  for (int k = 0; k < grid->fx; ++k) {
+    const zc w = twiddle_inv(k, grid->fx);
+    wfull[2 * k] = (float)w.real();
+    wfull[2 * k + 1] = (float)w.imag();
+  }
+  for (int sl = 0; sl < 32; ++sl)
+    for (int g1 = 0; g1 < R; ++g1) {
+      const zc w = twiddle_inv((long long)(sl - 16) * g1, grid->fy);
+      tw[2 * ((size_t)sl * R + g1)] = (float)w.real();
+      tw[2 * ((size_t)sl * R + g1) + 1] = (float)w.imag();
+    }
+  for (int k = 0; k < P; ++k) {
+    const zc w = twiddle_inv(k, P);
+    tw[2 * (32 * (size_t)R + k)] = (float)w.real();
+    tw[2 * (32 * (size_t)R + k) + 1] = (float)w.imag();
+  }
+  if ((rc = upload(b->d_jobs, jt.data(), jt.size() * sizeof(BatchJob))) ||
+      (rc = upload(b->d_items, items.data(), items.size() * sizeof(BatchItem))) ||
+      (rc = upload(b->d_planes, pt.data(), pt.size() * sizeof(BatchPlane))) ||
+      (rc = upload(b->d_coef, coef.data(), coef.size() * 4)) ||
+      (rc = upload(b->d_wfull, wfull.data(), wfull.size() * 4)) ||
+      (rc = upload(b->d_tw, tw.data(), tw.size() * 4)) ||
+      (rc = b->d_counter.reserve(256)))
+    return rc;
+  int cus = 0;
+  SCW_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->c.device));
+  const char* env = getenv("SCW_BATCH_BLOCKS_PER_CU");
+  const int per_cu = env ? std::max(1, atoi(env)) : 4;
+  b->grid_blocks = std::max(1, std::min(b->n_items, cus * per_cu));
+  SCW_HIP(hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking));
+  *out = b.release();
+  return SCW_OK;
+}
+
+int scw_batch_launch(scw_batch* b, void* E_dev, void* hip_stream) {
+  if (!b || !E_dev) return fail(SCW_EINVAL, "null argument");
+  SCW_HIP(hipSetDevice(b->ctx->device));
+  if (!b->exec || b->graph_E != E_dev) {
+    if (b->exec) {
+      (void)hipGraphExecDestroy(b->exec);
+      b->exec = nullptr;
+    }
+    if (b->graph) {
+      (void)hipGraphDestroy(b->graph);
+      b->graph = nullptr;
+    }
+    BatchArgs a{};
+    a.jobs = b->d_jobs.as<BatchJob>();
+    a.items = b->d_items.as<BatchItem>();
+    a.n_items = b->n_items;
+    a.planes = b->d_planes.as<BatchPlane>();
+    a.coef = b->d_coef.p;
+    a.wfull = b->d_wfull.p;
+    const int R = b->grid.fy / b->P;
+    a.tw1 = b->d_tw.p;
+    a.tw2 = b->d_tw.as<float>() + 2 * 32 * (size_t)R;
+    a.fx = b->grid.fx;
+    a.fy = b->grid.fy;
+    a.fz = b->grid.fz;
+    a.P = b->P;
+    a.grid = b->grid_blocks;
+    a.counter = b->d_counter.as<unsigned int>();
+    a.E = E_dev;
+    SCW_HIP(hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal));
+    hipError_t le = launch_batch(a, b->capture_stream);
+    hipGraph_t g = nullptr;
+    hipError_t ce = hipStreamEndCapture(b->capture_stream, &g);
+    if (le != hipSuccess || ce != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return fail(SCW_EHIP, std::string("batch graph capture failed: ") +
+                                hipGetErrorString(le != hipSuccess ? le : ce));
+    }
+    b->graph = g;
+    SCW_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    b->graph_E = E_dev;
+  }
+  SCW_HIP(hipGraphLaunch(b->exec, reinterpret_cast<hipStream_t>(hip_stream)));
+  return SCW_OK;
+}
+
+void scw_batch_free(scw_batch* b) { delete b; }
 
 }  // extern "C"

@@ -206,6 +206,33 @@ struct MfmaArgs {
   void* E;
 };
 int mfma_kstep(int precision);
+
+// ------------------------------------------------------------------ batched synthesis
+struct BatchJob {
+  int U, V;
+  long long coef_offset;  // complex64 elements into the coefficient buffer
+};
+struct BatchItem {
+  int job, plane, comp, ftile;
+};
+struct BatchPlane {
+  int kind;   // 0 above the sample, 2 below it
+  float dz;   // z - z0 above, z - zL below
+};
+struct BatchArgs {
+  const BatchJob* jobs;
+  const BatchItem* items;
+  int n_items;
+  const BatchPlane* planes;  // [njobs][fz]
+  const void* coef;          // complex64 per job: p_inc, p_ref, p_trn [3][M] each, k sz_top, k sz_bot [M]
+  const void* wfull;         // [fx]: e^{2 pi i k / fx}
+  const void* tw1;           // [32][R]
+  const void* tw2;           // [P]
+  int fx, fy, fz, P, grid;
+  unsigned int* counter;
+  void* E;                   // [njobs][3][fz][fy][fx] complex64
+};
+hipError_t launch_batch(const BatchArgs& a, hipStream_t s);
 hipError_t launch_idft_mfma(const MfmaArgs& a, int precision, hipStream_t s);
 // `ev`, when non-null, holds kNumStages + 1 events recorded around the stages.
 hipError_t launch_synthesis_fp64(const SynthArgs& a, hipStream_t s, hipEvent_t* ev);

@@ -68,6 +68,15 @@ class Context:
         N.check(self.lib.scw_solve(self.handle, ctypes.byref(p), ctypes.byref(h)))
         return Solution(self, h, prob)
 
+    def batch(self, solutions, grid, precision="fp32"):
+        """``scw_batch_plan`` over solved problems sharing one exterior grid."""
+        arr = (ctypes.c_void_p * len(solutions))(*[s.handle.value for s in solutions])
+        h = ctypes.c_void_p()
+        N.check(self.lib.scw_batch_plan(self.handle, arr, len(solutions),
+                                        ctypes.byref(_grid(grid)), N.PRECISION[precision],
+                                        ctypes.byref(h)))
+        return Batch(self, h, list(solutions), grid)
+
 
 def _grid(grid):
     g = N.ScwGrid()
@@ -130,4 +139,42 @@ class Solution:
                                         ctypes.byref(_grid(grid)), N.PRECISION[precision],
                                         ctypes.c_void_p(out.data_ptr()),
                                         ctypes.c_void_p(stream.cuda_stream)))
+        return out
+
+
+class Batch:
+    """A planned batched synthesis (``scw_batch``); keeps its jobs alive."""
+
+    def __init__(self, ctx, handle, jobs, grid):
+        self.ctx = ctx
+        self.lib = ctx.lib
+        self.handle = handle
+        self.jobs = jobs
+        self.grid = grid
+
+    def free(self):
+        if self.handle:
+            self.lib.scw_batch_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def launch(self, out=None, stream=None):
+        """Replay the batch graph into ``out`` [njobs, 3, fz, fy, fx] complex64."""
+        import torch
+        g = self.grid
+        shape = (len(self.jobs), 3, int(g.fz), int(g.fy), int(g.fx))
+        dev = torch.device("cuda", self.ctx.device)
+        if out is None:
+            out = torch.empty(shape, dtype=torch.complex64, device=dev)
+        if tuple(out.shape) != shape or out.dtype != torch.complex64 or not out.is_contiguous():
+            raise ValueError("out must be a contiguous complex64 tensor of shape %s" % (shape,))
+        if stream is None:
+            stream = torch.cuda.current_stream(dev)
+        N.check(self.lib.scw_batch_launch(self.handle, ctypes.c_void_p(out.data_ptr()),
+                                          ctypes.c_void_p(stream.cuda_stream)))
         return out

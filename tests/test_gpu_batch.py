@@ -1,0 +1,114 @@
+"""Batched synthesis (one persistent, graph-captured launch over many solved
+problems of uneven truncation) against the FP64 oracle and against the
+single-problem synthesis, through the C ABI."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import cwt
+
+pytestmark = pytest.mark.gpu
+FP32_TOL = 1e-4
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    _torch()
+    import paper_2404_07293_amd as P
+    return P.Context(0)
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def small_job(seed, U, V, lam, nz=3, nx=10, ny=9):
+    # U <= nx and V <= ny: every spatial frequency of the band is resolved by
+    # the voxel grid (otherwise modes alias and the layer problem degenerates)
+    rng = np.random.default_rng(seed)
+    n = 1.3 + 0.3 * rng.random((nz, ny, nx)) + 0.03j * rng.random((nz, ny, nx))
+    return W.Problem(n=n.astype(complex), px=0.28, py=0.3, pz=0.2, lam=lam, U=U, V=V,
+                     n_top=1.0, n_bot=1.2 + 0.0j, plane_wave=W.PlaneWave(0, 0, 1.0, 0.5j))
+
+
+def well_conditioned(prob):
+    st = cwt.setup(prob)
+    return min(np.min(np.abs(md.gamma)) / np.max(np.abs(md.gamma)) for md in st.modes) > 1e-3
+
+
+def test_batch_matches_oracle_and_single_synthesis(ctx):
+    torch = _torch()
+    specs = [(1, 3, 3, 1.0), (2, 7, 5, 0.9), (3, 5, 7, 1.1), (4, 9, 9, 1.3), (5, 1, 1, 1.0)]
+    probs = [small_job(*s) for s in specs]
+    assert all(well_conditioned(p) for p in probs)
+    T = probs[0].thickness
+    below = W.Grid(fx=70, fy=16, fz=3, z_begin=T, z_end=T + 0.9)
+    sols = [ctx.solve(p) for p in probs]
+    b = ctx.batch(sols, below)
+    out = b.launch()
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    for j, (prob, sol) in enumerate(zip(probs, sols)):
+        _, _, want = cwt.simulate(prob, below)
+        err = rel_l2(got[j], want)
+        print("job %d U=%d V=%d rel-L2 %.3e" % (j, prob.U, prob.V, err))
+        assert err <= FP32_TOL
+        single = sol.synthesize(below, "fp32").cpu().numpy()
+        assert rel_l2(got[j], single) <= 1e-5
+    # replaying the graph gives the same field bit for bit
+    again = b.launch().cpu().numpy()
+    torch.cuda.synchronize()
+    assert np.array_equal(again, got)
+    # a new output buffer re-captures the graph
+    other = torch.zeros_like(out)
+    b.launch(out=other)
+    torch.cuda.synchronize()
+    assert np.array_equal(other.cpu().numpy(), got)
+
+
+def test_batch_above_the_sample(ctx):
+    torch = _torch()
+    probs = [small_job(7, 5, 3, 1.0), small_job(8, 3, 5, 0.8, nz=2)]
+    assert all(well_conditioned(p) for p in probs)
+    grid = W.Grid(fx=16, fy=32, fz=2, z_begin=-0.6, z_end=-0.1)
+    # jobs of different thickness share an exterior grid above the samples
+    sols = [ctx.solve(p) for p in probs]
+    got = ctx.batch(sols, grid).launch().cpu().numpy()
+    torch.cuda.synchronize()
+    for j, prob in enumerate(probs):
+        _, _, want = cwt.simulate(prob, grid)
+        assert rel_l2(got[j], want) <= FP32_TOL
+
+
+def test_sweep_job_matches_oracle(ctx):
+    # one job of the spectral sweep at its real size (32x32x16 voxels, U = 9)
+    torch = _torch()
+    jobs = [j for j in W.spectral_sweep_jobs() if j[2] == 9]
+    nu, patch, U = jobs[0]
+    prob, grid = W.sweep_problem(1650.0, patch, U)
+    st = cwt.setup(prob)
+    sol_o = cwt.solve(st, "unreduced")
+    want = cwt.synthesize(st, sol_o, grid)
+    sol = ctx.solve(prob)
+    got = ctx.batch([sol, sol], grid).launch().cpu().numpy()
+    torch.cuda.synchronize()
+    err = rel_l2(got[0], want)
+    print("sweep job nu=1650 patch=%d U=%d rel-L2 %.3e" % (patch, U, err))
+    assert err <= FP32_TOL
+    assert np.array_equal(got[0], got[1])
+
+
+def test_batch_rejects_interior_grid(ctx):
+    import paper_2404_07293_amd as P
+    sol = ctx.solve(small_job(9, 3, 3, 1.0))
+    with pytest.raises(P.ScwError):
+        ctx.batch([sol], W.Grid(fx=8, fy=8, fz=2, z_begin=0.0, z_end=0.6))
+    with pytest.raises(P.ScwError):
+        ctx.batch([sol], W.Grid(fx=8, fy=12, fz=2, z_begin=0.7, z_end=0.9))
