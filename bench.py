@@ -219,6 +219,86 @@ def batched_sweep(ctx, torch, dev, stream, args):
     return rec
 
 
+SUR_DATA = os.path.join(ROOT, "paper_2404_07293_amd", "data", "surrogate_targets.npz")
+
+
+def surrogate_leg(ctx, torch, dev, stream, args):
+    """Train the spectral-convolution surrogate on CWT-generated pairs, then
+    time inference at batch 4096 and compare with plain CWT."""
+    import workloads as W
+    from paper_2404_07293_amd.surrogate import Surrogate, cwt_targets
+    d = np.load(SUR_DATA, allow_pickle=False)
+    seeds, targets = d["seeds"], d["targets"]
+    n_val = 128
+    patches = np.stack([W.surrogate_patch(int(s)) for s in seeds])
+    sur = Surrogate(ctx, max_batch=4096, seed=11)
+    x_all = sur.encode(patches)
+    t_all = torch.as_tensor(targets).to(dev)
+    n_tr = len(seeds) - n_val
+    xtr, ttr, xva, tva = x_all[:n_tr], t_all[:n_tr], x_all[n_tr:], t_all[n_tr:]
+    rng = np.random.Generator(np.random.PCG64(3))
+    bs, epochs, lr0 = 64, args.sur_epochs, 1e-3
+    steps = epochs * (n_tr // bs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    k = 0
+    for ep in range(epochs):
+        perm = torch.as_tensor(rng.permutation(n_tr), device=dev)
+        for i in range(n_tr // bs):
+            idx = perm[i * bs:(i + 1) * bs]
+            lr = 0.5 * lr0 * (1 + np.cos(np.pi * k / steps))   # cosine decay
+            sur.train_step(xtr[idx].contiguous(), ttr[idx].contiguous(), lr=lr, want_loss=False)
+            k += 1
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+
+    def err_on(x, t):
+        out = sur.forward(x.contiguous())
+        torch.cuda.synchronize()
+        o, w = out.cpu().numpy(), t.cpu().numpy()
+        return float(np.linalg.norm(o - w) / np.linalg.norm(w))
+
+    train_err, val_err = err_on(xtr[:512], ttr[:512]), err_on(xva, tva)
+    # inference throughput at batch 4096 (inputs encoded and resident)
+    reps = (4096 + len(seeds) - 1) // len(seeds)
+    xb = x_all.repeat(reps, 1, 1, 1)[:4096].contiguous()
+    out = torch.empty((4096, 3, 15, 15), dtype=torch.complex64, device=dev)
+    for _ in range(2):
+        sur.forward(xb, out=out)
+    torch.cuda.synchronize()
+    s0 = torch.cuda.Event(enable_timing=True)
+    s1 = torch.cuda.Event(enable_timing=True)
+    n_inf = max(3, args.steps // 5)
+    s0.record(stream)
+    for _ in range(n_inf):
+        sur.forward(xb, out=out)
+    s1.record(stream)
+    torch.cuda.synchronize()
+    ms_inf = s0.elapsed_time(s1) / n_inf
+    # plain CWT on a few validation patches (host FP64 setup + synthesis of p_trn)
+    t1 = time.perf_counter()
+    ncwt = 8
+    cwt_targets(ctx, patches[n_tr:n_tr + ncwt])
+    cwt_rate = ncwt / (time.perf_counter() - t1)
+    # checked inference with the CWT fallback on 64 validation patches
+    t2 = time.perf_counter()
+    _, fell, chk = sur.infer_checked(patches[n_tr:n_tr + 64], n_check=8, seed=5, tol=1e-2)
+    t_checked = time.perf_counter() - t2
+    rate = 4096 / (ms_inf * 1e-3)
+    log("surrogate: train %.1f s (%d steps), rel-L2 train %.3e val %.3e; %.0f patches/s "
+        "vs CWT %.2f patches/s; checked batch rel-L2 %.3e fallback %s" % (
+            t_train, steps, train_err, val_err, rate, cwt_rate, chk, fell))
+    rec = {"train_pairs": n_tr, "val_pairs": n_val, "train_steps": steps,
+           "train_seconds": t_train, "rel_l2_train": train_err, "rel_l2_val": val_err,
+           "infer_batch": 4096, "infer_ms": ms_inf, "patches_per_s": rate,
+           "cwt_patches_per_s": cwt_rate, "speedup_vs_cwt": rate / cwt_rate,
+           "checked_batch": 64, "check_rel_l2": chk, "fallback_fired": fell,
+           "checked_seconds": t_checked,
+           "note": "fallback threshold 1e-2 rel-L2 on 8 CWT-solved patches of the batch"}
+    sur.free()
+    return rec
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -228,6 +308,9 @@ def main(argv=None):
     ap.add_argument("--workload", default="working", choices=["working", "large"])
     ap.add_argument("--layers", type=int, default=None, help="keep only the first N layers")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--surrogate", type=int, default=1,
+                    help="also train and time the spectral-convolution surrogate")
+    ap.add_argument("--sur-epochs", type=int, default=60)
     ap.add_argument("--batched", type=int, default=1,
                     help="also time the batched spectral sweep (4096 jobs, one launch)")
     ap.add_argument("--variants", default="bf16x3,fp16x3",
@@ -348,6 +431,8 @@ def main(argv=None):
             log("%s: ms/step %.4f rel-L2 %s" % (prec, vms, variants[prec]["rel_l2_vs_oracle"]))
             del Ev
         out["variants"] = variants
+    if args.surrogate and os.path.exists(SUR_DATA):
+        out["surrogate"] = surrogate_leg(ctx, torch, dev, stream, args)
     if args.batched:
         out.setdefault("variants", {})["batched_sweep"] = batched_sweep(ctx, torch, dev, stream,
                                                                      args)

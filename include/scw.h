@@ -195,6 +195,43 @@ int scw_batch_plan(scw_ctx* ctx, scw_solution* const* jobs, int njobs, const scw
 int scw_batch_launch(scw_batch* batch, void* E_dev, void* hip_stream);
 void scw_batch_free(scw_batch* batch);
 
+/* Spectral-convolution surrogate of the transmitted field (Eq. 9 below the
+ * sample) for one patch family: 8 x 32 x 32 voxels at pitch lambda/4
+ * (lambda = 1), index 1 above and below, normal x-polarised plane wave of unit
+ * amplitude, 15 x 15 band (U = V = 15). Input patches are complex64
+ * [B][8][32][32]; encoded inputs are float [B][16][32][32]; outputs are the
+ * coefficients p_trn as complex64 [B][3][15][15] (component, then mode order
+ * of Sec. 2.2). The network (FP32) is a lift to 32 channels, four Fourier
+ * layers (truncated DFT2 on |ky| <= 8, 0 <= kx <= 8, per-mode complex 32 x 32
+ * mixing, real inverse DFT2, plus a pointwise 32 x 32 map and bias, GELU
+ * between layers) and a per-mode complex head on the 15 x 15 band.
+ * Parameters are one flat FP32 array of scw_sur_param_count() values. The
+ * training loss is sum |out - target|^2 / sum |target|^2 over the batch.
+ * Device pointers are caller-owned; every call may be enqueued on `stream`
+ * except those that return host values, which synchronise it. */
+typedef struct scw_sur scw_sur;
+long long scw_sur_param_count(void);
+int scw_sur_create(scw_ctx* ctx, int max_batch, unsigned long long seed, scw_sur** out);
+void scw_sur_free(scw_sur* sur);
+int scw_sur_get_params(scw_sur* sur, float* host);
+int scw_sur_set_params(scw_sur* sur, const float* host);  /* also resets Adam state */
+int scw_sur_encode(scw_sur* sur, const void* n_dev, int batch, void* x_dev, void* stream);
+int scw_sur_forward(scw_sur* sur, const void* x_dev, int batch, void* out_dev, void* stream);
+/* loss and, when grad_host is not NULL, dL/dparams (complex entries as
+ * dL/dRe + i dL/dIm) copied to the host */
+int scw_sur_loss_grad(scw_sur* sur, const void* x_dev, const void* target_dev, int batch,
+                      double* loss, float* grad_host, void* stream);
+/* one Adam step (beta1 0.9, beta2 0.999, eps 1e-8); loss may be NULL */
+int scw_sur_train_step(scw_sur* sur, const void* x_dev, const void* target_dev, int batch,
+                       float lr, double* loss, void* stream);
+/* Surrogate inference of host patches (complex128 [B][8][32][32]) with a CWT
+ * check on n_check seeded patches solved by scw_solve. When their rel-L2
+ * exceeds tol, every patch is solved by CWT instead and *fell_back = 1.
+ * out_host receives complex128 [B][3][15][15]. Synchronous. */
+int scw_sur_infer_checked(scw_ctx* ctx, scw_sur* sur, const double* n_host, int batch,
+                          int n_check, unsigned long long seed, double tol, double* out_host,
+                          int* fell_back, double* check_err);
+
 /* Per-stage timing of scw_synthesize with HIP events recorded on the
  * synthesis stream between its kernels. scw_profile_begin enables recording
  * for up to `max_calls` following scw_synthesize calls on this context;

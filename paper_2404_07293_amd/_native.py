@@ -80,6 +80,27 @@ SIGNATURES = {
                                       ctypes.POINTER(ctypes.c_void_p)]),
     "scw_batch_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "scw_batch_free": (None, [ctypes.c_void_p]),
+    "scw_sur_param_count": (ctypes.c_longlong, []),
+    "scw_sur_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_ulonglong,
+                                      ctypes.POINTER(ctypes.c_void_p)]),
+    "scw_sur_free": (None, [ctypes.c_void_p]),
+    "scw_sur_get_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "scw_sur_set_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "scw_sur_encode": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                      ctypes.c_void_p, ctypes.c_void_p]),
+    "scw_sur_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                       ctypes.c_void_p, ctypes.c_void_p]),
+    "scw_sur_loss_grad": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.c_void_p, ctypes.c_void_p]),
+    "scw_sur_train_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_int, ctypes.c_float,
+                                          ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
+    "scw_sur_infer_checked": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, c_dp,
+                                             ctypes.c_int, ctypes.c_int, ctypes.c_ulonglong,
+                                             ctypes.c_double, c_dp,
+                                             ctypes.POINTER(ctypes.c_int),
+                                             ctypes.POINTER(ctypes.c_double)]),
 }
 
 _lib = None

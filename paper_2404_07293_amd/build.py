@@ -22,6 +22,8 @@ SOURCES = [
     "kernels_synth.hip",
     "kernels_mfma.hip",
     "kernels_batch.hip",
+    "surrogate.cpp",
+    "kernels_surrogate.hip",
 ]
 
 ARCH = "gfx950"

@@ -662,4 +662,57 @@ int scw_batch_launch(scw_batch* b, void* E_dev, void* hip_stream) {
 
 void scw_batch_free(scw_batch* b) { delete b; }
 
+long long scw_sur_param_count(void) { return sur_param_count(); }
+
+int scw_sur_create(scw_ctx* ctx, int max_batch, unsigned long long seed, scw_sur** out) {
+  if (!ctx || !out) return fail(SCW_EINVAL, "null argument");
+  *out = nullptr;
+  SurNet* n = nullptr;
+  int rc = sur_create(ctx->c, max_batch, seed, &n);
+  if (rc) return rc;
+  *out = reinterpret_cast<scw_sur*>(n);
+  return SCW_OK;
+}
+
+void scw_sur_free(scw_sur* s) { sur_free(reinterpret_cast<SurNet*>(s)); }
+
+#define SUR(s) (*reinterpret_cast<SurNet*>(s))
+
+int scw_sur_get_params(scw_sur* s, float* host) {
+  if (!s || !host) return fail(SCW_EINVAL, "null argument");
+  return sur_get_params(SUR(s), host);
+}
+int scw_sur_set_params(scw_sur* s, const float* host) {
+  if (!s || !host) return fail(SCW_EINVAL, "null argument");
+  return sur_set_params(SUR(s), host);
+}
+int scw_sur_encode(scw_sur* s, const void* n_dev, int batch, void* x_dev, void* stream) {
+  if (!s || !n_dev || !x_dev) return fail(SCW_EINVAL, "null argument");
+  return sur_encode(SUR(s), n_dev, batch, x_dev, reinterpret_cast<hipStream_t>(stream));
+}
+int scw_sur_forward(scw_sur* s, const void* x_dev, int batch, void* out_dev, void* stream) {
+  if (!s || !x_dev || !out_dev) return fail(SCW_EINVAL, "null argument");
+  return sur_forward(SUR(s), x_dev, batch, out_dev, reinterpret_cast<hipStream_t>(stream));
+}
+int scw_sur_loss_grad(scw_sur* s, const void* x_dev, const void* target_dev, int batch,
+                      double* loss, float* grad_host, void* stream) {
+  if (!s || !x_dev || !target_dev) return fail(SCW_EINVAL, "null argument");
+  return sur_loss_grad(SUR(s), x_dev, target_dev, batch, loss, grad_host,
+                       reinterpret_cast<hipStream_t>(stream));
+}
+int scw_sur_train_step(scw_sur* s, const void* x_dev, const void* target_dev, int batch,
+                       float lr, double* loss, void* stream) {
+  if (!s || !x_dev || !target_dev) return fail(SCW_EINVAL, "null argument");
+  return sur_train_step(SUR(s), x_dev, target_dev, batch, lr, loss,
+                        reinterpret_cast<hipStream_t>(stream));
+}
+int scw_sur_infer_checked(scw_ctx* ctx, scw_sur* s, const double* n_host, int batch,
+                          int n_check, unsigned long long seed, double tol, double* out_host,
+                          int* fell_back, double* check_err) {
+  if (!ctx || !s) return fail(SCW_EINVAL, "null argument");
+  return sur_infer_checked(ctx->c, SUR(s), n_host, batch, n_check, seed, tol, out_host,
+                           fell_back, check_err);
+}
+#undef SUR
+
 }  // extern "C"

@@ -150,6 +150,23 @@ struct Context {
 // ------------------------------------------------------------------ setup
 int solve_problem(Context& ctx, const scw_problem& prob, Solution& sol);
 
+// ------------------------------------------------------------------ surrogate
+struct SurNet;
+long long sur_param_count();
+int sur_create(Context& ctx, int max_batch, unsigned long long seed, SurNet** out);
+void sur_free(SurNet* n);
+int sur_set_params(SurNet& n, const float* host);
+int sur_get_params(SurNet& n, float* host);
+int sur_encode(SurNet& n, const void* n_dev, int B, void* x_dev, hipStream_t s);
+int sur_forward(SurNet& n, const void* x_dev, int B, void* out_dev, hipStream_t s);
+int sur_loss_grad(SurNet& n, const void* x_dev, const void* tgt_dev, int B, double* loss,
+                  float* grad_host, hipStream_t s);
+int sur_train_step(SurNet& n, const void* x_dev, const void* tgt_dev, int B, float lr,
+                   double* loss, hipStream_t s);
+int sur_infer_checked(Context& ctx, SurNet& n, const double* n_host, int B, int n_check,
+                      unsigned long long seed, double tol, double* out_host, int* fell_back,
+                      double* check_err);
+
 // ------------------------------------------------------------------ kernels
 // All launchers enqueue on `s` and return a HIP status code.
 hipError_t launch_band_dft(const double* n, int L, int ny, int nx, int hu, int hv,
@@ -233,6 +250,33 @@ struct BatchArgs {
   void* E;                   // [njobs][3][fz][fy][fx] complex64
 };
 hipError_t launch_batch(const BatchArgs& a, hipStream_t s);
+
+// ------------------------------------------------------------------ surrogate kernels
+// C[b] = op(A[b]) op(B[b]) + beta C[b]; strides in elements of each operand's
+// type (complex operands interleaved). c_cplx = 0 keeps the real part.
+struct GemmOp {
+  int M, N, K, batch;
+  int a_cplx, b_cplx, c_cplx;
+  int conj_a, conj_b;
+  const float* A;
+  long long a_rs, a_cs, a_bs;
+  const float* B;
+  long long b_rs, b_cs, b_bs;
+  float* C;
+  long long c_rs, c_cs, c_bs;
+  float beta;
+};
+hipError_t launch_gemm(const GemmOp& op, hipStream_t s);
+hipError_t sur_bias_add(float* x, const float* bias, int B, int C, int P, hipStream_t s);
+hipError_t sur_gelu_fwd(const float* z, float* h, long long n, hipStream_t s);
+hipError_t sur_gelu_bwd(const float* z, float* g, long long n, hipStream_t s);
+hipError_t sur_sum_batch(const float* in, float* out, int B, long long per, hipStream_t s);
+hipError_t sur_bias_grad(const float* g, float* out, int B, int C, int P, hipStream_t s);
+hipError_t sur_loss(const float* out, const float* tgt, long long n, float* sums, float* g,
+                    hipStream_t s);
+hipError_t sur_adam(float* p, const float* g, float* m, float* v, long long n, float lr, int t,
+                    hipStream_t s);
+hipError_t sur_encode(const float* n, float* x, int B, hipStream_t s);
 hipError_t launch_idft_mfma(const MfmaArgs& a, int precision, hipStream_t s);
 // `ev`, when non-null, holds kNumStages + 1 events recorded around the stages.
 hipError_t launch_synthesis_fp64(const SynthArgs& a, hipStream_t s, hipEvent_t* ev);

@@ -1,0 +1,138 @@
+"""The HIP surrogate against its FP64 CPU reference (oracle/surrogate.py,
+itself pinned by finite differences): forward outputs and every parameter
+gradient, through the C ABI; plus training on CWT-generated pairs and the CWT
+fallback. FP32 kernels: forward and gradients agree with the FP64 reference to
+1e-5 and 1e-4 relative L2."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import surrogate as S
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    _torch()
+    import paper_2404_07293_amd as P
+    return P.Context(0)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _net_and_data(ctx, B=3, seed=5):
+    torch = _torch()
+    from paper_2404_07293_amd.surrogate import Surrogate
+    sur = Surrogate(ctx, max_batch=8, seed=1)
+    p = S.init_params(2)
+    for k in range(S.N_LAYERS):
+        p["spec%d" % k] *= 4.0
+    flat = S.flatten(p).astype(np.float32)
+    sur.set_params(flat)
+    p32 = S.unflatten(flat.astype(np.float64))
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal((B, 16, 32, 32)).astype(np.float32)
+    tgt = (rng.standard_normal((B, 3, 15, 15)) + 1j * rng.standard_normal((B, 3, 15, 15)))
+    tgt = tgt.astype(np.complex64)
+    xd = torch.as_tensor(x).cuda()
+    td = torch.as_tensor(tgt).cuda()
+    return sur, p32, x.astype(np.float64), tgt.astype(np.complex128), xd, td
+
+
+def test_forward_matches_reference(ctx):
+    torch = _torch()
+    sur, p, x, tgt, xd, td = _net_and_data(ctx)
+    got = sur.forward(xd).cpu().numpy()
+    torch.cuda.synchronize()
+    want = S.forward(p, x)
+    err = rel(got, want)
+    print("surrogate forward rel-L2 %.3e" % err)
+    assert err <= 1e-5
+
+
+def test_gradients_match_reference(ctx):
+    sur, p, x, tgt, xd, td = _net_and_data(ctx)
+    loss, g = sur.loss_grad(xd, td)
+    out, cache = S.forward(p, x, keep=True)
+    assert abs(loss - S.loss(out, tgt)) <= 1e-5 * S.loss(out, tgt)
+    gref = S.backward(p, cache, out, tgt)
+    gg = S.unflatten(g.astype(np.float64))
+    for name, _, _ in S.param_shapes():
+        err = rel(gg[name], gref[name])
+        print("grad %-7s rel-L2 %.3e" % (name, err))
+        assert err <= 1e-4, name
+
+
+def test_encode_matches_reference(ctx):
+    torch = _torch()
+    from paper_2404_07293_amd.surrogate import Surrogate
+    sur = Surrogate(ctx, max_batch=4)
+    n = np.stack([W.surrogate_patch(W.SURROGATE_SEED0 + i) for i in range(3)])
+    x = sur.encode(n).cpu().numpy()
+    torch.cuda.synchronize()
+    want = np.stack([S.encode(a) for a in n])
+    assert np.abs(x - want).max() <= 1e-4
+
+
+@pytest.fixture(scope="module")
+def small_set(ctx):
+    from paper_2404_07293_amd.surrogate import cwt_targets
+    n = np.stack([W.surrogate_patch(W.SURROGATE_SEED0 + i) for i in range(24)])
+    return n, cwt_targets(ctx, n)
+
+
+def test_training_reduces_loss(ctx, small_set):
+    torch = _torch()
+    from paper_2404_07293_amd.surrogate import Surrogate
+    n, tg = small_set
+    sur = Surrogate(ctx, max_batch=24, seed=3)
+    x = sur.encode(n)
+    t = torch.as_tensor(tg.astype(np.complex64)).cuda()
+    first = sur.train_step(x, t, lr=1e-3)
+    for _ in range(150):
+        last = sur.train_step(x, t, lr=1e-3)
+    print("training loss %.4f -> %.4f" % (first, last))
+    assert last < 0.5 * first
+
+
+def test_fallback_returns_cwt_solution(ctx, small_set):
+    from paper_2404_07293_amd.surrogate import Surrogate
+    n, tg = small_set
+    sur = Surrogate(ctx, max_batch=24, seed=3)
+    # an impossible tolerance forces the fallback: every patch is solved by CWT
+    out, fell, err = sur.infer_checked(n[:6], n_check=2, seed=1, tol=1e-12)
+    assert fell and err > 0
+    assert rel(out, tg[:6]) <= 1e-12
+    # a loose tolerance keeps the surrogate's own outputs
+    out2, fell2, err2 = sur.infer_checked(n[:6], n_check=2, seed=1, tol=1e9)
+    torch = _torch()
+    ref = sur.forward(sur.encode(n[:6])).cpu().numpy()
+    torch.cuda.synchronize()
+    assert not fell2 and abs(err2 - err) <= 1e-6 * err
+    assert rel(out2, ref) <= 1e-6
+
+
+def test_out_of_distribution_patch_triggers_fallback(ctx, small_set):
+    torch = _torch()
+    from paper_2404_07293_amd.surrogate import Surrogate
+    n, tg = small_set
+    sur = Surrogate(ctx, max_batch=24, seed=3)
+    x = sur.encode(n)
+    t = torch.as_tensor(tg.astype(np.complex64)).cuda()
+    for _ in range(100):
+        sur.train_step(x, t, lr=1e-3, want_loss=False)
+    odd = np.full((2, 8, 32, 32), 2.4 + 0.3j)
+    odd[:, :, 8:24, 8:24] = 1.0
+    out, fell, err = sur.infer_checked(odd, n_check=2, seed=0, tol=1e-2)
+    print("out-of-distribution check rel-L2 %.3e, fallback %s" % (err, fell))
+    assert fell and err > 1e-2

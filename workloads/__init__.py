@@ -18,6 +18,9 @@ from .configs import (
     random_field_config,
     spectral_sweep_jobs,
     sweep_problem,
+    surrogate_patch,
+    surrogate_problem,
+    SURROGATE_SEED0,
     CONFIG_NAMES,
 )
 
@@ -25,5 +28,6 @@ __all__ = [
     "Problem", "Grid", "PlaneWave",
     "sphere_sample", "smoothed_field", "random_index_sample",
     "focused_pupil_image", "lorentzian_kappa",
-    "sphere_config", "random_field_config", "spectral_sweep_jobs", "sweep_problem", "CONFIG_NAMES",
+    "sphere_config", "random_field_config", "spectral_sweep_jobs", "sweep_problem", "surrogate_patch", "surrogate_problem",
+    "SURROGATE_SEED0", "CONFIG_NAMES",
 ]

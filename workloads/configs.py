@@ -103,3 +103,20 @@ def sweep_problem(nu_cm1, patch, U, nz=16, nxy=32, planes=8, out_xy=64):
     T = nz * p
     grid = Grid(fx=out_xy, fy=out_xy, fz=planes, z_begin=T, z_end=T + planes * p)
     return prob, grid
+
+
+SURROGATE_SEED0 = 10000
+
+
+def surrogate_patch(seed):
+    """One 8 x 32 x 32 complex-index patch of the random-field family (the
+    surrogate's input distribution)."""
+    return random_index_sample((8, 32, 32), seed)
+
+
+def surrogate_problem(n):
+    """The CWT problem of a surrogate patch: pitch lambda/4 (lambda = 1),
+    index 1 above and below, 15 x 15 band, normal x-polarised plane wave."""
+    return Problem(n=np.asarray(n, dtype=np.complex128), px=0.25, py=0.25, pz=0.25, lam=1.0,
+                   U=15, V=15, n_top=1.0, n_bot=1.0 + 0.0j,
+                   plane_wave=PlaneWave(0, 0, 1.0, 0.0))
