@@ -173,6 +173,60 @@ int scw_solution_exterior(const scw_solution* sol, double* p_inc, double* p_ref,
 int scw_synthesize(scw_ctx* ctx, scw_solution* sol, const scw_grid* grid,
                    int precision, void* E_dev, void* hip_stream);
 
+/* Kernel configuration of scw_synthesize for one solution. Fields left 0
+ * take the library's choice: a configuration found by scw_tune_synthesis for
+ * the same shape on this context, else the built-in default.
+ *   modal_rows  rows of the synthesis matrix per wavefront in the modal sum
+ *               (FP32 and split modes): 2, 4, 8 or 16, lowered where needed
+ *               so that rows x planes-per-task stays <= 32;
+ *   transform   how Eq. 10 is evaluated: SCW_XFORM_FFT (Horner x pass and a
+ *               factored y pass fy = R * P; FP64/FP32, fy a power of two,
+ *               V <= 32), SCW_XFORM_MFMA (y pass as a GEMM on the matrix
+ *               cores; the only transform of the split modes), or
+ *               SCW_XFORM_DIRECT (Horner in x and y);
+ *   fft_radix   P of the factored y pass (2 .. 32, a power of two);
+ *   tiles       row tiles per plane (DIRECT) or plane-components per block
+ *               (MFMA); 0 = automatic.
+ * A configuration the solution's shape or precision cannot run makes the
+ * next scw_synthesize fail with SCW_EINVAL. cfg = NULL clears it. */
+typedef enum {
+  SCW_XFORM_AUTO = 0,
+  SCW_XFORM_FFT = 1,
+  SCW_XFORM_MFMA = 2,
+  SCW_XFORM_DIRECT = 3
+} scw_transform;
+
+typedef struct {
+  int modal_rows;
+  int transform;  /* scw_transform */
+  int fft_radix;
+  int tiles;
+} scw_synth_config;
+
+int scw_synthesis_configure(scw_solution* sol, const scw_synth_config* cfg);
+
+/* Autotuner result. Times are mean milliseconds per call, measured with HIP
+ * events on the caller's stream. */
+typedef struct {
+  int n_candidates;          /* configurations timed */
+  double default_ms;         /* the built-in default, same sweep */
+  double best_ms;            /* the chosen configuration */
+  scw_synth_config config;   /* chosen synthesis configuration */
+  int batch_radix;           /* batched synthesis: chosen P of the y pass */
+  int batch_blocks_per_cu;   /* batched synthesis: persistent blocks per CU */
+  int batch_chunk;           /* batched synthesis: work items per queue grab */
+} scw_tune_report;
+
+/* Time the candidate kernel configurations of scw_synthesize for this
+ * solution, grid and precision (modal-sum row blocking, then transform kind,
+ * radix and tiling, each stage timed alone with `reps` calls after one
+ * warm-up), keep the fastest in the solution and in the context's cache for
+ * solutions of the same shape, and report it. E_dev is a caller-owned output
+ * buffer as for scw_synthesize and holds the synthesized field on return.
+ * Synchronises `hip_stream`. */
+int scw_tune_synthesis(scw_ctx* ctx, scw_solution* sol, const scw_grid* grid, int precision,
+                       void* E_dev, void* hip_stream, int reps, scw_tune_report* report);
+
 /* Convenience: scw_solve + scw_synthesize + scw_solution_free. */
 int scw_field(scw_ctx* ctx, const scw_problem* prob, const scw_grid* grid,
               int precision, void* E_dev, void* hip_stream);
@@ -194,6 +248,13 @@ int scw_batch_plan(scw_ctx* ctx, scw_solution* const* jobs, int njobs, const scw
                    int precision, scw_batch** out);
 int scw_batch_launch(scw_batch* batch, void* E_dev, void* hip_stream);
 void scw_batch_free(scw_batch* batch);
+/* Time the batched kernel over its tunable shapes (P of the factored y
+ * pass, persistent blocks per CU, work items per queue grab), keep the fastest for later launches of
+ * this batch (the graph is captured again) and for batches of the same grid
+ * on this context, and report it. E_dev as for scw_batch_launch; it holds
+ * the batch's field on return. Synchronises `hip_stream`. */
+int scw_batch_tune(scw_batch* batch, void* E_dev, void* hip_stream, int reps,
+                   scw_tune_report* report);
 
 /* Spectral-convolution surrogate of the transmitted field (Eq. 9 below the
  * sample) for one patch family: 8 x 32 x 32 voxels at pitch lambda/4

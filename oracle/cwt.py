@@ -196,6 +196,21 @@ def half_space_map(sx, sy, sigma):
 # --------------------------------------------------------------------------
 # Problem setup.
 # --------------------------------------------------------------------------
+class BoundaryMatrices:
+    """T_l (which=0) or B_l (which=1) of every layer, formed from the layer's
+    modes when indexed, so that a deep stack holds one matrix per layer (Q)
+    rather than three."""
+
+    def __init__(self, modes, k, d, which):
+        self._modes, self._k, self._d, self._which = modes, k, d, which
+
+    def __len__(self):
+        return len(self._modes)
+
+    def __getitem__(self, layer):
+        return boundary_matrices(self._modes[layer], self._k, self._d)[self._which]
+
+
 @dataclass
 class Setup:
     U: int
@@ -217,8 +232,8 @@ class Setup:
     psi: List[np.ndarray]      # band coefficients of 1/n^2 per layer
     Psi: List[np.ndarray]      # M x M per layer
     modes: List[LayerModes]
-    T: List[np.ndarray]
-    B: List[np.ndarray]
+    T: "BoundaryMatrices"      # top-surface matrix of each layer
+    B: "BoundaryMatrices"      # bottom-surface matrix of each layer
     p_inc: np.ndarray          # [3M] incident coefficients at z0
 
 
@@ -261,7 +276,7 @@ def setup(prob, grazing_tol=1e-9):
     sz_bot = s_z(prob.n_bot, sx, sy)
     if np.min(np.abs(sz_top)) < grazing_tol or np.min(np.abs(sz_bot)) < grazing_tol:
         raise OracleError("grazing spatial frequency in a half-space")
-    phis, psis, Psis, modes, Ts, Bs = [], [], [], [], [], []
+    phis, psis, Psis, modes = [], [], [], []
     for layer in range(prob.nz):
         eps = prob.n[layer] ** 2
         phi = band_coefficients(eps, U, V)
@@ -269,19 +284,19 @@ def setup(prob, grazing_tol=1e-9):
         Phi = toeplitz_from_band(phi, u, v, U, V)
         Psi = toeplitz_from_band(psi, u, v, U, V)
         D = property_matrix(Phi, Psi, sx, sy)
+        del Phi
         md = layer_modes(D)
-        T, B = boundary_matrices(md, k, prob.pz)
+        del D
         phis.append(phi)
         psis.append(psi)
         Psis.append(Psi)
         modes.append(md)
-        Ts.append(T)
-        Bs.append(B)
     p_inc = incident_coefficients(prob, u, v, sx, sy, sz_top)
     return Setup(U=U, V=V, M=M, L=prob.nz, lam=lam, k=k, X=prob.X, Y=prob.Y,
                  d=prob.pz, u=u, v=v, sx=sx, sy=sy, sz_top=sz_top,
                  sz_bot=sz_bot, phi=phis, psi=psis, Psi=Psis, modes=modes,
-                 T=Ts, B=Bs, p_inc=p_inc)
+                 T=BoundaryMatrices(modes, k, prob.pz, 0),
+                 B=BoundaryMatrices(modes, k, prob.pz, 1), p_inc=p_inc)
 
 
 # --------------------------------------------------------------------------

@@ -54,6 +54,25 @@ class ScwSolutionInfo(ctypes.Structure):
     ]
 
 
+TRANSFORM = {"auto": 0, "fft": 1, "mfma": 2, "direct": 3}
+TRANSFORM_NAME = {v: k for k, v in TRANSFORM.items()}
+
+
+class ScwSynthConfig(ctypes.Structure):
+    _fields_ = [("modal_rows", ctypes.c_int), ("transform", ctypes.c_int),
+                ("fft_radix", ctypes.c_int), ("tiles", ctypes.c_int)]
+
+
+class ScwTuneReport(ctypes.Structure):
+    _fields_ = [("n_candidates", ctypes.c_int),
+                ("default_ms", ctypes.c_double),
+                ("best_ms", ctypes.c_double),
+                ("config", ScwSynthConfig),
+                ("batch_radix", ctypes.c_int),
+                ("batch_blocks_per_cu", ctypes.c_int),
+                ("batch_chunk", ctypes.c_int)]
+
+
 # name -> (restype, argtypes); every entry point of include/scw.h
 SIGNATURES = {
     "scw_last_error": (ctypes.c_char_p, []),
@@ -80,6 +99,14 @@ SIGNATURES = {
                                       ctypes.POINTER(ctypes.c_void_p)]),
     "scw_batch_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "scw_batch_free": (None, [ctypes.c_void_p]),
+    "scw_batch_tune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_int, ctypes.POINTER(ScwTuneReport)]),
+    "scw_synthesis_configure": (ctypes.c_int, [ctypes.c_void_p,
+                                               ctypes.POINTER(ScwSynthConfig)]),
+    "scw_tune_synthesis": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.POINTER(ScwGrid), ctypes.c_int,
+                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                          ctypes.POINTER(ScwTuneReport)]),
     "scw_sur_param_count": (ctypes.c_longlong, []),
     "scw_sur_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_ulonglong,
                                       ctypes.POINTER(ctypes.c_void_p)]),
@@ -114,6 +141,11 @@ def load(path=LIB_PATH):
     if not os.path.exists(path):
         raise ImportError("libscw.so is not built (%s); run python -m "
                           "paper_2404_07293_amd.build" % path)
+    # PyTorch ships its own HIP runtime under the same soname as the system
+    # one. Loading torch first makes the library bind to torch's runtime, so
+    # that both share one runtime (device pointers and streams); loading the
+    # library first would hand torch a runtime it was not built against.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)

@@ -18,6 +18,7 @@ SOURCES = [
     "lapack.cpp",
     "setup.cpp",
     "api.cpp",
+    "tune.cpp",
     "kernels_setup.hip",
     "kernels_synth.hip",
     "kernels_mfma.hip",

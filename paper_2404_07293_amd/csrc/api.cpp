@@ -9,30 +9,9 @@
 #include <new>
 #include <memory>
 #include <thread>
+#include <cstdio>
 
 #include "scw_internal.h"
-
-struct scw_ctx {
-  scw::Context c;
-};
-struct scw_solution {
-  scw::Solution s;
-};
-struct scw_batch {
-  scw::Context* ctx = nullptr;
-  int njobs = 0, n_items = 0, P = 0, grid_blocks = 0;
-  scw_grid grid{};
-  scw::DevBuf d_jobs, d_items, d_planes, d_coef, d_wfull, d_tw, d_counter;
-  hipStream_t capture_stream = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  void* graph_E = nullptr;
-  ~scw_batch() {
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
-    if (capture_stream) (void)hipStreamDestroy(capture_stream);
-  }
-};
 
 namespace scw {
 
@@ -141,7 +120,33 @@ int build_amat(Solution& s, const scw_grid& g, int precision, Plan& pl) {
 }
 
 // Plane classification, task grouping and device tables for one grid.
-int build_plan(Solution& s, const scw_grid& g, int precision) {
+// The configuration a plan is built with: the solution's explicit one, its
+// zero fields filled from the context's tuned entry for the same shape.
+scw_synth_config resolve_config(const Context& ctx, const Solution& s, const scw_grid& g,
+                                int precision) {
+  scw_synth_config c = s.cfg;
+  auto it = ctx.tuned_synth.find(synth_key(s, g, precision));
+  if (it != ctx.tuned_synth.end()) {
+    const scw_synth_config& t = it->second;
+    if (!c.modal_rows) c.modal_rows = t.modal_rows;
+    if (!c.transform) {
+      c.transform = t.transform;
+      if (!c.fft_radix) c.fft_radix = t.fft_radix;
+      if (!c.tiles) c.tiles = t.tiles;
+    }
+  }
+  return c;
+}
+
+bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
+
+// LDS bytes of the factored transform block for radix P.
+size_t fft_lds_bytes(const Solution& s, const scw_grid& g, int precision, int P) {
+  const size_t eb = precision == SCW_FP64 ? 16 : 8;
+  return ((size_t)s.U * s.V + 32 * 64 + 32 * (size_t)(g.fy / P) + P) * eb;
+}
+
+int build_plan(const Context& ctx, Solution& s, const scw_grid& g, int precision) {
   Plan& pl = s.plan;
   pl.valid = false;
   pl.grid = g;
@@ -230,14 +235,42 @@ int build_plan(Solution& s, const scw_grid& g, int precision) {
         (rc = upload(pl.d_twy, b.data(), b.size() * 4)))
       return rc;
   }
-  // factored y pass for FP64 / FP32 when fy = R * P (P <= 32 a power of two)
+  // kernel configuration: explicit, tuned, or the built-in default
+  const scw_synth_config cfg = resolve_config(ctx, s, g, precision);
+  pl.cfg = cfg;
+  const bool split = precision == SCW_BF16X3 || precision == SCW_FP16X3;
+  if (cfg.transform < SCW_XFORM_AUTO || cfg.transform > SCW_XFORM_DIRECT)
+    return fail(SCW_EINVAL, "unknown transform kind " + std::to_string(cfg.transform));
+  if (cfg.modal_rows && !(is_pow2(cfg.modal_rows) && cfg.modal_rows >= 2 && cfg.modal_rows <= 16))
+    return fail(SCW_EINVAL, "modal_rows must be 2, 4, 8 or 16");
+  if (cfg.tiles < 0 || cfg.tiles > 4096) return fail(SCW_EINVAL, "tiles out of range");
+  // FP32 modal sum: rows per wave, so that rows x planes stays <= 32
+  int rw = cfg.modal_rows ? cfg.modal_rows : (zt >= 8 ? 4 : (zt == 4 ? 8 : 16));
+  while (rw > 2 && rw * zt > 32) rw /= 2;
+  pl.modal_rw = rw;
+  pl.tiles = cfg.tiles;
+  // factored y pass: fy = R * P, P <= 32 a power of two, spectra V <= 32 rows
+  const int p_default = std::min(32, std::max(2, g.fy / 16));
+  const int P = cfg.fft_radix ? cfg.fft_radix : p_default;
+  const bool fft_ok = !split && s.V <= 32 && g.fy >= 2 && is_pow2(g.fy) && is_pow2(P) &&
+                      P >= 2 && P <= 32 && P <= g.fy &&
+                      fft_lds_bytes(s, g, precision, P) <= 64 * 1024;
+  int kind = cfg.transform;
+  if (kind == SCW_XFORM_AUTO)
+    kind = split ? SCW_XFORM_MFMA
+                 : (fft_ok ? SCW_XFORM_FFT
+                           : (precision == SCW_FP32 && s.V <= 32 ? SCW_XFORM_MFMA
+                                                                 : SCW_XFORM_DIRECT));
+  if (split && kind != SCW_XFORM_MFMA)
+    return fail(SCW_EINVAL, "split-precision synthesis evaluates the transform on the matrix cores");
+  if (kind == SCW_XFORM_FFT && !fft_ok)
+    return fail(SCW_EINVAL, "factored transform needs FP64/FP32, V <= 32, fy a power of two and "
+                            "a radix P (2..32, power of two) whose tables fit in 64 KB of LDS");
+  if (kind == SCW_XFORM_MFMA && (precision == SCW_FP64 || s.V > 32))
+    return fail(SCW_EINVAL, "matrix-core transform needs FP32 or split precision and V <= 32");
   pl.fft_p = 0;
-  const char* idft_mode = getenv("SCW_IDFT");
-  const bool want_fft = (precision == SCW_FP64 || precision == SCW_FP32) && s.V <= 32 &&
-                        !(idft_mode && (strcmp(idft_mode, "valu") == 0 ||
-                                        strcmp(idft_mode, "mfma") == 0));
-  if (want_fft && g.fy >= 2 && (g.fy & (g.fy - 1)) == 0) {
-    const int P = std::min(32, std::max(2, g.fy / 16));
+  pl.mfma = false;
+  if (kind == SCW_XFORM_FFT) {
     const int R = g.fy / P;
     pl.fft_p = P;
     std::vector<zc> tw(32 * (size_t)R + P);
@@ -254,17 +287,12 @@ int build_plan(Solution& s, const scw_grid& g, int precision) {
       pack(tw, b);
       if ((rc = upload(pl.d_fft_tw, b.data(), b.size() * 4))) return rc;
     }
-  }
-  // matrix-core inverse transform for the single-precision modes
-  const char* idft_env = getenv("SCW_IDFT");
-  pl.mfma = precision != SCW_FP64 && s.V <= 32 && pl.fft_p == 0 &&
-            !(idft_env && strcmp(idft_env, "valu") == 0);
-  if (precision == SCW_BF16X3 || precision == SCW_FP16X3) pl.mfma = s.V <= 32;
-  if (pl.mfma) {
+  } else if (kind == SCW_XFORM_MFMA) {
+    pl.mfma = true;
     const int ks = mfma_kstep(precision);
     pl.kp = ((2 * s.V + ks - 1) / ks) * ks;
     if ((rc = build_amat(s, g, precision, pl))) return rc;
-    const size_t ebyte = precision == SCW_FP32 ? 4 : 4;  // f32, or hi + lo 16-bit
+    const size_t ebyte = 4;  // f32, or hi + lo 16-bit
     if ((rc = pl.d_bmat.reserve((size_t)g.fz * 3 * pl.kp * g.fx * ebyte)) ||
         (rc = pl.d_bscale.reserve((size_t)g.fz * 3 * sizeof(float))))
       return rc;
@@ -368,27 +396,32 @@ int scw_solution_exterior(const scw_solution* sol, double* p_inc, double* p_ref,
   return SCW_OK;
 }
 
-int scw_synthesize(scw_ctx* ctx, scw_solution* sol, const scw_grid* grid, int precision,
-                   void* E_dev, void* hip_stream) {
-  if (!ctx || !sol || !E_dev) return fail(SCW_EINVAL, "null argument");
-  int rc = check_grid(grid);
-  if (rc) return rc;
-  if (precision < SCW_FP64 || precision > SCW_FP16X3)
-    return fail(SCW_EINVAL, "unknown precision " + std::to_string(precision));
-  if ((precision == SCW_BF16X3 || precision == SCW_FP16X3) && sol->s.V > 32)
-    return fail(SCW_EINVAL, "split-precision transform needs V <= 32");
-  Solution& s = sol->s;
-  if (s.device != ctx->c.device) return fail(SCW_EINVAL, "solution belongs to another device");
-  SCW_HIP(hipSetDevice(ctx->c.device));
-  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+}  // extern "C"
+
+namespace scw {
+
+std::string synth_key(const Solution& s, const scw_grid& g, int precision) {
+  char buf[160];
+  snprintf(buf, sizeof buf, "p%d U%d V%d L%d d%.17g fx%d fy%d fz%d z%.17g:%.17g", precision,
+           s.U, s.V, s.L, s.d, g.fx, g.fy, g.fz, g.z_begin, g.z_end);
+  return buf;
+}
+
+int synthesize(Context& c, Solution& s, const scw_grid& g, int precision, void* E,
+               hipStream_t st, int stages, hipEvent_t* ev) {
+  int rc;
+  if (s.device != c.device) return fail(SCW_EINVAL, "solution belongs to another device");
+  SCW_HIP(hipSetDevice(c.device));
   const size_t pl_elems = (size_t)s.L * 3 * s.M * 2 * s.M;
   if (precision != SCW_FP64 && s.d_P32.bytes < pl_elems * 8) {
     if ((rc = s.d_P32.reserve(pl_elems * 8))) return rc;
     SCW_HIP(launch_p_to_fp32(s.d_P64.as<double>(), s.d_P32.as<float>(), pl_elems, st));
   }
-  if (!s.plan.valid || s.plan.precision != precision || !same_grid(s.plan.grid, *grid)) {
+  if (!s.plan.valid || s.plan.precision != precision || !same_grid(s.plan.grid, g) ||
+      s.plan.epoch != c.tune_epoch) {
     SCW_HIP(hipStreamSynchronize(st));
-    if ((rc = build_plan(s, *grid, precision))) return rc;
+    if ((rc = build_plan(c, s, g, precision))) return rc;
+    s.plan.epoch = c.tune_epoch;
   }
   Plan& pl = s.plan;
   SynthArgs a{};
@@ -396,9 +429,9 @@ int scw_synthesize(scw_ctx* ctx, scw_solution* sol, const scw_grid* grid, int pr
   a.U = s.U;
   a.V = s.V;
   a.L = s.L;
-  a.fx = grid->fx;
-  a.fy = grid->fy;
-  a.fz = grid->fz;
+  a.fx = g.fx;
+  a.fy = g.fy;
+  a.fz = g.fz;
   a.zt = pl.zt;
   a.ntasks = (int)pl.tasks.size();
   a.n_ext = pl.n_exterior;
@@ -415,7 +448,7 @@ int scw_synthesize(scw_ctx* ctx, scw_solution* sol, const scw_grid* grid, int pr
   a.spec = pl.d_spec.p;
   a.twx = pl.d_twx.p;
   a.twy = pl.d_twy.p;
-  a.E = E_dev;
+  a.E = E;
   a.kgab32 = s.d_kgab32.p;
   a.task_dz32 = pl.d_task_dz32.p;
   a.precision = precision;
@@ -426,15 +459,38 @@ int scw_synthesize(scw_ctx* ctx, scw_solution* sol, const scw_grid* grid, int pr
   a.bmat = pl.d_bmat.p;
   a.bscale = pl.d_bscale.as<float>();
   a.amat = pl.d_amat.p;
-  {
-    const char* env = getenv("SCW_IDFT_GTILES");
-    a.idft_gtiles = env ? atoi(env) : 0;
-  }
+  a.idft_gtiles = pl.tiles;
+  a.modal_rw = pl.modal_rw;
+  a.stages = stages;
+  SCW_HIP(precision == SCW_FP64 ? launch_synthesis_fp64(a, st, ev)
+                                : launch_synthesis_fp32(a, st, ev));
+  return SCW_OK;
+}
+
+}  // namespace scw
+
+extern "C" {
+
+int scw_synthesize(scw_ctx* ctx, scw_solution* sol, const scw_grid* grid, int precision,
+                   void* E_dev, void* hip_stream) {
+  if (!ctx || !sol || !E_dev) return fail(SCW_EINVAL, "null argument");
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  if (precision < SCW_FP64 || precision > SCW_FP16X3)
+    return fail(SCW_EINVAL, "unknown precision " + std::to_string(precision));
+  if ((precision == SCW_BF16X3 || precision == SCW_FP16X3) && sol->s.V > 32)
+    return fail(SCW_EINVAL, "split-precision transform needs V <= 32");
   hipEvent_t* ev = nullptr;
   Context& c = ctx->c;
   if (c.prof_used < c.prof_max) ev = c.prof_events.data() + (size_t)c.prof_used++ * (kNumStages + 1);
-  SCW_HIP(precision == SCW_FP64 ? launch_synthesis_fp64(a, st, ev)
-                                : launch_synthesis_fp32(a, st, ev));
+  return synthesize(c, sol->s, *grid, precision, E_dev, reinterpret_cast<hipStream_t>(hip_stream),
+                    kStageAll, ev);
+}
+
+int scw_synthesis_configure(scw_solution* sol, const scw_synth_config* cfg) {
+  if (!sol) return fail(SCW_EINVAL, "null solution");
+  sol->s.cfg = cfg ? *cfg : scw_synth_config{};
+  sol->s.plan.valid = false;
   return SCW_OK;
 }
 
@@ -518,6 +574,86 @@ double scw_synthesis_bytes(const scw_solution* sol, const scw_grid* grid, int pr
   return pbytes + ebytes;
 }
 
+}  // extern "C"
+
+namespace scw {
+
+std::string batch_key(const scw_grid& g) {
+  char buf[96];
+  snprintf(buf, sizeof buf, "fx%d fy%d fz%d", g.fx, g.fy, g.fz);
+  return buf;
+}
+
+int batch_set_shape(scw_batch* b, int P, int blocks_per_cu, int chunk) {
+  const int fy = b->grid.fy;
+  if (!is_pow2(P) || P < 2 || P > 32 || P > fy || fy % P != 0)
+    return fail(SCW_EINVAL, "batch radix must be a power of two in [2, min(32, fy)]");
+  const int R = fy / P;
+  if (32 * (size_t)R * 8 > 64 * 1024) return fail(SCW_EINVAL, "batch radix too small for fy");
+  if (blocks_per_cu < 1 || blocks_per_cu > 64) return fail(SCW_EINVAL, "blocks per CU out of range");
+  if (chunk < 1 || chunk > 1024) return fail(SCW_EINVAL, "items per grab out of range");
+  std::vector<float> wfull(2 * (size_t)b->grid.fx), tw(2 * (32 * (size_t)R + P));
+  for (int k = 0; k < b->grid.fx; ++k) {
+    const zc w = twiddle_inv(k, b->grid.fx);
+    wfull[2 * k] = (float)w.real();
+    wfull[2 * k + 1] = (float)w.imag();
+  }
+  for (int sl = 0; sl < 32; ++sl)
+    for (int g1 = 0; g1 < R; ++g1) {
+      const zc w = twiddle_inv((long long)(sl - 16) * g1, fy);
+      tw[2 * ((size_t)sl * R + g1)] = (float)w.real();
+      tw[2 * ((size_t)sl * R + g1) + 1] = (float)w.imag();
+    }
+  for (int k = 0; k < P; ++k) {
+    const zc w = twiddle_inv(k, P);
+    tw[2 * (32 * (size_t)R + k)] = (float)w.real();
+    tw[2 * (32 * (size_t)R + k) + 1] = (float)w.imag();
+  }
+  int rc;
+  if ((rc = upload(b->d_wfull, wfull.data(), wfull.size() * 4)) ||
+      (rc = upload(b->d_tw, tw.data(), tw.size() * 4)))
+    return rc;
+  b->P = P;
+  b->chunk = chunk;
+  b->grid_blocks = std::max(1, std::min(b->n_items, b->cus * blocks_per_cu));
+  if (b->exec) {
+    (void)hipGraphExecDestroy(b->exec);
+    b->exec = nullptr;
+  }
+  if (b->graph) {
+    (void)hipGraphDestroy(b->graph);
+    b->graph = nullptr;
+  }
+  b->graph_E = nullptr;
+  return SCW_OK;
+}
+
+BatchArgs batch_args(const scw_batch* b, void* E) {
+  BatchArgs a{};
+  a.jobs = b->d_jobs.as<BatchJob>();
+  a.items = b->d_items.as<BatchItem>();
+  a.n_items = b->n_items;
+  a.planes = b->d_planes.as<BatchPlane>();
+  a.coef = b->d_coef.p;
+  a.wfull = b->d_wfull.p;
+  const int R = b->grid.fy / b->P;
+  a.tw1 = b->d_tw.p;
+  a.tw2 = b->d_tw.as<float>() + 2 * 32 * (size_t)R;
+  a.fx = b->grid.fx;
+  a.fy = b->grid.fy;
+  a.fz = b->grid.fz;
+  a.P = b->P;
+  a.grid = b->grid_blocks;
+  a.chunk = b->chunk;
+  a.counter = b->d_counter.as<unsigned int>();
+  a.E = E;
+  return a;
+}
+
+}  // namespace scw
+
+extern "C" {
+
 int scw_batch_plan(scw_ctx* ctx, scw_solution* const* jobs, int njobs, const scw_grid* grid,
                    int precision, scw_batch** out) {
   if (!ctx || !jobs || njobs < 1 || !out) return fail(SCW_EINVAL, "null or empty batch");
@@ -576,39 +712,17 @@ int scw_batch_plan(scw_ctx* ctx, scw_solution* const* jobs, int njobs, const scw
       for (int c = 0; c < 3; ++c)
         for (int ft = 0; ft < nft; ++ft) items.push_back({j, p, c, ft});
   b->n_items = (int)items.size();
-  const int P = std::min(32, std::max(2, grid->fy / 16));
-  const int R = grid->fy / P;
-  b->P = P;
-  std::vector<float> wfull(2 * (size_t)grid->fx), tw(2 * (32 * (size_t)R + P));
-  for (int k = 0; k < grid->fx; ++k) {
-    const zc w = twiddle_inv(k, grid->fx);
-    wfull[2 * k] = (float)w.real();
-    wfull[2 * k + 1] = (float)w.imag();
-  }
-  for (int sl = 0; sl < 32; ++sl)
-    for (int g1 = 0; g1 < R; ++g1) {
-      const zc w = twiddle_inv((long long)(sl - 16) * g1, grid->fy);
-      tw[2 * ((size_t)sl * R + g1)] = (float)w.real();
-      tw[2 * ((size_t)sl * R + g1) + 1] = (float)w.imag();
-    }
-  for (int k = 0; k < P; ++k) {
-    const zc w = twiddle_inv(k, P);
-    tw[2 * (32 * (size_t)R + k)] = (float)w.real();
-    tw[2 * (32 * (size_t)R + k) + 1] = (float)w.imag();
-  }
   if ((rc = upload(b->d_jobs, jt.data(), jt.size() * sizeof(BatchJob))) ||
       (rc = upload(b->d_items, items.data(), items.size() * sizeof(BatchItem))) ||
       (rc = upload(b->d_planes, pt.data(), pt.size() * sizeof(BatchPlane))) ||
       (rc = upload(b->d_coef, coef.data(), coef.size() * 4)) ||
-      (rc = upload(b->d_wfull, wfull.data(), wfull.size() * 4)) ||
-      (rc = upload(b->d_tw, tw.data(), tw.size() * 4)) ||
       (rc = b->d_counter.reserve(256)))
     return rc;
-  int cus = 0;
-  SCW_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->c.device));
-  const char* env = getenv("SCW_BATCH_BLOCKS_PER_CU");
-  const int per_cu = env ? std::max(1, atoi(env)) : 4;
-  b->grid_blocks = std::max(1, std::min(b->n_items, cus * per_cu));
+  SCW_HIP(hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, ctx->c.device));
+  Context::BatchShape sh{std::min(32, std::max(2, grid->fy / 16)), 4, 1};
+  auto it = ctx->c.tuned_batch.find(batch_key(*grid));
+  if (it != ctx->c.tuned_batch.end()) sh = it->second;
+  if ((rc = batch_set_shape(b.get(), sh.P, sh.blocks_per_cu, sh.chunk))) return rc;
   SCW_HIP(hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking));
   *out = b.release();
   return SCW_OK;
@@ -626,23 +740,7 @@ int scw_batch_launch(scw_batch* b, void* E_dev, void* hip_stream) {
       (void)hipGraphDestroy(b->graph);
       b->graph = nullptr;
     }
-    BatchArgs a{};
-    a.jobs = b->d_jobs.as<BatchJob>();
-    a.items = b->d_items.as<BatchItem>();
-    a.n_items = b->n_items;
-    a.planes = b->d_planes.as<BatchPlane>();
-    a.coef = b->d_coef.p;
-    a.wfull = b->d_wfull.p;
-    const int R = b->grid.fy / b->P;
-    a.tw1 = b->d_tw.p;
-    a.tw2 = b->d_tw.as<float>() + 2 * 32 * (size_t)R;
-    a.fx = b->grid.fx;
-    a.fy = b->grid.fy;
-    a.fz = b->grid.fz;
-    a.P = b->P;
-    a.grid = b->grid_blocks;
-    a.counter = b->d_counter.as<unsigned int>();
-    a.E = E_dev;
+    const BatchArgs a = batch_args(b, E_dev);
     SCW_HIP(hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal));
     hipError_t le = launch_batch(a, b->capture_stream);
     hipGraph_t g = nullptr;

@@ -5,11 +5,14 @@
 //
 // Work item = (job, plane, component, 64-column tile). Items are sorted by
 // cost (largest truncation first) and drained from an atomic counter by a
-// persistent grid; every block exits once the counter passes the item count.
-// Per item, in one block:
+// persistent grid, `chunk` consecutive items per grab (items next to each
+// other in the sorted order cost about the same, and fewer grabs mean less
+// contention on the one counter); every block exits once the counter passes
+// the item count. Per item, in one block:
 //   spectrum  S[v][u] = exterior coefficients of the job at the plane (LDS)
 //   x pass    T[v][f] by Horner over u, into 32 zero-padded frequency slots
-//   y pass    factored transform, fy = R * P (as in the single-problem path)
+//   y pass    factored transform, fy = R * P (as in the single-problem path);
+//             only the V occupied frequency slots of the 32 enter it
 #include <hip/hip_runtime.h>
 
 #include "scw_internal.h"
@@ -69,88 +72,107 @@ __global__ void reset_counter(unsigned int* counter) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0u;
 }
 
+// One work item by the whole block. S and Ts are the block's LDS staging; the
+// caller synchronises before S is overwritten.
+template <int P>
+__device__ __forceinline__ void batch_item(
+    const BatchItem item, const BatchJob* __restrict__ jobs,
+    const BatchPlane* __restrict__ planes, const c32* __restrict__ coef,
+    const c32* __restrict__ wfull, const c32* tw1, const c32* twr, int fx, int fy, int fz,
+    c32* S, c32* Ts, c32* __restrict__ E) {
+  const int R = fy / P;
+  const int t = threadIdx.x, col = t % COLS, q = t / COLS;
+  const BatchJob jb = jobs[item.job];
+  const BatchPlane pl = planes[(long long)item.job * fz + item.plane];
+  const int U = jb.U, V = jb.V, M = U * V;
+  const int comp = item.comp;
+  // exterior spectrum of this job, plane and component (Eq. 9)
+  const c32* cf = coef + jb.coef_offset;  // [3][M] p_inc, [3][M] p_ref, [3][M] p_trn, [M] k sz_top, [M] k sz_bot
+  for (int m = t; m < M; m += 256) {
+    c32 val;
+    if (pl.kind == 0) {
+      const c32 kz = cf[9 * M + m];
+      const c32 gi = cexpi(kz.x * pl.dz, kz.y * pl.dz);
+      const c32 gr = cexpi(-kz.x * pl.dz, -kz.y * pl.dz);
+      const c32 a = mul(cf[comp * M + m], gi), b = mul(cf[3 * M + comp * M + m], gr);
+      val = {a.x + b.x, a.y + b.y};
+    } else {
+      const c32 kz = cf[10 * M + m];
+      val = mul(cf[6 * M + comp * M + m], cexpi(kz.x * pl.dz, kz.y * pl.dz));
+    }
+    S[m] = val;
+  }
+  __syncthreads();
+  const int f = item.ftile * COLS + col;
+  const bool live = f < fx;
+  if (live) {
+    const c32 w = wfull[f];
+    int sidx = (int)(((long long)(-(U / 2)) * f) % fx);
+    if (sidx < 0) sidx += fx;
+    const c32 sh = wfull[sidx];
+    for (int vi = q; vi < V; vi += 4) {
+      const c32* row = S + vi * U;
+      c32 acc = row[U - 1];
+      for (int u = U - 2; u >= 0; --u) acc = muladd(acc, w, row[u]);
+      Ts[(vi - V / 2 + 16) * COLS + col] = mul(acc, sh);
+    }
+  }
+  __syncthreads();
+  if (!live) return;
+  // occupied slots 16 - V/2 .. 16 + V/2; the test is uniform over the block
+  const int lo = 16 - V / 2, hi = 16 + V / 2;
+  c32 tcol[32];
+#pragma unroll
+  for (int sl = 0; sl < 32; ++sl)
+    if (sl >= lo && sl <= hi) tcol[sl] = Ts[sl * COLS + col];
+  c32* dst = E + ((((long long)item.job * 3 + comp) * fz + item.plane) * fy) * fx + f;
+  for (int g1 = q; g1 < R; g1 += 4) {
+    c32 a[P];
+#pragma unroll
+    for (int r = 0; r < P; ++r) a[r] = {0.f, 0.f};
+#pragma unroll
+    for (int sl = 0; sl < 32; ++sl) {
+      if (sl < lo || sl > hi) continue;
+      const int r = ((sl - 16) % P + P) % P;
+      a[r] = muladd(tcol[sl], tw1[sl * R + g1], a[r]);
+    }
+    small_fft<P>(a, twr);
+    typedef float f2v __attribute__((ext_vector_type(2)));
+#pragma unroll
+    for (int g2 = 0; g2 < P; ++g2)
+      __builtin_nontemporal_store(f2v{a[g2].x, a[g2].y},
+                                  reinterpret_cast<f2v*>(dst + (long long)(g1 + R * g2) * fx));
+  }
+}
+
 template <int P>
 __global__ void __launch_bounds__(256) batch_kernel(
     const BatchJob* __restrict__ jobs, const BatchItem* __restrict__ items, int n_items,
     const BatchPlane* __restrict__ planes, const c32* __restrict__ coef,
     const c32* __restrict__ wfull, const c32* __restrict__ tw1g, const c32* __restrict__ tw2g,
-    int fx, int fy, int fz, unsigned int* __restrict__ counter, c32* __restrict__ E) {
+    int fx, int fy, int fz, int chunk, unsigned int* __restrict__ counter,
+    c32* __restrict__ E) {
   __shared__ c32 S[MAXU * MAXU];
   __shared__ c32 Ts[32 * COLS];
   __shared__ int s_item;
   extern __shared__ unsigned char smem_raw[];
   const int R = fy / P;
   c32* tw1 = reinterpret_cast<c32*>(smem_raw);  // [32][R]
-  const int t = threadIdx.x, col = t % COLS, q = t / COLS;
+  const int t = threadIdx.x;
   for (int i = t; i < 32 * R; i += 256) tw1[i] = tw1g[i];
   c32 twr[P];
 #pragma unroll
   for (int k = 0; k < P; ++k) twr[k] = tw2g[k];
   for (;;) {
+    __syncthreads();  // also: the previous grab's last item is consumed
+    if (t == 0) s_item = (int)atomicAdd(counter, (unsigned)chunk);
     __syncthreads();
-    if (t == 0) s_item = (int)atomicAdd(counter, 1u);
-    __syncthreads();
-    const int it = s_item;
-    if (it >= n_items) break;  // every block reaches this once the queue is drained
-    const BatchItem item = items[it];
-    const BatchJob jb = jobs[item.job];
-    const BatchPlane pl = planes[(long long)item.job * fz + item.plane];
-    const int U = jb.U, V = jb.V, M = U * V;
-    const int comp = item.comp;
-    // exterior spectrum of this job, plane and component (Eq. 9)
-    const c32* cf = coef + jb.coef_offset;  // [3][M] p_inc, [3][M] p_ref, [3][M] p_trn, [M] k sz_top, [M] k sz_bot
-    for (int m = t; m < M; m += 256) {
-      c32 val;
-      if (pl.kind == 0) {
-        const c32 kz = cf[9 * M + m];
-        const c32 gi = cexpi(kz.x * pl.dz, kz.y * pl.dz);
-        const c32 gr = cexpi(-kz.x * pl.dz, -kz.y * pl.dz);
-        const c32 a = mul(cf[comp * M + m], gi), b = mul(cf[3 * M + comp * M + m], gr);
-        val = {a.x + b.x, a.y + b.y};
-      } else {
-        const c32 kz = cf[10 * M + m];
-        val = mul(cf[6 * M + comp * M + m], cexpi(kz.x * pl.dz, kz.y * pl.dz));
-      }
-      S[m] = val;
-    }
-    for (int i = t; i < 32 * COLS; i += 256) Ts[i] = {0.f, 0.f};
-    __syncthreads();
-    const int f = item.ftile * COLS + col;
-    const bool live = f < fx;
-    if (live) {
-      const c32 w = wfull[f];
-      int sidx = (int)(((long long)(-(U / 2)) * f) % fx);
-      if (sidx < 0) sidx += fx;
-      const c32 sh = wfull[sidx];
-      for (int vi = q; vi < V; vi += 4) {
-        const c32* row = S + vi * U;
-        c32 acc = row[U - 1];
-        for (int u = U - 2; u >= 0; --u) acc = muladd(acc, w, row[u]);
-        Ts[(vi - V / 2 + 16) * COLS + col] = mul(acc, sh);
-      }
-    }
-    __syncthreads();
-    if (live) {
-      c32 tcol[32];
-#pragma unroll
-      for (int sl = 0; sl < 32; ++sl) tcol[sl] = Ts[sl * COLS + col];
-      c32* dst = E + ((((long long)item.job * 3 + comp) * fz + item.plane) * fy) * fx + f;
-      for (int g1 = q; g1 < R; g1 += 4) {
-        c32 a[P];
-#pragma unroll
-        for (int r = 0; r < P; ++r) a[r] = {0.f, 0.f};
-#pragma unroll
-        for (int sl = 0; sl < 32; ++sl) {
-          const int r = ((sl - 16) % P + P) % P;
-          a[r] = muladd(tcol[sl], tw1[sl * R + g1], a[r]);
-        }
-        small_fft<P>(a, twr);
-        typedef float f2v __attribute__((ext_vector_type(2)));
-#pragma unroll
-        for (int g2 = 0; g2 < P; ++g2)
-          __builtin_nontemporal_store(f2v{a[g2].x, a[g2].y},
-                                      reinterpret_cast<f2v*>(dst + (long long)(g1 + R * g2) * fx));
-      }
+    const int first = s_item;
+    if (first >= n_items) break;  // every block reaches this once the queue is drained
+    const int last = min(first + chunk, n_items);
+    for (int it = first; it < last; ++it) {
+      if (it > first) __syncthreads();  // the previous item's S and Ts are consumed
+      batch_item<P>(items[it], jobs, planes, coef, wfull, tw1, twr, fx, fy, fz, S, Ts, E);
     }
   }
 }
@@ -169,7 +191,7 @@ hipError_t launch_batch(const BatchArgs& a, hipStream_t s) {
                                   reinterpret_cast<const c32*>(a.wfull),
                                   reinterpret_cast<const c32*>(a.tw1),
                                   reinterpret_cast<const c32*>(a.tw2), a.fx, a.fy, a.fz,
-                                  a.counter, reinterpret_cast<c32*>(a.E));
+                                  a.chunk, a.counter, reinterpret_cast<c32*>(a.E));
   };
   switch (a.P) {
     case 2: go(batch_kernel<2>); break;

@@ -280,9 +280,8 @@ __global__ void __launch_bounds__(256) modal_f32_kernel(
   }
 }
 
-template <int ZT>
-hipError_t launch_modal_f32(const SynthArgs& a, hipStream_t s) {
-  constexpr int RW = ZT >= 8 ? 4 : (ZT == 4 ? 8 : 16);
+template <int ZT, int RW>
+hipError_t launch_modal_f32_rw(const SynthArgs& a, hipStream_t s) {
   const int n2 = 2 * a.M;
   const int rows_per_block = 4 * RW;
   const int nb_xy = (n2 + rows_per_block - 1) / rows_per_block;
@@ -298,6 +297,23 @@ hipError_t launch_modal_f32(const SynthArgs& a, hipStream_t s) {
       reinterpret_cast<const float2*>(a.task_dz32), a.M, a.L, nb_xy, nb_z, jc,
       reinterpret_cast<float2*>(a.spec));
   return hipGetLastError();
+}
+
+// Rows per wave RW with 2 RW ZT <= 64 accumulated values per lane.
+template <int ZT>
+hipError_t launch_modal_f32(const SynthArgs& a, hipStream_t s) {
+  switch (a.modal_rw) {
+    case 2: return launch_modal_f32_rw<ZT, 2>(a, s);
+    case 4: return launch_modal_f32_rw<ZT, 4>(a, s);
+    case 8:
+      if constexpr (ZT <= 4) return launch_modal_f32_rw<ZT, 8>(a, s);
+      break;
+    case 16:
+      if constexpr (ZT <= 2) return launch_modal_f32_rw<ZT, 16>(a, s);
+      break;
+    default: break;
+  }
+  return hipErrorInvalidValue;
 }
 
 // ---------------------------------------------------------------- exterior
@@ -477,7 +493,6 @@ __global__ void __launch_bounds__(256) idft_fft_kernel(
   const bool live = f < fx;
   const cx<T>* src = spec + (long long)pc * M;
   for (int i = t; i < M; i += 256) S[i] = src[i];
-  for (int i = t; i < 32 * FFT_COLS; i += 256) Ts[i] = {0, 0};
   for (int i = t; i < 32 * R; i += 256) tw1[i] = tw1g[i];
   for (int i = t; i < P; i += 256) tw2[i] = tw2g[i];
   __syncthreads();
@@ -492,9 +507,12 @@ __global__ void __launch_bounds__(256) idft_fft_kernel(
   }
   __syncthreads();
   if (!live) return;
+  // occupied slots 16 - V/2 .. 16 + V/2; the test is uniform over the grid
+  const int lo = 16 - V / 2, hi = 16 + V / 2;
   cx<T> tcol[32];
 #pragma unroll
-  for (int sl = 0; sl < 32; ++sl) tcol[sl] = Ts[sl * FFT_COLS + col];
+  for (int sl = 0; sl < 32; ++sl)
+    if (sl >= lo && sl <= hi) tcol[sl] = Ts[sl * FFT_COLS + col];
   cx<T> twr[P];
 #pragma unroll
   for (int k = 0; k < P; ++k) twr[k] = tw2[k];
@@ -505,8 +523,7 @@ __global__ void __launch_bounds__(256) idft_fft_kernel(
     for (int r = 0; r < P; ++r) a[r] = {0, 0};
 #pragma unroll
     for (int sl = 0; sl < 32; ++sl) {
-      constexpr int dummy = 0;
-      (void)dummy;
+      if (sl < lo || sl > hi) continue;
       const int r = ((sl - 16) % P + P) % P;
       const cx<T> w1 = tw1[sl * R + g1];
       a[r].x = fma(tcol[sl].x, w1.x, fma(-tcol[sl].y, w1.y, a[r].x));
@@ -593,7 +610,10 @@ hipError_t launch_synthesis(const SynthArgs& a, hipStream_t s, hipEvent_t* ev) {
   const int n2 = 2 * a.M;
   auto mark = [&](int i) -> hipError_t { return ev ? hipEventRecord(ev[i], s) : hipSuccess; };
   if ((e = mark(0)) != hipSuccess) return e;
-  if (a.ntasks > 0 && sizeof(T) == 8) {
+  const bool modal = (a.stages & kStageModal) != 0;
+  if (!modal) {
+    if ((e = mark(1)) != hipSuccess) return e;
+  } else if (a.ntasks > 0 && sizeof(T) == 8) {
     phase_kernel<T><<<blocks_for((long long)a.ntasks * n2, 256), 256, 0, s>>>(
         a.tasks, a.task_dz, reinterpret_cast<const zd*>(a.kg),
         reinterpret_cast<const zd*>(a.a), reinterpret_cast<const zd*>(a.b), n2, a.zt,
@@ -622,7 +642,7 @@ hipError_t launch_synthesis(const SynthArgs& a, hipStream_t s, hipEvent_t* ev) {
     return e;
   }
   if ((e = mark(2)) != hipSuccess) return e;
-  if (a.n_ext > 0) {
+  if (a.n_ext > 0 && (a.stages & kStageExterior)) {
     exterior_kernel<T><<<blocks_for((long long)a.n_ext * 3 * a.M, 256), 256, 0, s>>>(
         reinterpret_cast<const ExtPlane*>(a.ext_planes), a.n_ext, a.M,
         reinterpret_cast<const zd*>(a.ext), reinterpret_cast<const zd*>(a.ksz),
@@ -630,7 +650,9 @@ hipError_t launch_synthesis(const SynthArgs& a, hipStream_t s, hipEvent_t* ev) {
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if ((e = mark(3)) != hipSuccess) return e;
-  if (a.fft_p > 0) {
+  if (!(a.stages & kStageTransform)) {
+    // transform not requested
+  } else if (a.fft_p > 0) {
     if ((e = launch_idft_fft<T>(a, s)) != hipSuccess) return e;
   } else if (sizeof(T) == 4 && a.mfma) {
     MfmaArgs m{a.U, a.V, a.fx, a.fy, a.fz, a.kp, a.idft_gtiles, a.spec, a.twx, a.bmat, a.bscale, a.amat, a.E};

@@ -5,6 +5,7 @@
 
 #include <complex>
 #include <cstdint>
+#include <map>
 #include <memory>
 #include <string>
 #include <vector>
@@ -104,6 +105,10 @@ struct Plan {
   int fft_p = 0;                    // factored y pass (fy = R * P) when > 0
   DevBuf d_fft_tw;                  // its twiddles
   bool mfma = false;                // inverse transform on the matrix cores
+  int modal_rw = 0;                 // rows per wave of the FP32 modal sum
+  int tiles = 0;                    // DIRECT row tiles / MFMA plane-components per block
+  scw_synth_config cfg{};           // the configuration the plan was built for
+  unsigned epoch = 0;               // context tuning epoch the plan was built in
   DevBuf d_twx;                     // [2][fx] complex<T>: e^{2 pi i f/fx}, e^{-2 pi i (U/2) f/fx}
   DevBuf d_twy;                     // [2][fy] complex<T>: same for g, V
   bool valid = false;
@@ -131,6 +136,7 @@ struct Solution {
   DevBuf d_ext;      // [3][3M] complex128: p_inc, p_ref, p_trn
   DevBuf d_ksz;      // [2][M] complex128: k*sz_top, k*sz_bot
   Plan plan;
+  scw_synth_config cfg{};  // explicit kernel configuration (0 fields: library choice)
   int device = 0;
 };
 
@@ -145,7 +151,23 @@ struct Context {
   std::vector<hipEvent_t> prof_events;
   int prof_max = 0;
   int prof_used = 0;
+  // autotuner results, keyed by problem and grid shape
+  std::map<std::string, scw_synth_config> tuned_synth;
+  struct BatchShape {
+    int P, blocks_per_cu, chunk;
+  };
+  std::map<std::string, BatchShape> tuned_batch;
+  unsigned tune_epoch = 0;  // bumped when tuned_synth changes
 };
+
+// Stages of one synthesis call, selectable for timing.
+enum StageMask { kStageModal = 1, kStageExterior = 2, kStageTransform = 4, kStageAll = 7 };
+
+// Plan (if needed) and enqueue one synthesis; `stages` selects kernels and
+// `ev` (nullable) receives kNumStages + 1 stage events.
+int synthesize(Context& ctx, Solution& s, const scw_grid& g, int precision, void* E,
+               hipStream_t st, int stages, hipEvent_t* ev);
+std::string synth_key(const Solution& s, const scw_grid& g, int precision);
 
 // ------------------------------------------------------------------ setup
 int solve_problem(Context& ctx, const scw_problem& prob, Solution& sol);
@@ -202,6 +224,8 @@ struct SynthArgs {
   const void* kgab32;      // complex64 [3][L][2M]: k*gamma, a, b
   const void* task_dz32;   // float2 [ntasks][zt]
   int idft_gtiles;         // 0 = automatic
+  int modal_rw;            // rows per wave of the FP32 modal sum (2, 4, 8, 16)
+  int stages;              // StageMask
   int precision;           // scw_precision
   bool mfma;               // inverse transform on the matrix cores
   int kp;
@@ -246,10 +270,44 @@ struct BatchArgs {
   const void* tw1;           // [32][R]
   const void* tw2;           // [P]
   int fx, fy, fz, P, grid;
+  int chunk;                 // items per grab from the work counter
   unsigned int* counter;
   void* E;                   // [njobs][3][fz][fy][fx] complex64
 };
 hipError_t launch_batch(const BatchArgs& a, hipStream_t s);
+
+}  // namespace scw
+
+// ------------------------------------------------------------------ ABI handles
+struct scw_ctx {
+  scw::Context c;
+};
+struct scw_solution {
+  scw::Solution s;
+};
+struct scw_batch {
+  scw::Context* ctx = nullptr;
+  int njobs = 0, n_items = 0, P = 0, grid_blocks = 0, cus = 0, chunk = 1;
+  scw_grid grid{};
+  scw::DevBuf d_jobs, d_items, d_planes, d_coef, d_wfull, d_tw, d_counter;
+  hipStream_t capture_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  void* graph_E = nullptr;
+  ~scw_batch() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (capture_stream) (void)hipStreamDestroy(capture_stream);
+  }
+};
+
+namespace scw {
+
+// Batched synthesis shape: P of the factored y pass (fy = R * P) and the
+// persistent grid; rebuilds the twiddles and drops the captured graph.
+int batch_set_shape(scw_batch* b, int P, int blocks_per_cu, int chunk);
+BatchArgs batch_args(const scw_batch* b, void* E);
+std::string batch_key(const scw_grid& g);
 
 // ------------------------------------------------------------------ surrogate kernels
 // C[b] = op(A[b]) op(B[b]) + beta C[b]; strides in elements of each operand's

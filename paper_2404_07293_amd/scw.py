@@ -120,9 +120,7 @@ class Solution:
         return self.lib.scw_synthesis_bytes(self.handle, ctypes.byref(_grid(grid)),
                                             N.PRECISION[precision])
 
-    def synthesize(self, grid, precision="fp32", out=None, stream=None):
-        """Enqueue ``scw_synthesize`` into ``out`` (a CUDA tensor
-        [3, fz, fy, fx]); allocates it when None. Returns the tensor."""
+    def _out(self, grid, precision, out, stream):
         import torch
         dt = torch.complex128 if precision == "fp64" else torch.complex64
         shape = (3, int(grid.fz), int(grid.fy), int(grid.fx))
@@ -135,11 +133,41 @@ class Solution:
                              % (dt, shape, dev))
         if stream is None:
             stream = torch.cuda.current_stream(dev)
+        return out, stream
+
+    def synthesize(self, grid, precision="fp32", out=None, stream=None):
+        """Enqueue ``scw_synthesize`` into ``out`` (a CUDA tensor
+        [3, fz, fy, fx]); allocates it when None. Returns the tensor."""
+        out, stream = self._out(grid, precision, out, stream)
         N.check(self.lib.scw_synthesize(self.ctx.handle, self.handle,
                                         ctypes.byref(_grid(grid)), N.PRECISION[precision],
                                         ctypes.c_void_p(out.data_ptr()),
                                         ctypes.c_void_p(stream.cuda_stream)))
         return out
+
+    def configure(self, modal_rows=0, transform="auto", fft_radix=0, tiles=0):
+        """``scw_synthesis_configure``: explicit kernel configuration (0 /
+        "auto" fields leave the library's choice)."""
+        cfg = N.ScwSynthConfig(int(modal_rows), N.TRANSFORM[transform], int(fft_radix),
+                               int(tiles))
+        N.check(self.lib.scw_synthesis_configure(self.handle, ctypes.byref(cfg)))
+
+    def tune(self, grid, precision="fp32", out=None, stream=None, reps=5):
+        """``scw_tune_synthesis``: time the kernel configurations for this
+        grid and precision and keep the fastest. Returns the report as a dict;
+        ``out`` holds the field afterwards."""
+        out, stream = self._out(grid, precision, out, stream)
+        rep = N.ScwTuneReport()
+        N.check(self.lib.scw_tune_synthesis(self.ctx.handle, self.handle,
+                                            ctypes.byref(_grid(grid)), N.PRECISION[precision],
+                                            ctypes.c_void_p(out.data_ptr()),
+                                            ctypes.c_void_p(stream.cuda_stream), int(reps),
+                                            ctypes.byref(rep)))
+        c = rep.config
+        return {"n_candidates": rep.n_candidates, "default_ms": rep.default_ms,
+                "best_ms": rep.best_ms, "modal_rows": c.modal_rows,
+                "transform": N.TRANSFORM_NAME.get(c.transform, "?"),
+                "fft_radix": c.fft_radix, "tiles": c.tiles}
 
 
 class Batch:
@@ -163,8 +191,7 @@ class Batch:
         except Exception:
             pass
 
-    def launch(self, out=None, stream=None):
-        """Replay the batch graph into ``out`` [njobs, 3, fz, fy, fx] complex64."""
+    def _out(self, out, stream):
         import torch
         g = self.grid
         shape = (len(self.jobs), 3, int(g.fz), int(g.fy), int(g.fx))
@@ -175,6 +202,23 @@ class Batch:
             raise ValueError("out must be a contiguous complex64 tensor of shape %s" % (shape,))
         if stream is None:
             stream = torch.cuda.current_stream(dev)
+        return out, stream
+
+    def launch(self, out=None, stream=None):
+        """Replay the batch graph into ``out`` [njobs, 3, fz, fy, fx] complex64."""
+        out, stream = self._out(out, stream)
         N.check(self.lib.scw_batch_launch(self.handle, ctypes.c_void_p(out.data_ptr()),
                                           ctypes.c_void_p(stream.cuda_stream)))
         return out
+
+    def tune(self, out=None, stream=None, reps=3):
+        """``scw_batch_tune``: sweep the persistent kernel's shapes and keep
+        the fastest. Returns the report as a dict."""
+        out, stream = self._out(out, stream)
+        rep = N.ScwTuneReport()
+        N.check(self.lib.scw_batch_tune(self.handle, ctypes.c_void_p(out.data_ptr()),
+                                        ctypes.c_void_p(stream.cuda_stream), int(reps),
+                                        ctypes.byref(rep)))
+        return {"n_candidates": rep.n_candidates, "default_ms": rep.default_ms,
+                "best_ms": rep.best_ms, "radix": rep.batch_radix,
+                "blocks_per_cu": rep.batch_blocks_per_cu, "chunk": rep.batch_chunk}

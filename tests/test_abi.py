@@ -43,8 +43,15 @@ int main(void) {
   F(scw_grid, fx) F(scw_grid, z_begin) F(scw_grid, z_end)
   F(scw_solution_info, M) F(scw_solution_info, min_abs_sz)
   F(scw_solution_info, connection_rcond) F(scw_solution_info, assembly_device_ms)
+  F(scw_synth_config, modal_rows) F(scw_synth_config, transform)
+  F(scw_synth_config, fft_radix) F(scw_synth_config, tiles)
+  F(scw_tune_report, n_candidates) F(scw_tune_report, default_ms) F(scw_tune_report, best_ms)
+  F(scw_tune_report, config) F(scw_tune_report, batch_radix)
+  F(scw_tune_report, batch_blocks_per_cu) F(scw_tune_report, batch_chunk)
   printf("size scw_problem %zu\nsize scw_grid %zu\nsize scw_solution_info %zu\n",
          sizeof(scw_problem), sizeof(scw_grid), sizeof(scw_solution_info));
+  printf("size scw_synth_config %zu\nsize scw_tune_report %zu\n",
+         sizeof(scw_synth_config), sizeof(scw_tune_report));
   return 0;
 }
 '''
@@ -60,7 +67,8 @@ int main(void) {
 def test_ctypes_structures_match_c_layout():
     rename = {"lambda": "lam"}
     types = {"scw_problem": N.ScwProblem, "scw_grid": N.ScwGrid,
-             "scw_solution_info": N.ScwSolutionInfo}
+             "scw_solution_info": N.ScwSolutionInfo, "scw_synth_config": N.ScwSynthConfig,
+             "scw_tune_report": N.ScwTuneReport}
     for line in _c_layout():
         if not line:
             continue
@@ -90,3 +98,6 @@ def test_null_arguments_rejected_without_touching_the_gpu():
     assert lib.scw_synthesize(None, None, None, 1, None, None) == -1
     assert lib.scw_solution_info_get(None, None) == -1
     assert lib.scw_synthesis_bytes(None, None, 1) == 0.0
+    assert lib.scw_synthesis_configure(None, None) == -1
+    assert lib.scw_tune_synthesis(None, None, None, 1, None, None, 5, None) == -1
+    assert lib.scw_batch_tune(None, None, None, 3, None) == -1

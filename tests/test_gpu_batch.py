@@ -73,6 +73,34 @@ def test_batch_matches_oracle_and_single_synthesis(ctx):
     assert np.array_equal(other.cpu().numpy(), got)
 
 
+def test_batch_tuner_keeps_a_correct_shape(ctx):
+    torch = _torch()
+    specs = [(21, 5, 5, 1.0), (22, 9, 7, 0.9), (23, 3, 3, 1.2)]
+    probs = [small_job(*s) for s in specs]
+    assert all(well_conditioned(p) for p in probs)
+    T = max(p.thickness for p in probs)
+    grid = W.Grid(fx=40, fy=64, fz=2, z_begin=T + 0.05, z_end=T + 0.6)
+    sols = [ctx.solve(p) for p in probs]
+    b = ctx.batch(sols, grid)
+    base = b.launch().cpu().numpy()
+    out = torch.empty_like(b.launch())
+    rep = b.tune(out=out, reps=2)
+    print(rep)
+    assert rep["n_candidates"] >= 8
+    assert 0 < rep["best_ms"] <= rep["default_ms"]
+    assert rep["radix"] in (2, 4, 8, 16, 32) and rep["blocks_per_cu"] >= 1
+    tuned = b.launch(out=out).cpu().numpy()
+    torch.cuda.synchronize()
+    for j, prob in enumerate(probs):
+        _, _, want = cwt.simulate(prob, grid)
+        assert rel_l2(tuned[j], want) <= FP32_TOL
+        assert rel_l2(tuned[j], base[j]) <= 1e-5
+    # a new batch on the same grid starts from the tuned shape
+    again = ctx.batch(sols, grid).launch().cpu().numpy()
+    torch.cuda.synchronize()
+    assert np.array_equal(again, tuned)
+
+
 def test_batch_above_the_sample(ctx):
     torch = _torch()
     probs = [small_job(7, 5, 3, 1.0), small_job(8, 3, 5, 0.8, nz=2)]

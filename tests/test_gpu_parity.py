@@ -12,6 +12,7 @@ import pytest
 
 import workloads as W
 from oracle import cwt
+from paper_2404_07293_amd._native import ScwError
 
 pytestmark = pytest.mark.gpu
 
@@ -205,22 +206,86 @@ def test_split_precision_matches_oracle(ctx, precision, tol):
         assert err <= tol
 
 
-@pytest.mark.parametrize("mode", ["valu", "mfma", "fft"])
-def test_fp32_transform_variants_match_oracle(ctx, monkeypatch, mode):
-    # the FP32 inverse transform has three kernels: direct Horner sums on the
-    # VALU, MFMA GEMM, and the factored y pass (default when fy = R * P)
-    torch = _torch()
-    if mode != "fft":
-        monkeypatch.setenv("SCW_IDFT", mode)
+# every kernel configuration the FP32 and FP64 paths can take: the three
+# inverse transforms (factored FFT y pass at each radix, matrix-core y pass at
+# several plane tilings, direct Horner sums at several row tilings) and the
+# modal-sum row blockings
+CONFIGS = ([("fp32", dict(transform="fft", fft_radix=p)) for p in (2, 4, 8, 16, 32)]
+           + [("fp32", dict(transform="mfma", tiles=t)) for t in (0, 1, 3)]
+           + [("fp32", dict(transform="direct", tiles=t)) for t in (0, 1, 5)]
+           + [("fp32", dict(modal_rows=r)) for r in (2, 4, 8, 16)]
+           + [("fp64", dict(transform="fft", fft_radix=p)) for p in (4, 32)]
+           + [("fp64", dict(transform="direct", tiles=t)) for t in (0, 2)])
+
+
+@pytest.mark.parametrize("precision,cfg", CONFIGS)
+def test_kernel_configurations_match_oracle(ctx, precision, cfg):
+    tol = FP64_TOL if precision == "fp64" else FP32_TOL
     for prob, grid in (W.sphere_config(),
                        (ragged_problem(seed=12),
                         W.Grid(fx=24, fy=64, fz=7, z_begin=-0.2, z_end=0.8)),
                        (ragged_problem(seed=13, U=7, V=5),
                         W.Grid(fx=70, fy=512, fz=3, z_begin=0.1, z_end=0.5))):
-        _, _, want = cwt.simulate(prob, grid)
+        if cfg.get("fft_radix", 0) > grid.fy:
+            continue
         sol = ctx.solve(prob)
-        got = sol.synthesize(grid, "fp32").cpu().numpy()
-        torch.cuda.synchronize()
+        sol.configure(**cfg)
+        P = cfg.get("fft_radix", 0)
+        eb = 16 if precision == "fp64" else 8
+        if P and (prob.U * prob.V + 32 * 64 + 32 * (grid.fy // P) + P) * eb > 64 * 1024:
+            # the factored transform's tables must fit in 64 KB of LDS
+            with pytest.raises(ScwError) as e:
+                sol.synthesize(grid, precision)
+            assert e.value.code == -1
+            continue
+        _, _, want = cwt.simulate(prob, grid)
+        got = sol.synthesize(grid, precision).cpu().numpy()
         err = rel_l2(got, want)
-        print("fp32 %s fy=%d rel-L2 %.3e" % (mode, grid.fy, err))
-        assert err <= FP32_TOL
+        print("%s %s fy=%d rel-L2 %.3e" % (precision, cfg, grid.fy, err))
+        assert err <= tol
+
+
+def test_unsupported_configurations_are_rejected(ctx):
+    prob, grid = W.sphere_config(out=16)
+    sol = ctx.solve(prob)
+    bad = [("fp64", dict(transform="mfma")),
+           ("bf16x3", dict(transform="fft")),
+           ("fp16x3", dict(transform="direct")),
+           ("fp32", dict(modal_rows=3)),
+           ("fp32", dict(transform="fft", fft_radix=64)),
+           ("fp32", dict(transform="fft", fft_radix=12))]
+    for precision, cfg in bad:
+        sol.configure(**cfg)
+        with pytest.raises(ScwError) as e:
+            sol.synthesize(grid, precision)
+        assert e.value.code == -1, (precision, cfg)
+    sol.configure()
+    sol.synthesize(grid, "fp32")
+    # a factored transform needs fy a power of two
+    sol.configure(transform="fft")
+    with pytest.raises(ScwError):
+        sol.synthesize(W.Grid(fx=16, fy=12, fz=4, z_begin=0.0, z_end=1.0), "fp32")
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "fp64"])
+def test_autotuner_keeps_a_correct_and_no_slower_configuration(ctx, precision):
+    torch = _torch()
+    tol = {"fp64": FP64_TOL, "fp32": FP32_TOL, "bf16x3": BF16X3_TOL}[precision]
+    prob = ragged_problem(seed=14, nx=8, ny=10, U=7, V=9)
+    grid = W.Grid(fx=96, fy=128, fz=12, z_begin=-0.2, z_end=1.1)
+    _, _, want = cwt.simulate(prob, grid)
+    sol = ctx.solve(prob)
+    out = sol.synthesize(grid, precision)
+    rep = sol.tune(grid, precision, out=out, reps=3)
+    print(precision, rep)
+    assert rep["n_candidates"] >= 2
+    assert 0 < rep["best_ms"] <= rep["default_ms"]
+    assert rel_l2(out.cpu().numpy(), want) <= tol
+    if precision == "bf16x3":
+        assert rep["transform"] == "mfma"
+    # a second solution of the same shape takes the tuned configuration and
+    # computes the same field
+    sol2 = ctx.solve(prob)
+    got = sol2.synthesize(grid, precision)
+    torch.cuda.synchronize()
+    assert torch.equal(got, sol.synthesize(grid, precision))
