@@ -143,11 +143,11 @@ def cpu_baseline(prob_full, grid_full, n_layers=2, min_seconds=10.0):
                           prob.U * prob.V, reps, per, t1 - t0)}
 
 
-def golden_error(E, prob, grid, per_component=False):
+def golden_error(E, prob, grid, per_component=False, path=GOLDEN):
     """rel-L2 of the synthesised field at the stored oracle sample voxels."""
-    if not os.path.exists(GOLDEN):
+    if not os.path.exists(path):
         return None
-    g = np.load(GOLDEN, allow_pickle=False)
+    g = np.load(path, allow_pickle=False)
     if int(g["fx"]) != grid.fx or int(g["fz"]) != grid.fz or int(g["M"]) != prob.U * prob.V:
         return None
     j, gg, f = g["j"], g["g"], g["f"]
@@ -162,6 +162,52 @@ def golden_error(E, prob, grid, per_component=False):
 
 
 SWEEP_GOLDEN = os.path.join(ROOT, "tests", "golden", "sweep_job.npz")
+LARGE_GOLDEN = os.path.join(ROOT, "tests", "golden", "large_samples.npz")
+
+
+def large_leg(ctx, torch, dev, stream, args):
+    """The 128x128x64 random-field sample (M = 961, 64 layers) on the
+    512x512x256 grid: plain FP32 synthesis and the two split-precision forms,
+    each with its rel-L2 against the oracle, per component."""
+    import workloads as W
+    prob, grid = W.random_field_config("large")
+    t0 = time.perf_counter()
+    sol = ctx.solve(prob)
+    t_setup = time.perf_counter() - t0
+    info = sol.info()
+    log("large: setup %.1f s (eig %.1f s), growth exponent %.1f" % (
+        t_setup, info["eig_seconds"], info["growth_exponent"]))
+    E = torch.empty((3, grid.fz, grid.fy, grid.fx), dtype=torch.complex64, device=dev)
+    voxels = grid.fx * grid.fy * grid.fz
+    rec = {"workload": "large: %dx%dx%d random-field sample, M=%d, %dx%dx%d grid" % (
+        prob.nx, prob.ny, prob.nz, prob.U * prob.V, grid.fx, grid.fy, grid.fz),
+        "voxels_per_step": voxels, "setup_s": t_setup, "eig_s": info["eig_seconds"],
+        "growth_exponent": info["growth_exponent"]}
+    steps = max(3, args.steps // 5)
+    s0 = torch.cuda.Event(enable_timing=True)
+    s1 = torch.cuda.Event(enable_timing=True)
+    for prec in ("fp32", "bf16x3", "fp16x3"):
+        tune = sol.tune(grid, prec, out=E, stream=stream, reps=2) if args.tune else None
+        for _ in range(2):
+            sol.synthesize(grid, prec, out=E, stream=stream)
+        torch.cuda.synchronize()
+        s0.record(stream)
+        for _ in range(steps):
+            sol.synthesize(grid, prec, out=E, stream=stream)
+        s1.record(stream)
+        torch.cuda.synchronize()
+        ms = s0.elapsed_time(s1) / steps
+        err = golden_error(E, prob, grid, path=LARGE_GOLDEN)
+        per = golden_error(E, prob, grid, True, path=LARGE_GOLDEN)
+        rec[prec] = {"value": voxels / (ms * 1e-3), "ms_per_step": ms,
+                     "rel_l2_vs_oracle": err, "rel_l2_per_component": per,
+                     "hbm_bytes_algorithmic": sol.synthesis_bytes(grid, prec),
+                     "tuning": tune}
+        log("large %s: ms/step %.3f, %.3e voxels/s, rel-L2 %s per component %s" % (
+            prec, ms, voxels / (ms * 1e-3), err, per))
+    del E
+    sol.free()
+    return rec
 
 
 def batched_sweep(ctx, torch, dev, stream, args):
@@ -184,6 +230,9 @@ def batched_sweep(ctx, torch, dev, stream, args):
     b = ctx.batch([solved[p] for _, p, _ in jobs], grid)
     Eb = torch.empty((len(jobs), 3, grid.fz, grid.fy, grid.fx), dtype=torch.complex64,
                      device=dev)
+    tune = b.tune(out=Eb, stream=stream, reps=3) if args.tune else None
+    if tune:
+        log("tuned batch: %s" % tune)
     for _ in range(max(2, args.warmup)):
         b.launch(out=Eb, stream=stream)
     torch.cuda.synchronize()
@@ -210,7 +259,7 @@ def batched_sweep(ctx, torch, dev, stream, args):
     rec = {"value": voxels / (ms * 1e-3), "ms_per_step": ms, "jobs": len(jobs),
            "voxels_per_step": voxels, "rel_l2_vs_oracle": err,
            "hbm_write_gbps": bytes_out / (ms * 1e-3) / 1e9,
-           "solved_jobs": len(solved), "setup_s": t_setup,
+           "solved_jobs": len(solved), "setup_s": t_setup, "tuning": tune,
            "note": "one solve per patch; all 256 wavenumbers of a patch reuse it"}
     del Eb
     b.free()
@@ -220,6 +269,33 @@ def batched_sweep(ctx, torch, dev, stream, args):
 
 
 SUR_DATA = os.path.join(ROOT, "paper_2404_07293_amd", "data", "surrogate_targets.npz")
+
+
+def cwt_equal_accuracy(ctx, patches, targets, err_goal):
+    """Plain CWT on the surrogate's patches at truncation U = 1, 3, 5, ...:
+    rel-L2 of its transmitted coefficients (zero outside its band) against the
+    15 x 15 reference, and its patches/s. Returns the first U whose error is at
+    most err_goal, with the sweep."""
+    import workloads as W
+    sweep = []
+    for U in range(1, 16, 2):
+        got = np.zeros(targets.shape, np.complex128)
+        lo = 7 - U // 2
+        t0 = time.perf_counter()
+        for i, n in enumerate(patches):
+            prob = W.surrogate_problem(n)
+            prob = W.Problem(n=prob.n, px=prob.px, py=prob.py, pz=prob.pz, lam=prob.lam, U=U,
+                             V=U, n_top=prob.n_top, n_bot=prob.n_bot,
+                             plane_wave=prob.plane_wave)
+            sol = ctx.solve(prob)
+            got[i, :, lo:lo + U, lo:lo + U] = sol.exterior()[2].reshape(3, U, U)
+            sol.free()
+        rate = len(patches) / (time.perf_counter() - t0)
+        err = float(np.linalg.norm(got - targets) / np.linalg.norm(targets))
+        sweep.append({"U": U, "rel_l2": err, "patches_per_s": rate})
+        if err <= err_goal:
+            return dict(sweep[-1], sweep=sweep)
+    return {"U": None, "sweep": sweep}
 
 
 def surrogate_leg(ctx, torch, dev, stream, args):
@@ -237,7 +313,7 @@ def surrogate_leg(ctx, torch, dev, stream, args):
     n_tr = len(seeds) - n_val
     xtr, ttr, xva, tva = x_all[:n_tr], t_all[:n_tr], x_all[n_tr:], t_all[n_tr:]
     rng = np.random.Generator(np.random.PCG64(3))
-    bs, epochs, lr0 = 64, args.sur_epochs, 1e-3
+    bs, epochs, lr0 = args.sur_batch, args.sur_epochs, args.sur_lr
     steps = epochs * (n_tr // bs)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -280,6 +356,9 @@ def surrogate_leg(ctx, torch, dev, stream, args):
     ncwt = 8
     cwt_targets(ctx, patches[n_tr:n_tr + ncwt])
     cwt_rate = ncwt / (time.perf_counter() - t1)
+    # plain CWT at equal accuracy: the smallest truncation whose transmitted
+    # coefficients are as close to the 15 x 15 reference as the surrogate's
+    equal = cwt_equal_accuracy(ctx, patches[n_tr:n_tr + 8], targets[n_tr:n_tr + 8], val_err)
     # checked inference with the CWT fallback on 64 validation patches
     t2 = time.perf_counter()
     _, fell, chk = sur.infer_checked(patches[n_tr:n_tr + 64], n_check=8, seed=5, tol=1e-2)
@@ -293,7 +372,9 @@ def surrogate_leg(ctx, torch, dev, stream, args):
            "infer_batch": 4096, "infer_ms": ms_inf, "patches_per_s": rate,
            "cwt_patches_per_s": cwt_rate, "speedup_vs_cwt": rate / cwt_rate,
            "checked_batch": 64, "check_rel_l2": chk, "fallback_fired": fell,
-           "checked_seconds": t_checked,
+           "checked_seconds": t_checked, "cwt_equal_accuracy": equal,
+           "speedup_vs_cwt_equal_accuracy": (rate / equal["patches_per_s"]
+                                             if equal and equal.get("patches_per_s") else None),
            "note": "fallback threshold 1e-2 rel-L2 on 8 CWT-solved patches of the batch"}
     sur.free()
     return rec
@@ -310,11 +391,18 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--surrogate", type=int, default=1,
                     help="also train and time the spectral-convolution surrogate")
-    ap.add_argument("--sur-epochs", type=int, default=60)
+    ap.add_argument("--sur-epochs", type=int, default=400)
+    ap.add_argument("--sur-batch", type=int, default=32)
+    ap.add_argument("--sur-lr", type=float, default=2e-3)
     ap.add_argument("--batched", type=int, default=1,
                     help="also time the batched spectral sweep (4096 jobs, one launch)")
+    ap.add_argument("--large", type=int, default=1,
+                    help="also time the 128x128x64 / M=961 / 512^2x256 workload in FP32, "
+                         "BF16x3 and FP16x3")
     ap.add_argument("--variants", default="bf16x3,fp16x3",
                     help="other precisions timed in the same run ('' for none)")
+    ap.add_argument("--tune", type=int, default=1,
+                    help="run the library's autotuner before timing (0: built-in defaults)")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="also run N plain 256 MiB device copies (PMC scale reference)")
     args = ap.parse_args(argv)
@@ -341,6 +429,10 @@ def main(argv=None):
     stream = torch.cuda.current_stream(dev)
     dt = torch.complex128 if args.precision == "fp64" else torch.complex64
     E = torch.empty((3, grid.fz, grid.fy, grid.fx), dtype=dt, device=dev)
+    tuning = {}
+    if args.tune:
+        tuning[args.precision] = sol.tune(grid, args.precision, out=E, stream=stream, reps=5)
+        log("tuned %s: %s" % (args.precision, tuning[args.precision]))
     for _ in range(args.warmup):
         sol.synthesize(grid, args.precision, out=E, stream=stream)
     torch.cuda.synchronize()
@@ -417,11 +509,15 @@ def main(argv=None):
         "setup_s": info["setup_seconds"],
         "assembly_device_ms": info["assembly_device_ms"],
         "roofline": roof,
+        "tuning": tuning,
     }
     if args.variants:
         variants = {}
         for prec in args.variants.split(","):
             Ev = torch.empty((3, grid.fz, grid.fy, grid.fx), dtype=torch.complex64, device=dev)
+            if args.tune:
+                tuning[prec] = sol.tune(grid, prec, out=Ev, stream=stream, reps=5)
+                log("tuned %s: %s" % (prec, tuning[prec]))
             for _ in range(max(2, args.warmup)):
                 sol.synthesize(grid, prec, out=Ev, stream=stream)
             vms = timed_loop(prec, Ev, args.steps)
@@ -431,6 +527,8 @@ def main(argv=None):
             log("%s: ms/step %.4f rel-L2 %s" % (prec, vms, variants[prec]["rel_l2_vs_oracle"]))
             del Ev
         out["variants"] = variants
+    if args.large and args.workload == "working":
+        out.setdefault("variants", {})["large"] = large_leg(ctx, torch, dev, stream, args)
     if args.surrogate and os.path.exists(SUR_DATA):
         out["surrogate"] = surrogate_leg(ctx, torch, dev, stream, args)
     if args.batched:

@@ -220,8 +220,10 @@ typedef struct {
 /* Time the candidate kernel configurations of scw_synthesize for this
  * solution, grid and precision (modal-sum row blocking, then transform kind,
  * radix and tiling, each stage timed alone with `reps` calls after one
- * warm-up), keep the fastest in the solution and in the context's cache for
- * solutions of the same shape, and report it. E_dev is a caller-owned output
+ * warm-up), keep the fastest in the context, keyed by problem shape, grid and
+ * precision, and report it. Later calls of that shape and precision use it
+ * wherever their solution's explicit configuration leaves a field 0; the
+ * solution's own configuration is left as it was. E_dev is a caller-owned output
  * buffer as for scw_synthesize and holds the synthesized field on return.
  * Synchronises `hip_stream`. */
 int scw_tune_synthesis(scw_ctx* ctx, scw_solution* sol, const scw_grid* grid, int precision,

@@ -84,9 +84,22 @@ int sweep(int n, const std::function<int(int)>& prepare, const std::function<int
 
 }  // namespace
 
+// Restores a solution's explicit configuration when the tuner returns: the
+// tuner's result lives in the context, keyed by shape and precision.
+struct ConfigGuard {
+  Solution& s;
+  scw_synth_config saved;
+  explicit ConfigGuard(Solution& sol) : s(sol), saved(sol.cfg) {}
+  ~ConfigGuard() {
+    s.cfg = saved;
+    s.plan.valid = false;
+  }
+};
+
 int tune_synthesis(Context& c, Solution& s, const scw_grid& g, int precision, void* E,
                    hipStream_t st, int reps, scw_tune_report* rep) {
   const std::string key = synth_key(s, g, precision);
+  ConfigGuard guard(s);
   // candidates are timed without the context's tuned entry for this shape
   c.tuned_synth.erase(key);
   ++c.tune_epoch;
@@ -158,7 +171,9 @@ int tune_synthesis(Context& c, Solution& s, const scw_grid& g, int precision, vo
   }
   c.tuned_synth[key] = best;
   ++c.tune_epoch;
-  use(best);
+  // the field of the chosen configuration, as the caller's later calls
+  // without an explicit configuration will compute it
+  use(scw_synth_config{});
   int rc = synthesize(c, s, g, precision, E, st, kStageAll, nullptr);
   if (rc) return rc;
   SCW_HIP(hipStreamSynchronize(st));
