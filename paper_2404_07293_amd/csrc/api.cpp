@@ -143,7 +143,7 @@ bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
 // LDS bytes of the factored transform block for radix P.
 size_t fft_lds_bytes(const Solution& s, const scw_grid& g, int precision, int P) {
   const size_t eb = precision == SCW_FP64 ? 16 : 8;
-  return ((size_t)s.U * s.V + 32 * 64 + 32 * (size_t)(g.fy / P) + P) * eb;
+  return ((size_t)s.U * s.V + 32 * 64 + 32 * (size_t)(g.fy / P)) * eb;
 }
 
 int build_plan(const Context& ctx, Solution& s, const scw_grid& g, int precision) {
@@ -273,11 +273,10 @@ int build_plan(const Context& ctx, Solution& s, const scw_grid& g, int precision
   if (kind == SCW_XFORM_FFT) {
     const int R = g.fy / P;
     pl.fft_p = P;
-    std::vector<zc> tw(32 * (size_t)R + P);
+    std::vector<zc> tw(32 * (size_t)R);
     for (int sl = 0; sl < 32; ++sl)
       for (int g1 = 0; g1 < R; ++g1)
         tw[(size_t)sl * R + g1] = twiddle_inv((long long)(sl - 16) * g1, g.fy);
-    for (int k = 0; k < P; ++k) tw[32 * (size_t)R + k] = twiddle_inv(k, P);
     if (precision == SCW_FP64) {
       std::vector<double> b;
       pack(tw, b);
@@ -592,7 +591,7 @@ int batch_set_shape(scw_batch* b, int P, int blocks_per_cu, int chunk) {
   if (32 * (size_t)R * 8 > 64 * 1024) return fail(SCW_EINVAL, "batch radix too small for fy");
   if (blocks_per_cu < 1 || blocks_per_cu > 64) return fail(SCW_EINVAL, "blocks per CU out of range");
   if (chunk < 1 || chunk > 1024) return fail(SCW_EINVAL, "items per grab out of range");
-  std::vector<float> wfull(2 * (size_t)b->grid.fx), tw(2 * (32 * (size_t)R + P));
+  std::vector<float> wfull(2 * (size_t)b->grid.fx), tw(2 * (32 * (size_t)R));
   for (int k = 0; k < b->grid.fx; ++k) {
     const zc w = twiddle_inv(k, b->grid.fx);
     wfull[2 * k] = (float)w.real();
@@ -604,11 +603,6 @@ int batch_set_shape(scw_batch* b, int P, int blocks_per_cu, int chunk) {
       tw[2 * ((size_t)sl * R + g1)] = (float)w.real();
       tw[2 * ((size_t)sl * R + g1) + 1] = (float)w.imag();
     }
-  for (int k = 0; k < P; ++k) {
-    const zc w = twiddle_inv(k, P);
-    tw[2 * (32 * (size_t)R + k)] = (float)w.real();
-    tw[2 * (32 * (size_t)R + k) + 1] = (float)w.imag();
-  }
   int rc;
   if ((rc = upload(b->d_wfull, wfull.data(), wfull.size() * 4)) ||
       (rc = upload(b->d_tw, tw.data(), tw.size() * 4)))
@@ -636,9 +630,7 @@ BatchArgs batch_args(const scw_batch* b, void* E) {
   a.planes = b->d_planes.as<BatchPlane>();
   a.coef = b->d_coef.p;
   a.wfull = b->d_wfull.p;
-  const int R = b->grid.fy / b->P;
   a.tw1 = b->d_tw.p;
-  a.tw2 = b->d_tw.as<float>() + 2 * 32 * (size_t)R;
   a.fx = b->grid.fx;
   a.fy = b->grid.fy;
   a.fz = b->grid.fz;

@@ -36,8 +36,40 @@ __device__ __forceinline__ c32 cexpi(float re, float im) {  // exp(i (re + i im)
   return {m * cs, m * sn};
 }
 
+// cos(2 pi r / 32) for r = 0..8: the first quadrant of the twiddles of every
+// radix P <= 32.
+__device__ __forceinline__ float quarter_cos(int r) {
+  switch (r) {
+    case 0: return 1.0f;
+    case 1: return 0.98078528040323044913f;
+    case 2: return 0.92387953251128675613f;
+    case 3: return 0.83146961230254523708f;
+    case 4: return 0.70710678118654752440f;
+    case 5: return 0.55557023301960222474f;
+    case 6: return 0.38268343236508977173f;
+    case 7: return 0.19509032201612826785f;
+    default: return 0.0f;
+  }
+}
+
+// v * e^{2 pi i k / P}, k known at compile time after unrolling.
 template <int P>
-__device__ __forceinline__ void small_fft(c32* a, const c32* tw) {  // tw[k] = e^{2 pi i k/P}
+__device__ __forceinline__ c32 twiddle_mul(c32 v, int k) {
+  const int k32 = (k * (32 / P)) & 31;
+  if (k32 == 0) return v;
+  if (k32 == 8) return {-v.y, v.x};
+  if (k32 == 16) return {-v.x, -v.y};
+  if (k32 == 24) return {v.y, -v.x};
+  const int q = k32 >> 3, r = k32 & 7;
+  const float c0 = quarter_cos(r), s0 = quarter_cos(8 - r);
+  const float c = q == 0 ? c0 : (q == 1 ? -s0 : (q == 2 ? -c0 : s0));
+  const float sn = q == 0 ? s0 : (q == 1 ? c0 : (q == 2 ? -s0 : -c0));
+  return {v.x * c - v.y * sn, v.x * sn + v.y * c};
+}
+
+// In-register radix-2 FFT of length P, positive exponent.
+template <int P>
+__device__ __forceinline__ void small_fft(c32* a) {
 #pragma unroll
   for (int i = 0; i < P; ++i) {
     int r = 0;
@@ -55,9 +87,8 @@ __device__ __forceinline__ void small_fft(c32* a, const c32* tw) {  // tw[k] = e
     for (int i = 0; i < P; i += len) {
 #pragma unroll
       for (int j = 0; j < len / 2; ++j) {
-        const c32 w = tw[j * (P / len)];
-        const c32 u = a[i + j], v = a[i + j + len / 2];
-        const c32 t = mul(v, w);
+        const c32 u = a[i + j];
+        const c32 t = twiddle_mul<P>(a[i + j + len / 2], j * (P / len));
         a[i + j] = {u.x + t.x, u.y + t.y};
         a[i + j + len / 2] = {u.x - t.x, u.y - t.y};
       }
@@ -78,7 +109,7 @@ template <int P>
 __device__ __forceinline__ void batch_item(
     const BatchItem item, const BatchJob* __restrict__ jobs,
     const BatchPlane* __restrict__ planes, const c32* __restrict__ coef,
-    const c32* __restrict__ wfull, const c32* tw1, const c32* twr, int fx, int fy, int fz,
+    const c32* __restrict__ wfull, const c32* tw1, int fx, int fy, int fz,
     c32* S, c32* Ts, c32* __restrict__ E) {
   const int R = fy / P;
   const int t = threadIdx.x, col = t % COLS, q = t / COLS;
@@ -136,7 +167,7 @@ __device__ __forceinline__ void batch_item(
       const int r = ((sl - 16) % P + P) % P;
       a[r] = muladd(tcol[sl], tw1[sl * R + g1], a[r]);
     }
-    small_fft<P>(a, twr);
+    small_fft<P>(a);
     typedef float f2v __attribute__((ext_vector_type(2)));
 #pragma unroll
     for (int g2 = 0; g2 < P; ++g2)
@@ -149,8 +180,8 @@ template <int P>
 __global__ void __launch_bounds__(256) batch_kernel(
     const BatchJob* __restrict__ jobs, const BatchItem* __restrict__ items, int n_items,
     const BatchPlane* __restrict__ planes, const c32* __restrict__ coef,
-    const c32* __restrict__ wfull, const c32* __restrict__ tw1g, const c32* __restrict__ tw2g,
-    int fx, int fy, int fz, int chunk, unsigned int* __restrict__ counter,
+    const c32* __restrict__ wfull, const c32* __restrict__ tw1g, int fx, int fy, int fz,
+    int chunk, unsigned int* __restrict__ counter,
     c32* __restrict__ E) {
   __shared__ c32 S[MAXU * MAXU];
   __shared__ c32 Ts[32 * COLS];
@@ -160,9 +191,6 @@ __global__ void __launch_bounds__(256) batch_kernel(
   c32* tw1 = reinterpret_cast<c32*>(smem_raw);  // [32][R]
   const int t = threadIdx.x;
   for (int i = t; i < 32 * R; i += 256) tw1[i] = tw1g[i];
-  c32 twr[P];
-#pragma unroll
-  for (int k = 0; k < P; ++k) twr[k] = tw2g[k];
   for (;;) {
     __syncthreads();  // also: the previous grab's last item is consumed
     if (t == 0) s_item = (int)atomicAdd(counter, (unsigned)chunk);
@@ -172,7 +200,7 @@ __global__ void __launch_bounds__(256) batch_kernel(
     const int last = min(first + chunk, n_items);
     for (int it = first; it < last; ++it) {
       if (it > first) __syncthreads();  // the previous item's S and Ts are consumed
-      batch_item<P>(items[it], jobs, planes, coef, wfull, tw1, twr, fx, fy, fz, S, Ts, E);
+      batch_item<P>(items[it], jobs, planes, coef, wfull, tw1, fx, fy, fz, S, Ts, E);
     }
   }
 }
@@ -189,8 +217,7 @@ hipError_t launch_batch(const BatchArgs& a, hipStream_t s) {
     kern<<<a.grid, 256, lds, s>>>(a.jobs, a.items, a.n_items, a.planes,
                                   reinterpret_cast<const c32*>(a.coef),
                                   reinterpret_cast<const c32*>(a.wfull),
-                                  reinterpret_cast<const c32*>(a.tw1),
-                                  reinterpret_cast<const c32*>(a.tw2), a.fx, a.fy, a.fz,
+                                  reinterpret_cast<const c32*>(a.tw1), a.fx, a.fy, a.fz,
                                   a.chunk, a.counter, reinterpret_cast<c32*>(a.E));
   };
   switch (a.P) {

@@ -440,8 +440,43 @@ __global__ void __launch_bounds__(FT) idft_kernel(
 //     A[r] = sum_{v = r mod P} T[v] w^(v g1),
 //   so each (column, g1) costs 32 twiddle MACs plus one P-point FFT held in
 //   registers, and writes P outputs; each store writes 64 consecutive columns.
+// cos(2 pi r / 32) for r = 0..8: the first quadrant of the twiddles of every
+// radix P <= 32 (e^{2 pi i k / P} is entry k * 32 / P of the full circle).
+__device__ __forceinline__ double quarter_cos(int r) {
+  switch (r) {
+    case 0: return 1.0;
+    case 1: return 0.98078528040323044913;
+    case 2: return 0.92387953251128675613;
+    case 3: return 0.83146961230254523708;
+    case 4: return 0.70710678118654752440;
+    case 5: return 0.55557023301960222474;
+    case 6: return 0.38268343236508977173;
+    case 7: return 0.19509032201612826785;
+    default: return 0.0;
+  }
+}
+
+// v * e^{2 pi i k / P} for a k known at compile time once the caller's loops
+// are unrolled: no multiply for k = 0, a swap for the quarter turn, and the
+// constant folded in otherwise.
 template <typename T, int P>
-__device__ __forceinline__ void small_fft(cx<T>* a, const cx<T>* tw) {  // tw[k] = e^{2 pi i k/P}
+__device__ __forceinline__ cx<T> twiddle_mul(cx<T> v, int k) {
+  const int k32 = (k * (32 / P)) & 31;
+  if (k32 == 0) return v;
+  if (k32 == 8) return {-v.y, v.x};
+  if (k32 == 16) return {-v.x, -v.y};
+  if (k32 == 24) return {v.y, -v.x};
+  const int q = k32 >> 3, r = k32 & 7;
+  const T c0 = (T)quarter_cos(r), s0 = (T)quarter_cos(8 - r);
+  const T c = q == 0 ? c0 : (q == 1 ? -s0 : (q == 2 ? -c0 : s0));
+  const T sn = q == 0 ? s0 : (q == 1 ? c0 : (q == 2 ? -s0 : -c0));
+  return {v.x * c - v.y * sn, v.x * sn + v.y * c};
+}
+
+// In-register radix-2 FFT of length P with positive exponent:
+// a[g2] <- sum_r a[r] e^{2 pi i r g2 / P}.
+template <typename T, int P>
+__device__ __forceinline__ void small_fft(cx<T>* a) {
   // bit-reversal permutation
 #pragma unroll
   for (int i = 0; i < P; ++i) {
@@ -460,9 +495,8 @@ __device__ __forceinline__ void small_fft(cx<T>* a, const cx<T>* tw) {  // tw[k]
     for (int i = 0; i < P; i += len) {
 #pragma unroll
       for (int j = 0; j < len / 2; ++j) {
-        const cx<T> w = tw[j * (P / len)];
-        const cx<T> u = a[i + j], v = a[i + j + len / 2];
-        const cx<T> t = {v.x * w.x - v.y * w.y, v.x * w.y + v.y * w.x};
+        const cx<T> u = a[i + j];
+        const cx<T> t = twiddle_mul<T, P>(a[i + j + len / 2], j * (P / len));
         a[i + j] = {u.x + t.x, u.y + t.y};
         a[i + j + len / 2] = {u.x - t.x, u.y - t.y};
       }
@@ -486,13 +520,12 @@ __device__ __forceinline__ void store_nt(cx<double>* d, cx<double> v) {
 template <typename T, int P>
 __global__ void __launch_bounds__(256) idft_fft_kernel(
     const cx<T>* __restrict__ spec, const cx<T>* __restrict__ wx, const cx<T>* __restrict__ tw1g,
-    const cx<T>* __restrict__ tw2g, int U, int V, int fx, int fy, int fz, cx<T>* __restrict__ E) {
+    int U, int V, int fx, int fy, int fz, cx<T>* __restrict__ E) {
   extern __shared__ unsigned char smem_raw[];
   const int R = fy / P;
   cx<T>* S = reinterpret_cast<cx<T>*>(smem_raw);  // [V*U]
   cx<T>* Ts = S + U * V;                          // [32][FFT_COLS]
   cx<T>* tw1 = Ts + 32 * FFT_COLS;                // [32][R]: w^((s-16) g1)
-  cx<T>* tw2 = tw1 + 32 * R;                      // [P]: e^{2 pi i k / P}
   const int M = U * V;
   const int pc = blockIdx.y;
   const int plane = pc / 3, comp = pc % 3;
@@ -502,7 +535,6 @@ __global__ void __launch_bounds__(256) idft_fft_kernel(
   const cx<T>* src = spec + (long long)pc * M;
   for (int i = t; i < M; i += 256) S[i] = src[i];
   for (int i = t; i < 32 * R; i += 256) tw1[i] = tw1g[i];
-  for (int i = t; i < P; i += 256) tw2[i] = tw2g[i];
   __syncthreads();
   if (live) {
     const cx<T> w = wx[f], sh = wx[fx + f];
@@ -521,9 +553,6 @@ __global__ void __launch_bounds__(256) idft_fft_kernel(
 #pragma unroll
   for (int sl = 0; sl < 32; ++sl)
     if (sl >= lo && sl <= hi) tcol[sl] = Ts[sl * FFT_COLS + col];
-  cx<T> twr[P];
-#pragma unroll
-  for (int k = 0; k < P; ++k) twr[k] = tw2[k];
   cx<T>* dst = E + (((long long)comp * fz + plane) * fy) * fx + f;
   for (int g1 = q; g1 < R; g1 += 4) {
     cx<T> a[P];
@@ -537,7 +566,7 @@ __global__ void __launch_bounds__(256) idft_fft_kernel(
       a[r].x = fma(tcol[sl].x, w1.x, fma(-tcol[sl].y, w1.y, a[r].x));
       a[r].y = fma(tcol[sl].x, w1.y, fma(tcol[sl].y, w1.x, a[r].y));
     }
-    small_fft<T, P>(a, twr);
+    small_fft<T, P>(a);
 #pragma unroll
     for (int g2 = 0; g2 < P; ++g2) store_nt(dst + (long long)(g1 + R * g2) * fx, a[g2]);
   }
@@ -546,14 +575,12 @@ __global__ void __launch_bounds__(256) idft_fft_kernel(
 template <typename T>
 hipError_t launch_idft_fft(const SynthArgs& a, hipStream_t s) {
   const int P = a.fft_p, R = a.fy / P;
-  const size_t lds =
-      ((size_t)a.U * a.V + 32 * FFT_COLS + 32 * (size_t)R + (size_t)P) * sizeof(cx<T>);
+  const size_t lds = ((size_t)a.U * a.V + 32 * FFT_COLS + 32 * (size_t)R) * sizeof(cx<T>);
   dim3 grid((a.fx + FFT_COLS - 1) / FFT_COLS, a.fz * 3);
   const cx<T>* tw1 = reinterpret_cast<const cx<T>*>(a.fft_tw);
-  const cx<T>* tw2 = tw1 + 32 * (size_t)R;
   auto go = [&](auto kern) {
     kern<<<grid, 256, lds, s>>>(reinterpret_cast<const cx<T>*>(a.spec),
-                                reinterpret_cast<const cx<T>*>(a.twx), tw1, tw2, a.U, a.V, a.fx,
+                                reinterpret_cast<const cx<T>*>(a.twx), tw1, a.U, a.V, a.fx,
                                 a.fy, a.fz, reinterpret_cast<cx<T>*>(a.E));
   };
   switch (P) {

@@ -230,7 +230,7 @@ struct SynthArgs {
   bool mfma;               // inverse transform on the matrix cores
   int kp;
   int fft_p;               // > 0: factored transform with this P (fy = R * P)
-  const void* fft_tw;      // [32][R] then [P] twiddles of the factored transform
+  const void* fft_tw;      // [32][R] first-stage twiddles of the factored transform
   void* bmat;
   float* bscale;
   const void* amat;
@@ -268,7 +268,6 @@ struct BatchArgs {
   const void* coef;          // complex64 per job: p_inc, p_ref, p_trn [3][M] each, k sz_top, k sz_bot [M]
   const void* wfull;         // [fx]: e^{2 pi i k / fx}
   const void* tw1;           // [32][R]
-  const void* tw2;           // [P]
   int fx, fy, fz, P, grid;
   int chunk;                 // items per grab from the work counter
   unsigned int* counter;

@@ -232,7 +232,7 @@ def test_kernel_configurations_match_oracle(ctx, precision, cfg):
         sol.configure(**cfg)
         P = cfg.get("fft_radix", 0)
         eb = 16 if precision == "fp64" else 8
-        if P and (prob.U * prob.V + 32 * 64 + 32 * (grid.fy // P) + P) * eb > 64 * 1024:
+        if P and (prob.U * prob.V + 32 * 64 + 32 * (grid.fy // P)) * eb > 64 * 1024:
             # the factored transform's tables must fit in 64 KB of LDS
             with pytest.raises(ScwError) as e:
                 sol.synthesize(grid, precision)
