@@ -239,7 +239,9 @@ int scw_field(scw_ctx* ctx, const scw_problem* prob, const scw_grid* grid,
  * Every plane of `grid` must lie outside every job's sample (above z0 or
  * below its bottom surface): the field there follows from the exterior
  * coefficients alone (Eq. 9, then Eq. 10). Requirements: precision
- * SCW_FP32; U, V <= 31; grid->fy a power of two >= 2.
+ * SCW_FP32; U, V <= 31; grid->fy a power of two >= 2 with
+ * 256 * fy / 32 + 24 * max(U V) <= 48 KiB (the per-block tables of the
+ * factored y pass and the spectra of one plane; fy <= 2048 always fits).
  * `jobs` are borrowed: they must outlive the batch. E_dev receives
  * [njobs][3][fz][fy][fx] complex64, jobs in the order given.
  * scw_batch_launch enqueues the graph on `hip_stream` (NULL = default

@@ -588,7 +588,8 @@ int batch_set_shape(scw_batch* b, int P, int blocks_per_cu, int chunk) {
   if (!is_pow2(P) || P < 2 || P > 32 || P > fy || fy % P != 0)
     return fail(SCW_EINVAL, "batch radix must be a power of two in [2, min(32, fy)]");
   const int R = fy / P;
-  if (32 * (size_t)R * 8 > 64 * 1024) return fail(SCW_EINVAL, "batch radix too small for fy");
+  if ((32 * (size_t)R + 3 * (size_t)b->mmax) * 8 > 48 * 1024)
+    return fail(SCW_EINVAL, "batch radix too small for fy");
   if (blocks_per_cu < 1 || blocks_per_cu > 64) return fail(SCW_EINVAL, "blocks per CU out of range");
   if (chunk < 1 || chunk > 1024) return fail(SCW_EINVAL, "items per grab out of range");
   std::vector<float> wfull(2 * (size_t)b->grid.fx), tw(2 * (32 * (size_t)R));
@@ -636,6 +637,7 @@ BatchArgs batch_args(const scw_batch* b, void* E) {
   a.fz = b->grid.fz;
   a.P = b->P;
   a.grid = b->grid_blocks;
+  a.mmax = b->mmax;
   a.chunk = b->chunk;
   a.counter = b->d_counter.as<unsigned int>();
   a.E = E;
@@ -698,11 +700,12 @@ int scw_batch_plan(scw_ctx* ctx, scw_solution* const* jobs, int njobs, const scw
   });
   const int nft = (grid->fx + 63) / 64;
   std::vector<BatchItem> items;
-  items.reserve((size_t)njobs * fz * 3 * nft);
+  items.reserve((size_t)njobs * fz * nft);
   for (int j : order)
     for (int p = 0; p < fz; ++p)
-      for (int c = 0; c < 3; ++c)
-        for (int ft = 0; ft < nft; ++ft) items.push_back({j, p, c, ft});
+      for (int ft = 0; ft < nft; ++ft) items.push_back({j, p, ft, 0});
+  b->mmax = 1;
+  for (int j = 0; j < njobs; ++j) b->mmax = std::max(b->mmax, jt[j].U * jt[j].V);
   b->n_items = (int)items.size();
   if ((rc = upload(b->d_jobs, jt.data(), jt.size() * sizeof(BatchJob))) ||
       (rc = upload(b->d_items, items.data(), items.size() * sizeof(BatchItem))) ||

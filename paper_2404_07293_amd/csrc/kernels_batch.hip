@@ -3,13 +3,14 @@
 // samples (Eq. 9 then Eq. 10): the transmitted field below each sample, or
 // incident + reflected above it.
 //
-// Work item = (job, plane, component, 64-column tile). Items are sorted by
-// cost (largest truncation first) and drained from an atomic counter by a
-// persistent grid, `chunk` consecutive items per grab (items next to each
-// other in the sorted order cost about the same, and fewer grabs mean less
-// contention on the one counter); every block exits once the counter passes
-// the item count. Per item, in one block:
-//   spectrum  S[v][u] = exterior coefficients of the job at the plane (LDS)
+// Work item = (job, plane, 64-column tile), all three components. Items are
+// sorted by cost (largest truncation first) and drained from an atomic
+// counter by a persistent grid, `chunk` consecutive items per grab (items
+// next to each other in the sorted order cost about the same, and fewer grabs
+// mean less contention on the one counter); every block exits once the
+// counter passes the item count. Per item, in one block:
+//   spectra   S[c][v][u] = exterior coefficients of the job at the plane (LDS),
+//             one set of phase factors for the three components
 //   x pass    T[v][f] by Horner over u, into 32 zero-padded frequency slots
 //   y pass    factored transform, fy = R * P (as in the single-problem path);
 //             only the V occupied frequency slots of the 32 enter it
@@ -29,11 +30,16 @@ __device__ __forceinline__ c32 muladd(c32 a, c32 w, c32 c) {  // a*w + c
 __device__ __forceinline__ c32 mul(c32 a, c32 b) {
   return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
 }
-__device__ __forceinline__ c32 cexpi(float re, float im) {  // exp(i (re + i im))
-  float sn, cs;
-  sincosf(re, &sn, &cs);
-  const float m = expf(-im);
-  return {m * cs, m * sn};
+// exp(i (re + i im)): the angle reduced to [-pi, pi] by Cody and Waite's
+// two-constant subtraction of the nearest multiple of 2 pi, then the hardware
+// sine, cosine and exponential (absolute error near 1e-6 for the angles
+// k s_z dz of an exterior plane, a few tens of radians).
+__device__ __forceinline__ c32 cexpi(float re, float im) {
+  const float n = rintf(re * 0.159154943091895336f);
+  float r = fmaf(-n, 6.28318548202514648f, re);
+  r = fmaf(n, 1.74845553e-7f, r);
+  const float m = __expf(-im);
+  return {m * __cosf(r), m * __sinf(r)};
 }
 
 // cos(2 pi r / 32) for r = 0..8: the first quadrant of the twiddles of every
@@ -97,14 +103,16 @@ __device__ __forceinline__ void small_fft(c32* a) {
 }
 
 constexpr int COLS = 64;
-constexpr int MAXU = 31;
 
 __global__ void reset_counter(unsigned int* counter) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0u;
 }
 
-// One work item by the whole block. S and Ts are the block's LDS staging; the
-// caller synchronises before S is overwritten.
+// One work item by the whole block: the three field components of one (job,
+// plane, 64-column tile). The exterior phase factors of the plane are formed
+// once and applied to the three components' coefficients (Eq. 9), giving the
+// spectra S[3][M] in LDS; each component then takes the Horner x pass into Ts
+// and the factored y pass. The caller synchronises before S is overwritten.
 template <int P>
 __device__ __forceinline__ void batch_item(
     const BatchItem item, const BatchJob* __restrict__ jobs,
@@ -116,63 +124,70 @@ __device__ __forceinline__ void batch_item(
   const BatchJob jb = jobs[item.job];
   const BatchPlane pl = planes[(long long)item.job * fz + item.plane];
   const int U = jb.U, V = jb.V, M = U * V;
-  const int comp = item.comp;
-  // exterior spectrum of this job, plane and component (Eq. 9)
   const c32* cf = coef + jb.coef_offset;  // [3][M] p_inc, [3][M] p_ref, [3][M] p_trn, [M] k sz_top, [M] k sz_bot
   for (int m = t; m < M; m += 256) {
-    c32 val;
-    if (pl.kind == 0) {
+    if (pl.kind == 0) {  // above the sample: incident + reflected
       const c32 kz = cf[9 * M + m];
       const c32 gi = cexpi(kz.x * pl.dz, kz.y * pl.dz);
       const c32 gr = cexpi(-kz.x * pl.dz, -kz.y * pl.dz);
-      const c32 a = mul(cf[comp * M + m], gi), b = mul(cf[3 * M + comp * M + m], gr);
-      val = {a.x + b.x, a.y + b.y};
-    } else {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const c32 x = mul(cf[c * M + m], gi), y = mul(cf[(3 + c) * M + m], gr);
+        S[c * M + m] = {x.x + y.x, x.y + y.y};
+      }
+    } else {  // below: transmitted
       const c32 kz = cf[10 * M + m];
-      val = mul(cf[6 * M + comp * M + m], cexpi(kz.x * pl.dz, kz.y * pl.dz));
+      const c32 g = cexpi(kz.x * pl.dz, kz.y * pl.dz);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) S[c * M + m] = mul(cf[(6 + c) * M + m], g);
     }
-    S[m] = val;
   }
-  __syncthreads();
   const int f = item.ftile * COLS + col;
   const bool live = f < fx;
+  c32 w = {0.f, 0.f}, sh = {0.f, 0.f};
   if (live) {
-    const c32 w = wfull[f];
+    w = wfull[f];
     int sidx = (int)(((long long)(-(U / 2)) * f) % fx);
     if (sidx < 0) sidx += fx;
-    const c32 sh = wfull[sidx];
-    for (int vi = q; vi < V; vi += 4) {
-      const c32* row = S + vi * U;
-      c32 acc = row[U - 1];
-      for (int u = U - 2; u >= 0; --u) acc = muladd(acc, w, row[u]);
-      Ts[(vi - V / 2 + 16) * COLS + col] = mul(acc, sh);
-    }
+    sh = wfull[sidx];
   }
-  __syncthreads();
-  if (!live) return;
   // occupied slots 16 - V/2 .. 16 + V/2; the test is uniform over the block
   const int lo = 16 - V / 2, hi = 16 + V / 2;
-  c32 tcol[32];
-#pragma unroll
-  for (int sl = 0; sl < 32; ++sl)
-    if (sl >= lo && sl <= hi) tcol[sl] = Ts[sl * COLS + col];
-  c32* dst = E + ((((long long)item.job * 3 + comp) * fz + item.plane) * fy) * fx + f;
-  for (int g1 = q; g1 < R; g1 += 4) {
-    c32 a[P];
-#pragma unroll
-    for (int r = 0; r < P; ++r) a[r] = {0.f, 0.f};
-#pragma unroll
-    for (int sl = 0; sl < 32; ++sl) {
-      if (sl < lo || sl > hi) continue;
-      const int r = ((sl - 16) % P + P) % P;
-      a[r] = muladd(tcol[sl], tw1[sl * R + g1], a[r]);
+  for (int comp = 0; comp < 3; ++comp) {
+    __syncthreads();  // S complete (first component) / Ts consumed (later ones)
+    if (live) {
+      const c32* Sc = S + comp * M;
+      for (int vi = q; vi < V; vi += 4) {
+        const c32* row = Sc + vi * U;
+        c32 acc = row[U - 1];
+        for (int u = U - 2; u >= 0; --u) acc = muladd(acc, w, row[u]);
+        Ts[(vi - V / 2 + 16) * COLS + col] = mul(acc, sh);
+      }
     }
-    small_fft<P>(a);
-    typedef float f2v __attribute__((ext_vector_type(2)));
+    __syncthreads();
+    if (!live) continue;
+    c32 tcol[32];
 #pragma unroll
-    for (int g2 = 0; g2 < P; ++g2)
-      __builtin_nontemporal_store(f2v{a[g2].x, a[g2].y},
-                                  reinterpret_cast<f2v*>(dst + (long long)(g1 + R * g2) * fx));
+    for (int sl = 0; sl < 32; ++sl)
+      if (sl >= lo && sl <= hi) tcol[sl] = Ts[sl * COLS + col];
+    c32* dst = E + ((((long long)item.job * 3 + comp) * fz + item.plane) * fy) * fx + f;
+    for (int g1 = q; g1 < R; g1 += 4) {
+      c32 a[P];
+#pragma unroll
+      for (int r = 0; r < P; ++r) a[r] = {0.f, 0.f};
+#pragma unroll
+      for (int sl = 0; sl < 32; ++sl) {
+        if (sl < lo || sl > hi) continue;
+        const int r = ((sl - 16) % P + P) % P;
+        a[r] = muladd(tcol[sl], tw1[sl * R + g1], a[r]);
+      }
+      small_fft<P>(a);
+      typedef float f2v __attribute__((ext_vector_type(2)));
+#pragma unroll
+      for (int g2 = 0; g2 < P; ++g2)
+        __builtin_nontemporal_store(f2v{a[g2].x, a[g2].y},
+                                    reinterpret_cast<f2v*>(dst + (long long)(g1 + R * g2) * fx));
+    }
   }
 }
 
@@ -181,14 +196,13 @@ __global__ void __launch_bounds__(256) batch_kernel(
     const BatchJob* __restrict__ jobs, const BatchItem* __restrict__ items, int n_items,
     const BatchPlane* __restrict__ planes, const c32* __restrict__ coef,
     const c32* __restrict__ wfull, const c32* __restrict__ tw1g, int fx, int fy, int fz,
-    int chunk, unsigned int* __restrict__ counter,
-    c32* __restrict__ E) {
-  __shared__ c32 S[MAXU * MAXU];
+    int mmax, int chunk, unsigned int* __restrict__ counter, c32* __restrict__ E) {
   __shared__ c32 Ts[32 * COLS];
   __shared__ int s_item;
   extern __shared__ unsigned char smem_raw[];
   const int R = fy / P;
   c32* tw1 = reinterpret_cast<c32*>(smem_raw);  // [32][R]
+  c32* S = tw1 + 32 * R;                        // [3][mmax]
   const int t = threadIdx.x;
   for (int i = t; i < 32 * R; i += 256) tw1[i] = tw1g[i];
   for (;;) {
@@ -212,13 +226,13 @@ hipError_t launch_batch(const BatchArgs& a, hipStream_t s) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int R = a.fy / a.P;
-  const size_t lds = 32 * (size_t)R * sizeof(c32);
+  const size_t lds = (32 * (size_t)R + 3 * (size_t)a.mmax) * sizeof(c32);
   auto go = [&](auto kern) {
     kern<<<a.grid, 256, lds, s>>>(a.jobs, a.items, a.n_items, a.planes,
                                   reinterpret_cast<const c32*>(a.coef),
                                   reinterpret_cast<const c32*>(a.wfull),
                                   reinterpret_cast<const c32*>(a.tw1), a.fx, a.fy, a.fz,
-                                  a.chunk, a.counter, reinterpret_cast<c32*>(a.E));
+                                  a.mmax, a.chunk, a.counter, reinterpret_cast<c32*>(a.E));
   };
   switch (a.P) {
     case 2: go(batch_kernel<2>); break;

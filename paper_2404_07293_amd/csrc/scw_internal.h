@@ -253,8 +253,8 @@ struct BatchJob {
   int U, V;
   long long coef_offset;  // complex64 elements into the coefficient buffer
 };
-struct BatchItem {
-  int job, plane, comp, ftile;
+struct BatchItem {  // one (job, plane, 64-column tile), all three components
+  int job, plane, ftile, pad;
 };
 struct BatchPlane {
   int kind;   // 0 above the sample, 2 below it
@@ -269,6 +269,7 @@ struct BatchArgs {
   const void* wfull;         // [fx]: e^{2 pi i k / fx}
   const void* tw1;           // [32][R]
   int fx, fy, fz, P, grid;
+  int mmax;                  // largest U * V of the jobs (LDS spectra)
   int chunk;                 // items per grab from the work counter
   unsigned int* counter;
   void* E;                   // [njobs][3][fz][fy][fx] complex64
@@ -286,7 +287,7 @@ struct scw_solution {
 };
 struct scw_batch {
   scw::Context* ctx = nullptr;
-  int njobs = 0, n_items = 0, P = 0, grid_blocks = 0, cus = 0, chunk = 1;
+  int njobs = 0, n_items = 0, P = 0, grid_blocks = 0, cus = 0, chunk = 1, mmax = 1;
   scw_grid grid{};
   scw::DevBuf d_jobs, d_items, d_planes, d_coef, d_wfull, d_tw, d_counter;
   hipStream_t capture_stream = nullptr;

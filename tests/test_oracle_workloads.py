@@ -54,3 +54,37 @@ def test_working_golden_file_is_consistent():
     scale = np.abs(g["p_inc"]).max()
     assert np.abs(sx * pre[0] + sy * pre[1] - szt * pre[2]).max() < 1e-12 * scale
     assert np.abs(sx * ptr[0] + sy * ptr[1] + szt * ptr[2]).max() < 1e-12 * scale
+
+
+def test_large_family_reduced_equals_unreduced():
+    prob, _ = W.random_field_config("large", nz=2, U=7)
+    st = cwt.setup(prob)
+    a = cwt.solve(st, "unreduced")
+    b = cwt.solve(st, "reduced")
+    assert np.linalg.norm(a.p_trn - b.p_trn) < 1e-11 * np.linalg.norm(a.p_trn)
+    assert np.linalg.norm(a.p_ref - b.p_ref) < 1e-11 * np.linalg.norm(a.p_ref)
+
+
+def test_large_golden_file_is_consistent():
+    import os
+    g = np.load(os.path.join(os.path.dirname(__file__), "golden", "large_samples.npz"),
+                allow_pickle=False)
+    assert g["E"].shape == (3, 4096) and int(g["M"]) == 961
+    assert int(g["fx"]) == 512 and int(g["fz"]) == 256
+    assert np.all(np.isfinite(g["E"])) and np.abs(g["E"]).max() > 0
+    prob, _ = W.random_field_config("large", nz=1)
+    u, v = cwt.mode_indices(prob.U, prob.V)
+    sx, sy = cwt.spatial_frequencies(u, v, prob.X, prob.Y, prob.lam)
+    szt = cwt.s_z(1.0, sx, sy)
+    pin = g["p_inc"].reshape(3, -1)
+    pre = g["p_ref"].reshape(3, -1)
+    ptr = g["p_trn"].reshape(3, -1)
+    scale = np.abs(pin).max()
+    # transversality of the stored exterior waves (Eq. 14)
+    assert np.abs(sx * pre[0] + sy * pre[1] - szt * pre[2]).max() < 1e-12 * scale
+    assert np.abs(sx * ptr[0] + sy * ptr[1] + szt * ptr[2]).max() < 1e-12 * scale
+    # the absorbing sample takes energy: incident flux > reflected + transmitted
+    fi = cwt.z_flux(pin, cwt.h_coefficients(pin, sx, sy, szt))
+    fr = -cwt.z_flux(pre, cwt.h_coefficients(pre, sx, sy, -szt))
+    ft = cwt.z_flux(ptr, cwt.h_coefficients(ptr, sx, sy, szt))
+    assert fi > 0 and fr >= 0 and ft > 0 and fi - fr - ft > 0
