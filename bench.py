@@ -308,6 +308,7 @@ def surrogate_leg(ctx, torch, dev, stream, args):
     n_val = 128
     patches = np.stack([W.surrogate_patch(int(s)) for s in seeds])
     sur = Surrogate(ctx, max_batch=4096, seed=11)
+    sur.set_compute(bool(args.sur_bf16))
     x_all = sur.encode(patches)
     t_all = torch.as_tensor(targets).to(dev)
     n_tr = len(seeds) - n_val
@@ -351,6 +352,19 @@ def surrogate_leg(ctx, torch, dev, stream, args):
     s1.record(stream)
     torch.cuda.synchronize()
     ms_inf = s0.elapsed_time(s1) / n_inf
+    # the same trained parameters with the other arithmetic of the products
+    sur.set_compute(not args.sur_bf16)
+    other_err = err_on(xva, tva)
+    for _ in range(2):
+        sur.forward(xb, out=out)
+    torch.cuda.synchronize()
+    s0.record(stream)
+    for _ in range(n_inf):
+        sur.forward(xb, out=out)
+    s1.record(stream)
+    torch.cuda.synchronize()
+    ms_other = s0.elapsed_time(s1) / n_inf
+    sur.set_compute(bool(args.sur_bf16))
     # plain CWT on a few validation patches (host FP64 setup + synthesis of p_trn)
     t1 = time.perf_counter()
     ncwt = 8
@@ -367,12 +381,18 @@ def surrogate_leg(ctx, torch, dev, stream, args):
     log("surrogate: train %.1f s (%d steps), rel-L2 train %.3e val %.3e; %.0f patches/s "
         "vs CWT %.2f patches/s; checked batch rel-L2 %.3e fallback %s" % (
             t_train, steps, train_err, val_err, rate, cwt_rate, chk, fell))
-    rec = {"train_pairs": n_tr, "val_pairs": n_val, "train_steps": steps,
+    mode, other = ("bf16", "fp32") if args.sur_bf16 else ("fp32", "bf16")
+    log("surrogate %s products: val rel-L2 %.3e, %.2f ms per 4096; %s products with the same "
+        "parameters: val rel-L2 %.3e, %.2f ms" % (mode, val_err, ms_inf, other, other_err,
+                                                   ms_other))
+    rec = {"products": mode, "train_pairs": n_tr, "val_pairs": n_val, "train_steps": steps,
            "train_seconds": t_train, "rel_l2_train": train_err, "rel_l2_val": val_err,
            "infer_batch": 4096, "infer_ms": ms_inf, "patches_per_s": rate,
            "cwt_patches_per_s": cwt_rate, "speedup_vs_cwt": rate / cwt_rate,
            "checked_batch": 64, "check_rel_l2": chk, "fallback_fired": fell,
            "checked_seconds": t_checked, "cwt_equal_accuracy": equal,
+           "other_products": {"products": other, "rel_l2_val": other_err, "infer_ms": ms_other,
+                              "patches_per_s": 4096 / (ms_other * 1e-3)},
            "speedup_vs_cwt_equal_accuracy": (rate / equal["patches_per_s"]
                                              if equal and equal.get("patches_per_s") else None),
            "note": "fallback threshold 1e-2 rel-L2 on 8 CWT-solved patches of the batch"}
@@ -394,6 +414,8 @@ def main(argv=None):
     ap.add_argument("--sur-epochs", type=int, default=400)
     ap.add_argument("--sur-batch", type=int, default=32)
     ap.add_argument("--sur-lr", type=float, default=2e-3)
+    ap.add_argument("--sur-bf16", type=int, default=0,
+                    help="surrogate matrix products in bf16 on the matrix cores (1) or FP32 (0)")
     ap.add_argument("--batched", type=int, default=1,
                     help="also time the batched spectral sweep (4096 jobs, one launch)")
     ap.add_argument("--large", type=int, default=1,

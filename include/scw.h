@@ -266,7 +266,7 @@ int scw_batch_tune(scw_batch* batch, void* E_dev, void* hip_stream, int reps,
  * amplitude, 15 x 15 band (U = V = 15). Input patches are complex64
  * [B][8][32][32]; encoded inputs are float [B][16][32][32]; outputs are the
  * coefficients p_trn as complex64 [B][3][15][15] (component, then mode order
- * of Sec. 2.2). The network (FP32) is a lift to 32 channels, four Fourier
+ * of Sec. 2.2). The network is a lift to 32 channels, four Fourier
  * layers (truncated DFT2 on |ky| <= 8, 0 <= kx <= 8, per-mode complex 32 x 32
  * mixing, real inverse DFT2, plus a pointwise 32 x 32 map and bias, GELU
  * between layers) and a per-mode complex head on the 15 x 15 band.
@@ -280,6 +280,11 @@ int scw_sur_create(scw_ctx* ctx, int max_batch, unsigned long long seed, scw_sur
 void scw_sur_free(scw_sur* sur);
 int scw_sur_get_params(scw_sur* sur, float* host);
 int scw_sur_set_params(scw_sur* sur, const float* host);  /* also resets Adam state */
+/* Arithmetic of the network's matrix products: bf16 = 0 (default) computes
+ * them in FP32 on the vector units; bf16 = 1 rounds both operands of every
+ * product to bf16 and runs it on the matrix cores with FP32 accumulation
+ * (activations, parameters, Adam state and the elementwise steps stay FP32). */
+int scw_sur_set_compute(scw_sur* sur, int bf16);
 int scw_sur_encode(scw_sur* sur, const void* n_dev, int batch, void* x_dev, void* stream);
 int scw_sur_forward(scw_sur* sur, const void* x_dev, int batch, void* out_dev, void* stream);
 /* loss and, when grad_host is not NULL, dL/dparams (complex entries as

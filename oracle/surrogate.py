@@ -92,24 +92,43 @@ def gelu_grad(z):
     return 0.5 * (1.0 + erf(z / np.sqrt(2.0))) + z * np.exp(-0.5 * z * z) / np.sqrt(2 * np.pi)
 
 
-def forward(p, x, keep=False):
+def to_bf16(a):
+    """Round to bfloat16 (8-bit significand, round to nearest even) through
+    float32, as the library stages matrix-product operands; complex values
+    are rounded part by part. Returned in float64 / complex128."""
+    a = np.asarray(a)
+    if np.iscomplexobj(a):
+        return to_bf16(a.real) + 1j * to_bf16(a.imag)
+    bits = np.asarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    bits = (bits + 0x7FFF + ((bits >> 16) & 1)) & 0xFFFF0000
+    return bits.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def forward(p, x, keep=False, bf16=False):
     """x [B][16][32][32] -> out [B][3][15][15] complex; with keep, also the
-    intermediate values the backward pass needs."""
+    intermediate values the backward pass needs. With bf16, both operands of
+    every matrix product are rounded to bfloat16 first (the library's
+    matrix-core mode); sums, biases and GELU stay in float64."""
+    r = to_bf16 if bf16 else (lambda a: a)
     fy, fx, iy, ix, hy, hx = _dft_mats()
-    h = np.einsum("co,bcyx->boyx", p["lift_w"], x) + p["lift_b"][None, :, None, None]
+    h = np.einsum("co,bcyx->boyx", r(p["lift_w"]), r(x)) + p["lift_b"][None, :, None, None]
     cache = {"x": x, "h": [h], "z": [], "H": []}
     for k in range(N_LAYERS):
-        H = fy[None, None] @ (h @ fx[None, None])                   # [B][32][17][9]
-        G = np.einsum("bikm,iokm->bokm", H, p["spec%d" % k])
-        s = np.real((iy[None, None] @ G) @ ix[None, None])          # [B][32][32][32]
-        t = np.einsum("io,biyx->boyx", p["pw%d" % k], h) + p["pb%d" % k][None, :, None, None]
+        Hx = r(h) @ r(fx)[None, None]
+        H = r(fy)[None, None] @ r(Hx)                               # [B][32][17][9]
+        G = np.einsum("bikm,iokm->bokm", r(H), r(p["spec%d" % k]))
+        Gy = r(iy)[None, None] @ r(G)
+        s = np.real(r(Gy) @ r(ix)[None, None])                      # [B][32][32][32]
+        t = (np.einsum("io,biyx->boyx", r(p["pw%d" % k]), r(h))
+             + p["pb%d" % k][None, :, None, None])
         z = s + t
         cache["H"].append(H)
         cache["z"].append(z)
         h = gelu(z) if k < N_LAYERS - 1 else z
         cache["h"].append(h)
-    F = hy[None, None] @ (h @ hx[None, None])                       # [B][32][15][15]
-    out = np.einsum("bikm,ickm->bckm", F, p["head"])
+    Fx = r(h) @ r(hx)[None, None]
+    F = r(hy)[None, None] @ r(Fx)                                   # [B][32][15][15]
+    out = np.einsum("bikm,ickm->bckm", r(F), r(p["head"]))
     cache["F"] = F
     return (out, cache) if keep else out
 

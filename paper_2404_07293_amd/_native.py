@@ -113,6 +113,7 @@ SIGNATURES = {
     "scw_sur_free": (None, [ctypes.c_void_p]),
     "scw_sur_get_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "scw_sur_set_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "scw_sur_set_compute": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "scw_sur_encode": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                       ctypes.c_void_p, ctypes.c_void_p]),
     "scw_sur_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,

@@ -779,6 +779,11 @@ int scw_sur_set_params(scw_sur* s, const float* host) {
   if (!s || !host) return fail(SCW_EINVAL, "null argument");
   return sur_set_params(SUR(s), host);
 }
+int scw_sur_set_compute(scw_sur* s, int bf16) {
+  if (!s) return fail(SCW_EINVAL, "null argument");
+  if (bf16 != 0 && bf16 != 1) return fail(SCW_EINVAL, "bf16 must be 0 or 1");
+  return sur_set_compute(SUR(s), bf16 == 1);
+}
 int scw_sur_encode(scw_sur* s, const void* n_dev, int batch, void* x_dev, void* stream) {
   if (!s || !n_dev || !x_dev) return fail(SCW_EINVAL, "null argument");
   return sur_encode(SUR(s), n_dev, batch, x_dev, reinterpret_cast<hipStream_t>(stream));

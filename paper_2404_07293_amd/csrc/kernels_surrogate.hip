@@ -92,6 +92,117 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmOp op) {
     }
 }
 
+// The same product on the matrix cores with BF16 operands and FP32
+// accumulation: every operand element is rounded to bf16 (nearest even) as it
+// is staged in LDS. Block tile 64 x 64, four waves of 32 x 32, K steps of 16
+// (v_mfma_f32_32x32x16_bf16). A complex product takes four MFMAs per step:
+//   Re C += Re A Re B + (-Im A) Im B,   Im C += Re A Im B + Im A Re B,
+// with conjugation applied to the imaginary parts as they are staged.
+// MFMA lane layout (one wave, 32 x 32 x 16): lane l holds A[l % 32][8 (l / 32)
+// + 0..7] and B[8 (l / 32) + 0..7][l % 32]; accumulator r of lane l is
+// D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32].
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int BM = 64, BN = 64, BK = 16, LROW = 24;  // LDS row: 16 k + 8 pad (bf16)
+
+__global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmOp op) {
+  __shared__ __attribute__((aligned(16))) __bf16 As[2][BM * LROW];  // [re|im][row][k]
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[2][BN * LROW];  // [re|im][col][k]
+  const int b = blockIdx.y;
+  const int ntn = (op.N + BN - 1) / BN;
+  const int m0 = (blockIdx.x / ntn) * BM, n0 = (blockIdx.x % ntn) * BN;
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const float* A = op.A + (long long)b * op.a_bs * (op.a_cplx ? 2 : 1);
+  const float* B = op.B + (long long)b * op.b_bs * (op.b_cplx ? 2 : 1);
+  const float ca = op.conj_a ? -1.f : 1.f, cb = op.conj_b ? -1.f : 1.f;
+  floatx16 cre = {0}, cim = {0};
+  const int li = lane & 31, lk = 8 * (lane >> 5);
+  for (int k0 = 0; k0 < op.K; k0 += BK) {
+    // stage: 64 x 16 of A and 16 x 64 of B, four elements per thread each
+    // consecutive threads walk the operand's contiguous index where it has one
+    const bool a_kfast = op.a_cs == 1, b_kfast = op.b_rs == 1;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int i = t + 256 * e;
+      const int r = a_kfast ? i / BK : i % BM, k = a_kfast ? i % BK : i / BM;
+      const int gm = m0 + r, gk = k0 + k;
+      float re = 0.f, im = 0.f;
+      if (gm < op.M && gk < op.K) {
+        const long long o = (long long)gm * op.a_rs + (long long)gk * op.a_cs;
+        if (op.a_cplx) {
+          re = A[2 * o];
+          im = ca * A[2 * o + 1];
+        } else {
+          re = A[o];
+        }
+      }
+      As[0][r * LROW + k] = (__bf16)re;
+      As[1][r * LROW + k] = (__bf16)im;
+      const int c = b_kfast ? i / BK : i % BN, kb = b_kfast ? i % BK : i / BN;
+      const int gn = n0 + c, gkb = k0 + kb;
+      float bre = 0.f, bim = 0.f;
+      if (gn < op.N && gkb < op.K) {
+        const long long o = (long long)gkb * op.b_rs + (long long)gn * op.b_cs;
+        if (op.b_cplx) {
+          bre = B[2 * o];
+          bim = cb * B[2 * o + 1];
+        } else {
+          bre = B[o];
+        }
+      }
+      Bs[0][c * LROW + kb] = (__bf16)bre;
+      Bs[1][c * LROW + kb] = (__bf16)bim;
+    }
+    __syncthreads();
+    const u32x4 ar = *reinterpret_cast<const u32x4*>(&As[0][(wm + li) * LROW + lk]);
+    const u32x4 br = *reinterpret_cast<const u32x4*>(&Bs[0][(wn + li) * LROW + lk]);
+    cre = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, ar),
+                                                  __builtin_bit_cast(bf16x8, br), cre, 0, 0, 0);
+    if (op.b_cplx) {
+      const u32x4 bi = *reinterpret_cast<const u32x4*>(&Bs[1][(wn + li) * LROW + lk]);
+      cim = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, ar),
+                                                    __builtin_bit_cast(bf16x8, bi), cim, 0, 0, 0);
+      if (op.a_cplx) {
+        const u32x4 ai = *reinterpret_cast<const u32x4*>(&As[1][(wm + li) * LROW + lk]);
+        const u32x4 nai = ai ^ 0x80008000u;  // -Im A: flip every bf16 sign
+        cre = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, nai),
+                                                      __builtin_bit_cast(bf16x8, bi), cre, 0, 0, 0);
+        cim = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, ai),
+                                                      __builtin_bit_cast(bf16x8, br), cim, 0, 0, 0);
+      }
+    } else if (op.a_cplx) {
+      const u32x4 ai = *reinterpret_cast<const u32x4*>(&As[1][(wm + li) * LROW + lk]);
+      cim = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, ai),
+                                                    __builtin_bit_cast(bf16x8, br), cim, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  float* C = op.C + (long long)b * op.c_bs * (op.c_cplx ? 2 : 1);
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int gm = m0 + wm + 8 * (r / 4) + 4 * (lane >> 5) + (r % 4);
+    const int gn = n0 + wn + li;
+    if (gm >= op.M || gn >= op.N) continue;
+    const long long o = (long long)gm * op.c_rs + (long long)gn * op.c_cs;
+    if (op.c_cplx) {
+      float re = cre[r], im = cim[r];
+      if (op.beta != 0.f) {
+        re += op.beta * C[2 * o];
+        im += op.beta * C[2 * o + 1];
+      }
+      C[2 * o] = re;
+      C[2 * o + 1] = im;
+    } else {
+      float re = cre[r];
+      if (op.beta != 0.f) re += op.beta * C[o];
+      C[o] = re;
+    }
+  }
+}
+
 // x[b][c][p] += bias[c]
 __global__ void bias_add(float* x, const float* bias, int C, int P, long long total) {
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -202,7 +313,8 @@ inline unsigned blocks(long long n, int bs = 256) { return (unsigned)((n + bs - 
 
 hipError_t launch_gemm(const GemmOp& op, hipStream_t s) {
   if (op.M <= 0 || op.N <= 0 || op.K <= 0 || op.batch <= 0) return hipSuccess;
-  const long long tiles = (long long)((op.M + TM - 1) / TM) * ((op.N + TN - 1) / TN);
+  const int tm = op.bf16 ? BM : TM, tn = op.bf16 ? BN : TN;
+  const long long tiles = (long long)((op.M + tm - 1) / tm) * ((op.N + tn - 1) / tn);
   if (tiles > 0x7fffffffLL) return hipErrorInvalidValue;
   // the batch runs on grid.y in chunks of at most 65535
   for (int b0 = 0; b0 < op.batch; b0 += 65535) {
@@ -212,7 +324,10 @@ hipError_t launch_gemm(const GemmOp& op, hipStream_t s) {
     c.B += (long long)b0 * op.b_bs * (op.b_cplx ? 2 : 1);
     c.C += (long long)b0 * op.c_bs * (op.c_cplx ? 2 : 1);
     dim3 grid((unsigned)tiles, c.batch);
-    gemm_kernel<<<grid, 256, 0, s>>>(c);
+    if (op.bf16)
+      gemm_bf16_kernel<<<grid, 256, 0, s>>>(c);
+    else
+      gemm_kernel<<<grid, 256, 0, s>>>(c);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

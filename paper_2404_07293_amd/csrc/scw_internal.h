@@ -179,6 +179,7 @@ int sur_create(Context& ctx, int max_batch, unsigned long long seed, SurNet** ou
 void sur_free(SurNet* n);
 int sur_set_params(SurNet& n, const float* host);
 int sur_get_params(SurNet& n, float* host);
+int sur_set_compute(SurNet& n, bool bf16);
 int sur_encode(SurNet& n, const void* n_dev, int B, void* x_dev, hipStream_t s);
 int sur_forward(SurNet& n, const void* x_dev, int B, void* out_dev, hipStream_t s);
 int sur_loss_grad(SurNet& n, const void* x_dev, const void* tgt_dev, int B, double* loss,
@@ -323,6 +324,7 @@ struct GemmOp {
   float* C;
   long long c_rs, c_cs, c_bs;
   float beta;
+  int bf16;  // operands rounded to bf16, products on the matrix cores (FP32 accumulate)
 };
 hipError_t launch_gemm(const GemmOp& op, hipStream_t s);
 hipError_t sur_bias_add(float* x, const float* bias, int B, int C, int P, hipStream_t s);

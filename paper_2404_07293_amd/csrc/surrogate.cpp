@@ -4,7 +4,8 @@
 // Input: a complex-index patch of 8 layers x 32 x 32 voxels at pitch lambda/4
 // (lambda = 1), normal x-polarised plane wave, index 1 above and below. Output:
 // the transmitted plane-wave coefficients p_trn of Eq. 9 on the 15 x 15 band
-// (3 components, mode order of Sec. 2.2). Network (all FP32):
+// (3 components, mode order of Sec. 2.2). Network (FP32 storage; the matrix
+// products in FP32 on the vector units or in bf16 on the matrix cores):
 //   x (16 ch: Re and Im of each layer, normalised) -> lift to 32 channels ->
 //   4 x [ truncated DFT2 (ky in [-8,8], kx in [0,8]) -> per-mode complex 32x32
 //         mix -> real inverse DFT2  +  pointwise 32x32 map + bias -> GELU
@@ -52,6 +53,7 @@ struct SurNet {
   Context* ctx = nullptr;
   int max_batch = 0;
   int step = 0;
+  bool bf16 = false;  // GEMM operands in bf16 on the matrix cores (FP32 accumulate)
   DevBuf params, grads, adam_m, adam_v;
   DevBuf dft;  // fy, fx, iy, ix, hy, hx (complex64)
   long long o_fy, o_fx, o_iy, o_ix, o_hy, o_hx;
@@ -98,7 +100,10 @@ struct G {
     op.beta = beta;
     return *this;
   }
-  hipError_t run(hipStream_t s) { return launch_gemm(op, s); }
+  hipError_t run(hipStream_t s, bool bf16) {
+    op.bf16 = bf16 ? 1 : 0;
+    return launch_gemm(op, s);
+  }
 };
 
 #define SUR_HIP(x)                                                        \
@@ -153,7 +158,7 @@ int forward(SurNet& n, int B, hipStream_t s) {
   // lift
   SUR_HIP(G(W, NP, CIN, B).a(P + o.lw, false, 1, W, 0)
               .b(n.x.as<float>(), false, NP, 1, (long long)CIN * NP)
-              .c(n.h[0].as<float>(), false, NP, 1, act).run(s));
+              .c(n.h[0].as<float>(), false, NP, 1, act).run(s, n.bf16));
   SUR_HIP(sur_bias_add(n.h[0].as<float>(), P + o.lb, B, W, NP, s));
   for (int k = 0; k < NL; ++k) {
     const float* hin = n.h[k].as<float>();
@@ -161,36 +166,36 @@ int forward(SurNet& n, int B, hipStream_t s) {
     float* zk = (k < NL - 1) ? n.z[k].as<float>() : n.h[k + 1].as<float>();
     // Hx[b,i,y,kx] = sum_x h[b,i,y,x] fx[x,kx]
     SUR_HIP(G(B * NP, KXN, 32, 1).a(hin, false, 32, 1, 0).b(cx(n, n.o_fx), true, KXN, 1, 0)
-                .c(n.Hx.as<float>(), true, KXN, 1, 0).run(s));
+                .c(n.Hx.as<float>(), true, KXN, 1, 0).run(s, n.bf16));
     // H[b,i] = fy . Hx[b,i]
     SUR_HIP(G(KYN, KXN, 32, B * W).a(cx(n, n.o_fy), true, 32, 1, 0)
-                .b(n.Hx.as<float>(), true, KXN, 1, 32 * KXN).c(Hk, true, KXN, 1, NM).run(s));
+                .b(n.Hx.as<float>(), true, KXN, 1, 32 * KXN).c(Hk, true, KXN, 1, NM).run(s, n.bf16));
     // G[:, :, m] = H[:, :, m] W_k[:, :, m]
     SUR_HIP(G(B, W, W, NM).a(Hk, true, (long long)W * NM, NM, 1)
                 .b(P + o.spec(k), true, (long long)W * NM, NM, 1)
-                .c(n.G.as<float>(), true, (long long)W * NM, NM, 1).run(s));
+                .c(n.G.as<float>(), true, (long long)W * NM, NM, 1).run(s, n.bf16));
     // Gy[b,o] = iy . G[b,o]
     SUR_HIP(G(32, KXN, KYN, B * W).a(cx(n, n.o_iy), true, KYN, 1, 0)
                 .b(n.G.as<float>(), true, KXN, 1, NM).c(n.Gy.as<float>(), true, KXN, 1, 32 * KXN)
-                .run(s));
+                .run(s, n.bf16));
     // z = Re(Gy . ix)
     SUR_HIP(G(B * NP, 32, KXN, 1).a(n.Gy.as<float>(), true, KXN, 1, 0)
-                .b(cx(n, n.o_ix), true, 32, 1, 0).c(zk, false, 32, 1, 0).run(s));
+                .b(cx(n, n.o_ix), true, 32, 1, 0).c(zk, false, 32, 1, 0).run(s, n.bf16));
     // z[b] += P_k^T h[b] + c_k
     SUR_HIP(G(W, NP, W, B).a(P + o.pw(k), false, 1, W, 0).b(hin, false, NP, 1, act)
-                .c(zk, false, NP, 1, act, 1.f).run(s));
+                .c(zk, false, NP, 1, act, 1.f).run(s, n.bf16));
     SUR_HIP(sur_bias_add(zk, P + o.pb(k), B, W, NP, s));
     if (k < NL - 1) SUR_HIP(sur_gelu_fwd(zk, n.h[k + 1].as<float>(), (long long)B * act, s));
   }
   // head
   SUR_HIP(G(B * NP, HN, 32, 1).a(n.h[NL].as<float>(), false, 32, 1, 0)
-              .b(cx(n, n.o_hx), true, HN, 1, 0).c(n.Fx.as<float>(), true, HN, 1, 0).run(s));
+              .b(cx(n, n.o_hx), true, HN, 1, 0).c(n.Fx.as<float>(), true, HN, 1, 0).run(s, n.bf16));
   SUR_HIP(G(HN, HN, 32, B * W).a(cx(n, n.o_hy), true, 32, 1, 0)
               .b(n.Fx.as<float>(), true, HN, 1, 32 * HN).c(n.F.as<float>(), true, HN, 1, HM)
-              .run(s));
+              .run(s, n.bf16));
   SUR_HIP(G(B, OUT, W, HM).a(n.F.as<float>(), true, (long long)W * HM, HM, 1)
               .b(P + o.head(), true, (long long)OUT * HM, HM, 1)
-              .c(n.out.as<float>(), true, (long long)OUT * HM, HM, 1).run(s));
+              .c(n.out.as<float>(), true, (long long)OUT * HM, HM, 1).run(s, n.bf16));
   return SCW_OK;
 }
 
@@ -203,16 +208,16 @@ int backward(SurNet& n, int B, hipStream_t s) {
   // head
   SUR_HIP(G(W, OUT, B, HM).a(n.F.as<float>(), true, HM, (long long)W * HM, 1, true)
               .b(n.gout.as<float>(), true, (long long)OUT * HM, HM, 1)
-              .c(Gr + o.head(), true, (long long)OUT * HM, HM, 1).run(s));
+              .c(Gr + o.head(), true, (long long)OUT * HM, HM, 1).run(s, n.bf16));
   SUR_HIP(G(B, W, OUT, HM).a(n.gout.as<float>(), true, (long long)OUT * HM, HM, 1)
               .b(P + o.head(), true, HM, (long long)OUT * HM, 1, true)
-              .c(n.gF.as<float>(), true, (long long)W * HM, HM, 1).run(s));
+              .c(n.gF.as<float>(), true, (long long)W * HM, HM, 1).run(s, n.bf16));
   SUR_HIP(G(32, HN, HN, B * W).a(cx(n, n.o_hy), true, 1, 32, 0, true)
               .b(n.gF.as<float>(), true, HN, 1, HM).c(n.T1.as<float>(), true, HN, 1, 32 * HN)
-              .run(s));
+              .run(s, n.bf16));
   SUR_HIP(G(B * NP, 32, HN, 1).a(n.T1.as<float>(), true, HN, 1, 0)
               .b(cx(n, n.o_hx), true, 1, HN, 0, true).c(n.gh.as<float>(), false, 32, 1, 0)
-              .run(s));
+              .run(s, n.bf16));
   DevBuf* gh = &n.gh;
   DevBuf* gh2 = &n.gh2;
   for (int k = NL - 1; k >= 0; --k) {
@@ -221,35 +226,35 @@ int backward(SurNet& n, int B, hipStream_t s) {
     const float* hin = n.h[k].as<float>();
     // pointwise weight and bias
     SUR_HIP(G(W, W, NP, B).a(hin, false, NP, 1, act).b(gz, false, 1, NP, act)
-                .c(n.tmp.as<float>(), false, W, 1, W * W).run(s));
+                .c(n.tmp.as<float>(), false, W, 1, W * W).run(s, n.bf16));
     SUR_HIP(sur_sum_batch(n.tmp.as<float>(), Gr + o.pw(k), B, W * W, s));
     SUR_HIP(sur_bias_grad(gz, Gr + o.pb(k), B, W, NP, s));
     float* g2 = gh2->as<float>();
     SUR_HIP(G(W, NP, W, B).a(P + o.pw(k), false, W, 1, 0).b(gz, false, NP, 1, act)
-                .c(g2, false, NP, 1, act).run(s));
+                .c(g2, false, NP, 1, act).run(s, n.bf16));
     // spectral branch
     SUR_HIP(G(B * NP, KXN, 32, 1).a(gz, false, 32, 1, 0).b(cx(n, n.o_ix), true, 1, 32, 0, true)
-                .c(n.T2.as<float>(), true, KXN, 1, 0).run(s));
+                .c(n.T2.as<float>(), true, KXN, 1, 0).run(s, n.bf16));
     SUR_HIP(G(KYN, KXN, 32, B * W).a(cx(n, n.o_iy), true, 1, KYN, 0, true)
                 .b(n.T2.as<float>(), true, KXN, 1, 32 * KXN).c(n.gG.as<float>(), true, KXN, 1, NM)
-                .run(s));
+                .run(s, n.bf16));
     SUR_HIP(G(W, W, B, NM).a(n.Hk[k].as<float>(), true, NM, (long long)W * NM, 1, true)
                 .b(n.gG.as<float>(), true, (long long)W * NM, NM, 1)
-                .c(Gr + o.spec(k), true, (long long)W * NM, NM, 1).run(s));
+                .c(Gr + o.spec(k), true, (long long)W * NM, NM, 1).run(s, n.bf16));
     SUR_HIP(G(B, W, W, NM).a(n.gG.as<float>(), true, (long long)W * NM, NM, 1)
                 .b(P + o.spec(k), true, NM, (long long)W * NM, 1, true)
-                .c(n.gH.as<float>(), true, (long long)W * NM, NM, 1).run(s));
+                .c(n.gH.as<float>(), true, (long long)W * NM, NM, 1).run(s, n.bf16));
     SUR_HIP(G(32, KXN, KYN, B * W).a(cx(n, n.o_fy), true, 1, 32, 0, true)
                 .b(n.gH.as<float>(), true, KXN, 1, NM).c(n.T2.as<float>(), true, KXN, 1, 32 * KXN)
-                .run(s));
+                .run(s, n.bf16));
     SUR_HIP(G(B * NP, 32, KXN, 1).a(n.T2.as<float>(), true, KXN, 1, 0)
-                .b(cx(n, n.o_fx), true, 1, KXN, 0, true).c(g2, false, 32, 1, 0, 1.f).run(s));
+                .b(cx(n, n.o_fx), true, 1, KXN, 0, true).c(g2, false, 32, 1, 0, 1.f).run(s, n.bf16));
     std::swap(gh, gh2);
   }
   // lift
   SUR_HIP(G(CIN, W, NP, B).a(n.x.as<float>(), false, NP, 1, (long long)CIN * NP)
               .b(gh->as<float>(), false, 1, NP, act).c(n.tmp.as<float>(), false, W, 1, CIN * W)
-              .run(s));
+              .run(s, n.bf16));
   SUR_HIP(sur_sum_batch(n.tmp.as<float>(), Gr + o.lw, B, CIN * W, s));
   SUR_HIP(sur_bias_grad(gh->as<float>(), Gr + o.lb, B, W, NP, s));
   return SCW_OK;
@@ -320,6 +325,11 @@ int sur_set_params(SurNet& n, const float* host) {
   SCW_HIP(hipMemset(n.adam_m.p, 0, N_PARAMS * 4));
   SCW_HIP(hipMemset(n.adam_v.p, 0, N_PARAMS * 4));
   n.step = 0;
+  return SCW_OK;
+}
+
+int sur_set_compute(SurNet& n, bool bf16) {
+  n.bf16 = bf16;
   return SCW_OK;
 }
 

@@ -42,6 +42,11 @@ class Surrogate:
         assert p.size == self.n_params
         N.check(self.lib.scw_sur_set_params(self.handle, p.ctypes.data_as(ctypes.c_void_p)))
 
+    def set_compute(self, bf16):
+        """``scw_sur_set_compute``: bf16 matrix-core products (True) or FP32
+        vector products (False)."""
+        N.check(self.lib.scw_sur_set_compute(self.handle, 1 if bf16 else 0))
+
     def _stream(self, stream):
         import torch
         if stream is None:

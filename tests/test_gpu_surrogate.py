@@ -2,7 +2,15 @@
 itself pinned by finite differences): forward outputs and every parameter
 gradient, through the C ABI; plus training on CWT-generated pairs and the CWT
 fallback. FP32 kernels: forward and gradients agree with the FP64 reference to
-1e-5 and 1e-4 relative L2."""
+1e-5 and 1e-4 relative L2. BF16 matrix-core mode: two evaluations of the
+network on bf16-rounded operands do not agree element by element, because a
+relative change of 3e-7 in the values being rounded (FP32 against FP64
+accumulation) already moves the output of the rounded reference
+(oracle/surrogate.py, bf16=True) by about 0.6 of its own distance to the exact
+network (measured on the reference alone). The test therefore checks what is
+fixed: the GPU's distance to the exact network is that of the rounded
+reference within a factor 2, and the GPU is closer to the rounded reference
+than the rounded reference is to the exact network."""
 import numpy as np
 import pytest
 
@@ -58,6 +66,40 @@ def test_forward_matches_reference(ctx):
     err = rel(got, want)
     print("surrogate forward rel-L2 %.3e" % err)
     assert err <= 1e-5
+
+
+def test_bf16_forward_matches_rounded_reference(ctx):
+    torch = _torch()
+    sur, p, x, tgt, xd, td = _net_and_data(ctx)
+    sur.set_compute(True)
+    got = sur.forward(xd).cpu().numpy()
+    torch.cuda.synchronize()
+    want = S.forward(p, x, bf16=True)
+    exact = S.forward(p, x)
+    err, dist, ref = rel(got, want), rel(got, exact), rel(want, exact)
+    print("bf16 forward rel-L2 %.3e vs rounded reference, %.3e vs exact (reference %.3e)"
+          % (err, dist, ref))
+    assert 0.5 * ref <= dist <= 2.0 * ref
+    assert err <= ref
+    sur.set_compute(False)
+    back = sur.forward(xd).cpu().numpy()
+    torch.cuda.synchronize()
+    assert rel(back, exact) <= 1e-5
+
+
+def test_bf16_training_reduces_loss(ctx, small_set):
+    torch = _torch()
+    from paper_2404_07293_amd.surrogate import Surrogate
+    n, tg = small_set
+    sur = Surrogate(ctx, max_batch=24, seed=3)
+    sur.set_compute(True)
+    x = sur.encode(n)
+    t = torch.as_tensor(tg.astype(np.complex64)).cuda()
+    first = sur.train_step(x, t, lr=1e-3)
+    for _ in range(150):
+        last = sur.train_step(x, t, lr=1e-3)
+    print("bf16 training loss %.4f -> %.4f" % (first, last))
+    assert last < 0.5 * first
 
 
 def test_gradients_match_reference(ctx):

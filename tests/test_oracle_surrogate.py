@@ -63,3 +63,35 @@ def test_flatten_roundtrip():
     q = S.unflatten(S.flatten(p))
     for k in p:
         np.testing.assert_array_equal(q[k], p[k])
+
+
+def test_bf16_rounding_follows_the_format():
+    # bfloat16 keeps 8 significand bits: spacing 2^-7 on [1, 2)
+    one = 1.0
+    cases = [(one, one),
+             (one + 2.0 ** -9, one),                      # below half a step: down
+             (one + 2.0 ** -8, one),                      # tie: to even (1.0)
+             (one + 3 * 2.0 ** -8, one + 2.0 ** -6),      # tie: to even (1 + 2^-6)
+             (one + 2.0 ** -8 + 2.0 ** -20, one + 2.0 ** -7),  # above the tie: up
+             (-3.140625, -3.140625),                      # representable
+             (2.0 ** -130, 2.0 ** -130)]                  # subnormal, representable
+    for x, want in cases:
+        assert S.to_bf16(np.array([x]))[0] == want, (x, want)
+    z = S.to_bf16(np.array([1.0 + 2.0 ** -9 + 1j * (one + 2.0 ** -6)]))[0]
+    assert z == 1.0 + 1j * (one + 2.0 ** -6)
+    # relative rounding error never exceeds the unit roundoff u = 2^-8
+    rng = np.random.default_rng(1)
+    a = rng.standard_normal(10000) * 10.0 ** rng.uniform(-20, 20, 10000)
+    assert np.max(np.abs(S.to_bf16(a) - a) / np.abs(a)) <= 2.0 ** -8
+
+
+def test_bf16_forward_stays_near_the_exact_network():
+    # the rounded-operand network differs from the exact one by a few bf16
+    # unit roundoffs (u = 2^-8) along its chain of products
+    rng = np.random.default_rng(6)
+    p = S.init_params(2)
+    x = rng.standard_normal((1, S.CIN, S.N, S.N))
+    a = S.forward(p, x)
+    b = S.forward(p, x, bf16=True)
+    err = np.linalg.norm(a - b) / np.linalg.norm(a)
+    assert 2.0 ** -13 < err < 10 * 2.0 ** -8
