@@ -297,6 +297,244 @@ __global__ void adam(float* p, const float* g, float* m, float* v, long long n, 
   p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
+// ---------------------------------------------------------------- fused Fourier layer
+// The two halves of one Fourier layer around its per-mode mixing (which stays
+// a batched product over the patches, so that each mode's 32 x 32 weights are
+// read once per tile of patches rather than once per patch):
+//   forward  H[b][i][ky][kx] = sum_y fy[ky][y] sum_x h[b][i][y][x] fx[x][kx]
+//   inverse  z[b][o][y][x] = Re sum_kx (sum_ky iy[y][ky] G[b][o][ky][kx]) ix[kx][x]
+//                          + sum_i pw[i][o] h[b][i][y][x] + pb[o]
+//            h'[b][o] = GELU(z[b][o]) (or z itself after the last layer)
+// With BF16, both operands of every product are rounded to bf16 (nearest
+// even) first, as the matrix-core products of the unfused path round them;
+// sums stay FP32.
+constexpr int SN = 32, SKY = 17, SKX = 9, SNM = SKY * SKX, SW = 32;
+
+__device__ __forceinline__ float rbf(float x) {  // round to bf16, nearest even
+  unsigned u = __float_as_uint(x);
+  u = (u + 0x7FFFu + ((u >> 16) & 1u)) & 0xFFFF0000u;
+  return __uint_as_float(u);
+}
+template <bool BF16>
+__device__ __forceinline__ float op(float x) { return BF16 ? rbf(x) : x; }
+template <bool BF16>
+__device__ __forceinline__ f2 op(f2 x) { return BF16 ? f2{rbf(x.x), rbf(x.y)} : x; }
+
+// Truncated forward DFT of 8 channels of one patch per block:
+//   out[b][i][ky][kx] = sum_y fy[ky][y] sum_x h[b][i][y][x] fx[x][kx]
+// (KY x KX modes; fy is [KY][32], fx is [32][KX], both complex). Grid (4, B),
+// 256 threads. Thread (c, y) = (t / 32, t % 32) first transforms row y of
+// channel c in registers; the column transform then runs over (c, mode).
+template <bool BF16, int KY, int KX>
+__global__ void __launch_bounds__(256) fused_dft_fwd(const float* __restrict__ h,
+                                                     const f2* __restrict__ fy,
+                                                     const f2* __restrict__ fx,
+                                                     f2* __restrict__ H) {
+  __shared__ f2 hx[8][SN][KX];
+  __shared__ f2 fys[KY * SN], fxs[SN * KX];
+  const int t = threadIdx.x, b = blockIdx.y, c0 = blockIdx.x * 8;
+  for (int i = t; i < KY * SN; i += 256) fys[i] = op<BF16>(fy[i]);
+  for (int i = t; i < SN * KX; i += 256) fxs[i] = op<BF16>(fx[i]);
+  const int c = t >> 5, y = t & 31;
+  float row[SN];
+  const float4* src =
+      reinterpret_cast<const float4*>(h + (((long long)b * SW + c0 + c) * SN + y) * SN);
+#pragma unroll
+  for (int q = 0; q < SN / 4; ++q) {
+    const float4 v = src[q];
+    row[4 * q] = op<BF16>(v.x);
+    row[4 * q + 1] = op<BF16>(v.y);
+    row[4 * q + 2] = op<BF16>(v.z);
+    row[4 * q + 3] = op<BF16>(v.w);
+  }
+  __syncthreads();
+#pragma unroll 3
+  for (int kx = 0; kx < KX; ++kx) {
+    float re = 0.f, im = 0.f;
+#pragma unroll
+    for (int x = 0; x < SN; ++x) {
+      const f2 w = fxs[x * KX + kx];
+      re = fmaf(row[x], w.x, re);
+      im = fmaf(row[x], w.y, im);
+    }
+    hx[c][y][kx] = op<BF16>(f2{re, im});
+  }
+  __syncthreads();
+  constexpr int NMODE = KY * KX;
+  for (int i = t; i < 8 * NMODE; i += 256) {
+    const int cc = i / NMODE, m = i % NMODE, ky = m / KX, kx = m % KX;
+    float re = 0.f, im = 0.f;
+#pragma unroll 8
+    for (int yy = 0; yy < SN; ++yy) {
+      const f2 a = fys[ky * SN + yy], v = hx[cc][yy][kx];
+      re = fmaf(a.x, v.x, fmaf(-a.y, v.y, re));
+      im = fmaf(a.x, v.y, fmaf(a.y, v.x, im));
+    }
+    H[((long long)b * SW + c0 + cc) * NMODE + m] = f2{re, im};
+  }
+}
+
+__device__ __forceinline__ float gelu_fwd_f(float z) {
+  return 0.5f * z * (1.f + erff(z * 0.70710678118654752f));
+}
+
+// grid (B), 512 threads; thread t owns pixels 2t, 2t + 1 (row y = t / 16)
+constexpr int INV_T = 512, INV_PX = 2;
+template <bool BF16>
+__global__ void __launch_bounds__(INV_T) fused_dft_inv(
+    const f2* __restrict__ G, const float* __restrict__ h, const f2* __restrict__ iy,
+    const f2* __restrict__ ix, const float* __restrict__ pw, const float* __restrict__ pb,
+    float* __restrict__ z_out, float* __restrict__ h_out, int apply_gelu) {
+  __shared__ f2 gs[8][SNM];
+  __shared__ f2 gy[8][SN][SKX];
+  __shared__ f2 iys[SN * SKY], ixs[SKX * SN];
+  __shared__ float pws[SW * SW], pbs[SW];
+  const int t = threadIdx.x, b = blockIdx.x;
+  const int y = t / (SN / INV_PX), x0 = (t % (SN / INV_PX)) * INV_PX;
+  for (int i = t; i < SN * SKY; i += INV_T) iys[i] = op<BF16>(iy[i]);
+  for (int i = t; i < SKX * SN; i += INV_T) ixs[i] = op<BF16>(ix[i]);
+  for (int i = t; i < SW * SW; i += INV_T) pws[i] = op<BF16>(pw[i]);
+  if (t < SW) pbs[t] = pb[t];
+  // this thread's pixels of every input channel
+  float hr[SW][INV_PX];
+  const float* hb = h + (long long)b * SW * SN * SN;
+#pragma unroll
+  for (int i = 0; i < SW; ++i) {
+    const float2 v = *reinterpret_cast<const float2*>(hb + i * SN * SN + INV_PX * t);
+    hr[i][0] = op<BF16>(v.x);
+    hr[i][1] = op<BF16>(v.y);
+  }
+  const f2* gb = G + (long long)b * SW * SNM;
+  for (int og = 0; og < SW / 8; ++og) {
+    __syncthreads();  // gs / gy of the previous group consumed
+    for (int i = t; i < 8 * SNM; i += INV_T)
+      gs[i / SNM][i % SNM] = op<BF16>(gb[og * 8 * SNM + i]);
+    __syncthreads();
+    for (int i = t; i < 8 * SN * SKX; i += INV_T) {
+      const int c = i / (SN * SKX), yy = (i / SKX) % SN, kx = i % SKX;
+      float re = 0.f, im = 0.f;
+#pragma unroll
+      for (int ky = 0; ky < SKY; ++ky) {
+        const f2 a = iys[yy * SKY + ky], v = gs[c][ky * SKX + kx];
+        re = fmaf(a.x, v.x, fmaf(-a.y, v.y, re));
+        im = fmaf(a.x, v.y, fmaf(a.y, v.x, im));
+      }
+      gy[c][yy][kx] = op<BF16>(f2{re, im});
+    }
+    __syncthreads();
+#pragma unroll 2
+    for (int c = 0; c < 8; ++c) {
+      const int o = og * 8 + c;
+      float zz[INV_PX];
+#pragma unroll
+      for (int j = 0; j < INV_PX; ++j) zz[j] = pbs[o];
+#pragma unroll
+      for (int i = 0; i < SW; ++i) {
+        const float w = pws[i * SW + o];
+#pragma unroll
+        for (int j = 0; j < INV_PX; ++j) zz[j] = fmaf(w, hr[i][j], zz[j]);
+      }
+#pragma unroll
+      for (int kx = 0; kx < SKX; ++kx) {
+        const f2 g = gy[c][y][kx];
+#pragma unroll
+        for (int j = 0; j < INV_PX; ++j) {
+          const f2 e = ixs[kx * SN + x0 + j];
+          zz[j] = fmaf(g.x, e.x, fmaf(-g.y, e.y, zz[j]));
+        }
+      }
+      const long long off = ((long long)b * SW + o) * SN * SN + INV_PX * t;
+      if (z_out) *reinterpret_cast<float2*>(z_out + off) = make_float2(zz[0], zz[1]);
+      if (apply_gelu)
+        *reinterpret_cast<float2*>(h_out + off) = make_float2(gelu_fwd_f(zz[0]), gelu_fwd_f(zz[1]));
+      else if (h_out != z_out)
+        *reinterpret_cast<float2*>(h_out + off) = make_float2(zz[0], zz[1]);
+    }
+  }
+}
+
+// Per-mode channel mixing of a batch of patches:
+//   out[b][o][m] = sum_i A[b][i][m] W[i][o][m]     (complex; i < 32, o < O)
+// Block = MC consecutive modes x BT patches; the block's operands are staged
+// in LDS (modes contiguous, 32-byte runs of the m-fastest layouts), and every
+// thread writes MC consecutive modes of one (patch, output channel).
+template <bool BF16, int O, int MC, int BT>
+__global__ void __launch_bounds__(256) mode_mix(const f2* __restrict__ A,
+                                                const f2* __restrict__ Wt, int nmode, int B,
+                                                f2* __restrict__ out) {
+  __shared__ f2 as[BT][SW][MC];
+  __shared__ f2 ws[SW][MC][O];
+  const int t = threadIdx.x;
+  const int m0 = blockIdx.x * MC, b0 = blockIdx.y * BT;
+  for (int i = t; i < BT * SW * MC; i += 256) {
+    const int mm = i % MC, ch = (i / MC) % SW, bb = i / (MC * SW);
+    const int b = b0 + bb, m = m0 + mm;
+    as[bb][ch][mm] = (b < B && m < nmode) ? op<BF16>(A[((long long)b * SW + ch) * nmode + m])
+                                          : f2{0.f, 0.f};
+  }
+  for (int i = t; i < SW * O * MC; i += 256) {
+    const int mm = i % MC, o = (i / MC) % O, ch = i / (MC * O);
+    const int m = m0 + mm;
+    ws[ch][mm][o] = m < nmode ? op<BF16>(Wt[((long long)ch * O + o) * nmode + m]) : f2{0.f, 0.f};
+  }
+  __syncthreads();
+  for (int idx = t; idx < BT * O; idx += 256) {
+    const int bb = idx / O, o = idx % O, b = b0 + bb;
+    f2 acc[MC];
+#pragma unroll
+    for (int mm = 0; mm < MC; ++mm) acc[mm] = f2{0.f, 0.f};
+#pragma unroll 8
+    for (int ch = 0; ch < SW; ++ch) {
+#pragma unroll
+      for (int mm = 0; mm < MC; ++mm) {
+        const f2 a = as[bb][ch][mm], w = ws[ch][mm][o];
+        acc[mm].x = fmaf(a.x, w.x, fmaf(-a.y, w.y, acc[mm].x));
+        acc[mm].y = fmaf(a.x, w.y, fmaf(a.y, w.x, acc[mm].y));
+      }
+    }
+    if (b >= B) continue;
+    f2* dst = out + ((long long)b * O + o) * nmode + m0;
+#pragma unroll
+    for (int mm = 0; mm < MC; ++mm)
+      if (m0 + mm < nmode) dst[mm] = acc[mm];
+  }
+}
+
+// The lift: h[b][o][p] = sum_c lw[c][o] x[b][c][p] + lb[o], 16 input and 32
+// output channels; grid (B), 512 threads of 2 pixels each.
+template <bool BF16>
+__global__ void __launch_bounds__(512) lift_kernel(const float* __restrict__ x,
+                                                   const float* __restrict__ lw,
+                                                   const float* __restrict__ lb,
+                                                   float* __restrict__ h) {
+  constexpr int CI = 16;
+  __shared__ float lws[CI * SW], lbs[SW];
+  const int t = threadIdx.x, b = blockIdx.x;
+  for (int i = t; i < CI * SW; i += 512) lws[i] = op<BF16>(lw[i]);
+  if (t < SW) lbs[t] = lb[t];
+  float xr[CI][2];
+  const float* xb = x + (long long)b * CI * SN * SN;
+#pragma unroll
+  for (int c = 0; c < CI; ++c) {
+    const float2 v = *reinterpret_cast<const float2*>(xb + c * SN * SN + 2 * t);
+    xr[c][0] = op<BF16>(v.x);
+    xr[c][1] = op<BF16>(v.y);
+  }
+  __syncthreads();
+  float* hb = h + (long long)b * SW * SN * SN + 2 * t;
+#pragma unroll 4
+  for (int o = 0; o < SW; ++o) {
+    float a0 = lbs[o], a1 = lbs[o];
+#pragma unroll
+    for (int c = 0; c < CI; ++c) {
+      const float w = lws[c * SW + o];
+      a0 = fmaf(w, xr[c][0], a0);
+      a1 = fmaf(w, xr[c][1], a1);
+    }
+    *reinterpret_cast<float2*>(hb + o * SN * SN) = make_float2(a0, a1);
+  }
+}
+
 // complex64 index patches [B][8][32][32] -> channels [B][16][32][32]
 __global__ void encode(const float* n, float* x, long long per_layer_total, int P) {
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;  // over B*8*P
@@ -366,6 +604,57 @@ hipError_t sur_adam(float* p, const float* g, float* m, float* v, long long n, f
   const float b1 = 0.9f, b2 = 0.999f;
   const float c1 = 1.f - powf(b1, (float)t), c2 = 1.f - powf(b2, (float)t);
   adam<<<blocks(n), 256, 0, s>>>(p, g, m, v, n, lr, b1, b2, 1e-8f, c1, c2);
+  return hipGetLastError();
+}
+hipError_t sur_fused_dft_fwd(const float* h, const float* fy, const float* fx, float* H, int B,
+                            bool head, bool bf16, hipStream_t s) {
+  dim3 grid(SW / 8, B);
+  auto go = [&](auto kern) {
+    kern<<<grid, 256, 0, s>>>(h, reinterpret_cast<const f2*>(fy), reinterpret_cast<const f2*>(fx),
+                              reinterpret_cast<f2*>(H));
+  };
+  if (head) {  // the head's centred 15 x 15 band
+    if (bf16) go(fused_dft_fwd<true, 15, 15>);
+    else go(fused_dft_fwd<false, 15, 15>);
+  } else {  // a Fourier layer's 17 x 9 half plane
+    if (bf16) go(fused_dft_fwd<true, SKY, SKX>);
+    else go(fused_dft_fwd<false, SKY, SKX>);
+  }
+  return hipGetLastError();
+}
+hipError_t sur_fused_dft_inv(const float* G, const float* h, const float* iy, const float* ix,
+                             const float* pw, const float* pb, float* z_out, float* h_out,
+                             bool gelu, int B, bool bf16, hipStream_t s) {
+  auto go = [&](auto kern) {
+    kern<<<B, INV_T, 0, s>>>(reinterpret_cast<const f2*>(G), h, reinterpret_cast<const f2*>(iy),
+                           reinterpret_cast<const f2*>(ix), pw, pb, z_out, h_out, gelu ? 1 : 0);
+  };
+  if (bf16) go(fused_dft_inv<true>);
+  else go(fused_dft_inv<false>);
+  return hipGetLastError();
+}
+hipError_t sur_mode_mix(const float* A, const float* W, int nmode, int B, int O, float* out,
+                        bool bf16, hipStream_t s) {
+  const f2* a = reinterpret_cast<const f2*>(A);
+  const f2* w = reinterpret_cast<const f2*>(W);
+  f2* o = reinterpret_cast<f2*>(out);
+  if (O == SW) {  // LDS: 16 KB of patches + 32 KB of weights
+    dim3 grid((nmode + 3) / 4, (B + 15) / 16);
+    if (bf16) mode_mix<true, SW, 4, 16><<<grid, 256, 0, s>>>(a, w, nmode, B, o);
+    else mode_mix<false, SW, 4, 16><<<grid, 256, 0, s>>>(a, w, nmode, B, o);
+  } else if (O == 3) {  // LDS: 32 KB of patches + 3 KB of weights
+    dim3 grid((nmode + 3) / 4, (B + 31) / 32);
+    if (bf16) mode_mix<true, 3, 4, 32><<<grid, 256, 0, s>>>(a, w, nmode, B, o);
+    else mode_mix<false, 3, 4, 32><<<grid, 256, 0, s>>>(a, w, nmode, B, o);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+hipError_t sur_lift(const float* x, const float* lw, const float* lb, float* h, int B, bool bf16,
+                    hipStream_t s) {
+  if (bf16) lift_kernel<true><<<B, 512, 0, s>>>(x, lw, lb, h);
+  else lift_kernel<false><<<B, 512, 0, s>>>(x, lw, lb, h);
   return hipGetLastError();
 }
 hipError_t sur_encode(const float* n, float* x, int B, hipStream_t s) {

@@ -337,6 +337,22 @@ hipError_t sur_loss(const float* out, const float* tgt, long long n, float* sums
 hipError_t sur_adam(float* p, const float* g, float* m, float* v, long long n, float lr, int t,
                     hipStream_t s);
 hipError_t sur_encode(const float* n, float* x, int B, hipStream_t s);
+// One Fourier layer around its mixing: H = fy h fx per channel (17 x 9
+// modes, or the head's 15 x 15 with head), and z = Re(iy G ix) + pw^T h + pb
+// with h' = GELU(z) (gelu) or z; z_out may be null; h_out may equal z_out
+// when gelu is false.
+hipError_t sur_fused_dft_fwd(const float* h, const float* fy, const float* fx, float* H, int B,
+                            bool head, bool bf16, hipStream_t s);
+// out[b][o][m] = sum_i A[b][i][m] W[i][o][m] for 32 input channels and
+// O = 32 (a layer's mixing) or 3 (the head) output channels.
+hipError_t sur_mode_mix(const float* A, const float* W, int nmode, int B, int O, float* out,
+                        bool bf16, hipStream_t s);
+// h[b][o] = sum_c lw[c][o] x[b][c] + lb[o] over 16 input, 32 output channels.
+hipError_t sur_lift(const float* x, const float* lw, const float* lb, float* h, int B, bool bf16,
+                    hipStream_t s);
+hipError_t sur_fused_dft_inv(const float* G, const float* h, const float* iy, const float* ix,
+                             const float* pw, const float* pb, float* z_out, float* h_out,
+                             bool gelu, int B, bool bf16, hipStream_t s);
 hipError_t launch_idft_mfma(const MfmaArgs& a, int precision, hipStream_t s);
 // `ev`, when non-null, holds kNumStages + 1 events recorded around the stages.
 hipError_t launch_synthesis_fp64(const SynthArgs& a, hipStream_t s, hipEvent_t* ev);

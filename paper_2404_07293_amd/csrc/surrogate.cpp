@@ -57,7 +57,7 @@ struct SurNet {
   DevBuf params, grads, adam_m, adam_v;
   DevBuf dft;  // fy, fx, iy, ix, hy, hx (complex64)
   long long o_fy, o_fx, o_iy, o_ix, o_hy, o_hx;
-  DevBuf x, h[NL + 1], z[NL], Hk[NL], Hx, G, Gy, Fx, F, out, gout, gF, T1, gh, gh2, T2, gG, gH,
+  DevBuf x, h[NL + 1], z[NL], Hk[NL], G, F, out, gout, gF, T1, gh, gh2, T2, gG, gH,
       tmp, sums, enc_in;
 };
 
@@ -151,51 +151,30 @@ const float* cx(const SurNet& n, long long off) { return n.dft.as<float>() + 2 *
 
 // Forward pass; with keep, the per-layer H spectra and pre-activations stay
 // for the backward pass (h[] is always kept).
-int forward(SurNet& n, int B, hipStream_t s) {
+int forward(SurNet& n, const float* x, int B, hipStream_t s, bool keep) {
   const Off o;
   const float* P = n.params.as<float>();
-  const long long act = (long long)W * NP;
   // lift
-  SUR_HIP(G(W, NP, CIN, B).a(P + o.lw, false, 1, W, 0)
-              .b(n.x.as<float>(), false, NP, 1, (long long)CIN * NP)
-              .c(n.h[0].as<float>(), false, NP, 1, act).run(s, n.bf16));
-  SUR_HIP(sur_bias_add(n.h[0].as<float>(), P + o.lb, B, W, NP, s));
+  SUR_HIP(sur_lift(x, P + o.lw, P + o.lb, n.h[0].as<float>(), B, n.bf16, s));
   for (int k = 0; k < NL; ++k) {
     const float* hin = n.h[k].as<float>();
     float* Hk = n.Hk[k].as<float>();
-    float* zk = (k < NL - 1) ? n.z[k].as<float>() : n.h[k + 1].as<float>();
-    // Hx[b,i,y,kx] = sum_x h[b,i,y,x] fx[x,kx]
-    SUR_HIP(G(B * NP, KXN, 32, 1).a(hin, false, 32, 1, 0).b(cx(n, n.o_fx), true, KXN, 1, 0)
-                .c(n.Hx.as<float>(), true, KXN, 1, 0).run(s, n.bf16));
-    // H[b,i] = fy . Hx[b,i]
-    SUR_HIP(G(KYN, KXN, 32, B * W).a(cx(n, n.o_fy), true, 32, 1, 0)
-                .b(n.Hx.as<float>(), true, KXN, 1, 32 * KXN).c(Hk, true, KXN, 1, NM).run(s, n.bf16));
-    // G[:, :, m] = H[:, :, m] W_k[:, :, m]
-    SUR_HIP(G(B, W, W, NM).a(Hk, true, (long long)W * NM, NM, 1)
-                .b(P + o.spec(k), true, (long long)W * NM, NM, 1)
-                .c(n.G.as<float>(), true, (long long)W * NM, NM, 1).run(s, n.bf16));
-    // Gy[b,o] = iy . G[b,o]
-    SUR_HIP(G(32, KXN, KYN, B * W).a(cx(n, n.o_iy), true, KYN, 1, 0)
-                .b(n.G.as<float>(), true, KXN, 1, NM).c(n.Gy.as<float>(), true, KXN, 1, 32 * KXN)
-                .run(s, n.bf16));
-    // z = Re(Gy . ix)
-    SUR_HIP(G(B * NP, 32, KXN, 1).a(n.Gy.as<float>(), true, KXN, 1, 0)
-                .b(cx(n, n.o_ix), true, 32, 1, 0).c(zk, false, 32, 1, 0).run(s, n.bf16));
-    // z[b] += P_k^T h[b] + c_k
-    SUR_HIP(G(W, NP, W, B).a(P + o.pw(k), false, 1, W, 0).b(hin, false, NP, 1, act)
-                .c(zk, false, NP, 1, act, 1.f).run(s, n.bf16));
-    SUR_HIP(sur_bias_add(zk, P + o.pb(k), B, W, NP, s));
-    if (k < NL - 1) SUR_HIP(sur_gelu_fwd(zk, n.h[k + 1].as<float>(), (long long)B * act, s));
+    const bool last = k == NL - 1;
+    // H = fy h fx per channel (the layer's truncated forward transform)
+    SUR_HIP(sur_fused_dft_fwd(hin, cx(n, n.o_fy), cx(n, n.o_fx), Hk, B, false, n.bf16, s));
+    // G[:, :, m] = H[:, :, m] W_k[:, :, m], batched over the patches per mode
+    SUR_HIP(sur_mode_mix(Hk, P + o.spec(k), NM, B, W, n.G.as<float>(), n.bf16, s));
+    // z = Re(iy G ix) + P_k^T h + c_k; h' = GELU(z) except after the last layer
+    // the pre-activation is kept only for the backward pass
+    float* zk = last ? n.h[k + 1].as<float>() : (keep ? n.z[k].as<float>() : nullptr);
+    SUR_HIP(sur_fused_dft_inv(n.G.as<float>(), hin, cx(n, n.o_iy), cx(n, n.o_ix),
+                              P + o.pw(k), P + o.pb(k), zk, n.h[k + 1].as<float>(), !last, B,
+                              n.bf16, s));
   }
-  // head
-  SUR_HIP(G(B * NP, HN, 32, 1).a(n.h[NL].as<float>(), false, 32, 1, 0)
-              .b(cx(n, n.o_hx), true, HN, 1, 0).c(n.Fx.as<float>(), true, HN, 1, 0).run(s, n.bf16));
-  SUR_HIP(G(HN, HN, 32, B * W).a(cx(n, n.o_hy), true, 32, 1, 0)
-              .b(n.Fx.as<float>(), true, HN, 1, 32 * HN).c(n.F.as<float>(), true, HN, 1, HM)
-              .run(s, n.bf16));
-  SUR_HIP(G(B, OUT, W, HM).a(n.F.as<float>(), true, (long long)W * HM, HM, 1)
-              .b(P + o.head(), true, (long long)OUT * HM, HM, 1)
-              .c(n.out.as<float>(), true, (long long)OUT * HM, HM, 1).run(s, n.bf16));
+  // head: F = hy h hx per channel on the centred 15 x 15 band
+  SUR_HIP(sur_fused_dft_fwd(n.h[NL].as<float>(), cx(n, n.o_hy), cx(n, n.o_hx), n.F.as<float>(),
+                            B, true, n.bf16, s));
+  SUR_HIP(sur_mode_mix(n.F.as<float>(), P + o.head(), HM, B, OUT, n.out.as<float>(), n.bf16, s));
   return SCW_OK;
 }
 
@@ -282,8 +261,7 @@ int sur_create(Context& ctx, int max_batch, unsigned long long seed, SurNet** ou
   if ((rc = alloc(n->params, N_PARAMS)) || (rc = alloc(n->grads, N_PARAMS)) ||
       (rc = alloc(n->adam_m, N_PARAMS)) || (rc = alloc(n->adam_v, N_PARAMS)) ||
       (rc = alloc(n->x, B * CIN * NP)) || (rc = alloc(n->enc_in, B * 8 * NP * 2)) ||
-      (rc = alloc(n->Hx, B * W * 32 * KXN * 2)) || (rc = alloc(n->G, B * W * NM * 2)) ||
-      (rc = alloc(n->Gy, B * W * 32 * KXN * 2)) || (rc = alloc(n->Fx, B * W * 32 * HN * 2)) ||
+      (rc = alloc(n->G, B * W * NM * 2)) ||
       (rc = alloc(n->F, B * W * HM * 2)) || (rc = alloc(n->out, B * OUT * HM * 2)) ||
       (rc = alloc(n->gout, B * OUT * HM * 2)) || (rc = alloc(n->gF, B * W * HM * 2)) ||
       (rc = alloc(n->T1, B * W * 32 * HN * 2)) || (rc = alloc(n->gh, act)) ||
@@ -349,8 +327,7 @@ int sur_encode(SurNet& n, const void* n_dev, int B, void* x_dev, hipStream_t s) 
 int sur_forward(SurNet& n, const void* x_dev, int B, void* out_dev, hipStream_t s) {
   int rc = check_batch(n, B);
   if (rc) return rc;
-  SCW_HIP(hipMemcpyAsync(n.x.p, x_dev, (size_t)B * CIN * NP * 4, hipMemcpyDeviceToDevice, s));
-  if ((rc = forward(n, B, s))) return rc;
+  if ((rc = forward(n, reinterpret_cast<const float*>(x_dev), B, s, false))) return rc;
   SCW_HIP(hipMemcpyAsync(out_dev, n.out.p, (size_t)B * OUT * HM * 8, hipMemcpyDeviceToDevice, s));
   return SCW_OK;
 }
@@ -360,7 +337,7 @@ int sur_loss_grad(SurNet& n, const void* x_dev, const void* tgt_dev, int B, doub
   int rc = check_batch(n, B);
   if (rc) return rc;
   SCW_HIP(hipMemcpyAsync(n.x.p, x_dev, (size_t)B * CIN * NP * 4, hipMemcpyDeviceToDevice, s));
-  if ((rc = forward(n, B, s))) return rc;
+  if ((rc = forward(n, n.x.as<float>(), B, s, true))) return rc;
   SCW_HIP(sur_loss(n.out.as<float>(), reinterpret_cast<const float*>(tgt_dev),
                    (long long)B * OUT * HM, n.sums.as<float>(), n.gout.as<float>(), s));
   if ((rc = backward(n, B, s))) return rc;
@@ -402,7 +379,7 @@ int sur_infer_checked(Context& ctx, SurNet& n, const double* n_host, int B, int 
   for (size_t i = 0; i < f.size(); ++i) f[i] = (float)n_host[i];
   SCW_HIP(hipMemcpy(n.enc_in.p, f.data(), f.size() * 4, hipMemcpyHostToDevice));
   SCW_HIP(sur_encode(n.enc_in.as<float>(), n.x.as<float>(), B, nullptr));
-  if ((rc = forward(n, B, nullptr))) return rc;
+  if ((rc = forward(n, n.x.as<float>(), B, nullptr, false))) return rc;
   std::vector<float> o((size_t)B * OUT * HM * 2);
   SCW_HIP(hipMemcpy(o.data(), n.out.p, o.size() * 4, hipMemcpyDeviceToHost));
   for (size_t i = 0; i < o.size(); ++i) out_host[i] = o[i];
