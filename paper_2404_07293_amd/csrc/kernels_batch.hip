@@ -117,7 +117,7 @@ template <int P>
 __device__ __forceinline__ void batch_item(
     const BatchItem item, const BatchJob* __restrict__ jobs,
     const BatchPlane* __restrict__ planes, const c32* __restrict__ coef,
-    const c32* __restrict__ wfull, const c32* tw1, int fx, int fy, int fz,
+    const c32* __restrict__ wfull, const c32* tw1, const c32* wl, int fx, int fy, int fz,
     c32* S, c32* Ts, c32* __restrict__ E) {
   const int R = fy / P;
   const int t = threadIdx.x, col = t % COLS, q = t / COLS;
@@ -153,10 +153,34 @@ __device__ __forceinline__ void batch_item(
   }
   // occupied slots 16 - V/2 .. 16 + V/2; the test is uniform over the block
   const int lo = 16 - V / 2, hi = 16 + V / 2;
+  // x pass in factored form when the row is one tile of fx = 8 Rx columns:
+  // T[v][g1 + Rx g2] = sum_r e^{2 pi i r g2 / 8} A[r],
+  // A[r] = sum_{u = r mod 8} S[v][u] e^{2 pi i u g1 / fx}   (u from -U/2)
+  const bool xfact = wl != nullptr;
+  const int Rx = fx >> 3;
   for (int comp = 0; comp < 3; ++comp) {
     __syncthreads();  // S complete (first component) / Ts consumed (later ones)
-    if (live) {
-      const c32* Sc = S + comp * M;
+    const c32* Sc = S + comp * M;
+    if (xfact) {
+      if (t < V * Rx) {
+        const int v = t / Rx, g1 = t % Rx, h = U / 2;
+        const c32* row = Sc + v * U + h;  // row[u] for u in [-h, h]
+        c32 a[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          a[r] = {0.f, 0.f};
+          for (int u = -h + (((r + h) % 8) + 8) % 8; u <= h; u += 8) {
+            int k = (u * g1) % fx;
+            if (k < 0) k += fx;
+            a[r] = muladd(row[u], wl[k], a[r]);
+          }
+        }
+        small_fft<8>(a);
+        c32* trow = Ts + (v - V / 2 + 16) * COLS + g1;
+#pragma unroll
+        for (int g2 = 0; g2 < 8; ++g2) trow[Rx * g2] = a[g2];
+      }
+    } else if (live) {
       for (int vi = q; vi < V; vi += 4) {
         const c32* row = Sc + vi * U;
         c32 acc = row[U - 1];
@@ -198,6 +222,7 @@ __global__ void __launch_bounds__(256) batch_kernel(
     const c32* __restrict__ wfull, const c32* __restrict__ tw1g, int fx, int fy, int fz,
     int mmax, int chunk, unsigned int* __restrict__ counter, c32* __restrict__ E) {
   __shared__ c32 Ts[32 * COLS];
+  __shared__ c32 wls[COLS];
   __shared__ int s_item;
   extern __shared__ unsigned char smem_raw[];
   const int R = fy / P;
@@ -205,6 +230,9 @@ __global__ void __launch_bounds__(256) batch_kernel(
   c32* S = tw1 + 32 * R;                        // [3][mmax]
   const int t = threadIdx.x;
   for (int i = t; i < 32 * R; i += 256) tw1[i] = tw1g[i];
+  // the factored x pass needs fx = 8 Rx <= 64 columns, a power of two
+  const bool xfact = fx >= 8 && fx <= COLS && (fx & (fx - 1)) == 0;
+  if (xfact && t < fx) wls[t] = wfull[t];
   for (;;) {
     __syncthreads();  // also: the previous grab's last item is consumed
     if (t == 0) s_item = (int)atomicAdd(counter, (unsigned)chunk);
@@ -214,7 +242,8 @@ __global__ void __launch_bounds__(256) batch_kernel(
     const int last = min(first + chunk, n_items);
     for (int it = first; it < last; ++it) {
       if (it > first) __syncthreads();  // the previous item's S and Ts are consumed
-      batch_item<P>(items[it], jobs, planes, coef, wfull, tw1, fx, fy, fz, S, Ts, E);
+      batch_item<P>(items[it], jobs, planes, coef, wfull, tw1, xfact ? wls : nullptr, fx, fy, fz,
+                    S, Ts, E);
     }
   }
 }
