@@ -210,6 +210,18 @@ def large_leg(ctx, torch, dev, stream, args):
     return rec
 
 
+def roof_batch(jobs, grid, ms):
+    """Roofline of the batched launch: its algorithmic flops (the direct
+    separable transform, which the kernel's factored passes undercut) against
+    the FP32 peak, and its field writes against HBM."""
+    fl = sum(8.0 * 3 * grid.fz * (u * u * grid.fx + u * grid.fx * grid.fy) for _, _, u in jobs)
+    by = 8.0 * 3 * grid.fz * grid.fx * grid.fy * len(jobs)
+    t = ms * 1e-3
+    return {"bound": "alu", "achieved": fl / t / 1e12, "peak": FP32_PEAK / 1e12,
+            "unit": "TFLOP/s", "frac": fl / t / FP32_PEAK, "algorithmic_flops": fl,
+            "hbm_bytes": by, "hbm_frac": by / t / HBM_PEAK}
+
+
 def batched_sweep(ctx, torch, dev, stream, args):
     """The spectral sweep (256 wavenumbers x 16 patches of 32x32x16 voxels,
     truncation 9..25 per patch, 8 transmitted planes of 64x64) as one batched,
@@ -259,6 +271,9 @@ def batched_sweep(ctx, torch, dev, stream, args):
     rec = {"value": voxels / (ms * 1e-3), "ms_per_step": ms, "jobs": len(jobs),
            "voxels_per_step": voxels, "rel_l2_vs_oracle": err,
            "hbm_write_gbps": bytes_out / (ms * 1e-3) / 1e9,
+           # direct-sum work of the separable transform, 8 flops per complex MAC:
+           # per job, plane and component 8 (V U fx + V fx fy) over the grid
+           "roofline": roof_batch(jobs, grid, ms),
            "solved_jobs": len(solved), "setup_s": t_setup, "tuning": tune,
            "note": "one solve per patch; all 256 wavenumbers of a patch reuse it"}
     del Eb
@@ -269,6 +284,18 @@ def batched_sweep(ctx, torch, dev, stream, args):
 
 
 SUR_DATA = os.path.join(ROOT, "paper_2404_07293_amd", "data", "surrogate_targets.npz")
+
+
+def surrogate_flops_per_patch():
+    """Arithmetic of one inference (real flops; a complex MAC is 8, a real
+    by complex MAC 4): lift, four Fourier layers (row and column DFTs, per-mode
+    mixing, inverse DFTs with the real part only, pointwise map) and the head."""
+    n, w, cin, ky, kx, hk = 32, 32, 16, 17, 9, 15
+    lift = 2 * cin * w * n * n
+    layer = (w * n * kx * n * 4 + w * ky * kx * n * 8 + ky * kx * w * w * 8
+             + w * n * kx * ky * 8 + w * n * n * kx * 4 + 2 * w * w * n * n)
+    head = w * n * hk * n * 4 + w * hk * hk * n * 8 + hk * hk * w * 3 * 8
+    return lift + 4 * layer + head
 
 
 def cwt_equal_accuracy(ctx, patches, targets, err_goal):
@@ -389,6 +416,10 @@ def surrogate_leg(ctx, torch, dev, stream, args):
            "train_seconds": t_train, "rel_l2_train": train_err, "rel_l2_val": val_err,
            "infer_batch": 4096, "infer_ms": ms_inf, "patches_per_s": rate,
            "cwt_patches_per_s": cwt_rate, "speedup_vs_cwt": rate / cwt_rate,
+           "roofline": {"bound": "alu", "unit": "TFLOP/s", "peak": FP32_PEAK / 1e12,
+                        "achieved": surrogate_flops_per_patch() * rate / 1e12,
+                        "frac": surrogate_flops_per_patch() * rate / FP32_PEAK,
+                        "flops_per_patch": surrogate_flops_per_patch()},
            "checked_batch": 64, "check_rel_l2": chk, "fallback_fired": fell,
            "checked_seconds": t_checked, "cwt_equal_accuracy": equal,
            "other_products": {"products": other, "rel_l2_val": other_err, "infer_ms": ms_other,
