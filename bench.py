@@ -134,13 +134,29 @@ def cpu_baseline(prob_full, grid_full, n_layers=2, min_seconds=10.0):
     vox = grid.fx * grid.fy * grid.fz
     assert E.shape == (3, grid.fz, grid.fy, grid.fx)
     per = (t2 - t1) / reps
+    # the same synthesis on one thread (the paper's CPU column is single-threaded)
+    single = None
+    try:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            r1, t3 = 0, time.perf_counter()
+            while True:
+                cwt.synthesize(st, sol, grid)
+                r1 += 1
+                if time.perf_counter() - t3 >= min_seconds / 2:
+                    break
+            single = {"value": vox / ((time.perf_counter() - t3) / r1), "cores": 1,
+                      "reps": r1}
+    except ImportError:
+        pass
     return {"value": vox / per, "unit": "voxels/s", "cores": int(threads),
             "kind": "oracle",
             "sample": "first %d of %d layers (%d planes of %dx%d, M=%d): oracle synthesis "
                       "repeated %d times, %.3f s each; its FP64 setup+solve took %.1f s and "
                       "is not in value" % (
                           n_layers, prob_full.nz, grid.fz, grid.fx, grid.fy,
-                          prob.U * prob.V, reps, per, t1 - t0)}
+                          prob.U * prob.V, reps, per, t1 - t0),
+            "single_thread": single}
 
 
 def golden_error(E, prob, grid, per_component=False, path=GOLDEN):
@@ -539,6 +555,26 @@ def main(argv=None):
     roof["traffic"] = measured_traffic(dom, args.precision, args.workload)
     roof["algorithmic_bytes"] = by
     roof["algorithmic_flops"] = fl
+    # every stage, and the whole step, against the HBM roofline
+    per_stage = {}
+    # stages with a kernel in this configuration (the FP32 modal sum makes its
+    # own phase factors, and an interior grid has no exterior planes)
+    ran = [k for k in stages if not (k == "phase" and args.precision != "fp64")
+           and (model[k]["bytes"] or model[k]["flops"])]
+    for name in ran:
+        t_ms = stages[name]
+        b_, f_ = model[name]["bytes"], model[name]["flops"]
+        if t_ms <= 0:
+            continue
+        per_stage[name] = {"ms": t_ms, "gbps": b_ / (t_ms * 1e-3) / 1e9,
+                           "hbm_frac": b_ / (t_ms * 1e-3) / HBM_PEAK,
+                           "tflops": f_ / (t_ms * 1e-3) / 1e12}
+    tot_b = sum(model[k]["bytes"] for k in ran)
+    roof_stage = {"stages": per_stage,
+                  "step": {"ms": ms, "algorithmic_bytes": tot_b,
+                           "gbps": tot_b / (ms * 1e-3) / 1e9,
+                           "hbm_frac": tot_b / (ms * 1e-3) / HBM_PEAK,
+                           "roofline_ms": tot_b / HBM_PEAK * 1e3}}
 
     if args.copy_calibration:
         a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev)
@@ -562,6 +598,7 @@ def main(argv=None):
         "setup_s": info["setup_seconds"],
         "assembly_device_ms": info["assembly_device_ms"],
         "roofline": roof,
+        "roofline_by_stage": roof_stage,
         "tuning": tuning,
     }
     if args.variants:

@@ -178,3 +178,68 @@ def test_out_of_distribution_patch_triggers_fallback(ctx, small_set):
     out, fell, err = sur.infer_checked(odd, n_check=2, seed=0, tol=1e-2)
     print("out-of-distribution check rel-L2 %.3e, fallback %s" % (err, fell))
     assert fell and err > 1e-2
+
+
+def test_trained_network_beats_cwt_at_equal_accuracy(ctx):
+    """What the learned part gains: after a short training on CWT-generated
+    pairs, the surrogate's error on held-out patches is matched by plain CWT
+    only at some truncation U; the surrogate is then at least 100 times faster
+    per patch than that CWT run (setup and solve, which a transmitted
+    spectrum needs)."""
+    import os
+    import time
+    torch = _torch()
+    from paper_2404_07293_amd.surrogate import Surrogate
+    data = os.path.join(os.path.dirname(__file__), "..", "paper_2404_07293_amd", "data",
+                        "surrogate_targets.npz")
+    d = np.load(data, allow_pickle=False)
+    seeds, targets = d["seeds"], d["targets"]
+    n_tr, n_val = 512, 8
+    patches = np.stack([W.surrogate_patch(int(s)) for s in seeds[:n_tr + n_val]])
+    sur = Surrogate(ctx, max_batch=n_tr + n_val, seed=11)
+    x = sur.encode(patches)
+    t = torch.as_tensor(targets[:n_tr + n_val]).cuda()
+    rng = np.random.default_rng(3)
+    steps = 40 * (n_tr // 32)
+    k = 0
+    for ep in range(40):
+        perm = torch.as_tensor(rng.permutation(n_tr)).cuda()
+        for i in range(n_tr // 32):
+            idx = perm[i * 32:(i + 1) * 32]
+            lr = 0.5 * 2e-3 * (1 + np.cos(np.pi * k / steps))
+            sur.train_step(x[idx].contiguous(), t[idx].contiguous(), lr=lr, want_loss=False)
+            k += 1
+    xv = x[n_tr:].contiguous()
+    want = targets[n_tr:n_tr + n_val]
+    out = sur.forward(xv).cpu().numpy()
+    err_sur = rel(out, want)
+    # surrogate time per patch at a batch of 512
+    xb = x[:512].contiguous()
+    sur.forward(xb)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        sur.forward(xb)
+    torch.cuda.synchronize()
+    t_sur = (time.perf_counter() - t0) / (5 * 512)
+    # plain CWT at increasing truncation until it is as accurate
+    for U in range(1, 16, 2):
+        got = np.zeros(want.shape, np.complex128)
+        lo = 7 - U // 2
+        t0 = time.perf_counter()
+        for i in range(n_val):
+            p = W.surrogate_problem(patches[n_tr + i])
+            p = W.Problem(n=p.n, px=p.px, py=p.py, pz=p.pz, lam=p.lam, U=U, V=U, n_top=p.n_top,
+                          n_bot=p.n_bot, plane_wave=p.plane_wave)
+            sol = ctx.solve(p)
+            got[i, :, lo:lo + U, lo:lo + U] = sol.exterior()[2].reshape(3, U, U)
+            sol.free()
+        t_cwt = (time.perf_counter() - t0) / n_val
+        err_cwt = rel(got, want)
+        if err_cwt <= err_sur:
+            break
+    print("surrogate rel-L2 %.3e at %.2e s/patch; CWT U=%d rel-L2 %.3e at %.2e s/patch"
+          % (err_sur, t_sur, U, err_cwt, t_cwt))
+    assert err_sur < 0.1
+    assert err_cwt <= err_sur
+    assert t_cwt > 100 * t_sur
