@@ -476,7 +476,7 @@ def main(argv=None):
                     help="also run N plain 256 MiB device copies (PMC scale reference)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(requested --gpus %d)" % args.gpus, file=sys.stderr)
         return 2
 

@@ -136,7 +136,10 @@ typedef struct {
 const char* scw_last_error(void);
 
 /* Create a context on HIP device `hip_device`. It owns device workspaces and
- * a host thread pool of `host_threads` workers (<= 0: all hardware threads). */
+ * a host thread pool of `host_threads` workers (<= 0: all hardware threads).
+ * Calls that use one context, or one solution, must not overlap in time from
+ * several host threads: they update its plans, tuning cache and profiling
+ * state. Separate contexts are independent. */
 int scw_create(scw_ctx** out, int hip_device, int host_threads);
 void scw_destroy(scw_ctx* ctx);
 

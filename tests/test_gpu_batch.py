@@ -133,6 +133,46 @@ def test_sweep_job_matches_oracle(ctx):
     assert np.array_equal(got[0], got[1])
 
 
+def test_high_growth_sweep_job_matches_full_system(ctx):
+    """Patch 2 (U = 21, 16 layers) at 1000 cm^-1: the connection product's
+    growth exponent is about 42, where the paper's reduced route (K of Eq. 27)
+    degrades to a 2e-4 error against the full system in FP64 (stored with the
+    oracle values; well-conditioned stacks agree to 1e-13). The library's
+    default route eliminates from the bottom up with decaying exponentials
+    only; its coefficients must match the oracle's full boundary system
+    (tests/golden/sweep_hard_job.npz) to 1e-8 and its field to the precision
+    of the synthesis."""
+    import os
+    import paper_2404_07293_amd as P
+    torch = _torch()
+    g = np.load(os.path.join(os.path.dirname(__file__), "golden", "sweep_hard_job.npz"),
+                allow_pickle=False)
+    patch, U = int(g["patch"]), int(g["U"])
+    prob, grid = W.sweep_problem(float(g["nu"]), patch, U)
+    sol = ctx.solve(prob)
+    info = sol.info()
+    print("growth exponent %.1f; reduced route error in the oracle %.2e" % (
+        info["growth_exponent"], float(g["reduced_route_rel_l2"])))
+    assert info["growth_exponent"] > 30
+    assert float(g["reduced_route_rel_l2"]) > 1e-6  # the paper's route degrades here
+    p_trn = sol.exterior()[2].ravel()
+    assert rel_l2(p_trn, g["p_trn"]) <= 1e-8
+    want = g["E"]
+    e64 = sol.synthesize(grid, "fp64").cpu().numpy()
+    e32 = ctx.batch([sol], grid).launch().cpu().numpy()[0]
+    torch.cuda.synchronize()
+    print("rel-L2 fp64 %.3e, batched fp32 %.3e" % (rel_l2(e64, want), rel_l2(e32, want)))
+    assert rel_l2(e64, want) <= 1e-8
+    assert rel_l2(e32, want) <= FP32_TOL
+    # the paper's route, forced, reports the lost conditioning or misses
+    try:
+        bad = ctx.solve(prob, route="connection")
+    except P.ScwError as e:
+        assert e.code == -7  # SCW_EILLCOND
+    else:
+        assert rel_l2(bad.exterior()[2].ravel(), g["p_trn"]) > 1e-6
+
+
 def test_batch_rejects_interior_grid(ctx):
     import paper_2404_07293_amd as P
     sol = ctx.solve(small_job(9, 3, 3, 1.0))
