@@ -188,8 +188,8 @@ int scw_synthesize(scw_ctx* ctx, scw_solution* sol, const scw_grid* grid,
  *               cores; the only transform of the split modes), or
  *               SCW_XFORM_DIRECT (Horner in x and y);
  *   fft_radix   P of the factored y pass (2 .. 32, a power of two);
- *   tiles       row tiles per plane (DIRECT) or plane-components per block
- *               (MFMA); 0 = automatic.
+ *   tiles       row tiles per plane (DIRECT), plane-components per block
+ *               (MFMA) or columns per block, 32 or 64 (FFT); 0 = automatic.
  * A configuration the solution's shape or precision cannot run makes the
  * next scw_synthesize fail with SCW_EINVAL. cfg = NULL clears it. */
 typedef enum {

@@ -140,7 +140,7 @@ scw_synth_config resolve_config(const Context& ctx, const Solution& s, const scw
 
 bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
 
-// LDS bytes of the factored transform block for radix P.
+// LDS bytes of the factored transform block for radix P (64 columns).
 size_t fft_lds_bytes(const Solution& s, const scw_grid& g, int precision, int P) {
   const size_t eb = precision == SCW_FP64 ? 16 : 8;
   return ((size_t)s.U * s.V + 32 * 64 + 32 * (size_t)(g.fy / P)) * eb;
@@ -266,6 +266,8 @@ int build_plan(const Context& ctx, Solution& s, const scw_grid& g, int precision
   if (kind == SCW_XFORM_FFT && !fft_ok)
     return fail(SCW_EINVAL, "factored transform needs FP64/FP32, V <= 32, fy a power of two and "
                             "a radix P (2..32, power of two) whose tables fit in 64 KB of LDS");
+  if (kind == SCW_XFORM_FFT && cfg.tiles != 0 && cfg.tiles != 32 && cfg.tiles != 64)
+    return fail(SCW_EINVAL, "factored transform takes 32 or 64 columns per block (tiles)");
   if (kind == SCW_XFORM_MFMA && (precision == SCW_FP64 || s.V > 32))
     return fail(SCW_EINVAL, "matrix-core transform needs FP32 or split precision and V <= 32");
   pl.fft_p = 0;

@@ -504,8 +504,6 @@ __device__ __forceinline__ void small_fft(cx<T>* a) {
   }
 }
 
-constexpr int FFT_COLS = 64;
-
 // One non-temporal store of a whole complex value (the field is written once
 // and not read back by the synthesis).
 __device__ __forceinline__ void store_nt(cx<float>* d, cx<float> v) {
@@ -517,20 +515,24 @@ __device__ __forceinline__ void store_nt(cx<double>* d, cx<double> v) {
   __builtin_nontemporal_store(d2v{v.x, v.y}, reinterpret_cast<d2v*>(d));
 }
 
-template <typename T, int P>
+// COLS columns per block (64 or 32); the 256 threads are COLS columns x
+// 256 / COLS groups, each group taking every (256 / COLS)-th row in the x
+// pass and g1 value in the y pass.
+template <typename T, int P, int COLS>
 __global__ void __launch_bounds__(256) idft_fft_kernel(
     const cx<T>* __restrict__ spec, const cx<T>* __restrict__ wx, const cx<T>* __restrict__ tw1g,
     int U, int V, int fx, int fy, int fz, cx<T>* __restrict__ E) {
+  constexpr int NG = 256 / COLS;
   extern __shared__ unsigned char smem_raw[];
   const int R = fy / P;
   cx<T>* S = reinterpret_cast<cx<T>*>(smem_raw);  // [V*U]
-  cx<T>* Ts = S + U * V;                          // [32][FFT_COLS]
-  cx<T>* tw1 = Ts + 32 * FFT_COLS;                // [32][R]: w^((s-16) g1)
+  cx<T>* Ts = S + U * V;                          // [32][COLS]
+  cx<T>* tw1 = Ts + 32 * COLS;                    // [32][R]: w^((s-16) g1)
   const int M = U * V;
   const int pc = blockIdx.y;
   const int plane = pc / 3, comp = pc % 3;
-  const int t = threadIdx.x, col = t % FFT_COLS, q = t / FFT_COLS;
-  const int f = blockIdx.x * FFT_COLS + col;
+  const int t = threadIdx.x, col = t % COLS, q = t / COLS;
+  const int f = blockIdx.x * COLS + col;
   const bool live = f < fx;
   const cx<T>* src = spec + (long long)pc * M;
   for (int i = t; i < M; i += 256) S[i] = src[i];
@@ -538,11 +540,11 @@ __global__ void __launch_bounds__(256) idft_fft_kernel(
   __syncthreads();
   if (live) {
     const cx<T> w = wx[f], sh = wx[fx + f];
-    for (int vi = q; vi < V; vi += 4) {
+    for (int vi = q; vi < V; vi += NG) {
       const cx<T>* row = S + vi * U;
       cx<T> acc = row[U - 1];
       for (int u = U - 2; u >= 0; --u) acc = cmuladd(acc, w, row[u]);
-      Ts[(vi - V / 2 + 16) * FFT_COLS + col] = cmul(acc, sh);
+      Ts[(vi - V / 2 + 16) * COLS + col] = cmul(acc, sh);
     }
   }
   __syncthreads();
@@ -552,9 +554,9 @@ __global__ void __launch_bounds__(256) idft_fft_kernel(
   cx<T> tcol[32];
 #pragma unroll
   for (int sl = 0; sl < 32; ++sl)
-    if (sl >= lo && sl <= hi) tcol[sl] = Ts[sl * FFT_COLS + col];
+    if (sl >= lo && sl <= hi) tcol[sl] = Ts[sl * COLS + col];
   cx<T>* dst = E + (((long long)comp * fz + plane) * fy) * fx + f;
-  for (int g1 = q; g1 < R; g1 += 4) {
+  for (int g1 = q; g1 < R; g1 += NG) {
     cx<T> a[P];
 #pragma unroll
     for (int r = 0; r < P; ++r) a[r] = {0, 0};
@@ -575,23 +577,29 @@ __global__ void __launch_bounds__(256) idft_fft_kernel(
 template <typename T>
 hipError_t launch_idft_fft(const SynthArgs& a, hipStream_t s) {
   const int P = a.fft_p, R = a.fy / P;
-  const size_t lds = ((size_t)a.U * a.V + 32 * FFT_COLS + 32 * (size_t)R) * sizeof(cx<T>);
-  dim3 grid((a.fx + FFT_COLS - 1) / FFT_COLS, a.fz * 3);
+  const int cols = a.idft_gtiles == 32 ? 32 : 64;  // columns per block
+  const size_t lds = ((size_t)a.U * a.V + 32 * (size_t)cols + 32 * (size_t)R) * sizeof(cx<T>);
+  dim3 grid((a.fx + cols - 1) / cols, a.fz * 3);
   const cx<T>* tw1 = reinterpret_cast<const cx<T>*>(a.fft_tw);
   auto go = [&](auto kern) {
     kern<<<grid, 256, lds, s>>>(reinterpret_cast<const cx<T>*>(a.spec),
                                 reinterpret_cast<const cx<T>*>(a.twx), tw1, a.U, a.V, a.fx,
                                 a.fy, a.fz, reinterpret_cast<cx<T>*>(a.E));
   };
-  switch (P) {
-    case 2: go(idft_fft_kernel<T, 2>); break;
-    case 4: go(idft_fft_kernel<T, 4>); break;
-    case 8: go(idft_fft_kernel<T, 8>); break;
-    case 16: go(idft_fft_kernel<T, 16>); break;
-    case 32: go(idft_fft_kernel<T, 32>); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
+  auto radix = [&](auto cols_tag) -> hipError_t {
+    constexpr int C = decltype(cols_tag)::value;
+    switch (P) {
+      case 2: go(idft_fft_kernel<T, 2, C>); break;
+      case 4: go(idft_fft_kernel<T, 4, C>); break;
+      case 8: go(idft_fft_kernel<T, 8, C>); break;
+      case 16: go(idft_fft_kernel<T, 16, C>); break;
+      case 32: go(idft_fft_kernel<T, 32, C>); break;
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  };
+  return cols == 32 ? radix(std::integral_constant<int, 32>())
+                    : radix(std::integral_constant<int, 64>());
 }
 
 template <typename T>

@@ -140,7 +140,8 @@ int tune_synthesis(Context& c, Solution& s, const scw_grid& g, int precision, vo
     const bool split = precision == SCW_BF16X3 || precision == SCW_FP16X3;
     std::vector<scw_synth_config> cands;
     if (!split)
-      for (int P = 2; P <= 32; P *= 2) cands.push_back({best.modal_rows, SCW_XFORM_FFT, P, 0});
+      for (int P = 2; P <= 32; P *= 2)
+        for (int cols : {64, 32}) cands.push_back({best.modal_rows, SCW_XFORM_FFT, P, cols});
     if (precision != SCW_FP64)
       for (int t : {0, 1, 2, 4, 8}) cands.push_back({best.modal_rows, SCW_XFORM_MFMA, 0, t});
     if (!split)

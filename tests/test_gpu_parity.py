@@ -211,6 +211,8 @@ def test_split_precision_matches_oracle(ctx, precision, tol):
 # several plane tilings, direct Horner sums at several row tilings) and the
 # modal-sum row blockings
 CONFIGS = ([("fp32", dict(transform="fft", fft_radix=p)) for p in (2, 4, 8, 16, 32)]
+           + [("fp32", dict(transform="fft", fft_radix=p, tiles=32)) for p in (4, 16)]
+           + [("fp64", dict(transform="fft", fft_radix=8, tiles=32))]
            + [("fp32", dict(transform="mfma", tiles=t)) for t in (0, 1, 3)]
            + [("fp32", dict(transform="direct", tiles=t)) for t in (0, 1, 5)]
            + [("fp32", dict(modal_rows=r)) for r in (2, 4, 8, 16)]
@@ -253,7 +255,8 @@ def test_unsupported_configurations_are_rejected(ctx):
            ("fp16x3", dict(transform="direct")),
            ("fp32", dict(modal_rows=3)),
            ("fp32", dict(transform="fft", fft_radix=64)),
-           ("fp32", dict(transform="fft", fft_radix=12))]
+           ("fp32", dict(transform="fft", fft_radix=12)),
+           ("fp32", dict(transform="fft", fft_radix=8, tiles=48))]
     for precision, cfg in bad:
         sol.configure(**cfg)
         with pytest.raises(ScwError) as e:
@@ -289,3 +292,35 @@ def test_autotuner_keeps_a_correct_and_no_slower_configuration(ctx, precision):
     got = sol2.synthesize(grid, precision)
     torch.cuda.synchronize()
     assert torch.equal(got, sol.synthesize(grid, precision))
+
+
+def test_synthesis_replays_in_a_captured_graph(ctx):
+    """scw_synthesize enqueues plain kernels on the caller's stream, so once
+    its plan exists (first call) it can be captured in a HIP graph: every
+    replay, with eager work on the GPU in between, gives the eager field."""
+    torch = _torch()
+    prob = ragged_problem(seed=21, nx=8, ny=10, U=7, V=9)
+    grid = W.Grid(fx=48, fy=64, fz=10, z_begin=-0.3, z_end=1.0)
+    sol = ctx.solve(prob)
+    eager = sol.synthesize(grid, "fp32")
+    torch.cuda.synchronize()
+    want = eager.clone()
+    out = torch.zeros_like(eager)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        sol.synthesize(grid, "fp32", out=out)  # plan already built: no host sync
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    out.zero_()
+    with torch.cuda.graph(g):
+        sol.synthesize(grid, "fp32", out=out)
+    for k in range(3):
+        out.zero_()
+        junk = torch.randn(1 << 20, device="cuda") * k  # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, want), k
+        del junk
