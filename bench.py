@@ -177,6 +177,38 @@ def golden_error(E, prob, grid, per_component=False, path=GOLDEN):
     return float(np.linalg.norm(got - want) / np.linalg.norm(want))
 
 
+SPHERE_GOLDEN = os.path.join(ROOT, "tests", "golden", "sphere_samples.npz")
+
+
+def sphere_leg(ctx, torch, dev, stream, args):
+    """The 16x16x4 sphere (M = 25) on its 32^3 grid in FP64, the correctness
+    workload: time per synthesis and rel-L2 against the oracle's full-system
+    field at the stored sample voxels."""
+    import workloads as W
+    prob, grid = W.sphere_config()
+    sol = ctx.solve(prob)
+    E = torch.empty((3, grid.fz, grid.fy, grid.fx), dtype=torch.complex128, device=dev)
+    for _ in range(3):
+        sol.synthesize(grid, "fp64", out=E, stream=stream)
+    torch.cuda.synchronize()
+    s0 = torch.cuda.Event(enable_timing=True)
+    s1 = torch.cuda.Event(enable_timing=True)
+    s0.record(stream)
+    for _ in range(args.steps):
+        sol.synthesize(grid, "fp64", out=E, stream=stream)
+    s1.record(stream)
+    torch.cuda.synchronize()
+    ms = s0.elapsed_time(s1) / args.steps
+    err = golden_error(E, prob, grid, path=SPHERE_GOLDEN)
+    vox = grid.fx * grid.fy * grid.fz
+    log("sphere fp64: %.4f ms per synthesis, %.3e voxels/s, rel-L2 %s" % (
+        ms, vox / (ms * 1e-3), err))
+    sol.free()
+    return {"workload": "sphere: 16x16x4 sample, M=25, 32x32x32 grid", "dtype": "f64",
+            "value": vox / (ms * 1e-3), "ms_per_step": ms, "rel_l2_vs_oracle": err,
+            "note": "launch-latency bound; correctness workload"}
+
+
 SWEEP_GOLDEN = os.path.join(ROOT, "tests", "golden", "sweep_job.npz")
 LARGE_GOLDEN = os.path.join(ROOT, "tests", "golden", "large_samples.npz")
 
@@ -617,6 +649,8 @@ def main(argv=None):
             log("%s: ms/step %.4f rel-L2 %s" % (prec, vms, variants[prec]["rel_l2_vs_oracle"]))
             del Ev
         out["variants"] = variants
+    if args.workload == "working":
+        out.setdefault("variants", {})["sphere_fp64"] = sphere_leg(ctx, torch, dev, stream, args)
     if args.large and args.workload == "working":
         out.setdefault("variants", {})["large"] = large_leg(ctx, torch, dev, stream, args)
     if args.surrogate and os.path.exists(SUR_DATA):
