@@ -600,11 +600,11 @@ int batch_set_shape(scw_batch* b, int P, int blocks_per_cu, int chunk) {
     wfull[2 * k] = (float)w.real();
     wfull[2 * k + 1] = (float)w.imag();
   }
-  for (int sl = 0; sl < 32; ++sl)
-    for (int g1 = 0; g1 < R; ++g1) {
+  for (int g1 = 0; g1 < R; ++g1)  // [R][32]: e^{2 pi i (slot - 16) g1 / fy}
+    for (int sl = 0; sl < 32; ++sl) {
       const zc w = twiddle_inv((long long)(sl - 16) * g1, fy);
-      tw[2 * ((size_t)sl * R + g1)] = (float)w.real();
-      tw[2 * ((size_t)sl * R + g1) + 1] = (float)w.imag();
+      tw[2 * ((size_t)g1 * 32 + sl)] = (float)w.real();
+      tw[2 * ((size_t)g1 * 32 + sl) + 1] = (float)w.imag();
     }
   int rc;
   if ((rc = upload(b->d_wfull, wfull.data(), wfull.size() * 4)) ||

@@ -11,9 +11,11 @@
 // counter passes the item count. Per item, in one block:
 //   spectra   S[c][v][u] = exterior coefficients of the job at the plane (LDS),
 //             one set of phase factors for the three components
-//   x pass    T[v][f] by Horner over u, into 32 zero-padded frequency slots
-//   y pass    factored transform, fy = R * P (as in the single-problem path);
-//             only the V occupied frequency slots of the 32 enter it
+//   x pass    T[v][f] into 32 frequency slots: factored (one 8-point register
+//             FFT per row and column group) when fx is a power of two up to
+//             64, else by Horner over u per column
+//   y pass    factored transform, fy = R * P (as in the single-problem path),
+//             over the rounds of P slots that hold the V occupied ones
 #include <hip/hip_runtime.h>
 
 #include "scw_internal.h"
@@ -111,8 +113,9 @@ __global__ void reset_counter(unsigned int* counter) {
 // One work item by the whole block: the three field components of one (job,
 // plane, 64-column tile). The exterior phase factors of the plane are formed
 // once and applied to the three components' coefficients (Eq. 9), giving the
-// spectra S[3][M] in LDS; each component then takes the Horner x pass into Ts
-// and the factored y pass. The caller synchronises before S is overwritten.
+// spectra S[3][M] in LDS; each component then takes the x pass into Ts and
+// the factored y pass. The caller synchronises before S and Ts are
+// overwritten.
 template <int P>
 __device__ __forceinline__ void batch_item(
     const BatchItem item, const BatchJob* __restrict__ jobs,
@@ -151,28 +154,47 @@ __device__ __forceinline__ void batch_item(
     if (sidx < 0) sidx += fx;
     sh = wfull[sidx];
   }
-  // occupied slots 16 - V/2 .. 16 + V/2; the test is uniform over the block
+  // Occupied frequency slots lo..hi (slot = v + 16). The y pass runs over
+  // rounds of P slots that start at multiples of P, so that a slot's residue
+  // (slot - 16) mod P is fixed at compile time; the slots of those rounds
+  // outside lo..hi hold zeros, written once per item (the x pass writes only
+  // lo..hi, and the rows are the same for the three components).
   const int lo = 16 - V / 2, hi = 16 + V / 2;
+  const int s_begin = (lo / P) * P, s_end = (hi / P + 1) * P;
+  {
+    const int zl = lo - s_begin, zh = s_end - hi - 1;
+    for (int i = t; i < (zl + zh) * COLS; i += 256) {
+      const int rr = i / COLS, cc = i % COLS;
+      const int sl = rr < zl ? s_begin + rr : hi + 1 + (rr - zl);
+      Ts[sl * COLS + cc] = {0.f, 0.f};
+    }
+  }
   // x pass in factored form when the row is one tile of fx = 8 Rx columns:
   // T[v][g1 + Rx g2] = sum_r e^{2 pi i r g2 / 8} A[r],
-  // A[r] = sum_{u = r mod 8} S[v][u] e^{2 pi i u g1 / fx}   (u from -U/2)
+  // A[r] = sum_{u = r mod 8} S[v][u] e^{2 pi i u g1 / fx}   (u from -U/2).
+  // u runs in rounds of 8 from a multiple of 8, so u mod 8 is the position in
+  // the round; terms outside [-U/2, U/2] are skipped by a predicate.
   const bool xfact = wl != nullptr;
   const int Rx = fx >> 3;
+  const int h = U / 2, u0 = -((h + 7) & ~7), xmask = fx - 1;
   for (int comp = 0; comp < 3; ++comp) {
     __syncthreads();  // S complete (first component) / Ts consumed (later ones)
     const c32* Sc = S + comp * M;
     if (xfact) {
       if (t < V * Rx) {
-        const int v = t / Rx, g1 = t % Rx, h = U / 2;
+        const int v = t / Rx, g1 = t % Rx;
         const c32* row = Sc + v * U + h;  // row[u] for u in [-h, h]
         c32 a[8];
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
-          a[r] = {0.f, 0.f};
-          for (int u = -h + (((r + h) % 8) + 8) % 8; u <= h; u += 8) {
-            int k = (u * g1) % fx;
-            if (k < 0) k += fx;
-            a[r] = muladd(row[u], wl[k], a[r]);
+        for (int r = 0; r < 8; ++r) a[r] = {0.f, 0.f};
+        for (int ub = u0; ub <= h; ub += 8) {
+          const int kb = ub * g1;
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            const int u = ub + i;
+            c32 sv = {0.f, 0.f};
+            if ((unsigned)(u + h) <= (unsigned)(2 * h)) sv = row[u];
+            a[i] = muladd(sv, wl[(kb + i * g1) & xmask], a[i]);
           }
         }
         small_fft<8>(a);
@@ -190,27 +212,26 @@ __device__ __forceinline__ void batch_item(
     }
     __syncthreads();
     if (!live) continue;
-    c32 tcol[32];
-#pragma unroll
-    for (int sl = 0; sl < 32; ++sl)
-      if (sl >= lo && sl <= hi) tcol[sl] = Ts[sl * COLS + col];
+    const c32* tc = Ts + col;
     c32* dst = E + ((((long long)item.job * 3 + comp) * fz + item.plane) * fy) * fx + f;
     for (int g1 = q; g1 < R; g1 += 4) {
+      const c32* tw = tw1 + g1 * 32;  // e^{2 pi i (slot - 16) g1 / fy}
       c32 a[P];
 #pragma unroll
       for (int r = 0; r < P; ++r) a[r] = {0.f, 0.f};
+      for (int s0 = s_begin; s0 < s_end; s0 += P) {
 #pragma unroll
-      for (int sl = 0; sl < 32; ++sl) {
-        if (sl < lo || sl > hi) continue;
-        const int r = ((sl - 16) % P + P) % P;
-        a[r] = muladd(tcol[sl], tw1[sl * R + g1], a[r]);
+        for (int i = 0; i < P; ++i) {
+          const int r = (i - 16) & (P - 1);
+          a[r] = muladd(tc[(s0 + i) * COLS], tw[s0 + i], a[r]);
+        }
       }
       small_fft<P>(a);
       typedef float f2v __attribute__((ext_vector_type(2)));
+      f2v* d = reinterpret_cast<f2v*>(dst + (long long)g1 * fx);  // row g1 + R g2
+      const long long step = (long long)R * fx;
 #pragma unroll
-      for (int g2 = 0; g2 < P; ++g2)
-        __builtin_nontemporal_store(f2v{a[g2].x, a[g2].y},
-                                    reinterpret_cast<f2v*>(dst + (long long)(g1 + R * g2) * fx));
+      for (int g2 = 0; g2 < P; ++g2) __builtin_nontemporal_store(f2v{a[g2].x, a[g2].y}, d + g2 * step);
     }
   }
 }
@@ -226,7 +247,7 @@ __global__ void __launch_bounds__(256) batch_kernel(
   __shared__ int s_item;
   extern __shared__ unsigned char smem_raw[];
   const int R = fy / P;
-  c32* tw1 = reinterpret_cast<c32*>(smem_raw);  // [32][R]
+  c32* tw1 = reinterpret_cast<c32*>(smem_raw);  // [R][32]
   c32* S = tw1 + 32 * R;                        // [3][mmax]
   const int t = threadIdx.x;
   for (int i = t; i < 32 * R; i += 256) tw1[i] = tw1g[i];
