@@ -276,9 +276,9 @@ int build_plan(const Context& ctx, Solution& s, const scw_grid& g, int precision
     const int R = g.fy / P;
     pl.fft_p = P;
     std::vector<zc> tw(32 * (size_t)R);
-    for (int sl = 0; sl < 32; ++sl)
-      for (int g1 = 0; g1 < R; ++g1)
-        tw[(size_t)sl * R + g1] = twiddle_inv((long long)(sl - 16) * g1, g.fy);
+    for (int g1 = 0; g1 < R; ++g1)  // [R][32]: e^{2 pi i (slot - 16) g1 / fy}
+      for (int sl = 0; sl < 32; ++sl)
+        tw[(size_t)g1 * 32 + sl] = twiddle_inv((long long)(sl - 16) * g1, g.fy);
     if (precision == SCW_FP64) {
       std::vector<double> b;
       pack(tw, b);

@@ -517,7 +517,10 @@ __device__ __forceinline__ void store_nt(cx<double>* d, cx<double> v) {
 
 // COLS columns per block (64 or 32); the 256 threads are COLS columns x
 // 256 / COLS groups, each group taking every (256 / COLS)-th row in the x
-// pass and g1 value in the y pass.
+// pass and g1 value in the y pass. The occupied frequency slots are lo..hi
+// (slot = v + 16); the y pass runs over rounds of P slots that start at
+// multiples of P, so that a slot's residue (slot - 16) mod P is fixed at
+// compile time, and the slots of those rounds outside lo..hi hold zeros.
 template <typename T, int P, int COLS>
 __global__ void __launch_bounds__(256) idft_fft_kernel(
     const cx<T>* __restrict__ spec, const cx<T>* __restrict__ wx, const cx<T>* __restrict__ tw1g,
@@ -527,16 +530,26 @@ __global__ void __launch_bounds__(256) idft_fft_kernel(
   const int R = fy / P;
   cx<T>* S = reinterpret_cast<cx<T>*>(smem_raw);  // [V*U]
   cx<T>* Ts = S + U * V;                          // [32][COLS]
-  cx<T>* tw1 = Ts + 32 * COLS;                    // [32][R]: w^((s-16) g1)
+  cx<T>* tw1 = Ts + 32 * COLS;                    // [R][32]: w^((s-16) g1)
   const int M = U * V;
   const int pc = blockIdx.y;
   const int plane = pc / 3, comp = pc % 3;
   const int t = threadIdx.x, col = t % COLS, q = t / COLS;
   const int f = blockIdx.x * COLS + col;
   const bool live = f < fx;
+  const int lo = 16 - V / 2, hi = 16 + V / 2;
+  const int s_begin = (lo / P) * P, s_end = (hi / P + 1) * P;
   const cx<T>* src = spec + (long long)pc * M;
   for (int i = t; i < M; i += 256) S[i] = src[i];
   for (int i = t; i < 32 * R; i += 256) tw1[i] = tw1g[i];
+  {
+    const int zl = lo - s_begin, zh = s_end - hi - 1;
+    for (int i = t; i < (zl + zh) * COLS; i += 256) {
+      const int rr = i / COLS, cc = i % COLS;
+      const int sl = rr < zl ? s_begin + rr : hi + 1 + (rr - zl);
+      Ts[sl * COLS + cc] = {0, 0};
+    }
+  }
   __syncthreads();
   if (live) {
     const cx<T> w = wx[f], sh = wx[fx + f];
@@ -549,28 +562,27 @@ __global__ void __launch_bounds__(256) idft_fft_kernel(
   }
   __syncthreads();
   if (!live) return;
-  // occupied slots 16 - V/2 .. 16 + V/2; the test is uniform over the grid
-  const int lo = 16 - V / 2, hi = 16 + V / 2;
-  cx<T> tcol[32];
-#pragma unroll
-  for (int sl = 0; sl < 32; ++sl)
-    if (sl >= lo && sl <= hi) tcol[sl] = Ts[sl * COLS + col];
+  const cx<T>* tc = Ts + col;
   cx<T>* dst = E + (((long long)comp * fz + plane) * fy) * fx + f;
+  const long long step = (long long)R * fx;
   for (int g1 = q; g1 < R; g1 += NG) {
+    const cx<T>* tw = tw1 + g1 * 32;
     cx<T> a[P];
 #pragma unroll
     for (int r = 0; r < P; ++r) a[r] = {0, 0};
+    for (int s0 = s_begin; s0 < s_end; s0 += P) {
 #pragma unroll
-    for (int sl = 0; sl < 32; ++sl) {
-      if (sl < lo || sl > hi) continue;
-      const int r = ((sl - 16) % P + P) % P;
-      const cx<T> w1 = tw1[sl * R + g1];
-      a[r].x = fma(tcol[sl].x, w1.x, fma(-tcol[sl].y, w1.y, a[r].x));
-      a[r].y = fma(tcol[sl].x, w1.y, fma(tcol[sl].y, w1.x, a[r].y));
+      for (int i = 0; i < P; ++i) {
+        const int r = (i - 16) & (P - 1);
+        const cx<T> tv = tc[(s0 + i) * COLS], w1 = tw[s0 + i];
+        a[r].x = fma(tv.x, w1.x, fma(-tv.y, w1.y, a[r].x));
+        a[r].y = fma(tv.x, w1.y, fma(tv.y, w1.x, a[r].y));
+      }
     }
     small_fft<T, P>(a);
+    cx<T>* d = dst + (long long)g1 * fx;  // row g1 + R g2
 #pragma unroll
-    for (int g2 = 0; g2 < P; ++g2) store_nt(dst + (long long)(g1 + R * g2) * fx, a[g2]);
+    for (int g2 = 0; g2 < P; ++g2) store_nt(d + g2 * step, a[g2]);
   }
 }
 

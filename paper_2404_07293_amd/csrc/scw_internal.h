@@ -231,7 +231,7 @@ struct SynthArgs {
   bool mfma;               // inverse transform on the matrix cores
   int kp;
   int fft_p;               // > 0: factored transform with this P (fy = R * P)
-  const void* fft_tw;      // [32][R] first-stage twiddles of the factored transform
+  const void* fft_tw;      // [R][32] first-stage twiddles of the factored transform
   void* bmat;
   float* bscale;
   const void* amat;
