@@ -325,12 +325,15 @@ __device__ __forceinline__ f2 op(f2 x) { return BF16 ? f2{rbf(x.x), rbf(x.y)} : 
 // (KY x KX modes; fy is [KY][32], fx is [32][KX], both complex). Grid (4, B),
 // 256 threads. Thread (c, y) = (t / 32, t % 32) first transforms row y of
 // channel c in registers; the column transform then runs over (c, mode).
-template <bool BF16, int KY, int KX>
+// MM selects the mode-major output layout [mode][b][i] (a Fourier layer's
+// spectra, read per mode by the mixing); otherwise [b][i][mode] (the head).
+template <bool BF16, int KY, int KX, bool MM>
 __global__ void __launch_bounds__(256) fused_dft_fwd(const float* __restrict__ h,
                                                      const f2* __restrict__ fy,
                                                      const f2* __restrict__ fx,
                                                      f2* __restrict__ H) {
-  __shared__ f2 hx[8][SN][KX];
+  constexpr int HXS = SN * KX + 1;  // per-channel stride, padded against bank conflicts
+  __shared__ f2 hx[8 * HXS];
   __shared__ f2 fys[KY * SN], fxs[SN * KX];
   const int t = threadIdx.x, b = blockIdx.y, c0 = blockIdx.x * 8;
   for (int i = t; i < KY * SN; i += 256) fys[i] = op<BF16>(fy[i]);
@@ -357,20 +360,25 @@ __global__ void __launch_bounds__(256) fused_dft_fwd(const float* __restrict__ h
       re = fmaf(row[x], w.x, re);
       im = fmaf(row[x], w.y, im);
     }
-    hx[c][y][kx] = op<BF16>(f2{re, im});
+    hx[c * HXS + y * KX + kx] = op<BF16>(f2{re, im});
   }
   __syncthreads();
   constexpr int NMODE = KY * KX;
   for (int i = t; i < 8 * NMODE; i += 256) {
-    const int cc = i / NMODE, m = i % NMODE, ky = m / KX, kx = m % KX;
+    // mode-major: 8 consecutive threads take the 8 channels of one mode
+    const int cc = MM ? i % 8 : i / NMODE, m = MM ? i / 8 : i % NMODE;
+    const int ky = m / KX, kx = m % KX;
     float re = 0.f, im = 0.f;
 #pragma unroll 8
     for (int yy = 0; yy < SN; ++yy) {
-      const f2 a = fys[ky * SN + yy], v = hx[cc][yy][kx];
+      const f2 a = fys[ky * SN + yy], v = hx[cc * HXS + yy * KX + kx];
       re = fmaf(a.x, v.x, fmaf(-a.y, v.y, re));
       im = fmaf(a.x, v.y, fmaf(a.y, v.x, im));
     }
-    H[((long long)b * SW + c0 + cc) * NMODE + m] = f2{re, im};
+    if (MM)
+      H[((long long)m * gridDim.y + b) * SW + c0 + cc] = f2{re, im};
+    else
+      H[((long long)b * SW + c0 + cc) * NMODE + m] = f2{re, im};
   }
 }
 
@@ -385,7 +393,7 @@ __global__ void __launch_bounds__(INV_T) fused_dft_inv(
     const f2* __restrict__ G, const float* __restrict__ h, const f2* __restrict__ iy,
     const f2* __restrict__ ix, const float* __restrict__ pw, const float* __restrict__ pb,
     float* __restrict__ z_out, float* __restrict__ h_out, int apply_gelu) {
-  __shared__ f2 gs[8][SNM];
+  __shared__ f2 gs[16][SNM];  // half of the patch's output channels, all modes
   __shared__ f2 gy[8][SN][SKX];
   __shared__ f2 iys[SN * SKY], ixs[SKX * SN];
   __shared__ float pws[SW * SW], pbs[SW];
@@ -404,18 +412,21 @@ __global__ void __launch_bounds__(INV_T) fused_dft_inv(
     hr[i][0] = op<BF16>(v.x);
     hr[i][1] = op<BF16>(v.y);
   }
-  const f2* gb = G + (long long)b * SW * SNM;
   for (int og = 0; og < SW / 8; ++og) {
     __syncthreads();  // gs / gy of the previous group consumed
-    for (int i = t; i < 8 * SNM; i += INV_T)
-      gs[i / SNM][i % SNM] = op<BF16>(gb[og * 8 * SNM + i]);
+    // G is [b][mode][o]: each half of the channels is one 128-byte run per
+    // mode, read once for two groups of 8
+    if (og % 2 == 0)
+      for (int i = t; i < 16 * SNM; i += INV_T)
+        gs[i % 16][i / 16] = op<BF16>(G[((long long)b * SNM + i / 16) * SW + og * 8 + i % 16]);
     __syncthreads();
+    const int cg = (og % 2) * 8;
     for (int i = t; i < 8 * SN * SKX; i += INV_T) {
       const int c = i / (SN * SKX), yy = (i / SKX) % SN, kx = i % SKX;
       float re = 0.f, im = 0.f;
 #pragma unroll
       for (int ky = 0; ky < SKY; ++ky) {
-        const f2 a = iys[yy * SKY + ky], v = gs[c][ky * SKX + kx];
+        const f2 a = iys[yy * SKY + ky], v = gs[cg + c][ky * SKX + kx];
         re = fmaf(a.x, v.x, fmaf(-a.y, v.y, re));
         im = fmaf(a.x, v.y, fmaf(a.y, v.x, im));
       }
@@ -498,6 +509,71 @@ __global__ void __launch_bounds__(256) mode_mix(const f2* __restrict__ A,
     for (int mm = 0; mm < MC; ++mm)
       if (m0 + mm < nmode) dst[mm] = acc[mm];
   }
+}
+
+// Per-mode channel mixing of a Fourier layer on the matrix cores:
+//   out[b][m][o] = sum_i A[m][b][i] Wm[m][i][o]   (complex, i, o < 32)
+// with the spectra and the weights mode-major, as one real contraction over
+// k = (part, i), K = 64, per mode:
+//   Re(b, o) = sum_i Ar Wr - Ai Wi,   Im(b, o) = sum_i Ar Wi + Ai Wr,
+// into two 32 x 32 FP32 accumulators (patches x outputs). Block = 32 patches x
+// MM_G modes, one wave per mode. A mode's 32 x 32 tile of spectra is one
+// contiguous 8 KB run, staged in LDS (rows padded); each lane reads its
+// sixteen weights W[2s + half][lane] straight from memory (32 consecutive
+// outputs per half-wave) and uses them for both halves of K; each half-wave
+// writes the 32 outputs of one (patch, mode), one 256-byte run. With BF16 the operands are
+// rounded to bf16 as they are read (their products are exact in FP32).
+constexpr int MM_G = 4;
+template <bool BF16>
+__global__ void __launch_bounds__(256) mode_mix_mm(const f2* __restrict__ A,
+                                                   const f2* __restrict__ Wm, int nmode, int B,
+                                                   f2* __restrict__ out) {
+  __shared__ f2 as[MM_G][32][SW + 1];  // [mode][patch][i]
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63, li = lane & 31, lh = lane >> 5;
+  const int b0 = blockIdx.x * 32, m0 = blockIdx.y * MM_G;
+  for (int q = t; q < MM_G * 32 * SW; q += 256) {
+    const int mm = q / (32 * SW), bb = (q / SW) % 32, i = q % SW;
+    const int m = m0 + mm, b = b0 + bb;
+    as[mm][bb][i] = (m < nmode && b < B) ? op<BF16>(A[((long long)m * B + b) * SW + i])
+                                         : f2{0.f, 0.f};
+  }
+  __syncthreads();
+  const int m = m0 + wave;
+  if (m >= nmode) return;  // no barrier follows
+  const f2* wm = Wm + (long long)m * SW * SW + li;
+  f2 wv[SW / 2];
+#pragma unroll
+  for (int s = 0; s < SW / 2; ++s) wv[s] = op<BF16>(wm[(2 * s + lh) * SW]);
+  floatx16 cre = {0}, cim = {0};
+#pragma unroll
+  for (int s = 0; s < SW / 2; ++s) {  // real parts of A
+    const float a = as[wave][li][2 * s + lh].x;
+    cre = __builtin_amdgcn_mfma_f32_32x32x2f32(a, wv[s].x, cre, 0, 0, 0);
+    cim = __builtin_amdgcn_mfma_f32_32x32x2f32(a, wv[s].y, cim, 0, 0, 0);
+  }
+#pragma unroll
+  for (int s = 0; s < SW / 2; ++s) {  // imaginary parts of A
+    const float a = as[wave][li][2 * s + lh].y;
+    cre = __builtin_amdgcn_mfma_f32_32x32x2f32(a, -wv[s].y, cre, 0, 0, 0);
+    cim = __builtin_amdgcn_mfma_f32_32x32x2f32(a, wv[s].x, cim, 0, 0, 0);
+  }
+  f2* dst = out + ((long long)b0 * nmode + m) * SW + li;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int bb = 8 * (r / 4) + 4 * lh + (r % 4);
+    if (b0 + bb < B) dst[(long long)bb * nmode * SW] = f2{cre[r], cim[r]};
+  }
+}
+
+// Mode-major copy of the layers' spectral weights: Wm[k][m][i][o] from
+// W_k[i][o][m] (layer k at W + k * layer_stride complex values).
+__global__ void spec_mode_major(const f2* __restrict__ W, long long layer_stride, int nmode,
+                                f2* __restrict__ Wm) {
+  const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;  // (m, i, o), o fastest
+  if (q >= (long long)nmode * SW * SW) return;
+  const int k = blockIdx.y;
+  const int o = (int)(q % SW), i = (int)((q / SW) % SW), m = (int)(q / (SW * SW));
+  Wm[(long long)k * nmode * SW * SW + q] = W[k * layer_stride + ((long long)i * SW + o) * nmode + m];
 }
 
 // The lift: h[b][o][p] = sum_c lw[c][o] x[b][c][p] + lb[o], 16 input and 32
@@ -613,12 +689,12 @@ hipError_t sur_fused_dft_fwd(const float* h, const float* fy, const float* fx, f
     kern<<<grid, 256, 0, s>>>(h, reinterpret_cast<const f2*>(fy), reinterpret_cast<const f2*>(fx),
                               reinterpret_cast<f2*>(H));
   };
-  if (head) {  // the head's centred 15 x 15 band
-    if (bf16) go(fused_dft_fwd<true, 15, 15>);
-    else go(fused_dft_fwd<false, 15, 15>);
-  } else {  // a Fourier layer's 17 x 9 half plane
-    if (bf16) go(fused_dft_fwd<true, SKY, SKX>);
-    else go(fused_dft_fwd<false, SKY, SKX>);
+  if (head) {  // the head's centred 15 x 15 band, [b][i][mode]
+    if (bf16) go(fused_dft_fwd<true, 15, 15, false>);
+    else go(fused_dft_fwd<false, 15, 15, false>);
+  } else {  // a Fourier layer's 17 x 9 half plane, [mode][b][i]
+    if (bf16) go(fused_dft_fwd<true, SKY, SKX, true>);
+    else go(fused_dft_fwd<false, SKY, SKX, true>);
   }
   return hipGetLastError();
 }
@@ -638,17 +714,31 @@ hipError_t sur_mode_mix(const float* A, const float* W, int nmode, int B, int O,
   const f2* a = reinterpret_cast<const f2*>(A);
   const f2* w = reinterpret_cast<const f2*>(W);
   f2* o = reinterpret_cast<f2*>(out);
-  if (O == SW) {  // LDS: 16 KB of patches + 32 KB of weights
-    dim3 grid((nmode + 3) / 4, (B + 15) / 16);
-    if (bf16) mode_mix<true, SW, 4, 16><<<grid, 256, 0, s>>>(a, w, nmode, B, o);
-    else mode_mix<false, SW, 4, 16><<<grid, 256, 0, s>>>(a, w, nmode, B, o);
-  } else if (O == 3) {  // LDS: 32 KB of patches + 3 KB of weights
+  if (O == 3) {  // LDS: 32 KB of patches + 3 KB of weights
     dim3 grid((nmode + 3) / 4, (B + 31) / 32);
     if (bf16) mode_mix<true, 3, 4, 32><<<grid, 256, 0, s>>>(a, w, nmode, B, o);
     else mode_mix<false, 3, 4, 32><<<grid, 256, 0, s>>>(a, w, nmode, B, o);
   } else {
     return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+hipError_t sur_mode_mix_layer(const float* A, const float* Wm, int nmode, int B, float* out,
+                              bool bf16, hipStream_t s) {
+  dim3 grid((B + 31) / 32, (nmode + MM_G - 1) / MM_G);
+  const f2* a = reinterpret_cast<const f2*>(A);
+  const f2* w = reinterpret_cast<const f2*>(Wm);
+  f2* o = reinterpret_cast<f2*>(out);
+  if (bf16) mode_mix_mm<true><<<grid, 256, 0, s>>>(a, w, nmode, B, o);
+  else mode_mix_mm<false><<<grid, 256, 0, s>>>(a, w, nmode, B, o);
+  return hipGetLastError();
+}
+hipError_t sur_spec_mode_major(const float* W, long long layer_stride_floats, int nmode,
+                               int layers, float* Wm, hipStream_t s) {
+  if (layer_stride_floats % 2 != 0) return hipErrorInvalidValue;
+  dim3 grid(blocks((long long)nmode * SW * SW), layers);
+  spec_mode_major<<<grid, 256, 0, s>>>(reinterpret_cast<const f2*>(W), layer_stride_floats / 2,
+                                       nmode, reinterpret_cast<f2*>(Wm));
   return hipGetLastError();
 }
 hipError_t sur_lift(const float* x, const float* lw, const float* lb, float* h, int B, bool bf16,

@@ -338,15 +338,24 @@ hipError_t sur_adam(float* p, const float* g, float* m, float* v, long long n, f
                     hipStream_t s);
 hipError_t sur_encode(const float* n, float* x, int B, hipStream_t s);
 // One Fourier layer around its mixing: H = fy h fx per channel (17 x 9
-// modes, or the head's 15 x 15 with head), and z = Re(iy G ix) + pw^T h + pb
-// with h' = GELU(z) (gelu) or z; z_out may be null; h_out may equal z_out
-// when gelu is false.
+// modes, mode-major [mode][b][i]; or the head's 15 x 15 with head, [b][i][mode]),
+// and z = Re(iy G ix) + pw^T h + pb with G laid out [b][mode][o] and
+// h' = GELU(z) (gelu) or z; z_out may be null; h_out may equal z_out when
+// gelu is false.
 hipError_t sur_fused_dft_fwd(const float* h, const float* fy, const float* fx, float* H, int B,
                             bool head, bool bf16, hipStream_t s);
-// out[b][o][m] = sum_i A[b][i][m] W[i][o][m] for 32 input channels and
-// O = 32 (a layer's mixing) or 3 (the head) output channels.
+// The head's mixing, out[b][o][m] = sum_i A[b][i][m] W[i][o][m] for 32 input
+// and O = 3 output channels.
 hipError_t sur_mode_mix(const float* A, const float* W, int nmode, int B, int O, float* out,
                         bool bf16, hipStream_t s);
+// A layer's mixing on the matrix cores, from mode-major spectra and weights:
+// out[b][m][o] = sum_i A[m][b][i] Wm[m][i][o], 32 input and output channels.
+hipError_t sur_mode_mix_layer(const float* A, const float* Wm, int nmode, int B, float* out,
+                              bool bf16, hipStream_t s);
+// Wm[k][m][i][o] = W_k[i][o][m] for `layers` layers whose weights start
+// layer_stride_floats apart.
+hipError_t sur_spec_mode_major(const float* W, long long layer_stride_floats, int nmode,
+                               int layers, float* Wm, hipStream_t s);
 // h[b][o] = sum_c lw[c][o] x[b][c] + lb[o] over 16 input, 32 output channels.
 hipError_t sur_lift(const float* x, const float* lw, const float* lb, float* h, int B, bool bf16,
                     hipStream_t s);

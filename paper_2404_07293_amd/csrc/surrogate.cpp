@@ -57,7 +57,7 @@ struct SurNet {
   DevBuf params, grads, adam_m, adam_v;
   DevBuf dft;  // fy, fx, iy, ix, hy, hx (complex64)
   long long o_fy, o_fx, o_iy, o_ix, o_hy, o_hx;
-  DevBuf x, h[NL + 1], z[NL], Hk[NL], G, F, out, gout, gF, T1, gh, gh2, T2, gG, gH,
+  DevBuf x, h[NL + 1], z[NL], Hk[NL], G, Wm, F, out, gout, gF, T1, gh, gh2, T2, gG, gH,
       tmp, sums, enc_in;
 };
 
@@ -154,6 +154,8 @@ const float* cx(const SurNet& n, long long off) { return n.dft.as<float>() + 2 *
 int forward(SurNet& n, const float* x, int B, hipStream_t s, bool keep) {
   const Off o;
   const float* P = n.params.as<float>();
+  // mode-major copy of the spectral weights, for the mixing
+  SUR_HIP(sur_spec_mode_major(P + o.spec(0), SZ_LAYER, NM, NL, n.Wm.as<float>(), s));
   // lift
   SUR_HIP(sur_lift(x, P + o.lw, P + o.lb, n.h[0].as<float>(), B, n.bf16, s));
   for (int k = 0; k < NL; ++k) {
@@ -162,8 +164,9 @@ int forward(SurNet& n, const float* x, int B, hipStream_t s, bool keep) {
     const bool last = k == NL - 1;
     // H = fy h fx per channel (the layer's truncated forward transform)
     SUR_HIP(sur_fused_dft_fwd(hin, cx(n, n.o_fy), cx(n, n.o_fx), Hk, B, false, n.bf16, s));
-    // G[:, :, m] = H[:, :, m] W_k[:, :, m], batched over the patches per mode
-    SUR_HIP(sur_mode_mix(Hk, P + o.spec(k), NM, B, W, n.G.as<float>(), n.bf16, s));
+    // G[b][m] = H[m][b] W_k[m] per mode over the patches (H mode-major)
+    SUR_HIP(sur_mode_mix_layer(Hk, n.Wm.as<float>() + 2LL * k * NM * W * W, NM, B,
+                               n.G.as<float>(), n.bf16, s));
     // z = Re(iy G ix) + P_k^T h + c_k; h' = GELU(z) except after the last layer
     // the pre-activation is kept only for the backward pass
     float* zk = last ? n.h[k + 1].as<float>() : (keep ? n.z[k].as<float>() : nullptr);
@@ -217,7 +220,7 @@ int backward(SurNet& n, int B, hipStream_t s) {
     SUR_HIP(G(KYN, KXN, 32, B * W).a(cx(n, n.o_iy), true, 1, KYN, 0, true)
                 .b(n.T2.as<float>(), true, KXN, 1, 32 * KXN).c(n.gG.as<float>(), true, KXN, 1, NM)
                 .run(s, n.bf16));
-    SUR_HIP(G(W, W, B, NM).a(n.Hk[k].as<float>(), true, NM, (long long)W * NM, 1, true)
+    SUR_HIP(G(W, W, B, NM).a(n.Hk[k].as<float>(), true, 1, W, (long long)B * W, true)
                 .b(n.gG.as<float>(), true, (long long)W * NM, NM, 1)
                 .c(Gr + o.spec(k), true, (long long)W * NM, NM, 1).run(s, n.bf16));
     SUR_HIP(G(B, W, W, NM).a(n.gG.as<float>(), true, (long long)W * NM, NM, 1)
@@ -261,7 +264,7 @@ int sur_create(Context& ctx, int max_batch, unsigned long long seed, SurNet** ou
   if ((rc = alloc(n->params, N_PARAMS)) || (rc = alloc(n->grads, N_PARAMS)) ||
       (rc = alloc(n->adam_m, N_PARAMS)) || (rc = alloc(n->adam_v, N_PARAMS)) ||
       (rc = alloc(n->x, B * CIN * NP)) || (rc = alloc(n->enc_in, B * 8 * NP * 2)) ||
-      (rc = alloc(n->G, B * W * NM * 2)) ||
+      (rc = alloc(n->G, B * W * NM * 2)) || (rc = alloc(n->Wm, (long long)NL * NM * W * W * 2)) ||
       (rc = alloc(n->F, B * W * HM * 2)) || (rc = alloc(n->out, B * OUT * HM * 2)) ||
       (rc = alloc(n->gout, B * OUT * HM * 2)) || (rc = alloc(n->gF, B * W * HM * 2)) ||
       (rc = alloc(n->T1, B * W * 32 * HN * 2)) || (rc = alloc(n->gh, act)) ||
