@@ -464,6 +464,87 @@ __global__ void __launch_bounds__(INV_T) fused_dft_inv(
   }
 }
 
+// The same inverse half of a Fourier layer with its two dense parts on the
+// matrix cores. For one patch and image row y, the 32 outputs x 32 pixels
+//   z[o][y][x] = sum_i pw[i][o] h[i][y][x]
+//              + sum_kx (Re gy[o][y][kx] Re ix[kx][x] - Im gy[o][y][kx] Im ix[kx][x])
+//              + pb[o]
+// are one 32 x 32 FP32 tile with K = 32 + 18: the pointwise weights and the
+// row transform's twiddles are fixed operands held in registers, the pixels
+// come straight from memory (32 consecutive x per half-wave) and the column
+// transform gy[o][y][kx] = sum_ky iy[y][ky] G[o][ky][kx] is formed on the
+// vector units, 8 rows at a time, into LDS. One patch per block of 8 waves;
+// wave w takes row w of each group of 8, and its pixel loads for that row are
+// issued before the group's column transform.
+constexpr int INVM_T = 512, GYS = 19;  // gy row stride (floats), odd against bank conflicts
+template <bool BF16>
+__global__ void __launch_bounds__(INVM_T) fused_dft_inv_mfma(
+    const f2* __restrict__ G, const float* __restrict__ h, const f2* __restrict__ iy,
+    const f2* __restrict__ ix, const float* __restrict__ pw, const float* __restrict__ pb,
+    float* __restrict__ z_out, float* __restrict__ h_out, int apply_gelu) {
+  __shared__ f2 gsm[SNM][SW];            // the patch's G, [mode][o]
+  __shared__ f2 iys[SN * SKY];           // [y][ky]
+  __shared__ float gyl[8][SW][GYS];      // [row of the group][o][kx re | kx im]
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63, li = lane & 31, lh = lane >> 5;
+  const int b = blockIdx.x;
+  const f2* gb = G + (long long)b * SNM * SW;
+  for (int i = t; i < SNM * SW; i += INVM_T) (&gsm[0][0])[i] = op<BF16>(gb[i]);
+  for (int i = t; i < SN * SKY; i += INVM_T) iys[i] = op<BF16>(iy[i]);
+  // fixed operands: A = pw^T (row o = li, k = i), B = row-transform twiddles
+  // (k' < 9: Re ix[k'][x], else -Im ix[k' - 9][x]; column x = li)
+  float pwa[SW / 2], ixb[SKX];
+#pragma unroll
+  for (int s = 0; s < SW / 2; ++s) pwa[s] = op<BF16>(pw[(2 * s + lh) * SW + li]);
+#pragma unroll
+  for (int s = 0; s < SKX; ++s) {
+    const int k = 2 * s + lh;
+    ixb[s] = k < SKX ? op<BF16>(ix[k * SN + li]).x : -op<BF16>(ix[(k - SKX) * SN + li]).y;
+  }
+  float bias[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) bias[r] = pb[8 * (r / 4) + 4 * lh + (r % 4)];
+  const float* hb = h + (long long)b * SW * SN * SN;
+  for (int yc = 0; yc < SN / 8; ++yc) {
+    const int y = yc * 8 + wave;
+    // this wave's pixels of row y: B operand of the pointwise part (k = i)
+    float hv[SW / 2];
+#pragma unroll
+    for (int s = 0; s < SW / 2; ++s) hv[s] = op<BF16>(hb[((2 * s + lh) * SN + y) * SN + li]);
+    __syncthreads();  // G staged (first group) / the previous group's gy consumed
+    // column transform of rows yc*8 .. yc*8+7: items (row, kx, o), o fastest
+    for (int it = t; it < 8 * SKX * SW; it += INVM_T) {
+      const int o = it % SW, kx = (it / SW) % SKX, yl = it / (SW * SKX);
+      const int yy = yc * 8 + yl;
+      float re = 0.f, im = 0.f;
+#pragma unroll
+      for (int ky = 0; ky < SKY; ++ky) {
+        const f2 a = iys[yy * SKY + ky], v = gsm[ky * SKX + kx][o];
+        re = fmaf(a.x, v.x, fmaf(-a.y, v.y, re));
+        im = fmaf(a.x, v.y, fmaf(a.y, v.x, im));
+      }
+      gyl[yl][o][kx] = op<BF16>(re);
+      gyl[yl][o][SKX + kx] = op<BF16>(im);
+    }
+    __syncthreads();
+    floatx16 acc = {0};
+#pragma unroll
+    for (int s = 0; s < SW / 2; ++s)
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(pwa[s], hv[s], acc, 0, 0, 0);
+#pragma unroll
+    for (int s = 0; s < SKX; ++s)
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(gyl[wave][li][2 * s + lh], ixb[s], acc, 0, 0, 0);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int o = 8 * (r / 4) + 4 * lh + (r % 4);
+      const float z = acc[r] + bias[r];
+      const long long off = (((long long)b * SW + o) * SN + y) * SN + li;
+      if (z_out) z_out[off] = z;
+      if (apply_gelu) h_out[off] = gelu_fwd_f(z);
+      else if (h_out != z_out) h_out[off] = z;
+    }
+  }
+}
+
 // Per-mode channel mixing of a batch of patches:
 //   out[b][o][m] = sum_i A[b][i][m] W[i][o][m]     (complex; i < 32, o < O)
 // Block = MC consecutive modes x BT patches; the block's operands are staged
@@ -702,11 +783,11 @@ hipError_t sur_fused_dft_inv(const float* G, const float* h, const float* iy, co
                              const float* pw, const float* pb, float* z_out, float* h_out,
                              bool gelu, int B, bool bf16, hipStream_t s) {
   auto go = [&](auto kern) {
-    kern<<<B, INV_T, 0, s>>>(reinterpret_cast<const f2*>(G), h, reinterpret_cast<const f2*>(iy),
-                           reinterpret_cast<const f2*>(ix), pw, pb, z_out, h_out, gelu ? 1 : 0);
+    kern<<<B, INVM_T, 0, s>>>(reinterpret_cast<const f2*>(G), h, reinterpret_cast<const f2*>(iy),
+                            reinterpret_cast<const f2*>(ix), pw, pb, z_out, h_out, gelu ? 1 : 0);
   };
-  if (bf16) go(fused_dft_inv<true>);
-  else go(fused_dft_inv<false>);
+  if (bf16) go(fused_dft_inv_mfma<true>);
+  else go(fused_dft_inv_mfma<false>);
   return hipGetLastError();
 }
 hipError_t sur_mode_mix(const float* A, const float* W, int nmode, int B, int O, float* out,
