@@ -337,7 +337,8 @@ __global__ void __launch_bounds__(256) fused_dft_fwd(const float* __restrict__ h
   __shared__ f2 fys[KY * SN], fxs[SN * KX];
   const int t = threadIdx.x, b = blockIdx.y, c0 = blockIdx.x * 8;
   for (int i = t; i < KY * SN; i += 256) fys[i] = op<BF16>(fy[i]);
-  for (int i = t; i < SN * KX; i += 256) fxs[i] = op<BF16>(fx[i]);
+  if (BF16)
+    for (int i = t; i < SN * KX; i += 256) fxs[i] = op<BF16>(fx[i]);
   const int c = t >> 5, y = t & 31;
   float row[SN];
   const float4* src =
@@ -356,29 +357,43 @@ __global__ void __launch_bounds__(256) fused_dft_fwd(const float* __restrict__ h
     float re = 0.f, im = 0.f;
 #pragma unroll
     for (int x = 0; x < SN; ++x) {
-      const f2 w = fxs[x * KX + kx];
+      // wave-uniform index: FP32 twiddles come through the scalar cache
+      const f2 w = BF16 ? fxs[x * KX + kx] : fx[x * KX + kx];
       re = fmaf(row[x], w.x, re);
       im = fmaf(row[x], w.y, im);
     }
     hx[c * HXS + y * KX + kx] = op<BF16>(f2{re, im});
   }
   __syncthreads();
+  // column transform: items (ky group of KG, kx, channel), channel fastest;
+  // each hx value read serves KG modes
   constexpr int NMODE = KY * KX;
-  for (int i = t; i < 8 * NMODE; i += 256) {
-    // mode-major: 8 consecutive threads take the 8 channels of one mode
-    const int cc = MM ? i % 8 : i / NMODE, m = MM ? i / 8 : i % NMODE;
-    const int ky = m / KX, kx = m % KX;
-    float re = 0.f, im = 0.f;
-#pragma unroll 8
+  constexpr int KG = 3, NKG = (KY + KG - 1) / KG;
+  for (int i = t; i < 8 * KX * NKG; i += 256) {
+    const int cc = i % 8, kx = (i / 8) % KX, g = i / (8 * KX);
+    float re[KG], im[KG];
+#pragma unroll
+    for (int j = 0; j < KG; ++j) re[j] = im[j] = 0.f;
+#pragma unroll 4
     for (int yy = 0; yy < SN; ++yy) {
-      const f2 a = fys[ky * SN + yy], v = hx[cc * HXS + yy * KX + kx];
-      re = fmaf(a.x, v.x, fmaf(-a.y, v.y, re));
-      im = fmaf(a.x, v.y, fmaf(a.y, v.x, im));
+      const f2 v = hx[cc * HXS + yy * KX + kx];
+#pragma unroll
+      for (int j = 0; j < KG; ++j) {
+        const f2 a = fys[min(g * KG + j, KY - 1) * SN + yy];
+        re[j] = fmaf(a.x, v.x, fmaf(-a.y, v.y, re[j]));
+        im[j] = fmaf(a.x, v.y, fmaf(a.y, v.x, im[j]));
+      }
     }
-    if (MM)
-      H[((long long)m * gridDim.y + b) * SW + c0 + cc] = f2{re, im};
-    else
-      H[((long long)b * SW + c0 + cc) * NMODE + m] = f2{re, im};
+#pragma unroll
+    for (int j = 0; j < KG; ++j) {
+      const int ky = g * KG + j;
+      if (ky >= KY) break;
+      const int m = ky * KX + kx;
+      if (MM)
+        H[((long long)m * gridDim.y + b) * SW + c0 + cc] = f2{re[j], im[j]};
+      else
+        H[((long long)b * SW + c0 + cc) * NMODE + m] = f2{re[j], im[j]};
+    }
   }
 }
 
@@ -478,7 +493,8 @@ __global__ void __launch_bounds__(INV_T) fused_dft_inv(
 // issued before the group's column transform.
 constexpr int INVM_T = 512, GYS = 19;  // gy row stride (floats), odd against bank conflicts
 template <bool BF16>
-__global__ void __launch_bounds__(INVM_T) fused_dft_inv_mfma(
+__global__ void __launch_bounds__(INVM_T)
+fused_dft_inv_mfma(
     const f2* __restrict__ G, const float* __restrict__ h, const f2* __restrict__ iy,
     const f2* __restrict__ ix, const float* __restrict__ pw, const float* __restrict__ pb,
     float* __restrict__ z_out, float* __restrict__ h_out, int apply_gelu) {
@@ -500,9 +516,6 @@ __global__ void __launch_bounds__(INVM_T) fused_dft_inv_mfma(
     const int k = 2 * s + lh;
     ixb[s] = k < SKX ? op<BF16>(ix[k * SN + li]).x : -op<BF16>(ix[(k - SKX) * SN + li]).y;
   }
-  float bias[16];
-#pragma unroll
-  for (int r = 0; r < 16; ++r) bias[r] = pb[8 * (r / 4) + 4 * lh + (r % 4)];
   const float* hb = h + (long long)b * SW * SN * SN;
   for (int yc = 0; yc < SN / 8; ++yc) {
     const int y = yc * 8 + wave;
@@ -536,7 +549,7 @@ __global__ void __launch_bounds__(INVM_T) fused_dft_inv_mfma(
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int o = 8 * (r / 4) + 4 * lh + (r % 4);
-      const float z = acc[r] + bias[r];
+      const float z = acc[r] + pb[o];
       const long long off = (((long long)b * SW + o) * SN + y) * SN + li;
       if (z_out) z_out[off] = z;
       if (apply_gelu) h_out[off] = gelu_fwd_f(z);
@@ -545,51 +558,35 @@ __global__ void __launch_bounds__(INVM_T) fused_dft_inv_mfma(
   }
 }
 
-// Per-mode channel mixing of a batch of patches:
-//   out[b][o][m] = sum_i A[b][i][m] W[i][o][m]     (complex; i < 32, o < O)
-// Block = MC consecutive modes x BT patches; the block's operands are staged
-// in LDS (modes contiguous, 32-byte runs of the m-fastest layouts), and every
-// thread writes MC consecutive modes of one (patch, output channel).
-template <bool BF16, int O, int MC, int BT>
-__global__ void __launch_bounds__(256) mode_mix(const f2* __restrict__ A,
-                                                const f2* __restrict__ Wt, int nmode, int B,
-                                                f2* __restrict__ out) {
-  __shared__ f2 as[BT][SW][MC];
-  __shared__ f2 ws[SW][MC][O];
-  const int t = threadIdx.x;
-  const int m0 = blockIdx.x * MC, b0 = blockIdx.y * BT;
-  for (int i = t; i < BT * SW * MC; i += 256) {
-    const int mm = i % MC, ch = (i / MC) % SW, bb = i / (MC * SW);
-    const int b = b0 + bb, m = m0 + mm;
-    as[bb][ch][mm] = (b < B && m < nmode) ? op<BF16>(A[((long long)b * SW + ch) * nmode + m])
-                                          : f2{0.f, 0.f};
-  }
-  for (int i = t; i < SW * O * MC; i += 256) {
-    const int mm = i % MC, o = (i / MC) % O, ch = i / (MC * O);
-    const int m = m0 + mm;
-    ws[ch][mm][o] = m < nmode ? op<BF16>(Wt[((long long)ch * O + o) * nmode + m]) : f2{0.f, 0.f};
-  }
-  __syncthreads();
-  for (int idx = t; idx < BT * O; idx += 256) {
-    const int bb = idx / O, o = idx % O, b = b0 + bb;
-    f2 acc[MC];
+// The head's mixing, 3 outputs: out[b][o][m] = sum_i A[b][i][m] W[i][o][m].
+// One thread per (patch, mode), modes fastest: every channel's spectra of a
+// patch are read as 64 consecutive modes per wave, the weights (small, cached)
+// likewise, and each spectral value serves the three outputs.
+template <bool BF16>
+__global__ void __launch_bounds__(256) mode_mix_head(const f2* __restrict__ A,
+                                                     const f2* __restrict__ Wt, int nmode, int B,
+                                                     f2* __restrict__ out) {
+  constexpr int O = 3;
+  const int m = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int b = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (m >= nmode || b >= B) return;
+  const f2* a = A + (long long)b * SW * nmode + m;
+  const f2* w = Wt + m;
+  f2 acc[O];
 #pragma unroll
-    for (int mm = 0; mm < MC; ++mm) acc[mm] = f2{0.f, 0.f};
+  for (int o = 0; o < O; ++o) acc[o] = f2{0.f, 0.f};
 #pragma unroll 8
-    for (int ch = 0; ch < SW; ++ch) {
+  for (int i = 0; i < SW; ++i) {
+    const f2 v = op<BF16>(a[(long long)i * nmode]);
 #pragma unroll
-      for (int mm = 0; mm < MC; ++mm) {
-        const f2 a = as[bb][ch][mm], w = ws[ch][mm][o];
-        acc[mm].x = fmaf(a.x, w.x, fmaf(-a.y, w.y, acc[mm].x));
-        acc[mm].y = fmaf(a.x, w.y, fmaf(a.y, w.x, acc[mm].y));
-      }
+    for (int o = 0; o < O; ++o) {
+      const f2 c = op<BF16>(w[(i * O + o) * nmode]);
+      acc[o].x = fmaf(v.x, c.x, fmaf(-v.y, c.y, acc[o].x));
+      acc[o].y = fmaf(v.x, c.y, fmaf(v.y, c.x, acc[o].y));
     }
-    if (b >= B) continue;
-    f2* dst = out + ((long long)b * O + o) * nmode + m0;
-#pragma unroll
-    for (int mm = 0; mm < MC; ++mm)
-      if (m0 + mm < nmode) dst[mm] = acc[mm];
   }
+#pragma unroll
+  for (int o = 0; o < O; ++o) out[((long long)b * O + o) * nmode + m] = acc[o];
 }
 
 // Per-mode channel mixing of a Fourier layer on the matrix cores:
@@ -795,10 +792,10 @@ hipError_t sur_mode_mix(const float* A, const float* W, int nmode, int B, int O,
   const f2* a = reinterpret_cast<const f2*>(A);
   const f2* w = reinterpret_cast<const f2*>(W);
   f2* o = reinterpret_cast<f2*>(out);
-  if (O == 3) {  // LDS: 32 KB of patches + 3 KB of weights
-    dim3 grid((nmode + 3) / 4, (B + 31) / 32);
-    if (bf16) mode_mix<true, 3, 4, 32><<<grid, 256, 0, s>>>(a, w, nmode, B, o);
-    else mode_mix<false, 3, 4, 32><<<grid, 256, 0, s>>>(a, w, nmode, B, o);
+  if (O == 3) {
+    dim3 grid((nmode + 63) / 64, (B + 3) / 4);
+    if (bf16) mode_mix_head<true><<<grid, 256, 0, s>>>(a, w, nmode, B, o);
+    else mode_mix_head<false><<<grid, 256, 0, s>>>(a, w, nmode, B, o);
   } else {
     return hipErrorInvalidValue;
   }
