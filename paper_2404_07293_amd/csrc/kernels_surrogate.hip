@@ -332,11 +332,15 @@ __global__ void __launch_bounds__(256) fused_dft_fwd(const float* __restrict__ h
                                                      const f2* __restrict__ fy,
                                                      const f2* __restrict__ fx,
                                                      f2* __restrict__ H) {
-  constexpr int HXS = SN * KX + 1;  // per-channel stride, padded against bank conflicts
+  // Padded strides against LDS bank conflicts (16 lanes of 8 bytes per
+  // cycle): a channel's rows start 2 (mod 16) complex values apart, so that 8
+  // channels x 2 consecutive kx hit distinct banks; the ky rows of fy are 33
+  // apart, so that a wave reading two ky groups hits two banks.
+  constexpr int HXS = SN * KX + 2, FYS = SN + 1;
   __shared__ f2 hx[8 * HXS];
-  __shared__ f2 fys[KY * SN], fxs[SN * KX];
+  __shared__ f2 fys[KY * FYS], fxs[SN * KX];
   const int t = threadIdx.x, b = blockIdx.y, c0 = blockIdx.x * 8;
-  for (int i = t; i < KY * SN; i += 256) fys[i] = op<BF16>(fy[i]);
+  for (int i = t; i < KY * SN; i += 256) fys[(i / SN) * FYS + i % SN] = op<BF16>(fy[i]);
   if (BF16)
     for (int i = t; i < SN * KX; i += 256) fxs[i] = op<BF16>(fx[i]);
   const int c = t >> 5, y = t & 31;
@@ -352,17 +356,44 @@ __global__ void __launch_bounds__(256) fused_dft_fwd(const float* __restrict__ h
     row[4 * q + 3] = op<BF16>(v.w);
   }
   __syncthreads();
+  if constexpr (BF16) {  // every product of two rounded operands, as defined
 #pragma unroll 3
-  for (int kx = 0; kx < KX; ++kx) {
-    float re = 0.f, im = 0.f;
+    for (int kx = 0; kx < KX; ++kx) {
+      float re = 0.f, im = 0.f;
 #pragma unroll
-    for (int x = 0; x < SN; ++x) {
-      // wave-uniform index: FP32 twiddles come through the scalar cache
-      const f2 w = BF16 ? fxs[x * KX + kx] : fx[x * KX + kx];
-      re = fmaf(row[x], w.x, re);
-      im = fmaf(row[x], w.y, im);
+      for (int x = 0; x < SN; ++x) {
+        const f2 w = fxs[x * KX + kx];
+        re = fmaf(row[x], w.x, re);
+        im = fmaf(row[x], w.y, im);
+      }
+      hx[c * HXS + y * KX + kx] = op<BF16>(f2{re, im});
     }
-    hx[c * HXS + y * KX + kx] = op<BF16>(f2{re, im});
+  } else {
+    // The twiddles of x and 32 - x are conjugate: with s = row[x] + row[32-x]
+    // and d = row[x] - row[32-x], the pair adds s Re w to the real part and
+    // d Im w to the imaginary part (x = 0 and 16 stand alone; a layer's table
+    // holds kx = 0..8, the head's kx = -7..7 scaled by 1/32, both conjugate
+    // symmetric). The index is wave-uniform, so the twiddles come through the
+    // scalar cache.
+    float sx[SN / 2], dx[SN / 2];
+#pragma unroll
+    for (int x = 1; x < SN / 2; ++x) {
+      sx[x] = row[x] + row[SN - x];
+      dx[x] = row[x] - row[SN - x];
+    }
+#pragma unroll 3
+    for (int kx = 0; kx < KX; ++kx) {
+      const f2 w0 = fx[kx], w16 = fx[(SN / 2) * KX + kx];
+      float re = fmaf(row[0], w0.x, row[SN / 2] * w16.x);
+      float im = fmaf(row[0], w0.y, row[SN / 2] * w16.y);
+#pragma unroll
+      for (int x = 1; x < SN / 2; ++x) {
+        const f2 w = fx[x * KX + kx];
+        re = fmaf(sx[x], w.x, re);
+        im = fmaf(dx[x], w.y, im);
+      }
+      hx[c * HXS + y * KX + kx] = f2{re, im};
+    }
   }
   __syncthreads();
   // column transform: items (ky group of KG, kx, channel), channel fastest;
@@ -374,14 +405,41 @@ __global__ void __launch_bounds__(256) fused_dft_fwd(const float* __restrict__ h
     float re[KG], im[KG];
 #pragma unroll
     for (int j = 0; j < KG; ++j) re[j] = im[j] = 0.f;
+    const f2* hc = hx + cc * HXS + kx;  // hc[yy * KX]
+    if constexpr (BF16) {
 #pragma unroll 4
-    for (int yy = 0; yy < SN; ++yy) {
-      const f2 v = hx[cc * HXS + yy * KX + kx];
+      for (int yy = 0; yy < SN; ++yy) {
+        const f2 v = hc[yy * KX];
 #pragma unroll
-      for (int j = 0; j < KG; ++j) {
-        const f2 a = fys[min(g * KG + j, KY - 1) * SN + yy];
-        re[j] = fmaf(a.x, v.x, fmaf(-a.y, v.y, re[j]));
-        im[j] = fmaf(a.x, v.y, fmaf(a.y, v.x, im[j]));
+        for (int j = 0; j < KG; ++j) {
+          const f2 a = fys[min(g * KG + j, KY - 1) * FYS + yy];
+          re[j] = fmaf(a.x, v.x, fmaf(-a.y, v.y, re[j]));
+          im[j] = fmaf(a.x, v.y, fmaf(a.y, v.x, im[j]));
+        }
+      }
+    } else {
+      // rows yy and 32 - yy have conjugate twiddles: w a + conj(w) b =
+      // Re w (a + b) + i Im w (a - b); rows 0 and 16 stand alone
+#pragma unroll
+      for (int yy = 0; yy <= SN / 2; yy += SN / 2) {
+        const f2 v = hc[yy * KX];
+#pragma unroll
+        for (int j = 0; j < KG; ++j) {
+          const f2 a = fys[min(g * KG + j, KY - 1) * FYS + yy];
+          re[j] = fmaf(a.x, v.x, fmaf(-a.y, v.y, re[j]));
+          im[j] = fmaf(a.x, v.y, fmaf(a.y, v.x, im[j]));
+        }
+      }
+#pragma unroll 3
+      for (int yy = 1; yy < SN / 2; ++yy) {
+        const f2 va = hc[yy * KX], vb = hc[(SN - yy) * KX];
+        const f2 p = f2{va.x + vb.x, va.y + vb.y}, q = f2{va.x - vb.x, va.y - vb.y};
+#pragma unroll
+        for (int j = 0; j < KG; ++j) {
+          const f2 a = fys[min(g * KG + j, KY - 1) * FYS + yy];
+          re[j] = fmaf(a.x, p.x, fmaf(-a.y, q.y, re[j]));
+          im[j] = fmaf(a.x, p.y, fmaf(a.y, q.x, im[j]));
+        }
       }
     }
 #pragma unroll
