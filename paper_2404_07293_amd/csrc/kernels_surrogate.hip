@@ -203,24 +203,12 @@ __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmOp op) {
   }
 }
 
-// x[b][c][p] += bias[c]
-__global__ void bias_add(float* x, const float* bias, int C, int P, long long total) {
-  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < total) x[i] += bias[(i / P) % C];
-}
-
-__device__ __forceinline__ float gelu_f(float z) {
-  return 0.5f * z * (1.f + erff(z * 0.70710678118654752f));
-}
+// d GELU / dz for the backward pass (exact erf)
 __device__ __forceinline__ float gelu_grad_f(float z) {
   return 0.5f * (1.f + erff(z * 0.70710678118654752f)) +
          z * expf(-0.5f * z * z) * 0.39894228040143268f;
 }
 
-__global__ void gelu_fwd(const float* z, float* h, long long n) {
-  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) h[i] = gelu_f(z[i]);
-}
 __global__ void gelu_bwd(const float* z, float* g, long long n) {
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) g[i] *= gelu_grad_f(z[i]);
@@ -455,86 +443,21 @@ __global__ void __launch_bounds__(256) fused_dft_fwd(const float* __restrict__ h
   }
 }
 
+// GELU(z) = z (1 + erf(z / sqrt 2)) / 2 for the forward pass, with erf from
+// Abramowitz and Stegun 7.1.26 (Hastings' rational approximation, absolute
+// error at most 1.5e-7): erf(x) = 1 - t (a1 + t (a2 + ... + t a5)) e^{-x^2},
+// t = 1 / (1 + p x), x >= 0. Branch-free: one reciprocal and one exponential.
+// For z < 0, 1 + erf(z / sqrt 2) is formed directly as the product, without
+// the cancellation of 1 - (1 - product).
 __device__ __forceinline__ float gelu_fwd_f(float z) {
-  return 0.5f * z * (1.f + erff(z * 0.70710678118654752f));
-}
-
-// grid (B), 512 threads; thread t owns pixels 2t, 2t + 1 (row y = t / 16)
-constexpr int INV_T = 512, INV_PX = 2;
-template <bool BF16>
-__global__ void __launch_bounds__(INV_T) fused_dft_inv(
-    const f2* __restrict__ G, const float* __restrict__ h, const f2* __restrict__ iy,
-    const f2* __restrict__ ix, const float* __restrict__ pw, const float* __restrict__ pb,
-    float* __restrict__ z_out, float* __restrict__ h_out, int apply_gelu) {
-  __shared__ f2 gs[16][SNM];  // half of the patch's output channels, all modes
-  __shared__ f2 gy[8][SN][SKX];
-  __shared__ f2 iys[SN * SKY], ixs[SKX * SN];
-  __shared__ float pws[SW * SW], pbs[SW];
-  const int t = threadIdx.x, b = blockIdx.x;
-  const int y = t / (SN / INV_PX), x0 = (t % (SN / INV_PX)) * INV_PX;
-  for (int i = t; i < SN * SKY; i += INV_T) iys[i] = op<BF16>(iy[i]);
-  for (int i = t; i < SKX * SN; i += INV_T) ixs[i] = op<BF16>(ix[i]);
-  for (int i = t; i < SW * SW; i += INV_T) pws[i] = op<BF16>(pw[i]);
-  if (t < SW) pbs[t] = pb[t];
-  // this thread's pixels of every input channel
-  float hr[SW][INV_PX];
-  const float* hb = h + (long long)b * SW * SN * SN;
-#pragma unroll
-  for (int i = 0; i < SW; ++i) {
-    const float2 v = *reinterpret_cast<const float2*>(hb + i * SN * SN + INV_PX * t);
-    hr[i][0] = op<BF16>(v.x);
-    hr[i][1] = op<BF16>(v.y);
-  }
-  for (int og = 0; og < SW / 8; ++og) {
-    __syncthreads();  // gs / gy of the previous group consumed
-    // G is [b][mode][o]: each half of the channels is one 128-byte run per
-    // mode, read once for two groups of 8
-    if (og % 2 == 0)
-      for (int i = t; i < 16 * SNM; i += INV_T)
-        gs[i % 16][i / 16] = op<BF16>(G[((long long)b * SNM + i / 16) * SW + og * 8 + i % 16]);
-    __syncthreads();
-    const int cg = (og % 2) * 8;
-    for (int i = t; i < 8 * SN * SKX; i += INV_T) {
-      const int c = i / (SN * SKX), yy = (i / SKX) % SN, kx = i % SKX;
-      float re = 0.f, im = 0.f;
-#pragma unroll
-      for (int ky = 0; ky < SKY; ++ky) {
-        const f2 a = iys[yy * SKY + ky], v = gs[cg + c][ky * SKX + kx];
-        re = fmaf(a.x, v.x, fmaf(-a.y, v.y, re));
-        im = fmaf(a.x, v.y, fmaf(a.y, v.x, im));
-      }
-      gy[c][yy][kx] = op<BF16>(f2{re, im});
-    }
-    __syncthreads();
-#pragma unroll 2
-    for (int c = 0; c < 8; ++c) {
-      const int o = og * 8 + c;
-      float zz[INV_PX];
-#pragma unroll
-      for (int j = 0; j < INV_PX; ++j) zz[j] = pbs[o];
-#pragma unroll
-      for (int i = 0; i < SW; ++i) {
-        const float w = pws[i * SW + o];
-#pragma unroll
-        for (int j = 0; j < INV_PX; ++j) zz[j] = fmaf(w, hr[i][j], zz[j]);
-      }
-#pragma unroll
-      for (int kx = 0; kx < SKX; ++kx) {
-        const f2 g = gy[c][y][kx];
-#pragma unroll
-        for (int j = 0; j < INV_PX; ++j) {
-          const f2 e = ixs[kx * SN + x0 + j];
-          zz[j] = fmaf(g.x, e.x, fmaf(-g.y, e.y, zz[j]));
-        }
-      }
-      const long long off = ((long long)b * SW + o) * SN * SN + INV_PX * t;
-      if (z_out) *reinterpret_cast<float2*>(z_out + off) = make_float2(zz[0], zz[1]);
-      if (apply_gelu)
-        *reinterpret_cast<float2*>(h_out + off) = make_float2(gelu_fwd_f(zz[0]), gelu_fwd_f(zz[1]));
-      else if (h_out != z_out)
-        *reinterpret_cast<float2*>(h_out + off) = make_float2(zz[0], zz[1]);
-    }
-  }
+  const float x = fabsf(z) * 0.70710678118654752f;
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, x, 1.f));
+  float q = fmaf(1.061405429f, t, -1.453152027f);
+  q = fmaf(q, t, 1.421413741f);
+  q = fmaf(q, t, -0.284496736f);
+  q = fmaf(q, t, 0.254829592f);
+  const float pe = q * t * __expf(-x * x);  // 1 - erf(x)
+  return 0.5f * z * (z >= 0.f ? 2.f - pe : pe);
 }
 
 // The same inverse half of a Fourier layer with its two dense parts on the
@@ -546,12 +469,26 @@ __global__ void __launch_bounds__(INV_T) fused_dft_inv(
 // row transform's twiddles are fixed operands held in registers, the pixels
 // come straight from memory (32 consecutive x per half-wave) and the column
 // transform gy[o][y][kx] = sum_ky iy[y][ky] G[o][ky][kx] is formed on the
-// vector units, 8 rows at a time, into LDS. One patch per block of 8 waves;
-// wave w takes row w of each group of 8, and its pixel loads for that row are
-// issued before the group's column transform.
+// vector units, 8 rows at a time, into LDS. The rows y and 32 - y have
+// conjugate twiddles, so one set of products gives both: with A = sum Re iy G
+// and B = sum Im iy G, gy[y] = A + i B and gy[32 - y] = A - i B (per complex
+// part below); each group of 8 rows is 4 such pairs (rows 0 and 16 use direct
+// sums). With BF16 these are still products of two rounded operands: rounding
+// to nearest even is symmetric, so the rounded twiddles of 32 - y remain the
+// conjugates of those of y.
+// One patch per block of 8 waves; wave w takes slot w of each group, and its
+// pixel loads for the next group are issued once the current ones are used.
 constexpr int INVM_T = 512, GYS = 19;  // gy row stride (floats), odd against bank conflicts
+// The image rows of group k (0..3), slot w (0..7): conjugate pairs (y, 32 - y)
+// in slots w and w + 4, y = 4k + 1 + (w mod 4); the last group's slots 3 and
+// 7 hold the self-paired rows 0 and 16.
+__device__ __forceinline__ int inv_row(int k, int w) {
+  const int base = 4 * k + 1 + (w & 3);
+  if (k == 3 && (w & 3) == 3) return w < 4 ? 0 : SN / 2;
+  return w < 4 ? base : SN - base;
+}
 template <bool BF16>
-__global__ void __launch_bounds__(INVM_T)
+__global__ void __launch_bounds__(INVM_T) __attribute__((amdgpu_waves_per_eu(4)))
 fused_dft_inv_mfma(
     const f2* __restrict__ G, const float* __restrict__ h, const f2* __restrict__ iy,
     const f2* __restrict__ ix, const float* __restrict__ pw, const float* __restrict__ pb,
@@ -575,32 +512,58 @@ fused_dft_inv_mfma(
     ixb[s] = k < SKX ? op<BF16>(ix[k * SN + li]).x : -op<BF16>(ix[(k - SKX) * SN + li]).y;
   }
   const float* hb = h + (long long)b * SW * SN * SN;
+  // this wave's pixels of its row: B operand of the pointwise part (k = i);
+  // the next row's are loaded as soon as the current ones are consumed
+  float hv[SW / 2];
+#pragma unroll
+  for (int s = 0; s < SW / 2; ++s)
+    hv[s] = op<BF16>(hb[((2 * s + lh) * SN + inv_row(0, wave)) * SN + li]);
   for (int yc = 0; yc < SN / 8; ++yc) {
-    const int y = yc * 8 + wave;
-    // this wave's pixels of row y: B operand of the pointwise part (k = i)
-    float hv[SW / 2];
-#pragma unroll
-    for (int s = 0; s < SW / 2; ++s) hv[s] = op<BF16>(hb[((2 * s + lh) * SN + y) * SN + li]);
+    const int y = inv_row(yc, wave);
     __syncthreads();  // G staged (first group) / the previous group's gy consumed
-    // column transform of rows yc*8 .. yc*8+7: items (row, kx, o), o fastest
-    for (int it = t; it < 8 * SKX * SW; it += INVM_T) {
-      const int o = it % SW, kx = (it / SW) % SKX, yl = it / (SW * SKX);
-      const int yy = yc * 8 + yl;
-      float re = 0.f, im = 0.f;
+    // column transform of the group's 4 row pairs: items (pair, kx, o), o fastest
+    for (int it = t; it < 4 * SKX * SW; it += INVM_T) {
+      const int o = it % SW, kx = (it / SW) % SKX, pr = it / (SW * SKX);
+      const int ya = inv_row(yc, pr), yb = inv_row(yc, pr + 4);
+      float ra = 0.f, ia = 0.f, rb = 0.f, ib = 0.f;
+      if (ya == 0) {  // rows 0 and 16
+#pragma unroll 4
+        for (int ky = 0; ky < SKY; ++ky) {
+          const f2 v = gsm[ky * SKX + kx][o], a = iys[ya * SKY + ky], c = iys[yb * SKY + ky];
+          ra = fmaf(a.x, v.x, fmaf(-a.y, v.y, ra));
+          ia = fmaf(a.x, v.y, fmaf(a.y, v.x, ia));
+          rb = fmaf(c.x, v.x, fmaf(-c.y, v.y, rb));
+          ib = fmaf(c.x, v.y, fmaf(c.y, v.x, ib));
+        }
+      } else {
+        float ar = 0.f, ai = 0.f, br = 0.f, bi = 0.f;
 #pragma unroll
-      for (int ky = 0; ky < SKY; ++ky) {
-        const f2 a = iys[yy * SKY + ky], v = gsm[ky * SKX + kx][o];
-        re = fmaf(a.x, v.x, fmaf(-a.y, v.y, re));
-        im = fmaf(a.x, v.y, fmaf(a.y, v.x, im));
+        for (int ky = 0; ky < SKY; ++ky) {
+          const f2 v = gsm[ky * SKX + kx][o], a = iys[ya * SKY + ky];
+          ar = fmaf(a.x, v.x, ar);
+          ai = fmaf(a.x, v.y, ai);
+          br = fmaf(a.y, v.y, br);
+          bi = fmaf(a.y, v.x, bi);
+        }
+        ra = ar - br;
+        ia = ai + bi;
+        rb = ar + br;
+        ib = ai - bi;
       }
-      gyl[yl][o][kx] = op<BF16>(re);
-      gyl[yl][o][SKX + kx] = op<BF16>(im);
+      gyl[pr][o][kx] = op<BF16>(ra);
+      gyl[pr][o][SKX + kx] = op<BF16>(ia);
+      gyl[pr + 4][o][kx] = op<BF16>(rb);
+      gyl[pr + 4][o][SKX + kx] = op<BF16>(ib);
     }
     __syncthreads();
     floatx16 acc = {0};
 #pragma unroll
     for (int s = 0; s < SW / 2; ++s)
       acc = __builtin_amdgcn_mfma_f32_32x32x2f32(pwa[s], hv[s], acc, 0, 0, 0);
+    if (yc + 1 < SN / 8)
+#pragma unroll
+      for (int s = 0; s < SW / 2; ++s)
+        hv[s] = op<BF16>(hb[((2 * s + lh) * SN + inv_row(yc + 1, wave)) * SN + li]);
 #pragma unroll
     for (int s = 0; s < SKX; ++s)
       acc = __builtin_amdgcn_mfma_f32_32x32x2f32(gyl[wave][li][2 * s + lh], ixb[s], acc, 0, 0, 0);
@@ -784,15 +747,6 @@ hipError_t launch_gemm(const GemmOp& op, hipStream_t s) {
   return hipSuccess;
 }
 
-hipError_t sur_bias_add(float* x, const float* bias, int B, int C, int P, hipStream_t s) {
-  const long long n = (long long)B * C * P;
-  bias_add<<<blocks(n), 256, 0, s>>>(x, bias, C, P, n);
-  return hipGetLastError();
-}
-hipError_t sur_gelu_fwd(const float* z, float* h, long long n, hipStream_t s) {
-  gelu_fwd<<<blocks(n), 256, 0, s>>>(z, h, n);
-  return hipGetLastError();
-}
 hipError_t sur_gelu_bwd(const float* z, float* g, long long n, hipStream_t s) {
   gelu_bwd<<<blocks(n), 256, 0, s>>>(z, g, n);
   return hipGetLastError();

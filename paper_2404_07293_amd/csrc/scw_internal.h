@@ -327,8 +327,6 @@ struct GemmOp {
   int bf16;  // operands rounded to bf16, products on the matrix cores (FP32 accumulate)
 };
 hipError_t launch_gemm(const GemmOp& op, hipStream_t s);
-hipError_t sur_bias_add(float* x, const float* bias, int B, int C, int P, hipStream_t s);
-hipError_t sur_gelu_fwd(const float* z, float* h, long long n, hipStream_t s);
 hipError_t sur_gelu_bwd(const float* z, float* g, long long n, hipStream_t s);
 hipError_t sur_sum_batch(const float* in, float* out, int B, long long per, hipStream_t s);
 hipError_t sur_bias_grad(const float* g, float* out, int B, int C, int P, hipStream_t s);
