@@ -516,8 +516,7 @@ fused_dft_inv_mfma(
   // the next row's are loaded as soon as the current ones are consumed
   float hv[SW / 2];
 #pragma unroll
-  for (int s = 0; s < SW / 2; ++s)
-    hv[s] = op<BF16>(hb[((2 * s + lh) * SN + inv_row(0, wave)) * SN + li]);
+  for (int s = 0; s < SW / 2; ++s) hv[s] = hb[((2 * s + lh) * SN + inv_row(0, wave)) * SN + li];
   for (int yc = 0; yc < SN / 8; ++yc) {
     const int y = inv_row(yc, wave);
     __syncthreads();  // G staged (first group) / the previous group's gy consumed
@@ -559,11 +558,11 @@ fused_dft_inv_mfma(
     floatx16 acc = {0};
 #pragma unroll
     for (int s = 0; s < SW / 2; ++s)
-      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(pwa[s], hv[s], acc, 0, 0, 0);
-    if (yc + 1 < SN / 8)
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(pwa[s], op<BF16>(hv[s]), acc, 0, 0, 0);
+    if (yc + 1 < SN / 8)  // rounded (BF16) where used, so the loads stay in flight
 #pragma unroll
       for (int s = 0; s < SW / 2; ++s)
-        hv[s] = op<BF16>(hb[((2 * s + lh) * SN + inv_row(yc + 1, wave)) * SN + li]);
+        hv[s] = hb[((2 * s + lh) * SN + inv_row(yc + 1, wave)) * SN + li];
 #pragma unroll
     for (int s = 0; s < SKX; ++s)
       acc = __builtin_amdgcn_mfma_f32_32x32x2f32(gyl[wave][li][2 * s + lh], ixb[s], acc, 0, 0, 0);
