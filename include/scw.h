@@ -262,6 +262,12 @@ void scw_batch_free(scw_batch* batch);
  * the batch's field on return. Synchronises `hip_stream`. */
 int scw_batch_tune(scw_batch* batch, void* E_dev, void* hip_stream, int reps,
                    scw_tune_report* report);
+/* Set the batched kernel's shape explicitly: radix P of the factored y pass
+ * (a power of two in [2, min(32, fy)] whose per-block tables fit, see above),
+ * persistent blocks per CU (1..64) and work items per queue grab (1..1024).
+ * Later launches capture the graph again. Returns SCW_EINVAL (the batch
+ * unchanged) for a shape outside these ranges. Host-only; no device work. */
+int scw_batch_configure(scw_batch* batch, int radix, int blocks_per_cu, int chunk);
 
 /* Spectral-convolution surrogate of the transmitted field (Eq. 9 below the
  * sample) for one patch family: 8 x 32 x 32 voxels at pitch lambda/4

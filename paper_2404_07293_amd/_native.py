@@ -101,6 +101,8 @@ SIGNATURES = {
     "scw_batch_free": (None, [ctypes.c_void_p]),
     "scw_batch_tune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                       ctypes.c_int, ctypes.POINTER(ScwTuneReport)]),
+    "scw_batch_configure": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                           ctypes.c_int]),
     "scw_synthesis_configure": (ctypes.c_int, [ctypes.c_void_p,
                                                ctypes.POINTER(ScwSynthConfig)]),
     "scw_tune_synthesis": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,

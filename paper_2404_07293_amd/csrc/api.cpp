@@ -757,6 +757,13 @@ int scw_batch_launch(scw_batch* b, void* E_dev, void* hip_stream) {
 
 void scw_batch_free(scw_batch* b) { delete b; }
 
+int scw_batch_configure(scw_batch* b, int radix, int blocks_per_cu, int chunk) {
+  if (!b) return fail(SCW_EINVAL, "null argument");
+  SCW_HIP(hipSetDevice(b->ctx->device));
+  // validates every argument before it changes the batch
+  return batch_set_shape(b, radix, blocks_per_cu, chunk);
+}
+
 long long scw_sur_param_count(void) { return sur_param_count(); }
 
 int scw_sur_create(scw_ctx* ctx, int max_batch, unsigned long long seed, scw_sur** out) {

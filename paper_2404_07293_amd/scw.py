@@ -211,6 +211,11 @@ class Batch:
                                           ctypes.c_void_p(stream.cuda_stream)))
         return out
 
+    def configure(self, radix, blocks_per_cu, chunk):
+        """``scw_batch_configure``: set the persistent kernel's shape."""
+        N.check(self.lib.scw_batch_configure(self.handle, int(radix), int(blocks_per_cu),
+                                             int(chunk)))
+
     def tune(self, out=None, stream=None, reps=3):
         """``scw_batch_tune``: sweep the persistent kernel's shapes and keep
         the fastest. Returns the report as a dict."""

@@ -101,4 +101,5 @@ def test_null_arguments_rejected_without_touching_the_gpu():
     assert lib.scw_synthesis_configure(None, None) == -1
     assert lib.scw_tune_synthesis(None, None, None, 1, None, None, 5, None) == -1
     assert lib.scw_batch_tune(None, None, None, 3, None) == -1
+    assert lib.scw_batch_configure(None, 16, 4, 1) == -1
     assert lib.scw_sur_set_compute(None, 1) == -1

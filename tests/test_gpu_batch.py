@@ -101,6 +101,43 @@ def test_batch_tuner_keeps_a_correct_shape(ctx):
     assert np.array_equal(again, tuned)
 
 
+@pytest.mark.parametrize("fx,fy", [(64, 64), (40, 32)])
+def test_batch_every_radix_matches_oracle(ctx, fx, fy):
+    """Every radix of the factored y pass, with the factored x pass (fx = 64,
+    one 8-point FFT per row and column group) and with Horner's rule (fx =
+    40), on jobs of uneven truncation; each shape against the FP64 oracle."""
+    import paper_2404_07293_amd as P
+    torch = _torch()
+    specs = [(31, 9, 9, 1.0), (32, 3, 5, 0.9), (33, 7, 3, 1.2), (34, 1, 1, 1.1)]
+    probs = [small_job(*s) for s in specs]
+    assert all(well_conditioned(p) for p in probs)
+    T = max(p.thickness for p in probs)
+    grid = W.Grid(fx=fx, fy=fy, fz=2, z_begin=T + 0.05, z_end=T + 0.7)
+    want = [cwt.simulate(p, grid)[2] for p in probs]
+    sols = [ctx.solve(p) for p in probs]
+    b = ctx.batch(sols, grid)
+    out = torch.empty_like(b.launch())
+    radix = 2
+    while radix <= min(32, fy):
+        for per_cu, chunk in ((1, 1), (4, 16)):
+            b.configure(radix, per_cu, chunk)
+            got = b.launch(out=out).cpu().numpy()
+            torch.cuda.synchronize()
+            errs = [rel_l2(got[j], want[j]) for j in range(len(probs))]
+            print("fx %d fy %d radix %d blocks/CU %d chunk %d: max rel-L2 %.3e" % (
+                fx, fy, radix, per_cu, chunk, max(errs)))
+            assert max(errs) <= FP32_TOL
+        radix *= 2
+    with pytest.raises(P.ScwError):
+        b.configure(3, 1, 1)
+    with pytest.raises(P.ScwError):
+        b.configure(2 * fy, 1, 1)
+    with pytest.raises(P.ScwError):
+        b.configure(2, 0, 1)
+    with pytest.raises(P.ScwError):
+        b.configure(2, 1, 0)
+
+
 def test_batch_above_the_sample(ctx):
     torch = _torch()
     probs = [small_job(7, 5, 3, 1.0), small_job(8, 3, 5, 0.8, nz=2)]
