@@ -41,7 +41,7 @@ def rel(a, b):
 def _net_and_data(ctx, B=3, seed=5):
     torch = _torch()
     from paper_2404_07293_amd.surrogate import Surrogate
-    sur = Surrogate(ctx, max_batch=8, seed=1)
+    sur = Surrogate(ctx, max_batch=max(8, B), seed=1)
     p = S.init_params(2)
     for k in range(S.N_LAYERS):
         p["spec%d" % k] *= 4.0
@@ -66,6 +66,19 @@ def test_forward_matches_reference(ctx):
     err = rel(got, want)
     print("surrogate forward rel-L2 %.3e" % err)
     assert err <= 1e-5
+
+
+def test_forward_matches_reference_over_several_tiles(ctx):
+    """37 patches: the layer mixing takes two tiles of 32 patches (the second
+    ragged) and the head's mixing ends on a partial group of 4."""
+    torch = _torch()
+    sur, p, x, tgt, xd, td = _net_and_data(ctx, B=37, seed=9)
+    got = sur.forward(xd).cpu().numpy()
+    torch.cuda.synchronize()
+    want = S.forward(p, x)
+    errs = [rel(got[i], want[i]) for i in range(len(x))]
+    print("surrogate forward, 37 patches: max per-patch rel-L2 %.3e" % max(errs))
+    assert max(errs) <= 1e-5
 
 
 def test_bf16_forward_matches_rounded_reference(ctx):
