@@ -232,6 +232,31 @@ typedef struct {
 int scw_tune_synthesis(scw_ctx* ctx, scw_solution* sol, const scw_grid* grid, int precision,
                        void* E_dev, void* hip_stream, int reps, scw_tune_report* report);
 
+/* The field on a lateral slice instead of a volume: Eq. 10 evaluated on an
+ * x-z plane (axis SCW_SLICE_XZ: x_f = f X / n for f < n, at y = position)
+ * or a y-z plane (SCW_SLICE_YZ: y_g = g Y / n, at x = position), for the fz
+ * cell-centred planes z_j = z_begin + (j + 1/2)(z_end - z_begin)/fz, inside
+ * or outside the sample as for scw_synthesize (X, Y: the lateral period;
+ * position: any real value, in the units of lambda). Per plane and
+ * component the spectrum is summed over the other lateral frequency with the
+ * phase of `position`, then over the kept one on the n samples.
+ * Precision SCW_FP64 (E_dev complex128) or SCW_FP32 (complex64); E_dev
+ * receives [3][fz][n], caller-owned. Enqueued on hip_stream after the
+ * solution's slice plan is built (the first call for a slice shape
+ * synchronises the stream). Errors: SCW_EINVAL for a null argument, an
+ * unknown axis, n < 1, fz < 1 or above 21845, z_end <= z_begin, or another
+ * precision. */
+enum { SCW_SLICE_XZ = 0, SCW_SLICE_YZ = 1 };
+typedef struct {
+    int axis;          /* SCW_SLICE_XZ or SCW_SLICE_YZ */
+    double position;   /* y of an x-z slice, x of a y-z slice */
+    int n;             /* samples along the kept lateral axis */
+    int fz;
+    double z_begin, z_end;
+} scw_slice;
+int scw_synthesize_slice(scw_ctx* ctx, scw_solution* sol, const scw_slice* slice, int precision,
+                         void* E_dev, void* hip_stream);
+
 /* Convenience: scw_solve + scw_synthesize + scw_solution_free. */
 int scw_field(scw_ctx* ctx, const scw_problem* prob, const scw_grid* grid,
               int precision, void* E_dev, void* hip_stream);

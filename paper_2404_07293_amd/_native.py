@@ -41,6 +41,14 @@ class ScwGrid(ctypes.Structure):
                 ("z_begin", ctypes.c_double), ("z_end", ctypes.c_double)]
 
 
+class ScwSlice(ctypes.Structure):
+    _fields_ = [("axis", ctypes.c_int), ("position", ctypes.c_double), ("n", ctypes.c_int),
+                ("fz", ctypes.c_int), ("z_begin", ctypes.c_double), ("z_end", ctypes.c_double)]
+
+
+SLICE_AXIS = {"xz": 0, "yz": 1}
+
+
 class ScwSolutionInfo(ctypes.Structure):
     _fields_ = [
         ("M", ctypes.c_int), ("L", ctypes.c_int),
@@ -83,6 +91,9 @@ SIGNATURES = {
     "scw_solution_free": (None, [ctypes.c_void_p]),
     "scw_solution_info_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ScwSolutionInfo)]),
     "scw_solution_exterior": (ctypes.c_int, [ctypes.c_void_p, c_dp, c_dp, c_dp]),
+    "scw_synthesize_slice": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.POINTER(ScwSlice), ctypes.c_int,
+                                            ctypes.c_void_p, ctypes.c_void_p]),
     "scw_synthesize": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ScwGrid),
                                       ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
     "scw_field": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ScwProblem),

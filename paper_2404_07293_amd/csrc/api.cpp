@@ -146,8 +146,8 @@ size_t fft_lds_bytes(const Solution& s, const scw_grid& g, int precision, int P)
   return ((size_t)s.U * s.V + 32 * 64 + 32 * (size_t)(g.fy / P)) * eb;
 }
 
-int build_plan(const Context& ctx, Solution& s, const scw_grid& g, int precision) {
-  Plan& pl = s.plan;
+int build_plan(const Context& ctx, Solution& s, Plan& pl, const scw_grid& g, int precision,
+               bool direct_only) {
   pl.valid = false;
   pl.grid = g;
   pl.precision = precision;
@@ -236,7 +236,8 @@ int build_plan(const Context& ctx, Solution& s, const scw_grid& g, int precision
       return rc;
   }
   // kernel configuration: explicit, tuned, or the built-in default
-  const scw_synth_config cfg = resolve_config(ctx, s, g, precision);
+  scw_synth_config cfg = resolve_config(ctx, s, g, precision);
+  if (direct_only) cfg = scw_synth_config{cfg.modal_rows, SCW_XFORM_DIRECT, 0, 0};
   pl.cfg = cfg;
   const bool split = precision == SCW_BF16X3 || precision == SCW_FP16X3;
   if (cfg.transform < SCW_XFORM_AUTO || cfg.transform > SCW_XFORM_DIRECT)
@@ -410,6 +411,11 @@ std::string synth_key(const Solution& s, const scw_grid& g, int precision) {
 
 int synthesize(Context& c, Solution& s, const scw_grid& g, int precision, void* E,
                hipStream_t st, int stages, hipEvent_t* ev) {
+  return synthesize(c, s, s.plan, g, precision, E, st, stages, ev, false);
+}
+
+int synthesize(Context& c, Solution& s, Plan& pl, const scw_grid& g, int precision, void* E,
+               hipStream_t st, int stages, hipEvent_t* ev, bool direct_only) {
   int rc;
   if (s.device != c.device) return fail(SCW_EINVAL, "solution belongs to another device");
   SCW_HIP(hipSetDevice(c.device));
@@ -418,13 +424,12 @@ int synthesize(Context& c, Solution& s, const scw_grid& g, int precision, void* 
     if ((rc = s.d_P32.reserve(pl_elems * 8))) return rc;
     SCW_HIP(launch_p_to_fp32(s.d_P64.as<double>(), s.d_P32.as<float>(), pl_elems, st));
   }
-  if (!s.plan.valid || s.plan.precision != precision || !same_grid(s.plan.grid, g) ||
-      s.plan.epoch != c.tune_epoch) {
+  if (!pl.valid || pl.precision != precision || !same_grid(pl.grid, g) ||
+      pl.epoch != c.tune_epoch) {
     SCW_HIP(hipStreamSynchronize(st));
-    if ((rc = build_plan(c, s, g, precision))) return rc;
-    s.plan.epoch = c.tune_epoch;
+    if ((rc = build_plan(c, s, pl, g, precision, direct_only))) return rc;
+    pl.epoch = c.tune_epoch;
   }
-  Plan& pl = s.plan;
   SynthArgs a{};
   a.M = s.M;
   a.U = s.U;
@@ -488,10 +493,43 @@ int scw_synthesize(scw_ctx* ctx, scw_solution* sol, const scw_grid* grid, int pr
                     kStageAll, ev);
 }
 
+int scw_synthesize_slice(scw_ctx* ctx, scw_solution* sol, const scw_slice* slice, int precision,
+                         void* E_dev, void* hip_stream) {
+  if (!ctx || !sol || !slice || !E_dev) return fail(SCW_EINVAL, "null argument");
+  if (slice->axis != SCW_SLICE_XZ && slice->axis != SCW_SLICE_YZ)
+    return fail(SCW_EINVAL, "slice axis must be SCW_SLICE_XZ or SCW_SLICE_YZ");
+  if (precision != SCW_FP64 && precision != SCW_FP32)
+    return fail(SCW_EINVAL, "a slice is synthesized in SCW_FP64 or SCW_FP32");
+  if (!std::isfinite(slice->position)) return fail(SCW_EINVAL, "slice position is not finite");
+  // the planes and lateral tables of an n x n grid; only its spectra are formed
+  const scw_grid g{slice->n, slice->n, slice->fz, slice->z_begin, slice->z_end};
+  int rc = check_grid(&g);
+  if (rc) return rc;
+  Solution& s = sol->s;
+  const hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  if ((rc = synthesize(ctx->c, s, s.slice_plan, g, precision, nullptr, st,
+                       kStageModal | kStageExterior, nullptr, true)))
+    return rc;
+  const Plan& pl = s.slice_plan;
+  SliceArgs a{};
+  a.spec = pl.d_spec.p;
+  a.tw = slice->axis == SCW_SLICE_XZ ? pl.d_twx.p : pl.d_twy.p;
+  a.U = s.U;
+  a.V = s.V;
+  a.n = slice->n;
+  a.fz = slice->fz;
+  a.axis = slice->axis;
+  a.frac = slice->axis == SCW_SLICE_XZ ? slice->position / s.Y : slice->position / s.X;
+  a.E = E_dev;
+  SCW_HIP(launch_slice(a, precision == SCW_FP64, st));
+  return SCW_OK;
+}
+
 int scw_synthesis_configure(scw_solution* sol, const scw_synth_config* cfg) {
   if (!sol) return fail(SCW_EINVAL, "null solution");
   sol->s.cfg = cfg ? *cfg : scw_synth_config{};
   sol->s.plan.valid = false;
+  sol->s.slice_plan.valid = false;
   return SCW_OK;
 }
 

@@ -586,6 +586,47 @@ __global__ void __launch_bounds__(256) idft_fft_kernel(
   }
 }
 
+// ---------------------------------------------------------------- lateral slice
+// Eq. 10 on an x-z (axis 0) or y-z (axis 1) plane. One block per plane and
+// component: the spectrum's other lateral index is summed first with the
+// phase of the slice position, T[k] = sum_j S e^{2 pi i (j - J/2) frac}
+// (in FP64; the J phases per block are few), then the kept index runs on the
+// n samples by Horner's rule as in the volume's x pass.
+template <typename T>
+__global__ void __launch_bounds__(256) slice_kernel(const cx<T>* __restrict__ spec,
+                                                    const cx<T>* __restrict__ tw, int U, int V,
+                                                    int n, int fz, int axis, double frac,
+                                                    cx<T>* __restrict__ E) {
+  extern __shared__ unsigned char smem_raw[];
+  cx<T>* S = reinterpret_cast<cx<T>*>(smem_raw);  // [V][U]
+  cx<T>* Tk = S + U * V;                          // [K]
+  const int M = U * V, pc = blockIdx.x;
+  const cx<T>* src = spec + (long long)pc * M;
+  for (int i = threadIdx.x; i < M; i += blockDim.x) S[i] = src[i];
+  __syncthreads();
+  const int K = axis == 0 ? U : V, J = axis == 0 ? V : U;
+  for (int k = threadIdx.x; k < K; k += blockDim.x) {
+    double re = 0.0, im = 0.0;
+    for (int j = 0; j < J; ++j) {
+      double sn, cs;
+      sincospi(2.0 * (j - J / 2) * frac, &sn, &cs);
+      const cx<T> v = axis == 0 ? S[j * U + k] : S[k * U + j];
+      re += (double)v.x * cs - (double)v.y * sn;
+      im += (double)v.x * sn + (double)v.y * cs;
+    }
+    Tk[k] = {(T)re, (T)im};
+  }
+  __syncthreads();
+  const int plane = pc / 3, comp = pc % 3;
+  cx<T>* dst = E + ((long long)comp * fz + plane) * n;
+  for (int f = threadIdx.x; f < n; f += blockDim.x) {
+    const cx<T> w = tw[f], sh = tw[n + f];
+    cx<T> acc = Tk[K - 1];
+    for (int k = K - 2; k >= 0; --k) acc = cmuladd(acc, w, Tk[k]);
+    dst[f] = cmul(acc, sh);
+  }
+}
+
 template <typename T>
 hipError_t launch_idft_fft(const SynthArgs& a, hipStream_t s) {
   const int P = a.fft_p, R = a.fy / P;
@@ -723,6 +764,20 @@ hipError_t launch_synthesis(const SynthArgs& a, hipStream_t s, hipEvent_t* ev) {
 hipError_t launch_synthesis_fp64(const SynthArgs& a, hipStream_t s, hipEvent_t* ev) {
   return launch_synthesis<double>(a, s, ev);
 }
+hipError_t launch_slice(const SliceArgs& a, bool fp64, hipStream_t s) {
+  const int K = a.axis == 0 ? a.U : a.V;
+  if (a.fz * 3 < 1) return hipSuccess;
+  auto go = [&](auto tag) -> hipError_t {
+    using T = decltype(tag);
+    const size_t lds = ((size_t)a.U * a.V + K) * sizeof(cx<T>);
+    slice_kernel<T><<<a.fz * 3, 256, lds, s>>>(
+        reinterpret_cast<const cx<T>*>(a.spec), reinterpret_cast<const cx<T>*>(a.tw), a.U, a.V,
+        a.n, a.fz, a.axis, a.frac, reinterpret_cast<cx<T>*>(a.E));
+    return hipGetLastError();
+  };
+  return fp64 ? go(double{}) : go(float{});
+}
+
 hipError_t launch_synthesis_fp32(const SynthArgs& a, hipStream_t s, hipEvent_t* ev) {
   return launch_synthesis<float>(a, s, ev);
 }

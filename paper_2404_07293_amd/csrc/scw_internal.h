@@ -136,6 +136,7 @@ struct Solution {
   DevBuf d_ext;      // [3][3M] complex128: p_inc, p_ref, p_trn
   DevBuf d_ksz;      // [2][M] complex128: k*sz_top, k*sz_bot
   Plan plan;
+  Plan slice_plan;         // spectra of the planes of the last slice shape
   scw_synth_config cfg{};  // explicit kernel configuration (0 fields: library choice)
   int device = 0;
 };
@@ -167,6 +168,10 @@ enum StageMask { kStageModal = 1, kStageExterior = 2, kStageTransform = 4, kStag
 // `ev` (nullable) receives kNumStages + 1 stage events.
 int synthesize(Context& ctx, Solution& s, const scw_grid& g, int precision, void* E,
                hipStream_t st, int stages, hipEvent_t* ev);
+// The same with an explicit plan; direct_only builds it for the direct-sum
+// transform, which accepts any lateral size (the slices use only its tables).
+int synthesize(Context& ctx, Solution& s, Plan& pl, const scw_grid& g, int precision, void* E,
+               hipStream_t st, int stages, hipEvent_t* ev, bool direct_only);
 std::string synth_key(const Solution& s, const scw_grid& g, int precision);
 
 // ------------------------------------------------------------------ setup
@@ -364,5 +369,17 @@ hipError_t launch_idft_mfma(const MfmaArgs& a, int precision, hipStream_t s);
 // `ev`, when non-null, holds kNumStages + 1 events recorded around the stages.
 hipError_t launch_synthesis_fp64(const SynthArgs& a, hipStream_t s, hipEvent_t* ev);
 hipError_t launch_synthesis_fp32(const SynthArgs& a, hipStream_t s, hipEvent_t* ev);
+// A lateral slice from the per-plane spectra [fz][3M] (complex<T>): axis 0
+// sums over v with e^{2 pi i (v - V/2) frac} and runs u on the n samples with
+// tw = [2][n] (e^{2 pi i f/n}, e^{-2 pi i (U/2) f/n}); axis 1 the same with
+// u and v exchanged. E: [3][fz][n] complex<T>.
+struct SliceArgs {
+  const void* spec;
+  const void* tw;
+  int U, V, n, fz, axis;
+  double frac;  // position / period of the summed axis
+  void* E;
+};
+hipError_t launch_slice(const SliceArgs& a, bool fp64, hipStream_t s);
 
 }  // namespace scw

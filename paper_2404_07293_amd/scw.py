@@ -145,6 +145,34 @@ class Solution:
                                         ctypes.c_void_p(stream.cuda_stream)))
         return out
 
+    def synthesize_slice(self, axis, position, n, fz, z_begin, z_end, precision="fp32",
+                         out=None, stream=None):
+        """Enqueue ``scw_synthesize_slice``: the field on an x-z ("xz", at
+        y = position) or y-z ("yz", at x = position) plane with n lateral
+        samples and fz planes over [z_begin, z_end), into ``out`` (a CUDA
+        tensor [3, fz, n]; allocated when None). Returns the tensor."""
+        import torch
+        if precision not in ("fp32", "fp64"):
+            raise ValueError("a slice is synthesized in fp32 or fp64")
+        dt = torch.complex128 if precision == "fp64" else torch.complex64
+        dev = torch.device("cuda", self.ctx.device)
+        shape = (3, int(fz), int(n))
+        if out is None:
+            out = torch.empty(shape, dtype=dt, device=dev)
+        if tuple(out.shape) != shape or out.dtype != dt or not out.is_contiguous() \
+                or out.device != dev:
+            raise ValueError("out must be a contiguous %s tensor of shape %s on %s"
+                             % (dt, shape, dev))
+        if stream is None:
+            stream = torch.cuda.current_stream(dev)
+        sl = N.ScwSlice(N.SLICE_AXIS[axis], float(position), int(n), int(fz), float(z_begin),
+                        float(z_end))
+        N.check(self.lib.scw_synthesize_slice(self.ctx.handle, self.handle, ctypes.byref(sl),
+                                              N.PRECISION[precision],
+                                              ctypes.c_void_p(out.data_ptr()),
+                                              ctypes.c_void_p(stream.cuda_stream)))
+        return out
+
     def configure(self, modal_rows=0, transform="auto", fft_radix=0, tiles=0):
         """``scw_synthesis_configure``: explicit kernel configuration (0 /
         "auto" fields leave the library's choice)."""

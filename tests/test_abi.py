@@ -48,6 +48,9 @@ int main(void) {
   F(scw_tune_report, n_candidates) F(scw_tune_report, default_ms) F(scw_tune_report, best_ms)
   F(scw_tune_report, config) F(scw_tune_report, batch_radix)
   F(scw_tune_report, batch_blocks_per_cu) F(scw_tune_report, batch_chunk)
+  F(scw_slice, axis) F(scw_slice, position) F(scw_slice, n) F(scw_slice, fz)
+  F(scw_slice, z_begin) F(scw_slice, z_end)
+  printf("size scw_slice %zu\n", sizeof(scw_slice));
   printf("size scw_problem %zu\nsize scw_grid %zu\nsize scw_solution_info %zu\n",
          sizeof(scw_problem), sizeof(scw_grid), sizeof(scw_solution_info));
   printf("size scw_synth_config %zu\nsize scw_tune_report %zu\n",
@@ -68,7 +71,7 @@ def test_ctypes_structures_match_c_layout():
     rename = {"lambda": "lam"}
     types = {"scw_problem": N.ScwProblem, "scw_grid": N.ScwGrid,
              "scw_solution_info": N.ScwSolutionInfo, "scw_synth_config": N.ScwSynthConfig,
-             "scw_tune_report": N.ScwTuneReport}
+             "scw_tune_report": N.ScwTuneReport, "scw_slice": N.ScwSlice}
     for line in _c_layout():
         if not line:
             continue
@@ -102,4 +105,5 @@ def test_null_arguments_rejected_without_touching_the_gpu():
     assert lib.scw_tune_synthesis(None, None, None, 1, None, None, 5, None) == -1
     assert lib.scw_batch_tune(None, None, None, 3, None) == -1
     assert lib.scw_batch_configure(None, 16, 4, 1) == -1
+    assert lib.scw_synthesize_slice(None, None, None, 1, None, None) == -1
     assert lib.scw_sur_set_compute(None, 1) == -1
