@@ -498,6 +498,32 @@ def field_at_points(st, sol, x, y, z):
     return out
 
 
+# --------------------------------------------------------------------------
+# Optics: an ideal objective acting on the plane-wave spectrum (Sec. 1: the
+# Fourier representation lets an optical system be applied directly to the
+# field's spectrum).
+# --------------------------------------------------------------------------
+def objective_pass(st, na):
+    """Coherent transfer function of an ideal objective of numerical aperture
+    na, unit magnification: 1 for the modes whose direction sine
+    |s_bar| = sqrt(s_x^2 + s_y^2) is at most na, else 0."""
+    return (st.sx ** 2 + st.sy ** 2 <= na * na).astype(float)
+
+
+def image(st, sol, grid, na):
+    """The field through the objective on the grid (Eq. 10 with every mode's
+    coefficients multiplied by the transfer function) and its intensity
+    |E_x|^2 + |E_y|^2 + |E_z|^2; returns (E [3, fz, fy, fx], I [fz, fy, fx])."""
+    H = objective_pass(st, na)
+    Wx, Wy = dft_matrices(st, grid.fx, grid.fy)
+    E = np.zeros((3, grid.fz, grid.fy, grid.fx), dtype=np.complex128)
+    for j, z in enumerate(grid.z_planes()):
+        p = plane_coefficients(st, sol, z) * H
+        for c in range(3):
+            E[c, j] = Wy @ p[c].reshape(st.V, st.U) @ Wx.T
+    return E, np.sum(np.abs(E) ** 2, axis=0)
+
+
 def simulate(prob, grid, route="unreduced"):
     st = setup(prob)
     sol = solve(st, route)
