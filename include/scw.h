@@ -257,6 +257,18 @@ typedef struct {
 int scw_synthesize_slice(scw_ctx* ctx, scw_solution* sol, const scw_slice* slice, int precision,
                          void* E_dev, void* hip_stream);
 
+/* Coherent imaging through an ideal objective (Sec. 1: an optical system
+ * applied to the field's plane-wave spectrum): the field of scw_synthesize on
+ * `grid`, with every mode whose direction sine |s_bar| = sqrt(s_x^2 + s_y^2)
+ * exceeds `na` removed before Eq. 10 (the objective's coherent transfer
+ * function, unit magnification), and its intensity |E_x|^2 + |E_y|^2 +
+ * |E_z|^2. E_dev as for scw_synthesize (it receives the filtered field);
+ * I_dev, when not null, receives [fz][fy][fx] float (double for SCW_FP64),
+ * caller-owned. Errors as scw_synthesize, and SCW_EINVAL for na < 0 or not
+ * finite. */
+int scw_synthesize_image(scw_ctx* ctx, scw_solution* sol, const scw_grid* grid, int precision,
+                         double na, void* E_dev, void* I_dev, void* hip_stream);
+
 /* Convenience: scw_solve + scw_synthesize + scw_solution_free. */
 int scw_field(scw_ctx* ctx, const scw_problem* prob, const scw_grid* grid,
               int precision, void* E_dev, void* hip_stream);

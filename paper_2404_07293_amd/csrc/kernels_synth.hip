@@ -627,6 +627,27 @@ __global__ void __launch_bounds__(256) slice_kernel(const cx<T>* __restrict__ sp
   }
 }
 
+// ---------------------------------------------------------------- objective, intensity
+// An ideal objective's coherent transfer function on the per-plane spectra:
+// modes whose direction sine exceeds the numerical aperture are removed.
+template <typename T>
+__global__ void objective_kernel(cx<T>* __restrict__ spec, long long n, int M, int U, int V,
+                                 double sx_step, double sy_step, double na2) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int m = (int)(i % M);
+  const double sx = (m % U - U / 2) * sx_step, sy = (m / U - V / 2) * sy_step;
+  if (sx * sx + sy * sy > na2) spec[i] = {0, 0};
+}
+
+template <typename T>
+__global__ void intensity_kernel(const cx<T>* __restrict__ E, T* __restrict__ I, long long npix) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npix) return;
+  const cx<T> a = E[i], b = E[npix + i], c = E[2 * npix + i];
+  I[i] = a.x * a.x + a.y * a.y + b.x * b.x + b.y * b.y + c.x * c.x + c.y * c.y;
+}
+
 template <typename T>
 hipError_t launch_idft_fft(const SynthArgs& a, hipStream_t s) {
   const int P = a.fft_p, R = a.fy / P;
@@ -764,6 +785,31 @@ hipError_t launch_synthesis(const SynthArgs& a, hipStream_t s, hipEvent_t* ev) {
 hipError_t launch_synthesis_fp64(const SynthArgs& a, hipStream_t s, hipEvent_t* ev) {
   return launch_synthesis<double>(a, s, ev);
 }
+hipError_t launch_objective(void* spec, long long n, int M, int U, int V, double sx_step,
+                            double sy_step, double na, bool fp64, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const unsigned nb = blocks_for(n, 256);
+  if (fp64)
+    objective_kernel<double><<<nb, 256, 0, s>>>(reinterpret_cast<cx<double>*>(spec), n, M, U, V,
+                                                sx_step, sy_step, na * na);
+  else
+    objective_kernel<float><<<nb, 256, 0, s>>>(reinterpret_cast<cx<float>*>(spec), n, M, U, V,
+                                               sx_step, sy_step, na * na);
+  return hipGetLastError();
+}
+
+hipError_t launch_intensity(const void* E, void* I, long long npix, bool fp64, hipStream_t s) {
+  if (npix <= 0) return hipSuccess;
+  const unsigned nb = blocks_for(npix, 256);
+  if (fp64)
+    intensity_kernel<double><<<nb, 256, 0, s>>>(reinterpret_cast<const cx<double>*>(E),
+                                                reinterpret_cast<double*>(I), npix);
+  else
+    intensity_kernel<float><<<nb, 256, 0, s>>>(reinterpret_cast<const cx<float>*>(E),
+                                               reinterpret_cast<float*>(I), npix);
+  return hipGetLastError();
+}
+
 hipError_t launch_slice(const SliceArgs& a, bool fp64, hipStream_t s) {
   const int K = a.axis == 0 ? a.U : a.V;
   if (a.fz * 3 < 1) return hipSuccess;

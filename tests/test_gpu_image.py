@@ -1,0 +1,71 @@
+"""Coherent imaging through an ideal objective (scw_synthesize_image) against
+the FP64 oracle (cwt.image): the filtered field and its intensity, on planes
+above, inside and below a lossy sample, for apertures from the axial wave
+alone to the whole spectrum."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import cwt
+
+pytestmark = pytest.mark.gpu
+TOL = {"fp64": 1e-10, "fp32": 1e-4, "bf16x3": 1e-4}
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    _torch()
+    import paper_2404_07293_amd as P
+    return P.Context(0)
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def case(ctx):
+    rng = np.random.default_rng(12)
+    n = 1.3 + 0.3 * rng.random((3, 6, 8)) + 0.04j * rng.random((3, 6, 8))
+    prob = W.Problem(n=n.astype(complex), px=0.31, py=0.27, pz=0.19, lam=1.0, U=5, V=5,
+                     n_top=1.0, n_bot=1.45 + 0.01j,
+                     plane_wave=W.PlaneWave(1, -1, 0.8, 0.3 - 0.2j))
+    st = cwt.setup(prob)
+    ref = cwt.solve(st)
+    grid = W.Grid(fx=12, fy=10, fz=9, z_begin=-0.35, z_end=prob.thickness + 0.35)
+    return prob, st, ref, grid, ctx.solve(prob)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
+def test_image_matches_oracle(case, precision):
+    torch = _torch()
+    prob, st, ref, grid, sol = case
+    r = np.sqrt(st.sx ** 2 + st.sy ** 2)
+    for na in (0.0, 0.3, 0.75, 1.1, 10.0):
+        # the aperture stays clear of every mode's direction sine, so both
+        # sides take the same pass/stop decision for every mode
+        assert na == 0.0 or np.min(np.abs(r - na)) > 1e-6
+        E, I = sol.image(grid, na, precision)
+        E, I = E.cpu().numpy(), I.cpu().numpy()
+        torch.cuda.synchronize()
+        want_E, want_I = cwt.image(st, ref, grid, na)
+        eE, eI = rel_l2(E, want_E), rel_l2(I, want_I)
+        print("%s NA %.2f: %d of %d modes pass; field rel-L2 %.3e, intensity rel-L2 %.3e"
+              % (precision, na, int(np.sum(r <= na)), st.M, eE, eI))
+        assert eE <= TOL[precision]
+        assert eI <= 2 * TOL[precision]
+
+
+def test_image_rejects_bad_aperture(case):
+    import paper_2404_07293_amd as P
+    prob, st, ref, grid, sol = case
+    for na in (-0.1, float("nan"), float("inf")):
+        with pytest.raises(P.ScwError):
+            sol.image(grid, na)
