@@ -209,6 +209,55 @@ def sphere_leg(ctx, torch, dev, stream, args):
             "note": "launch-latency bound; correctness workload"}
 
 
+def optics_leg(sol, prob, grid, E_volume, torch, dev, stream, args):
+    """Lateral slice and objective image on the working workload: an x-z
+    slice through all planes at y = Y/3 (n = fx), and the image through an
+    NA 0.8 objective with its intensity on the whole grid. The slice is
+    checked against the volume's row where the two coincide (y = Y/2 here),
+    the wide-aperture image against the stored oracle samples."""
+    Y = prob.ny * prob.py
+    Es = torch.empty((3, grid.fz, grid.fx), dtype=torch.complex64, device=dev)
+    Ei = torch.empty((3, grid.fz, grid.fy, grid.fx), dtype=torch.complex64, device=dev)
+    Ii = torch.empty((grid.fz, grid.fy, grid.fx), dtype=torch.float32, device=dev)
+
+    def timed(call):
+        for _ in range(max(2, args.warmup)):
+            call()
+        torch.cuda.synchronize()
+        s0 = torch.cuda.Event(enable_timing=True)
+        s1 = torch.cuda.Event(enable_timing=True)
+        s0.record(stream)
+        for _ in range(args.steps):
+            call()
+        s1.record(stream)
+        torch.cuda.synchronize()
+        return s0.elapsed_time(s1) / args.steps
+
+    slice_ms = timed(lambda: sol.synthesize_slice("xz", Y / 3, grid.fx, grid.fz, grid.z_begin,
+                                                  grid.z_end, "fp32", out=Es, stream=stream))
+    g0 = grid.fy // 2
+    sol.synthesize_slice("xz", g0 * Y / grid.fy, grid.fx, grid.fz, grid.z_begin, grid.z_end,
+                         "fp32", out=Es, stream=stream)
+    row = E_volume[:, :, g0, :]
+    slice_vs_volume = float(torch.linalg.vector_norm(Es - row) / torch.linalg.vector_norm(row))
+    image_ms = timed(lambda: sol.image(grid, 0.8, "fp32", out=Ei, intensity=Ii, stream=stream))
+    sol.image(grid, 100.0, "fp32", out=Ei, intensity=Ii, stream=stream)
+    torch.cuda.synchronize()
+    wide_err = golden_error(Ei, prob, grid)
+    vox = grid.fx * grid.fz
+    log("x-z slice: %.4f ms (%d planes x %d samples), rel-L2 vs the volume row %.2e; "
+        "NA 0.8 image + intensity: %.4f ms, full-aperture image rel-L2 %s" % (
+            slice_ms, grid.fz, grid.fx, slice_vs_volume, image_ms, wide_err))
+    return {"slice_xz": {"ms": slice_ms, "samples": vox, "planes": grid.fz,
+                         "rel_l2_vs_volume_row": slice_vs_volume,
+                         "note": "spectra of every plane (the modal sum) + one slice transform"},
+            "image_na08": {"ms": image_ms, "voxels_per_s": grid.fx * grid.fy * grid.fz /
+                           (image_ms * 1e-3),
+                           "full_aperture_rel_l2_vs_oracle": wide_err,
+                           "note": "synthesis with the objective's transfer function on the "
+                                   "spectra, plus the intensity pass"}}
+
+
 SWEEP_GOLDEN = os.path.join(ROOT, "tests", "golden", "sweep_job.npz")
 LARGE_GOLDEN = os.path.join(ROOT, "tests", "golden", "large_samples.npz")
 
@@ -649,6 +698,9 @@ def main(argv=None):
             log("%s: ms/step %.4f rel-L2 %s" % (prec, vms, variants[prec]["rel_l2_vs_oracle"]))
             del Ev
         out["variants"] = variants
+    if args.workload == "working" and args.precision == "fp32":
+        out.setdefault("variants", {})["optics"] = optics_leg(sol, prob, grid, E, torch, dev,
+                                                             stream, args)
     if args.workload == "working":
         out.setdefault("variants", {})["sphere_fp64"] = sphere_leg(ctx, torch, dev, stream, args)
     if args.large and args.workload == "working":
