@@ -524,6 +524,21 @@ def image(st, sol, grid, na):
     return E, np.sum(np.abs(E) ** 2, axis=0)
 
 
+def filtered(st, sol, grid, H):
+    """The field with a transfer function H[m] (complex, one value per mode in
+    mode order) applied to every plane's plane-wave coefficients before Eq. 10
+    (Sec. 1: optical elements act linearly on the spectrum), and its
+    intensity; returns (E [3, fz, fy, fx], I [fz, fy, fx])."""
+    H = np.asarray(H, dtype=np.complex128)
+    Wx, Wy = dft_matrices(st, grid.fx, grid.fy)
+    E = np.zeros((3, grid.fz, grid.fy, grid.fx), dtype=np.complex128)
+    for j, z in enumerate(grid.z_planes()):
+        p = plane_coefficients(st, sol, z) * H
+        for c in range(3):
+            E[c, j] = Wy @ p[c].reshape(st.V, st.U) @ Wx.T
+    return E, np.sum(np.abs(E) ** 2, axis=0)
+
+
 def simulate(prob, grid, route="unreduced"):
     st = setup(prob)
     sol = solve(st, route)

@@ -74,3 +74,33 @@ def test_objective_on_a_plane_wave_in_a_uniform_medium():
     np.testing.assert_allclose(I, 1.0, rtol=1e-12)
     E0, I0 = cwt.image(st, sol, grid, 0.95 * sx)
     assert np.abs(E0).max() < 1e-14 and np.abs(I0).max() < 1e-28
+
+
+def test_transfer_function_of_ones_and_of_the_objective():
+    prob = _lossy_problem(seed=7)
+    st = cwt.setup(prob)
+    sol = cwt.solve(st)
+    grid = _grid(prob)
+    E1, _ = cwt.filtered(st, sol, grid, np.ones(st.M))
+    np.testing.assert_array_equal(E1, cwt.synthesize(st, sol, grid))
+    Eo, Io = cwt.filtered(st, sol, grid, cwt.objective_pass(st, 0.7))
+    Ei, Ii = cwt.image(st, sol, grid, 0.7)
+    np.testing.assert_array_equal(Eo, Ei)
+    np.testing.assert_array_equal(Io, Ii)
+
+
+def test_propagation_transfer_function_moves_the_transmitted_field():
+    # below the sample every mode is a plane wave exp(i k s_z (z - zL)) of the
+    # bottom medium: the transfer function exp(i k s_z dz) applied at z must
+    # give the field at z + dz
+    prob = _lossy_problem(seed=8)
+    st = cwt.setup(prob)
+    sol = cwt.solve(st)
+    T = prob.thickness
+    dz = 0.23
+    near = W.Grid(fx=9, fy=7, fz=4, z_begin=T + 0.05, z_end=T + 0.45)
+    far = W.Grid(fx=9, fy=7, fz=4, z_begin=T + 0.05 + dz, z_end=T + 0.45 + dz)
+    H = np.exp(1j * st.k * st.sz_bot * dz)
+    E, I = cwt.filtered(st, sol, near, H)
+    want = cwt.synthesize(st, sol, far)
+    np.testing.assert_allclose(E, want, rtol=1e-11, atol=1e-13 * np.abs(want).max())
