@@ -269,6 +269,19 @@ int scw_synthesize_slice(scw_ctx* ctx, scw_solution* sol, const scw_slice* slice
 int scw_synthesize_image(scw_ctx* ctx, scw_solution* sol, const scw_grid* grid, int precision,
                          double na, void* E_dev, void* I_dev, void* hip_stream);
 
+/* The field of scw_synthesize with a transfer function applied to the
+ * plane-wave spectrum before Eq. 10 (Sec. 1: optical elements act linearly on
+ * the spectrum): on every plane, each mode m's coefficients are multiplied by
+ * H[m]. Examples: apodization or phase plates; an ideal objective,
+ * H[m] = [|s_bar_m| <= NA] (as scw_synthesize_image); propagation by dz in a
+ * half-space whose s_z is s_z,m, H[m] = exp(i k s_z,m dz). H_dev: device
+ * complex128 [M] in mode order m = (v + V/2) U + (u + U/2), caller-owned,
+ * read by the kernels enqueued on hip_stream. E_dev and I_dev as for
+ * scw_synthesize_image. Errors as scw_synthesize, and SCW_EINVAL for a null
+ * H_dev. */
+int scw_synthesize_filtered(scw_ctx* ctx, scw_solution* sol, const scw_grid* grid, int precision,
+                            const void* H_dev, void* E_dev, void* I_dev, void* hip_stream);
+
 /* Convenience: scw_solve + scw_synthesize + scw_solution_free. */
 int scw_field(scw_ctx* ctx, const scw_problem* prob, const scw_grid* grid,
               int precision, void* E_dev, void* hip_stream);

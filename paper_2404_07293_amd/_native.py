@@ -91,6 +91,10 @@ SIGNATURES = {
     "scw_solution_free": (None, [ctypes.c_void_p]),
     "scw_solution_info_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ScwSolutionInfo)]),
     "scw_solution_exterior": (ctypes.c_int, [ctypes.c_void_p, c_dp, c_dp, c_dp]),
+    "scw_synthesize_filtered": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
+                                               ctypes.POINTER(ScwGrid), ctypes.c_int,
+                                               ctypes.c_void_p, ctypes.c_void_p,
+                                               ctypes.c_void_p, ctypes.c_void_p]),
     "scw_synthesize_image": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
                                             ctypes.POINTER(ScwGrid), ctypes.c_int,
                                             ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <functional>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -525,8 +526,11 @@ int scw_synthesize_slice(scw_ctx* ctx, scw_solution* sol, const scw_slice* slice
   return SCW_OK;
 }
 
-int scw_synthesize_image(scw_ctx* ctx, scw_solution* sol, const scw_grid* grid, int precision,
-                         double na, void* E_dev, void* I_dev, void* hip_stream) {
+// The spectra of the grid's planes, `op` on them, then Eq. 10 and (when I_dev
+// is not null) the intensity.
+static int synthesize_with(scw_ctx* ctx, scw_solution* sol, const scw_grid* grid, int precision,
+                           void* E_dev, void* I_dev, void* hip_stream,
+                           const std::function<hipError_t(Solution&, hipStream_t)>& op) {
   if (!ctx || !sol || !E_dev) return fail(SCW_EINVAL, "null argument");
   int rc = check_grid(grid);
   if (rc) return rc;
@@ -534,20 +538,40 @@ int scw_synthesize_image(scw_ctx* ctx, scw_solution* sol, const scw_grid* grid, 
     return fail(SCW_EINVAL, "unknown precision " + std::to_string(precision));
   if ((precision == SCW_BF16X3 || precision == SCW_FP16X3) && sol->s.V > 32)
     return fail(SCW_EINVAL, "split-precision transform needs V <= 32");
-  if (!(na >= 0.0) || !std::isfinite(na)) return fail(SCW_EINVAL, "na must be finite and >= 0");
   Context& c = ctx->c;
   Solution& s = sol->s;
   const hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
-  // the spectra of the planes, the objective on them, then Eq. 10
   if ((rc = synthesize(c, s, *grid, precision, E_dev, st, kStageModal | kStageExterior, nullptr)))
     return rc;
-  const bool fp64 = precision == SCW_FP64;
-  SCW_HIP(launch_objective(s.plan.d_spec.p, (long long)grid->fz * 3 * s.M, s.M, s.U, s.V,
-                           s.lam / s.X, s.lam / s.Y, na, fp64, st));
+  SCW_HIP(op(s, st));
   if ((rc = synthesize(c, s, *grid, precision, E_dev, st, kStageTransform, nullptr))) return rc;
   if (I_dev)
-    SCW_HIP(launch_intensity(E_dev, I_dev, (long long)grid->fz * grid->fy * grid->fx, fp64, st));
+    SCW_HIP(launch_intensity(E_dev, I_dev, (long long)grid->fz * grid->fy * grid->fx,
+                             precision == SCW_FP64, st));
   return SCW_OK;
+}
+
+int scw_synthesize_image(scw_ctx* ctx, scw_solution* sol, const scw_grid* grid, int precision,
+                         double na, void* E_dev, void* I_dev, void* hip_stream) {
+  if (!(na >= 0.0) || !std::isfinite(na)) return fail(SCW_EINVAL, "na must be finite and >= 0");
+  return synthesize_with(ctx, sol, grid, precision, E_dev, I_dev, hip_stream,
+                         [&](Solution& s, hipStream_t st) {
+                           return launch_objective(s.plan.d_spec.p,
+                                                   (long long)grid->fz * 3 * s.M, s.M, s.U, s.V,
+                                                   s.lam / s.X, s.lam / s.Y, na,
+                                                   precision == SCW_FP64, st);
+                         });
+}
+
+int scw_synthesize_filtered(scw_ctx* ctx, scw_solution* sol, const scw_grid* grid, int precision,
+                            const void* H_dev, void* E_dev, void* I_dev, void* hip_stream) {
+  if (!H_dev) return fail(SCW_EINVAL, "null transfer function");
+  return synthesize_with(ctx, sol, grid, precision, E_dev, I_dev, hip_stream,
+                         [&](Solution& s, hipStream_t st) {
+                           return launch_transfer(s.plan.d_spec.p,
+                                                  (long long)grid->fz * 3 * s.M, s.M, H_dev,
+                                                  precision == SCW_FP64, st);
+                         });
 }
 
 int scw_synthesis_configure(scw_solution* sol, const scw_synth_config* cfg) {

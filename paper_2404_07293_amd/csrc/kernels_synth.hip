@@ -640,6 +640,18 @@ __global__ void objective_kernel(cx<T>* __restrict__ spec, long long n, int M, i
   if (sx * sx + sy * sy > na2) spec[i] = {0, 0};
 }
 
+// A general transfer function on the per-plane spectra: every mode's
+// coefficients times H[m] (complex128, applied in FP64).
+template <typename T>
+__global__ void transfer_kernel(cx<T>* __restrict__ spec, long long n, int M,
+                                const double2* __restrict__ H) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double2 h = H[i % M];
+  const cx<T> v = spec[i];
+  spec[i] = {(T)((double)v.x * h.x - (double)v.y * h.y), (T)((double)v.x * h.y + (double)v.y * h.x)};
+}
+
 template <typename T>
 __global__ void intensity_kernel(const cx<T>* __restrict__ E, T* __restrict__ I, long long npix) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -795,6 +807,18 @@ hipError_t launch_objective(void* spec, long long n, int M, int U, int V, double
   else
     objective_kernel<float><<<nb, 256, 0, s>>>(reinterpret_cast<cx<float>*>(spec), n, M, U, V,
                                                sx_step, sy_step, na * na);
+  return hipGetLastError();
+}
+
+hipError_t launch_transfer(void* spec, long long n, int M, const void* H, bool fp64,
+                           hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const unsigned nb = blocks_for(n, 256);
+  const double2* h = reinterpret_cast<const double2*>(H);
+  if (fp64)
+    transfer_kernel<double><<<nb, 256, 0, s>>>(reinterpret_cast<cx<double>*>(spec), n, M, h);
+  else
+    transfer_kernel<float><<<nb, 256, 0, s>>>(reinterpret_cast<cx<float>*>(spec), n, M, h);
   return hipGetLastError();
 }
 

@@ -385,6 +385,9 @@ hipError_t launch_slice(const SliceArgs& a, bool fp64, hipStream_t s);
 // (u sx_step)^2 + (v sy_step)^2 > na^2 (u, v the mode's frequency indices).
 hipError_t launch_objective(void* spec, long long n, int M, int U, int V, double sx_step,
                             double sy_step, double na, bool fp64, hipStream_t s);
+// spec[i] *= H[i mod M] over the spectra [n / M][M] (H: complex128 [M]).
+hipError_t launch_transfer(void* spec, long long n, int M, const void* H, bool fp64,
+                           hipStream_t s);
 // I[i] = sum_c |E[c][i]|^2 over the three components of [3][npix].
 hipError_t launch_intensity(const void* E, void* I, long long npix, bool fp64, hipStream_t s);
 

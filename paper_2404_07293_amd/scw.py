@@ -167,6 +167,35 @@ class Solution:
                                               ctypes.c_void_p(stream.cuda_stream)))
         return out, intensity
 
+    def filtered(self, grid, H, precision="fp32", out=None, intensity=None, stream=None):
+        """Enqueue ``scw_synthesize_filtered``: the field with the transfer
+        function ``H`` (M complex values in mode order, numpy or torch)
+        applied to every plane's spectrum, into ``out`` [3, fz, fy, fx], and
+        its intensity into ``intensity`` [fz, fy, fx]; both allocated when
+        None. Returns (out, intensity)."""
+        import torch
+        out, stream = self._out(grid, precision, out, stream)
+        dt = torch.float64 if precision == "fp64" else torch.float32
+        shape = (int(grid.fz), int(grid.fy), int(grid.fx))
+        if intensity is None:
+            intensity = torch.empty(shape, dtype=dt, device=out.device)
+        if tuple(intensity.shape) != shape or intensity.dtype != dt \
+                or not intensity.is_contiguous() or intensity.device != out.device:
+            raise ValueError("intensity must be a contiguous %s tensor of shape %s on %s"
+                             % (dt, shape, out.device))
+        h = torch.as_tensor(H).to(device=out.device, dtype=torch.complex128).contiguous()
+        if h.numel() != self.info()["M"]:
+            raise ValueError("H must hold one value per mode (%d)" % self.info()["M"])
+        self._transfer = h  # stays alive while the enqueued kernels may read it
+        N.check(self.lib.scw_synthesize_filtered(self.ctx.handle, self.handle,
+                                                 ctypes.byref(_grid(grid)),
+                                                 N.PRECISION[precision],
+                                                 ctypes.c_void_p(h.data_ptr()),
+                                                 ctypes.c_void_p(out.data_ptr()),
+                                                 ctypes.c_void_p(intensity.data_ptr()),
+                                                 ctypes.c_void_p(stream.cuda_stream)))
+        return out, intensity
+
     def synthesize_slice(self, axis, position, n, fz, z_begin, z_end, precision="fp32",
                          out=None, stream=None):
         """Enqueue ``scw_synthesize_slice``: the field on an x-z ("xz", at

@@ -107,4 +107,5 @@ def test_null_arguments_rejected_without_touching_the_gpu():
     assert lib.scw_batch_configure(None, 16, 4, 1) == -1
     assert lib.scw_synthesize_slice(None, None, None, 1, None, None) == -1
     assert lib.scw_synthesize_image(None, None, None, 1, 0.5, None, None, None) == -1
+    assert lib.scw_synthesize_filtered(None, None, None, 1, None, None, None, None) == -1
     assert lib.scw_sur_set_compute(None, 1) == -1

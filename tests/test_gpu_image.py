@@ -63,9 +63,44 @@ def test_image_matches_oracle(case, precision):
         assert eI <= 2 * TOL[precision]
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_transfer_function_matches_oracle(case, precision):
+    torch = _torch()
+    prob, st, ref, grid, sol = case
+    rng = np.random.default_rng(21)
+    H = rng.standard_normal(st.M) + 1j * rng.standard_normal(st.M)
+    E, I = sol.filtered(grid, H, precision)
+    E, I = E.cpu().numpy(), I.cpu().numpy()
+    torch.cuda.synchronize()
+    want_E, want_I = cwt.filtered(st, ref, grid, H)
+    eE, eI = rel_l2(E, want_E), rel_l2(I, want_I)
+    print("%s random transfer function: field rel-L2 %.3e, intensity rel-L2 %.3e"
+          % (precision, eE, eI))
+    assert eE <= TOL[precision]
+    assert eI <= 2 * TOL[precision]
+
+
+def test_propagation_transfer_function_on_the_device(case):
+    # exp(i k s_z dz) of the bottom medium moves the transmitted field by dz
+    torch = _torch()
+    prob, st, ref, grid, sol = case
+    T, dz = prob.thickness, 0.31
+    near = W.Grid(fx=12, fy=10, fz=5, z_begin=T + 0.02, z_end=T + 0.5)
+    far = W.Grid(fx=12, fy=10, fz=5, z_begin=T + 0.02 + dz, z_end=T + 0.5 + dz)
+    H = np.exp(1j * st.k * st.sz_bot * dz)
+    E, _ = sol.filtered(near, H, "fp64")
+    E = E.cpu().numpy()
+    torch.cuda.synchronize()
+    err = rel_l2(E, cwt.synthesize(st, ref, far))
+    print("transmitted field moved by %.2f through the transfer function: rel-L2 %.3e" % (dz, err))
+    assert err <= TOL["fp64"]
+
+
 def test_image_rejects_bad_aperture(case):
     import paper_2404_07293_amd as P
     prob, st, ref, grid, sol = case
     for na in (-0.1, float("nan"), float("inf")):
         with pytest.raises(P.ScwError):
             sol.image(grid, na)
+    with pytest.raises(ValueError):
+        sol.filtered(grid, np.ones(st.M + 1))
