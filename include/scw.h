@@ -165,6 +165,39 @@ int scw_solution_info_get(const scw_solution* sol, scw_solution_info* info);
 int scw_solution_exterior(const scw_solution* sol, double* p_inc, double* p_ref,
                           double* p_trn);
 
+/* One plane-wave illumination: integer spatial frequency (u, v) inside the
+ * U x V band and complex (re, im) transverse amplitudes, as the problem's
+ * pw_* fields. */
+typedef struct {
+    int u, v;
+    double ex[2];
+    double ey[2];
+} scw_plane_wave;
+
+/* Several illuminations of one sample (Sec. 2.3's incident field, one plane
+ * wave each, e.g. the directions of a condenser aperture) sharing one setup:
+ * the band coefficients, eigendecompositions, synthesis matrices P and the
+ * factorisation of the boundary system are computed once; each illumination
+ * adds only its right-hand side and mode coefficients. The problem's own
+ * incident fields (inc_ex, inc_ey, pw_*) are ignored. `waves`: host array of
+ * n_waves (1..4096) entries, read during the call. The solution behaves as a
+ * scw_solve result for illumination 0 in every other entry point
+ * (scw_synthesize, scw_solution_exterior, ...). Errors as scw_solve, and
+ * SCW_EINVAL for a wave outside the band or a bad count. */
+int scw_solve_illuminations(scw_ctx* ctx, const scw_problem* prob, int n_waves,
+                            const scw_plane_wave* waves, scw_solution** out);
+
+/* The fields of every illumination of a scw_solve_illuminations solution on
+ * `grid`, as n_waves scw_synthesize calls would give them. The modal sum of
+ * all illuminations reads each layer's P once, on the matrix cores (FP32
+ * inputs, FP32 accumulation), then each illumination's exterior planes and
+ * inverse transform follow. precision: SCW_FP32 only. E_dev: caller-owned
+ * device complex64 [n_waves][3][fz][fy][fx]. Work is enqueued on hip_stream;
+ * the first call for a grid builds its plan synchronously. Errors:
+ * SCW_EINVAL for a null argument, another precision or a bad grid. */
+int scw_synthesize_illuminations(scw_ctx* ctx, scw_solution* sol, const scw_grid* grid,
+                                 int precision, void* E_dev, void* hip_stream);
+
 /* Field synthesis, the hot path (Eqs. 9, 10, 30-34):
  *   for every plane, p(m, z) = P_l (alpha_l o g(z)) inside layer l, or the
  *   exterior plane waves outside; then E(x, y, z) = sum_m p(m, z)

@@ -49,6 +49,11 @@ class ScwSlice(ctypes.Structure):
 SLICE_AXIS = {"xz": 0, "yz": 1}
 
 
+class ScwPlaneWave(ctypes.Structure):
+    _fields_ = [("u", ctypes.c_int), ("v", ctypes.c_int), ("ex", ctypes.c_double * 2),
+                ("ey", ctypes.c_double * 2)]
+
+
 class ScwSolutionInfo(ctypes.Structure):
     _fields_ = [
         ("M", ctypes.c_int), ("L", ctypes.c_int),
@@ -88,6 +93,12 @@ SIGNATURES = {
     "scw_destroy": (None, [ctypes.c_void_p]),
     "scw_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ScwProblem),
                                  ctypes.POINTER(ctypes.c_void_p)]),
+    "scw_solve_illuminations": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ScwProblem),
+                                               ctypes.c_int, ctypes.POINTER(ScwPlaneWave),
+                                               ctypes.POINTER(ctypes.c_void_p)]),
+    "scw_synthesize_illuminations": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
+                                                    ctypes.POINTER(ScwGrid), ctypes.c_int,
+                                                    ctypes.c_void_p, ctypes.c_void_p]),
     "scw_solution_free": (None, [ctypes.c_void_p]),
     "scw_solution_info_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ScwSolutionInfo)]),
     "scw_solution_exterior": (ctypes.c_int, [ctypes.c_void_p, c_dp, c_dp, c_dp]),

@@ -358,14 +358,15 @@ void scw_destroy(scw_ctx* ctx) {
   delete ctx;
 }
 
-int scw_solve(scw_ctx* ctx, const scw_problem* prob, scw_solution** out) {
+static int solve_into(scw_ctx* ctx, const scw_problem* prob, int n_waves,
+                      const scw_plane_wave* waves, scw_solution** out) {
   if (!ctx || !prob || !out) return fail(SCW_EINVAL, "null argument");
   *out = nullptr;
   scw_solution* sol = new (std::nothrow) scw_solution();
   if (!sol) return fail(SCW_ENOMEM, "solution allocation failed");
   int rc;
   try {
-    rc = solve_problem(ctx->c, *prob, sol->s);
+    rc = solve_problem(ctx->c, *prob, sol->s, n_waves, waves);
   } catch (const std::bad_alloc&) {
     rc = fail(SCW_ENOMEM, "host allocation failed during setup");
   } catch (const std::exception& e) {
@@ -377,6 +378,28 @@ int scw_solve(scw_ctx* ctx, const scw_problem* prob, scw_solution** out) {
   }
   *out = sol;
   return SCW_OK;
+}
+
+int scw_solve(scw_ctx* ctx, const scw_problem* prob, scw_solution** out) {
+  return solve_into(ctx, prob, 0, nullptr, out);
+}
+
+int scw_solve_illuminations(scw_ctx* ctx, const scw_problem* prob, int n_waves,
+                            const scw_plane_wave* waves, scw_solution** out) {
+  if (n_waves < 1 || n_waves > 4096 || !waves)
+    return fail(SCW_EINVAL, "n_waves must be 1..4096 with a non-null list");
+  return solve_into(ctx, prob, n_waves, waves, out);
+}
+
+int scw_synthesize_illuminations(scw_ctx* ctx, scw_solution* sol, const scw_grid* grid,
+                                 int precision, void* E_dev, void* hip_stream) {
+  if (!ctx || !sol || !E_dev) return fail(SCW_EINVAL, "null argument");
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  if (precision != SCW_FP32)
+    return fail(SCW_EINVAL, "illuminations are synthesized in SCW_FP32");
+  return synthesize_illuminations(ctx->c, sol->s, *grid, E_dev,
+                                  reinterpret_cast<hipStream_t>(hip_stream));
 }
 
 void scw_solution_free(scw_solution* sol) { delete sol; }
@@ -392,10 +415,10 @@ int scw_solution_exterior(const scw_solution* sol, double* p_inc, double* p_ref,
   if (!sol) return fail(SCW_EINVAL, "null solution");
   const Solution& s = sol->s;
   const size_t n = 3 * (size_t)s.M;
-  if (p_inc) std::copy(s.p_inc.begin(), s.p_inc.end(), reinterpret_cast<zc*>(p_inc));
-  if (p_ref) std::copy(s.p_ref.begin(), s.p_ref.end(), reinterpret_cast<zc*>(p_ref));
-  if (p_trn) std::copy(s.p_trn.begin(), s.p_trn.end(), reinterpret_cast<zc*>(p_trn));
-  (void)n;
+  // illumination 0 (the first 3M of each)
+  if (p_inc) std::copy(s.p_inc.begin(), s.p_inc.begin() + n, reinterpret_cast<zc*>(p_inc));
+  if (p_ref) std::copy(s.p_ref.begin(), s.p_ref.begin() + n, reinterpret_cast<zc*>(p_ref));
+  if (p_trn) std::copy(s.p_trn.begin(), s.p_trn.begin() + n, reinterpret_cast<zc*>(p_trn));
   return SCW_OK;
 }
 
@@ -415,8 +438,9 @@ int synthesize(Context& c, Solution& s, const scw_grid& g, int precision, void* 
   return synthesize(c, s, s.plan, g, precision, E, st, stages, ev, false);
 }
 
-int synthesize(Context& c, Solution& s, Plan& pl, const scw_grid& g, int precision, void* E,
-               hipStream_t st, int stages, hipEvent_t* ev, bool direct_only) {
+// The FP32 copy of P (first use) and the plan of (grid, precision).
+static int prepare(Context& c, Solution& s, Plan& pl, const scw_grid& g, int precision,
+                   hipStream_t st, bool direct_only) {
   int rc;
   if (s.device != c.device) return fail(SCW_EINVAL, "solution belongs to another device");
   SCW_HIP(hipSetDevice(c.device));
@@ -431,6 +455,11 @@ int synthesize(Context& c, Solution& s, Plan& pl, const scw_grid& g, int precisi
     if ((rc = build_plan(c, s, pl, g, precision, direct_only))) return rc;
     pl.epoch = c.tune_epoch;
   }
+  return SCW_OK;
+}
+
+static SynthArgs synth_args(const Solution& s, const Plan& pl, const scw_grid& g, int precision,
+                            void* E, int stages) {
   SynthArgs a{};
   a.M = s.M;
   a.U = s.U;
@@ -469,8 +498,46 @@ int synthesize(Context& c, Solution& s, Plan& pl, const scw_grid& g, int precisi
   a.idft_gtiles = pl.tiles;
   a.modal_rw = pl.modal_rw;
   a.stages = stages;
+  return a;
+}
+
+int synthesize(Context& c, Solution& s, Plan& pl, const scw_grid& g, int precision, void* E,
+               hipStream_t st, int stages, hipEvent_t* ev, bool direct_only) {
+  int rc = prepare(c, s, pl, g, precision, st, direct_only);
+  if (rc) return rc;
+  const SynthArgs a = synth_args(s, pl, g, precision, E, stages);
   SCW_HIP(precision == SCW_FP64 ? launch_synthesis_fp64(a, st, ev)
                                 : launch_synthesis_fp32(a, st, ev));
+  return SCW_OK;
+}
+
+// Every illumination of a solution: the modal sum of up to 32 / zt
+// illuminations per launch on the matrix cores, then each illumination's
+// exterior planes and transform into its block of E.
+int synthesize_illuminations(Context& c, Solution& s, const scw_grid& g, void* E,
+                             hipStream_t st) {
+  int rc = prepare(c, s, s.plan, g, SCW_FP32, st, false);
+  if (rc) return rc;
+  const Plan& pl = s.plan;
+  const size_t per = (size_t)g.fz * 3 * s.M;
+  if (s.d_spec_multi.bytes < per * s.K * 8 && (rc = s.d_spec_multi.reserve(per * s.K * 8)))
+    return rc;
+  const size_t lm = (size_t)s.L * 2 * s.M;  // complex per [L][2M] block
+  // with one illumination, (a, b) are the last two blocks of k*gamma, a, b
+  const void* ab = s.K > 1 ? s.d_ab32.p : (const void*)(s.d_kgab32.as<float>() + 2 * lm);
+  const int group = 32 / pl.zt;
+  for (int k0 = 0; k0 < s.K && !pl.tasks.empty(); k0 += group)
+    SCW_HIP(launch_modal_multi(s.d_P32.p, s.d_kgab32.p, ab, pl.d_tasks.as<Task>(),
+                               pl.d_task_dz32.p, (int)pl.tasks.size(), pl.zt, s.M, s.L, g.fz,
+                               k0, std::min(group, s.K - k0), s.d_spec_multi.p, st));
+  const size_t vol = (size_t)3 * g.fz * g.fy * g.fx;
+  for (int k = 0; k < s.K; ++k) {
+    SynthArgs a = synth_args(s, pl, g, SCW_FP32, static_cast<char*>(E) + k * vol * 8,
+                             kStageExterior | kStageTransform);
+    a.ext = s.d_ext.as<double>() + (size_t)k * 9 * s.M * 2;
+    a.spec = s.d_spec_multi.as<char>() + k * per * 8;
+    SCW_HIP(launch_synthesis_fp32(a, st, nullptr));
+  }
   return SCW_OK;
 }
 
@@ -775,9 +842,9 @@ int scw_batch_plan(scw_ctx* ctx, scw_solution* const* jobs, int njobs, const scw
       coef.push_back((float)c.real());
       coef.push_back((float)c.imag());
     };
-    for (zc c : s.p_inc) put(c);
-    for (zc c : s.p_ref) put(c);
-    for (zc c : s.p_trn) put(c);
+    for (int i = 0; i < 3 * M; ++i) put(s.p_inc[i]);  // illumination 0
+    for (int i = 0; i < 3 * M; ++i) put(s.p_ref[i]);
+    for (int i = 0; i < 3 * M; ++i) put(s.p_trn[i]);
     for (int m = 0; m < M; ++m) put(s.k * s.sz_top[m]);
     for (int m = 0; m < M; ++m) put(s.k * s.sz_bot[m]);
   }

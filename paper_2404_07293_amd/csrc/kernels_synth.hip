@@ -324,6 +324,132 @@ hipError_t launch_modal_f32(const SynthArgs& a, hipStream_t s) {
   return hipErrorInvalidValue;
 }
 
+// ---------------------------------------------------------------- modal sum, many illuminations
+// With several illuminations the columns of a task are (illumination, plane)
+// pairs c = ki * zt + p, 32 per launch group, and the product P_l W becomes a
+// real GEMM pair on the matrix cores: spec_re = P_re W_re - P_im W_im and
+// spec_im = P_re W_im + P_im W_re, four v_mfma_f32_32x32x2f32 per pair of j.
+// One block = two waves on the same 32 rows of one sign category; they take
+// alternate 16-j steps of every chunk and add their tiles through LDS at the
+// end. Per chunk of kMultiJC columns j the block first writes the phase
+// factors g_f(z_p), g_b(z_p) (shared by the illuminations), then the table
+// W_k(sign)[c][j] = a_kj g_f + sign b_kj g_b into LDS. In the s-th product of a
+// step, lane (i, h) (i = lane % 32, h = lane / 32) feeds j = step + 8 h + s,
+// so it reads 8 consecutive complex of its row (64 bytes; the two lanes of a
+// row read one 128-byte run) and 8 consecutive table entries of column i.
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+constexpr int kMultiJC = 128;             // j per LDS chunk (= threads per block)
+constexpr int kMultiLd = kMultiJC + 2;    // table row pitch in complex (bank spread)
+
+__global__ void __launch_bounds__(128) modal_multi_kernel(
+    const float4* __restrict__ P, const float2* __restrict__ kg, const float2* __restrict__ ab,
+    const Task* __restrict__ tasks, const float2* __restrict__ tdz, int zt, int M, int L,
+    int fz, int k0, int kcount, int nb_xy, int nb_z, float2* __restrict__ spec) {
+  __shared__ float4 tab4[32 * kMultiLd / 2];  // [32][kMultiLd] complex
+  __shared__ float4 ph4[8 * kMultiJC];        // [zt][kMultiJC] (g_f, g_b)
+  float2* tab = reinterpret_cast<float2*>(tab4);
+  const int n2 = 2 * M, n3 = 3 * M;
+  const int nb = nb_xy + nb_z;
+  const int task = blockIdx.x / nb;
+  const int rb = blockIdx.x % nb;
+  const Task tk = tasks[task];
+  const bool zrows = rb >= nb_xy;
+  const int r0 = zrows ? n2 + (rb - nb_xy) * 32 : rb * 32;
+  const int row_end = zrows ? n3 : n2;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int li = lane & 31, lh = lane >> 5;
+  const float sgn = zrows ? -1.f : 1.f;
+  const int kper = 32 / zt;  // illuminations per table
+  // this lane's row of P (rows past the end are computed from the last row, not stored)
+  const float4* prow = P + ((long long)tk.layer * n3 + min(r0 + li, row_end - 1)) * (n2 / 2);
+  const float2* kgl = kg + (long long)tk.layer * n2;
+  auto load = [&](int j, float4* v) {  // 8 complex from j (even): 4 x 16 bytes
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      v[q] = j + 2 * q < n2 ? prow[(j >> 1) + q] : make_float4(0.f, 0.f, 0.f, 0.f);
+  };
+  f32x16 cre, cim;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) cre[r] = cim[r] = 0.f;
+  float4 cur[4];
+  load(wave * 16 + 8 * lh, cur);
+  for (int j0 = 0; j0 < n2; j0 += kMultiJC) {
+    const int jn = min(kMultiJC, n2 - j0);
+    const int jj = threadIdx.x;
+    const bool live = jj < jn;
+    __syncthreads();
+    if (live) {
+      const float2 g = kgl[j0 + jj];
+      for (int p = 0; p < zt; ++p) {
+        const float2 dz = tdz[task * zt + p];
+        const float2 gf = cexpi_f(g.x * dz.x, g.y * dz.x);
+        const float2 gb = cexpi_f(-g.x * dz.y, -g.y * dz.y);
+        ph4[p * kMultiJC + jj] = make_float4(gf.x, gf.y, gb.x, gb.y);
+      }
+    }
+    for (int ki = 0; ki < kper; ++ki) {
+      float2 a = make_float2(0.f, 0.f), b = a;
+      if (live && ki < kcount) {
+        const float2* abk = ab + (long long)(k0 + ki) * 2 * L * n2;
+        a = abk[(long long)tk.layer * n2 + j0 + jj];
+        b = abk[((long long)L + tk.layer) * n2 + j0 + jj];
+      }
+      for (int p = 0; p < zt; ++p) {
+        const float4 f = live ? ph4[p * kMultiJC + jj] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float wx = a.x * f.x - a.y * f.y + sgn * (b.x * f.z - b.y * f.w);
+        const float wy = a.x * f.y + a.y * f.x + sgn * (b.x * f.w + b.y * f.z);
+        tab[(ki * zt + p) * kMultiLd + jj] = make_float2(wx, wy);
+      }
+    }
+    __syncthreads();
+    for (int st = wave; st * 16 < jn; st += 2) {
+      const int jl = st * 16 + 8 * lh;
+      float4 nxt[4];
+      // prefetch: this wave's next step here, else its first step of the next chunk
+      load(st * 16 + 32 < jn ? j0 + jl + 32 : j0 + kMultiJC + wave * 16 + 8 * lh, nxt);
+      float4 wb[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) wb[q] = tab4[(li * kMultiLd + jl + 2 * q) >> 1];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        cre = __builtin_amdgcn_mfma_f32_32x32x2f32(cur[q].x, wb[q].x, cre, 0, 0, 0);
+        cre = __builtin_amdgcn_mfma_f32_32x32x2f32(-cur[q].y, wb[q].y, cre, 0, 0, 0);
+        cim = __builtin_amdgcn_mfma_f32_32x32x2f32(cur[q].x, wb[q].y, cim, 0, 0, 0);
+        cim = __builtin_amdgcn_mfma_f32_32x32x2f32(cur[q].y, wb[q].x, cim, 0, 0, 0);
+        cre = __builtin_amdgcn_mfma_f32_32x32x2f32(cur[q].z, wb[q].z, cre, 0, 0, 0);
+        cre = __builtin_amdgcn_mfma_f32_32x32x2f32(-cur[q].w, wb[q].w, cre, 0, 0, 0);
+        cim = __builtin_amdgcn_mfma_f32_32x32x2f32(cur[q].z, wb[q].w, cim, 0, 0, 0);
+        cim = __builtin_amdgcn_mfma_f32_32x32x2f32(cur[q].w, wb[q].z, cim, 0, 0, 0);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) cur[q] = nxt[q];
+    }
+  }
+  // the second wave's tile joins the first through LDS
+  __syncthreads();
+  float* red = reinterpret_cast<float*>(tab4);  // [32][64]
+  if (wave == 1) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      red[r * 64 + lane] = cre[r];
+      red[(16 + r) * 64 + lane] = cim[r];
+    }
+  }
+  __syncthreads();
+  if (wave == 0) {
+    const int ki = li / zt, p = li % zt;
+    if (ki < kcount && p < tk.count) {
+      float2* dst = spec + ((long long)(k0 + ki) * fz + tk.plane0 + p) * n3;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = r0 + 8 * (r / 4) + 4 * lh + (r % 4);
+        if (row < row_end)
+          dst[row] = make_float2(cre[r] + red[r * 64 + lane], cim[r] + red[(16 + r) * 64 + lane]);
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------- exterior
 template <typename T>
 __global__ void exterior_kernel(const ExtPlane* __restrict__ ext, int n_ext, int M,
@@ -793,6 +919,21 @@ hipError_t launch_synthesis(const SynthArgs& a, hipStream_t s, hipEvent_t* ev) {
 }
 
 }  // namespace
+
+hipError_t launch_modal_multi(const void* P, const void* kg, const void* ab, const Task* tasks,
+                              const void* task_dz32, int ntasks, int zt, int M, int L, int fz,
+                              int k0, int kcount, void* spec, hipStream_t s) {
+  if (zt < 1 || zt > 8 || 32 % zt != 0 || kcount < 1 || kcount * zt > 32)
+    return hipErrorInvalidValue;
+  const int nb_xy = (2 * M + 31) / 32, nb_z = (M + 31) / 32;
+  const long long nblocks = (long long)ntasks * (nb_xy + nb_z);
+  if (nblocks == 0) return hipSuccess;
+  modal_multi_kernel<<<(unsigned)nblocks, 128, 0, s>>>(
+      reinterpret_cast<const float4*>(P), reinterpret_cast<const float2*>(kg),
+      reinterpret_cast<const float2*>(ab), tasks, reinterpret_cast<const float2*>(task_dz32), zt,
+      M, L, fz, k0, kcount, nb_xy, nb_z, reinterpret_cast<float2*>(spec));
+  return hipGetLastError();
+}
 
 hipError_t launch_synthesis_fp64(const SynthArgs& a, hipStream_t s, hipEvent_t* ev) {
   return launch_synthesis<double>(a, s, ev);

@@ -117,23 +117,26 @@ struct Plan {
 // ------------------------------------------------------------------ solution
 struct Solution {
   int U = 0, V = 0, M = 0, L = 0;
+  int K = 1;  // illuminations sharing the eigendecomposition
   double lam = 0, k = 0, X = 0, Y = 0, d = 0;
   std::vector<int> u, v;
   std::vector<double> sx, sy;
   std::vector<zc> sz_top, sz_bot;
-  std::vector<zc> p_inc, p_ref, p_trn;   // [3M]
+  std::vector<zc> p_inc, p_ref, p_trn;   // [K][3M]
   // per layer, forward-branch eigenvalues and mode coefficients
   std::vector<zc> gamma;                 // [L][2M]
-  std::vector<zc> a, b;                  // [L][2M]
+  std::vector<zc> a, b;                  // [K][L][2M]
   scw_solution_info info{};
 
   // device copies
   DevBuf d_P64;      // [L][3M][2M] complex128, row-major
   DevBuf d_P32;      // [L][3M][2M] complex64 (lazy)
   DevBuf d_kg;       // [L][2M] complex128: k * gamma
-  DevBuf d_a, d_b;   // [L][2M] complex128
-  DevBuf d_kgab32;   // [3][L][2M] complex64: k*gamma, a, b
-  DevBuf d_ext;      // [3][3M] complex128: p_inc, p_ref, p_trn
+  DevBuf d_a, d_b;   // [K][L][2M] complex128
+  DevBuf d_kgab32;   // [3][L][2M] complex64: k*gamma, a, b of illumination 0
+  DevBuf d_ab32;     // [K][2][L][2M] complex64: a, b of every illumination (K > 1)
+  DevBuf d_ext;      // [K][3][3M] complex128: p_inc, p_ref, p_trn
+  DevBuf d_spec_multi;  // [K][fz][3M] complex64: spectra of every illumination
   DevBuf d_ksz;      // [2][M] complex128: k*sz_top, k*sz_bot
   Plan plan;
   Plan slice_plan;         // spectra of the planes of the last slice shape
@@ -173,9 +176,15 @@ int synthesize(Context& ctx, Solution& s, const scw_grid& g, int precision, void
 int synthesize(Context& ctx, Solution& s, Plan& pl, const scw_grid& g, int precision, void* E,
                hipStream_t st, int stages, hipEvent_t* ev, bool direct_only);
 std::string synth_key(const Solution& s, const scw_grid& g, int precision);
+// FP32 fields of every illumination, E: [K][3][fz][fy][fx] complex64.
+int synthesize_illuminations(Context& ctx, Solution& s, const scw_grid& g, void* E,
+                             hipStream_t st);
 
 // ------------------------------------------------------------------ setup
-int solve_problem(Context& ctx, const scw_problem& prob, Solution& sol);
+// n_waves > 0: one plane-wave illumination per entry of `waves` (the
+// problem's own incident field is then ignored), sharing one setup.
+int solve_problem(Context& ctx, const scw_problem& prob, Solution& sol, int n_waves = 0,
+                  const scw_plane_wave* waves = nullptr);
 
 // ------------------------------------------------------------------ surrogate
 struct SurNet;
@@ -369,6 +378,13 @@ hipError_t launch_idft_mfma(const MfmaArgs& a, int precision, hipStream_t s);
 // `ev`, when non-null, holds kNumStages + 1 events recorded around the stages.
 hipError_t launch_synthesis_fp64(const SynthArgs& a, hipStream_t s, hipEvent_t* ev);
 hipError_t launch_synthesis_fp32(const SynthArgs& a, hipStream_t s, hipEvent_t* ev);
+// FP32 modal sum of illuminations k0 .. k0 + kcount - 1 on the matrix cores:
+// spec[k][plane][r] = sum_j P_l[r][j] W_k(sign(r))[plane][j] for every
+// interior plane, kcount * zt <= 32. kg: complex64 [L][2M] (k * gamma);
+// ab: complex64 [K][2][L][2M]; spec: complex64 [K][fz][3M].
+hipError_t launch_modal_multi(const void* P, const void* kg, const void* ab, const Task* tasks,
+                              const void* task_dz32, int ntasks, int zt, int M, int L, int fz,
+                              int k0, int kcount, void* spec, hipStream_t s);
 // A lateral slice from the per-plane spectra [fz][3M] (complex<T>): axis 0
 // sums over v with e^{2 pi i (v - V/2) frac} and runs u on the n samples with
 // tw = [2][n] (e^{2 pi i f/n}, e^{-2 pi i (U/2) f/n}); axis 1 the same with

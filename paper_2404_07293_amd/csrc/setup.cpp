@@ -249,37 +249,47 @@ int solve_stable(const Lin& lin, Solution& s, std::vector<LayerHost>& layers) {
     }
   }
   Mat Ci = c_map(s, s.sz_top);
-  std::vector<zc> rhs(n4, zc(0));
-  for (int c = 0; c < 3 * M; ++c)
-    for (int rr = 0; rr < n4; ++rr) rhs[rr] -= Ci[(size_t)c * n4 + rr] * s.p_inc[c];
   std::vector<int> piv;
   if (lin.lu(n4, S.data(), piv) != 0)
     return fail(SCW_EILLCOND, "singular top-surface system in the stable route");
-  lin.lu_solve(n4, 1, S.data(), piv, rhs.data());
-  s.p_ref.assign(3 * M, zc(0));
-  for (int m = 0; m < M; ++m) {
-    const zc px = rhs[m], py = rhs[M + m];
-    s.p_ref[m] = px;
-    s.p_ref[M + m] = py;
-    s.p_ref[2 * M + m] = (s.sx[m] * px + s.sy[m] * py) / s.sz_top[m];
-  }
-  std::vector<zc> a(rhs.begin() + n2, rhs.end()), ea(n2), nxt(n2);
-  s.a.assign((size_t)L * n2, zc(0));
-  s.b.assign((size_t)L * n2, zc(0));
-  for (int l = 0; l < L; ++l) {
-    std::copy(a.begin(), a.end(), s.a.begin() + (size_t)l * n2);
-    for (int j = 0; j < n2; ++j) ea[j] = layers[l].E[j] * a[j];
-    lin.gemm('N', 'N', n2, 1, n2, 1.0, r[l].data(), n2, ea.data(), n2, 0.0,
-             s.b.data() + (size_t)l * n2, n2);
-    lin.gemm('N', 'N', n2, 1, n2, 1.0, t[l].data(), n2, ea.data(), n2, 0.0, nxt.data(), n2);
-    a = nxt;
-  }
-  s.p_trn.assign(3 * M, zc(0));
-  for (int m = 0; m < M; ++m) {
-    const zc px = a[m], py = a[M + m];
-    s.p_trn[m] = px;
-    s.p_trn[M + m] = py;
-    s.p_trn[2 * M + m] = -(s.sx[m] * px + s.sy[m] * py) / s.sz_bot[m];
+  // every illumination shares the factorisation and the t_l, r_l above
+  const int K = s.K;
+  s.p_ref.assign((size_t)K * 3 * M, zc(0));
+  s.p_trn.assign((size_t)K * 3 * M, zc(0));
+  s.a.assign((size_t)K * L * n2, zc(0));
+  s.b.assign((size_t)K * L * n2, zc(0));
+  std::vector<zc> rhs(n4), ea(n2), nxt(n2);
+  for (int kk = 0; kk < K; ++kk) {
+    const zc* pin = s.p_inc.data() + (size_t)kk * 3 * M;
+    std::fill(rhs.begin(), rhs.end(), zc(0));
+    for (int c = 0; c < 3 * M; ++c)
+      for (int rr = 0; rr < n4; ++rr) rhs[rr] -= Ci[(size_t)c * n4 + rr] * pin[c];
+    lin.lu_solve(n4, 1, S.data(), piv, rhs.data());
+    zc* pref = s.p_ref.data() + (size_t)kk * 3 * M;
+    for (int m = 0; m < M; ++m) {
+      const zc px = rhs[m], py = rhs[M + m];
+      pref[m] = px;
+      pref[M + m] = py;
+      pref[2 * M + m] = (s.sx[m] * px + s.sy[m] * py) / s.sz_top[m];
+    }
+    std::vector<zc> a(rhs.begin() + n2, rhs.end());
+    zc* ak = s.a.data() + (size_t)kk * L * n2;
+    zc* bk = s.b.data() + (size_t)kk * L * n2;
+    for (int l = 0; l < L; ++l) {
+      std::copy(a.begin(), a.end(), ak + (size_t)l * n2);
+      for (int j = 0; j < n2; ++j) ea[j] = layers[l].E[j] * a[j];
+      lin.gemm('N', 'N', n2, 1, n2, 1.0, r[l].data(), n2, ea.data(), n2, 0.0,
+               bk + (size_t)l * n2, n2);
+      lin.gemm('N', 'N', n2, 1, n2, 1.0, t[l].data(), n2, ea.data(), n2, 0.0, nxt.data(), n2);
+      a = nxt;
+    }
+    zc* ptrn = s.p_trn.data() + (size_t)kk * 3 * M;
+    for (int m = 0; m < M; ++m) {
+      const zc px = a[m], py = a[M + m];
+      ptrn[m] = px;
+      ptrn[M + m] = py;
+      ptrn[2 * M + m] = -(s.sx[m] * px + s.sy[m] * py) / s.sz_bot[m];
+    }
   }
   return SCW_OK;
 }
@@ -329,10 +339,6 @@ int solve_connection(const Lin& lin, Solution& s, std::vector<LayerHost>& layers
   Mat Ci = c_map(s, s.sz_top), Cr = c_map(s, msz), Ct = c_map(s, s.sz_bot);
   Mat KCr((size_t)n4 * 3 * M);
   lin.gemm('N', 'N', n4, 3 * M, n4, 1.0, K.data(), n4, Cr.data(), n4, 0.0, KCr.data(), n4);
-  std::vector<zc> cip(n4, zc(0)), rhs(n6, zc(0));
-  for (int c = 0; c < 3 * M; ++c)
-    for (int rr = 0; rr < n4; ++rr) cip[rr] += Ci[(size_t)c * n4 + rr] * s.p_inc[c];
-  lin.gemm('N', 'N', n4, 1, n4, 1.0, K.data(), n4, cip.data(), n4, 0.0, rhs.data(), n6);
   Mat A((size_t)n6 * n6, zc(0));
   for (int c = 0; c < 3 * M; ++c)
     for (int rr = 0; rr < n4; ++rr) {
@@ -361,25 +367,40 @@ int solve_connection(const Lin& lin, Solution& s, std::vector<LayerHost>& layers
   if (!(rcond > 1e-15))
     return fail(SCW_EILLCOND, "connection system is numerically singular (rcond " +
                                   std::to_string(rcond) + ")");
-  lin.lu_solve(n6, 1, A.data(), piv, rhs.data());
-  s.p_ref.assign(rhs.begin(), rhs.begin() + 3 * M);
-  s.p_trn.assign(rhs.begin() + 3 * M, rhs.end());
-  // alpha_1 = T_1^-1 (C_i p_inc + C_r p_ref); alpha_l = T_l^-1 B_{l-1} alpha_{l-1}
-  std::vector<zc> alpha(cip);
-  for (int c = 0; c < 3 * M; ++c)
-    for (int rr = 0; rr < n4; ++rr) alpha[rr] += Cr[(size_t)c * n4 + rr] * s.p_ref[c];
-  s.a.assign((size_t)L * n2, zc(0));
-  s.b.assign((size_t)L * n2, zc(0));
-  std::vector<zc> nxt(n4);
-  for (int l = 0; l < L; ++l) {
-    if (l > 0) {
-      lin.gemm('N', 'N', n4, 1, n4, 1.0, Bm[l - 1].data(), n4, alpha.data(), n4, 0.0,
-               nxt.data(), n4);
-      alpha = nxt;
+  // every illumination shares the factorisation of A and the layer matrices
+  const int nk = s.K;
+  s.p_ref.assign((size_t)nk * 3 * M, zc(0));
+  s.p_trn.assign((size_t)nk * 3 * M, zc(0));
+  s.a.assign((size_t)nk * L * n2, zc(0));
+  s.b.assign((size_t)nk * L * n2, zc(0));
+  std::vector<zc> cip(n4), rhs(n6), nxt(n4);
+  for (int kk = 0; kk < nk; ++kk) {
+    const zc* pin = s.p_inc.data() + (size_t)kk * 3 * M;
+    std::fill(cip.begin(), cip.end(), zc(0));
+    std::fill(rhs.begin(), rhs.end(), zc(0));
+    for (int c = 0; c < 3 * M; ++c)
+      for (int rr = 0; rr < n4; ++rr) cip[rr] += Ci[(size_t)c * n4 + rr] * pin[c];
+    lin.gemm('N', 'N', n4, 1, n4, 1.0, K.data(), n4, cip.data(), n4, 0.0, rhs.data(), n6);
+    lin.lu_solve(n6, 1, A.data(), piv, rhs.data());
+    zc* pref = s.p_ref.data() + (size_t)kk * 3 * M;
+    std::copy(rhs.begin(), rhs.begin() + 3 * M, pref);
+    std::copy(rhs.begin() + 3 * M, rhs.end(), s.p_trn.begin() + (size_t)kk * 3 * M);
+    // alpha_1 = T_1^-1 (C_i p_inc + C_r p_ref); alpha_l = T_l^-1 B_{l-1} alpha_{l-1}
+    std::vector<zc> alpha(cip);
+    for (int c = 0; c < 3 * M; ++c)
+      for (int rr = 0; rr < n4; ++rr) alpha[rr] += Cr[(size_t)c * n4 + rr] * pref[c];
+    zc* ak = s.a.data() + (size_t)kk * L * n2;
+    zc* bk = s.b.data() + (size_t)kk * L * n2;
+    for (int l = 0; l < L; ++l) {
+      if (l > 0) {
+        lin.gemm('N', 'N', n4, 1, n4, 1.0, Bm[l - 1].data(), n4, alpha.data(), n4, 0.0,
+                 nxt.data(), n4);
+        alpha = nxt;
+      }
+      lin.lu_solve(n4, 1, Tlu[l].data(), Tpiv[l], alpha.data());
+      std::copy(alpha.begin(), alpha.begin() + n2, ak + (size_t)l * n2);
+      std::copy(alpha.begin() + n2, alpha.end(), bk + (size_t)l * n2);
     }
-    lin.lu_solve(n4, 1, Tlu[l].data(), Tpiv[l], alpha.data());
-    std::copy(alpha.begin(), alpha.begin() + n2, s.a.begin() + (size_t)l * n2);
-    std::copy(alpha.begin() + n2, alpha.end(), s.b.begin() + (size_t)l * n2);
   }
   return SCW_OK;
 }
@@ -387,8 +408,11 @@ int solve_connection(const Lin& lin, Solution& s, std::vector<LayerHost>& layers
 }  // namespace
 
 // ---------------------------------------------------------------- driver
-int solve_problem(Context& ctx, const scw_problem& p, Solution& s) {
+int solve_problem(Context& ctx, const scw_problem& p, Solution& s, int n_waves,
+                  const scw_plane_wave* waves) {
   const double t_start = now_s();
+  if (n_waves < 0 || (n_waves > 0 && !waves) || n_waves > 4096)
+    return fail(SCW_EINVAL, "illumination count must be 0..4096 with a non-null list");
   if (p.nx < 1 || p.ny < 1 || p.nz < 1 || !p.n)
     return fail(SCW_EINVAL, "sample shape must be positive and n non-null");
   if (p.U < 1 || p.V < 1 || p.U % 2 == 0 || p.V % 2 == 0)
@@ -398,7 +422,7 @@ int solve_problem(Context& ctx, const scw_problem& p, Solution& s) {
   if (!(p.n_top > 0)) return fail(SCW_EINVAL, "n_top must be positive");
   if (p.route != SCW_ROUTE_STABLE && p.route != SCW_ROUTE_CONNECTION)
     return fail(SCW_EINVAL, "unknown route");
-  const bool image = p.inc_ex || p.inc_ey;
+  const bool image = !waves && (p.inc_ex || p.inc_ey);
   if (image && (p.inc_nx < 1 || p.inc_ny < 1))
     return fail(SCW_EINVAL, "incident image shape must be positive");
   if ((long long)p.U * p.V > 8192) return fail(SCW_EINVAL, "U*V above 8192");
@@ -506,9 +530,22 @@ int solve_problem(Context& ctx, const scw_problem& p, Solution& s) {
   d_A.release();
   d_C.release();
 
-  // ---- incident coefficients (Sec. 2.3): in-band DFT of the images / plane wave
-  s.p_inc.assign(3 * M, zc(0));
-  if (image) {
+  // ---- incident coefficients (Sec. 2.3): in-band DFT of the images / plane
+  // wave, or one plane wave per illumination (illumination-major [K][3M])
+  s.K = waves ? n_waves : 1;
+  s.p_inc.assign((size_t)s.K * 3 * M, zc(0));
+  if (waves) {
+    for (int kk = 0; kk < s.K; ++kk) {
+      int hit = -1;
+      for (int m = 0; m < M; ++m)
+        if (s.u[m] == waves[kk].u && s.v[m] == waves[kk].v) hit = m;
+      if (hit < 0)
+        return fail(SCW_EINVAL, "illumination " + std::to_string(kk) +
+                                    ": plane-wave frequency outside the U x V band");
+      s.p_inc[(size_t)kk * 3 * M + hit] = zc(waves[kk].ex[0], waves[kk].ex[1]);
+      s.p_inc[(size_t)kk * 3 * M + M + hit] = zc(waves[kk].ey[0], waves[kk].ey[1]);
+    }
+  } else if (image) {
     const int hu = U / 2, hv = V / 2;
     const size_t npx = (size_t)p.inc_nx * p.inc_ny;
     DevBuf d_img, d_irow, d_ic;
@@ -535,8 +572,11 @@ int solve_problem(Context& ctx, const scw_problem& p, Solution& s) {
     s.p_inc[hit] = zc(p.pw_ex[0], p.pw_ex[1]);
     s.p_inc[M + hit] = zc(p.pw_ey[0], p.pw_ey[1]);
   }
-  for (int m = 0; m < M; ++m)  // Gauss (Eq. 14)
-    s.p_inc[2 * M + m] = -(s.sx[m] * s.p_inc[m] + s.sy[m] * s.p_inc[M + m]) / s.sz_top[m];
+  for (int kk = 0; kk < s.K; ++kk) {  // Gauss (Eq. 14)
+    zc* pin = s.p_inc.data() + (size_t)kk * 3 * M;
+    for (int m = 0; m < M; ++m)
+      pin[2 * M + m] = -(s.sx[m] * pin[m] + s.sy[m] * pin[M + m]) / s.sz_top[m];
+  }
 
   // ---- host: eigendecompositions, one layer per worker (Sec. 3.2, Sec. 4.2)
   const double t_eig = now_s();
@@ -598,13 +638,16 @@ int solve_problem(Context& ctx, const scw_problem& p, Solution& s) {
     SCW_HIP(hipStreamSynchronize(st));
   }
   // per-layer k*gamma, a, b and the exterior coefficients
-  std::vector<zc> kg((size_t)L * n2), ext(9 * (size_t)M), ksz(2 * (size_t)M);
+  // (a, b and the exterior coefficients illumination-major: [K][L][2M], [K][3][3M])
+  std::vector<zc> kg((size_t)L * n2), ext(9 * (size_t)M * s.K), ksz(2 * (size_t)M);
   for (size_t i = 0; i < kg.size(); ++i) kg[i] = s.k * s.gamma[i];
-  for (int i = 0; i < 3 * M; ++i) {
-    ext[i] = s.p_inc[i];
-    ext[3 * M + i] = s.p_ref[i];
-    ext[6 * M + i] = s.p_trn[i];
-  }
+  for (int kk = 0; kk < s.K; ++kk)
+    for (int i = 0; i < 3 * M; ++i) {
+      const size_t o = (size_t)kk * 3 * M + i;
+      ext[(size_t)kk * 9 * M + i] = s.p_inc[o];
+      ext[(size_t)kk * 9 * M + 3 * M + i] = s.p_ref[o];
+      ext[(size_t)kk * 9 * M + 6 * M + i] = s.p_trn[o];
+    }
   for (int m = 0; m < M; ++m) {
     ksz[m] = s.k * s.sz_top[m];
     ksz[M + m] = s.k * s.sz_bot[m];
@@ -620,13 +663,27 @@ int solve_problem(Context& ctx, const scw_problem& p, Solution& s) {
   }
   if ((rc = s.d_kgab32.reserve(kgab32.size() * 4))) return rc;
   SCW_HIP(hipMemcpyAsync(s.d_kgab32.p, kgab32.data(), kgab32.size() * 4, hipMemcpyHostToDevice, st));
-  if ((rc = s.d_kg.reserve(kg.size() * 16)) || (rc = s.d_a.reserve(kg.size() * 16)) ||
-      (rc = s.d_b.reserve(kg.size() * 16)) || (rc = s.d_ext.reserve(ext.size() * 16)) ||
+  if (s.K > 1) {  // complex64 [K][2][L][2M]: a, b of every illumination
+    std::vector<float> ab32(4 * s.a.size());
+    for (int kk = 0; kk < s.K; ++kk)
+      for (size_t i = 0; i < kg.size(); ++i) {
+        const zc av = s.a[(size_t)kk * kg.size() + i], bv = s.b[(size_t)kk * kg.size() + i];
+        float* o = ab32.data() + (size_t)kk * 4 * kg.size();
+        o[2 * i] = (float)av.real();
+        o[2 * i + 1] = (float)av.imag();
+        o[2 * (kg.size() + i)] = (float)bv.real();
+        o[2 * (kg.size() + i) + 1] = (float)bv.imag();
+      }
+    if ((rc = s.d_ab32.reserve(ab32.size() * 4))) return rc;
+    SCW_HIP(hipMemcpyAsync(s.d_ab32.p, ab32.data(), ab32.size() * 4, hipMemcpyHostToDevice, st));
+  }
+  if ((rc = s.d_kg.reserve(kg.size() * 16)) || (rc = s.d_a.reserve(s.a.size() * 16)) ||
+      (rc = s.d_b.reserve(s.b.size() * 16)) || (rc = s.d_ext.reserve(ext.size() * 16)) ||
       (rc = s.d_ksz.reserve(ksz.size() * 16)))
     return rc;
   SCW_HIP(hipMemcpyAsync(s.d_kg.p, kg.data(), kg.size() * 16, hipMemcpyHostToDevice, st));
-  SCW_HIP(hipMemcpyAsync(s.d_a.p, s.a.data(), kg.size() * 16, hipMemcpyHostToDevice, st));
-  SCW_HIP(hipMemcpyAsync(s.d_b.p, s.b.data(), kg.size() * 16, hipMemcpyHostToDevice, st));
+  SCW_HIP(hipMemcpyAsync(s.d_a.p, s.a.data(), s.a.size() * 16, hipMemcpyHostToDevice, st));
+  SCW_HIP(hipMemcpyAsync(s.d_b.p, s.b.data(), s.b.size() * 16, hipMemcpyHostToDevice, st));
   SCW_HIP(hipMemcpyAsync(s.d_ext.p, ext.data(), ext.size() * 16, hipMemcpyHostToDevice, st));
   SCW_HIP(hipMemcpyAsync(s.d_ksz.p, ksz.data(), ksz.size() * 16, hipMemcpyHostToDevice, st));
   SCW_HIP(hipStreamSynchronize(st));

@@ -36,8 +36,11 @@ class Context:
         except Exception:
             pass
 
-    def solve(self, prob, route="stable"):
-        """Run ``scw_solve`` on a ``workloads.Problem``; returns a Solution."""
+    def solve(self, prob, route="stable", waves=None):
+        """Run ``scw_solve`` on a ``workloads.Problem``; returns a Solution.
+        With ``waves`` (a list of ``workloads.PlaneWave``) it runs
+        ``scw_solve_illuminations`` instead: one illumination per wave, the
+        problem's own incident field ignored."""
         n = np.ascontiguousarray(prob.n, dtype=np.complex128)
         keep = [n]
         p = N.ScwProblem()
@@ -65,8 +68,18 @@ class Context:
         p.pw_ey[0], p.pw_ey[1] = ey.real, ey.imag
         p.route = N.ROUTE[route]
         h = ctypes.c_void_p()
-        N.check(self.lib.scw_solve(self.handle, ctypes.byref(p), ctypes.byref(h)))
-        return Solution(self, h, prob)
+        if waves is None:
+            N.check(self.lib.scw_solve(self.handle, ctypes.byref(p), ctypes.byref(h)))
+            return Solution(self, h, prob)
+        arr = (N.ScwPlaneWave * len(waves))()
+        for i, w in enumerate(waves):
+            ex, ey = complex(w.ex), complex(w.ey)
+            arr[i].u, arr[i].v = int(w.u), int(w.v)
+            arr[i].ex[0], arr[i].ex[1] = ex.real, ex.imag
+            arr[i].ey[0], arr[i].ey[1] = ey.real, ey.imag
+        N.check(self.lib.scw_solve_illuminations(self.handle, ctypes.byref(p), len(waves), arr,
+                                                 ctypes.byref(h)))
+        return Solution(self, h, prob, n_illuminations=len(waves))
 
     def batch(self, solutions, grid, precision="fp32"):
         """``scw_batch_plan`` over solved problems sharing one exterior grid."""
@@ -88,11 +101,12 @@ def _grid(grid):
 class Solution:
     """A solved problem (``scw_solution``) living on the context's device."""
 
-    def __init__(self, ctx, handle, prob):
+    def __init__(self, ctx, handle, prob, n_illuminations=1):
         self.ctx = ctx
         self.lib = ctx.lib
         self.handle = handle
         self.M = int(prob.U) * int(prob.V)
+        self.n_illuminations = int(n_illuminations)
 
     def free(self):
         if self.handle:
@@ -143,6 +157,28 @@ class Solution:
                                         ctypes.byref(_grid(grid)), N.PRECISION[precision],
                                         ctypes.c_void_p(out.data_ptr()),
                                         ctypes.c_void_p(stream.cuda_stream)))
+        return out
+
+    def synthesize_illuminations(self, grid, out=None, stream=None):
+        """Enqueue ``scw_synthesize_illuminations`` (FP32): the field of every
+        illumination into ``out`` [K, 3, fz, fy, fx] complex64, allocated
+        when None. Returns the tensor."""
+        import torch
+        dev = torch.device("cuda", self.ctx.device)
+        shape = (self.n_illuminations, 3, int(grid.fz), int(grid.fy), int(grid.fx))
+        if out is None:
+            out = torch.empty(shape, dtype=torch.complex64, device=dev)
+        if tuple(out.shape) != shape or out.dtype != torch.complex64 \
+                or not out.is_contiguous() or out.device != dev:
+            raise ValueError("out must be a contiguous complex64 tensor of shape %s on %s"
+                             % (shape, dev))
+        if stream is None:
+            stream = torch.cuda.current_stream(dev)
+        N.check(self.lib.scw_synthesize_illuminations(self.ctx.handle, self.handle,
+                                                      ctypes.byref(_grid(grid)),
+                                                      N.PRECISION["fp32"],
+                                                      ctypes.c_void_p(out.data_ptr()),
+                                                      ctypes.c_void_p(stream.cuda_stream)))
         return out
 
     def image(self, grid, na, precision="fp32", out=None, intensity=None, stream=None):

@@ -50,6 +50,8 @@ int main(void) {
   F(scw_tune_report, batch_blocks_per_cu) F(scw_tune_report, batch_chunk)
   F(scw_slice, axis) F(scw_slice, position) F(scw_slice, n) F(scw_slice, fz)
   F(scw_slice, z_begin) F(scw_slice, z_end)
+  F(scw_plane_wave, u) F(scw_plane_wave, v) F(scw_plane_wave, ex) F(scw_plane_wave, ey)
+  printf("size scw_plane_wave %zu\n", sizeof(scw_plane_wave));
   printf("size scw_slice %zu\n", sizeof(scw_slice));
   printf("size scw_problem %zu\nsize scw_grid %zu\nsize scw_solution_info %zu\n",
          sizeof(scw_problem), sizeof(scw_grid), sizeof(scw_solution_info));
@@ -71,7 +73,8 @@ def test_ctypes_structures_match_c_layout():
     rename = {"lambda": "lam"}
     types = {"scw_problem": N.ScwProblem, "scw_grid": N.ScwGrid,
              "scw_solution_info": N.ScwSolutionInfo, "scw_synth_config": N.ScwSynthConfig,
-             "scw_tune_report": N.ScwTuneReport, "scw_slice": N.ScwSlice}
+             "scw_tune_report": N.ScwTuneReport, "scw_slice": N.ScwSlice,
+             "scw_plane_wave": N.ScwPlaneWave}
     for line in _c_layout():
         if not line:
             continue
@@ -108,4 +111,6 @@ def test_null_arguments_rejected_without_touching_the_gpu():
     assert lib.scw_synthesize_slice(None, None, None, 1, None, None) == -1
     assert lib.scw_synthesize_image(None, None, None, 1, 0.5, None, None, None) == -1
     assert lib.scw_synthesize_filtered(None, None, None, 1, None, None, None, None) == -1
+    assert lib.scw_solve_illuminations(None, None, 0, None, None) == -1
+    assert lib.scw_synthesize_illuminations(None, None, None, 1, None, None) == -1
     assert lib.scw_sur_set_compute(None, 1) == -1
