@@ -258,6 +258,58 @@ def optics_leg(sol, prob, grid, E_volume, torch, dev, stream, args):
                                    "spectra, plus the intensity pass"}}
 
 
+def illumination_leg(ctx, prob, grid, single_ms, torch, dev, stream, args):
+    """K plane-wave illuminations of the working sample sharing one setup
+    (scw_solve_illuminations): the axial x-polarised wave plus K - 1 seeded
+    lattice directions with random polarisation. Times one synthesis of all
+    K fields (the modal sum of every illumination on the matrix cores, then
+    each field's transform) against K plain single syntheses, and the shared
+    setup against one single setup. Illumination 0 is checked against the
+    single-illumination path on the same solution."""
+    import workloads as W
+    res = {}
+    for K in [int(k) for k in args.illuminations.split(",") if k]:
+        rng = np.random.default_rng(41)
+        h = prob.U // 2
+        ws = [W.PlaneWave(0, 0, 1.0, 0.0)]
+        for _ in range(K - 1):
+            ex, ey = rng.standard_normal(2) + 1j * rng.standard_normal(2)
+            ws.append(W.PlaneWave(int(rng.integers(-h, h + 1)), int(rng.integers(-h, h + 1)),
+                                  complex(ex), complex(ey)))
+        t0 = time.perf_counter()
+        sol = ctx.solve(prob, waves=ws)
+        setup_s = time.perf_counter() - t0
+        out = torch.empty((K, 3, grid.fz, grid.fy, grid.fx), dtype=torch.complex64, device=dev)
+        for _ in range(max(2, args.warmup)):
+            sol.synthesize_illuminations(grid, out=out, stream=stream)
+        torch.cuda.synchronize()
+        s0 = torch.cuda.Event(enable_timing=True)
+        s1 = torch.cuda.Event(enable_timing=True)
+        s0.record(stream)
+        for _ in range(args.steps):
+            sol.synthesize_illuminations(grid, out=out, stream=stream)
+        s1.record(stream)
+        torch.cuda.synchronize()
+        ms = s0.elapsed_time(s1) / args.steps
+        E0 = sol.synthesize(grid, "fp32", stream=stream)
+        torch.cuda.synchronize()
+        err = float(torch.linalg.vector_norm(out[0] - E0) / torch.linalg.vector_norm(E0))
+        vox = K * grid.fx * grid.fy * grid.fz
+        cols = K * grid.fz  # (illumination, plane) columns of the modal sum
+        flops = 8.0 * 3 * sol.M * 2 * sol.M * cols
+        log("%d illuminations: %.4f ms (%.4f ms per field vs %.4f single), %.3e voxels/s; "
+            "setup %.2f s; illumination 0 vs single path rel-L2 %.2e" % (
+                K, ms, ms / K, single_ms, vox / (ms * 1e-3), setup_s, err))
+        res["K%d" % K] = {"illuminations": K, "ms": ms, "ms_per_field": ms / K,
+                          "voxels_per_s": vox / (ms * 1e-3),
+                          "speedup_vs_single_syntheses": single_ms * K / ms,
+                          "setup_s": setup_s, "modal_sum_flops": flops,
+                          "rel_l2_illum0_vs_single_path": err}
+        del out, E0
+        sol.free()
+    return res
+
+
 SWEEP_GOLDEN = os.path.join(ROOT, "tests", "golden", "sweep_job.npz")
 LARGE_GOLDEN = os.path.join(ROOT, "tests", "golden", "large_samples.npz")
 
@@ -553,6 +605,8 @@ def main(argv=None):
                     help="other precisions timed in the same run ('' for none)")
     ap.add_argument("--tune", type=int, default=1,
                     help="run the library's autotuner before timing (0: built-in defaults)")
+    ap.add_argument("--illuminations", default="8,16",
+                    help="illumination counts timed on the working sample ('' for none)")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="also run N plain 256 MiB device copies (PMC scale reference)")
     args = ap.parse_args(argv)
@@ -701,6 +755,9 @@ def main(argv=None):
     if args.workload == "working" and args.precision == "fp32":
         out.setdefault("variants", {})["optics"] = optics_leg(sol, prob, grid, E, torch, dev,
                                                              stream, args)
+        if args.illuminations:
+            out["variants"]["illuminations"] = illumination_leg(ctx, prob, grid, ms, torch, dev,
+                                                                stream, args)
     if args.workload == "working":
         out.setdefault("variants", {})["sphere_fp64"] = sphere_leg(ctx, torch, dev, stream, args)
     if args.large and args.workload == "working":

@@ -522,6 +522,8 @@ int synthesize_illuminations(Context& c, Solution& s, const scw_grid& g, void* E
   const size_t per = (size_t)g.fz * 3 * s.M;
   if (s.d_spec_multi.bytes < per * s.K * 8 && (rc = s.d_spec_multi.reserve(per * s.K * 8)))
     return rc;
+  const size_t wb = multi_table_bytes((int)pl.tasks.size(), s.M);
+  if (s.d_wmulti.bytes < wb && (rc = s.d_wmulti.reserve(wb))) return rc;
   const size_t lm = (size_t)s.L * 2 * s.M;  // complex per [L][2M] block
   // with one illumination, (a, b) are the last two blocks of k*gamma, a, b
   const void* ab = s.K > 1 ? s.d_ab32.p : (const void*)(s.d_kgab32.as<float>() + 2 * lm);
@@ -529,7 +531,8 @@ int synthesize_illuminations(Context& c, Solution& s, const scw_grid& g, void* E
   for (int k0 = 0; k0 < s.K && !pl.tasks.empty(); k0 += group)
     SCW_HIP(launch_modal_multi(s.d_P32.p, s.d_kgab32.p, ab, pl.d_tasks.as<Task>(),
                                pl.d_task_dz32.p, (int)pl.tasks.size(), pl.zt, s.M, s.L, g.fz,
-                               k0, std::min(group, s.K - k0), s.d_spec_multi.p, st));
+                               k0, std::min(group, s.K - k0), s.d_wmulti.p,
+                               s.d_spec_multi.p, st));
   const size_t vol = (size_t)3 * g.fz * g.fy * g.fx;
   for (int k = 0; k < s.K; ++k) {
     SynthArgs a = synth_args(s, pl, g, SCW_FP32, static_cast<char*>(E) + k * vol * 8,

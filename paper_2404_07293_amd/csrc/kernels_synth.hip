@@ -329,110 +329,153 @@ hipError_t launch_modal_f32(const SynthArgs& a, hipStream_t s) {
 // pairs c = ki * zt + p, 32 per launch group, and the product P_l W becomes a
 // real GEMM pair on the matrix cores: spec_re = P_re W_re - P_im W_im and
 // spec_im = P_re W_im + P_im W_re, four v_mfma_f32_32x32x2f32 per pair of j.
-// One block = two waves on the same 32 rows of one sign category; they take
-// alternate 16-j steps of every chunk and add their tiles through LDS at the
-// end. Per chunk of kMultiJC columns j the block first writes the phase
-// factors g_f(z_p), g_b(z_p) (shared by the illuminations), then the table
-// W_k(sign)[c][j] = a_kj g_f + sign b_kj g_b into LDS. In the s-th product of a
-// step, lane (i, h) (i = lane % 32, h = lane / 32) feeds j = step + 8 h + s,
-// so it reads 8 consecutive complex of its row (64 bytes; the two lanes of a
-// row read one 128-byte run) and 8 consecutive table entries of column i.
+//
+// multi_phase_kernel writes the group's phase table once,
+// W[task][sign][c][j] = a_kj g_f(z_p) +- b_kj g_b(z_p), zero for j >= 2M
+// (rows padded to n2p, a multiple of 16) and for columns past the group.
+// modal_multi_kernel: one block = four waves on the same 32 rows of one sign
+// category of one task. P and W are staged through LDS in chunks of 64 j,
+// read from memory in 512-byte runs per row (the operand layout read straight
+// from memory would fetch 128-byte pieces of 32 rows 7 KB apart). Of a
+// chunk's four 16-j steps wave w takes step w; the four tiles are added
+// through LDS at the end. In the s-th product of a step, lane (i, h)
+// (i = lane % 32, h = lane / 32) feeds j = step + 8 h + s: 8 consecutive
+// complex of row i of each tile. The next chunk's loads are issued before the
+// current chunk's products.
 typedef float f32x16 __attribute__((ext_vector_type(16)));
-constexpr int kMultiJC = 128;             // j per LDS chunk (= threads per block)
-constexpr int kMultiLd = kMultiJC + 2;    // table row pitch in complex (bank spread)
 
-__global__ void __launch_bounds__(128) modal_multi_kernel(
-    const float4* __restrict__ P, const float2* __restrict__ kg, const float2* __restrict__ ab,
-    const Task* __restrict__ tasks, const float2* __restrict__ tdz, int zt, int M, int L,
-    int fz, int k0, int kcount, int nb_xy, int nb_z, float2* __restrict__ spec) {
-  __shared__ float4 tab4[32 * kMultiLd / 2];  // [32][kMultiLd] complex
-  __shared__ float4 ph4[8 * kMultiJC];        // [zt][kMultiJC] (g_f, g_b)
-  float2* tab = reinterpret_cast<float2*>(tab4);
+__global__ void multi_phase_kernel(const float2* __restrict__ kg, const float2* __restrict__ ab,
+                                   const Task* __restrict__ tasks,
+                                   const float2* __restrict__ tdz, int zt, int M, int L, int n2p,
+                                   int k0, int kcount, int ntasks, float2* __restrict__ W) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long per_task = 32LL * n2p;
+  if (t >= (long long)ntasks * per_task) return;
+  const int task = (int)(t / per_task);
+  const int rem = (int)(t % per_task);
+  const int c = rem / n2p, j = rem % n2p;
+  const int ki = c / zt, p = c % zt;
+  const int n2 = 2 * M;
+  float2 wp = make_float2(0.f, 0.f), wm = wp;
+  if (j < n2 && ki < kcount) {
+    const int layer = tasks[task].layer;
+    const float2 g = kg[(long long)layer * n2 + j];
+    const float2 dz = tdz[task * zt + p];
+    const float2 gf = cexpi_f(g.x * dz.x, g.y * dz.x);
+    const float2 gb = cexpi_f(-g.x * dz.y, -g.y * dz.y);
+    const float2* abk = ab + (long long)(k0 + ki) * 2 * L * n2;
+    const float2 a = abk[(long long)layer * n2 + j];
+    const float2 b = abk[((long long)L + layer) * n2 + j];
+    const float fx = a.x * gf.x - a.y * gf.y, fy = a.x * gf.y + a.y * gf.x;
+    const float bx = b.x * gb.x - b.y * gb.y, by = b.x * gb.y + b.y * gb.x;
+    wp = make_float2(fx + bx, fy + by);
+    wm = make_float2(fx - bx, fy - by);
+  }
+  W[(((long long)task * 2 + 0) * 32 + c) * n2p + j] = wp;
+  W[(((long long)task * 2 + 1) * 32 + c) * n2p + j] = wm;
+}
+
+constexpr int kMultiJ = 64;  // j per staged chunk: four 16-j steps, one per wave
+
+// (up to three waves per SIMD: the staging and operand registers and the
+// three accumulators need about 150 registers)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 3)))
+modal_multi_kernel(
+    const float4* __restrict__ P, const float4* __restrict__ W, const Task* __restrict__ tasks,
+    int zt, int M, int fz, int n2p, int k0, int kcount, int ntasks, int nb_xy, int nb_z,
+    float2* __restrict__ spec) {
+  // the chunk's tiles: [0] 32 rows of P, [1] 32 columns of W, 64 j each,
+  // padded by one float4 per row (bank spread); reused for the reduction
+  __shared__ float4 tile[2][32][kMultiJ / 2 + 1];
   const int n2 = 2 * M, n3 = 3 * M;
   const int nb = nb_xy + nb_z;
-  const int task = blockIdx.x / nb;
-  const int rb = blockIdx.x % nb;
+  // Consecutive workgroups go to the eight XCDs in turn; numbering them so
+  // that XCD x runs the logical blocks [x per, (x + 1) per) keeps a task's
+  // blocks, which all read that task's W, on one XCD and its L2. The grid is
+  // padded to 8 per blocks; the padding exits at once.
+  const int per = gridDim.x / 8;
+  const int blk = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (blk >= ntasks * nb) return;
+  const int task = blk / nb;
+  const int rb = blk % nb;
   const Task tk = tasks[task];
   const bool zrows = rb >= nb_xy;
   const int r0 = zrows ? n2 + (rb - nb_xy) * 32 : rb * 32;
   const int row_end = zrows ? n3 : n2;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int li = lane & 31, lh = lane >> 5;
-  const float sgn = zrows ? -1.f : 1.f;
-  const int kper = 32 / zt;  // illuminations per table
-  // this lane's row of P (rows past the end are computed from the last row, not stored)
-  const float4* prow = P + ((long long)tk.layer * n3 + min(r0 + li, row_end - 1)) * (n2 / 2);
-  const float2* kgl = kg + (long long)tk.layer * n2;
-  auto load = [&](int j, float4* v) {  // 8 complex from j (even): 4 x 16 bytes
+  // staging: thread t copies float4 8 q + t % 8 (q = 0..3) of row t / 8 of
+  // both tiles, so that eight lanes read one 128-byte run per load and a
+  // row's 512 bytes are read by eight lanes (rows past the end repeat the
+  // last row; j past 2M meets zero entries of W, so P there only has to be
+  // finite and its index is clamped to the row's last pair)
+  const int srow = threadIdx.x >> 3, spart = threadIdx.x & 7;
+  const float4* psrc =
+      P + ((long long)tk.layer * n3 + min(r0 + srow, row_end - 1)) * (n2 / 2);
+  const float4* wsrc = W + (((long long)task * 2 + (zrows ? 1 : 0)) * 32 + srow) * (n2p / 2);
+  const int pmax = n2 / 2 - 1, wmax = n2p / 2 - 1;
+  const int nsteps = n2p / 16;
+  const int nchunks = (nsteps + 3) / 4;
+  // three accumulators, so that no operand needs a sign flip:
+  // spec_re = rr - ii, spec_im = im
+  f32x16 rr, ii, im;
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-      v[q] = j + 2 * q < n2 ? prow[(j >> 1) + q] : make_float4(0.f, 0.f, 0.f, 0.f);
-  };
-  f32x16 cre, cim;
-#pragma unroll
-  for (int r = 0; r < 16; ++r) cre[r] = cim[r] = 0.f;
-  float4 cur[4];
-  load(wave * 16 + 8 * lh, cur);
-  for (int j0 = 0; j0 < n2; j0 += kMultiJC) {
-    const int jn = min(kMultiJC, n2 - j0);
-    const int jj = threadIdx.x;
-    const bool live = jj < jn;
+  for (int r = 0; r < 16; ++r) rr[r] = ii[r] = im[r] = 0.f;
+  // staging registers of one chunk (named scalars, so that they stay in VGPRs)
+  float4 p0, p1, p2, p3, w0, w1, w2, w3;
+#define SCW_MULTI_LOAD(c)                                 \
+  {                                                       \
+    const int i0 = (c) * (kMultiJ / 2) + spart;           \
+    p0 = psrc[min(i0, pmax)];                             \
+    p1 = psrc[min(i0 + 8, pmax)];                         \
+    p2 = psrc[min(i0 + 16, pmax)];                        \
+    p3 = psrc[min(i0 + 24, pmax)];                        \
+    w0 = wsrc[min(i0, wmax)];                             \
+    w1 = wsrc[min(i0 + 8, wmax)];                         \
+    w2 = wsrc[min(i0 + 16, wmax)];                        \
+    w3 = wsrc[min(i0 + 24, wmax)];                        \
+  }
+  SCW_MULTI_LOAD(0);
+  for (int c = 0; c < nchunks; ++c) {
+    __syncthreads();  // the previous tiles have been read
+    tile[0][srow][spart] = p0;
+    tile[0][srow][8 + spart] = p1;
+    tile[0][srow][16 + spart] = p2;
+    tile[0][srow][24 + spart] = p3;
+    tile[1][srow][spart] = w0;
+    tile[1][srow][8 + spart] = w1;
+    tile[1][srow][16 + spart] = w2;
+    tile[1][srow][24 + spart] = w3;
     __syncthreads();
-    if (live) {
-      const float2 g = kgl[j0 + jj];
-      for (int p = 0; p < zt; ++p) {
-        const float2 dz = tdz[task * zt + p];
-        const float2 gf = cexpi_f(g.x * dz.x, g.y * dz.x);
-        const float2 gb = cexpi_f(-g.x * dz.y, -g.y * dz.y);
-        ph4[p * kMultiJC + jj] = make_float4(gf.x, gf.y, gb.x, gb.y);
-      }
-    }
-    for (int ki = 0; ki < kper; ++ki) {
-      float2 a = make_float2(0.f, 0.f), b = a;
-      if (live && ki < kcount) {
-        const float2* abk = ab + (long long)(k0 + ki) * 2 * L * n2;
-        a = abk[(long long)tk.layer * n2 + j0 + jj];
-        b = abk[((long long)L + tk.layer) * n2 + j0 + jj];
-      }
-      for (int p = 0; p < zt; ++p) {
-        const float4 f = live ? ph4[p * kMultiJC + jj] : make_float4(0.f, 0.f, 0.f, 0.f);
-        const float wx = a.x * f.x - a.y * f.y + sgn * (b.x * f.z - b.y * f.w);
-        const float wy = a.x * f.y + a.y * f.x + sgn * (b.x * f.w + b.y * f.z);
-        tab[(ki * zt + p) * kMultiLd + jj] = make_float2(wx, wy);
-      }
-    }
-    __syncthreads();
-    for (int st = wave; st * 16 < jn; st += 2) {
-      const int jl = st * 16 + 8 * lh;
-      float4 nxt[4];
-      // prefetch: this wave's next step here, else its first step of the next chunk
-      load(st * 16 + 32 < jn ? j0 + jl + 32 : j0 + kMultiJC + wave * 16 + 8 * lh, nxt);
-      float4 wb[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) wb[q] = tab4[(li * kMultiLd + jl + 2 * q) >> 1];
+    // the next chunk's loads are in flight during this chunk's products (the
+    // last chunk loads itself again)
+    SCW_MULTI_LOAD(min(c + 1, nchunks - 1));
+    __builtin_amdgcn_sched_barrier(0);
+    if (4 * c + wave < nsteps) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        cre = __builtin_amdgcn_mfma_f32_32x32x2f32(cur[q].x, wb[q].x, cre, 0, 0, 0);
-        cre = __builtin_amdgcn_mfma_f32_32x32x2f32(-cur[q].y, wb[q].y, cre, 0, 0, 0);
-        cim = __builtin_amdgcn_mfma_f32_32x32x2f32(cur[q].x, wb[q].y, cim, 0, 0, 0);
-        cim = __builtin_amdgcn_mfma_f32_32x32x2f32(cur[q].y, wb[q].x, cim, 0, 0, 0);
-        cre = __builtin_amdgcn_mfma_f32_32x32x2f32(cur[q].z, wb[q].z, cre, 0, 0, 0);
-        cre = __builtin_amdgcn_mfma_f32_32x32x2f32(-cur[q].w, wb[q].w, cre, 0, 0, 0);
-        cim = __builtin_amdgcn_mfma_f32_32x32x2f32(cur[q].z, wb[q].w, cim, 0, 0, 0);
-        cim = __builtin_amdgcn_mfma_f32_32x32x2f32(cur[q].w, wb[q].z, cim, 0, 0, 0);
+        const float4 a = tile[0][li][8 * wave + 4 * lh + q];
+        const float4 b = tile[1][li][8 * wave + 4 * lh + q];
+        rr = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.x, rr, 0, 0, 0);
+        ii = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b.y, ii, 0, 0, 0);
+        im = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.y, im, 0, 0, 0);
+        im = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b.x, im, 0, 0, 0);
+        rr = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, b.z, rr, 0, 0, 0);
+        ii = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, b.w, ii, 0, 0, 0);
+        im = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, b.w, im, 0, 0, 0);
+        im = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, b.z, im, 0, 0, 0);
       }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) cur[q] = nxt[q];
     }
   }
-  // the second wave's tile joins the first through LDS
+#undef SCW_MULTI_LOAD
+  // the four waves' tiles are added through LDS
   __syncthreads();
-  float* red = reinterpret_cast<float*>(tab4);  // [32][64]
-  if (wave == 1) {
+  float* red = reinterpret_cast<float*>(tile);  // [3][32][64]
+  if (wave > 0) {
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      red[r * 64 + lane] = cre[r];
-      red[(16 + r) * 64 + lane] = cim[r];
+      red[((wave - 1) * 32 + r) * 64 + lane] = rr[r] - ii[r];
+      red[((wave - 1) * 32 + 16 + r) * 64 + lane] = im[r];
     }
   }
   __syncthreads();
@@ -443,8 +486,13 @@ __global__ void __launch_bounds__(128) modal_multi_kernel(
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int row = r0 + 8 * (r / 4) + 4 * lh + (r % 4);
-        if (row < row_end)
-          dst[row] = make_float2(cre[r] + red[r * 64 + lane], cim[r] + red[(16 + r) * 64 + lane]);
+        float x = rr[r] - ii[r], y = im[r];
+#pragma unroll
+        for (int w = 0; w < 3; ++w) {
+          x += red[(w * 32 + r) * 64 + lane];
+          y += red[(w * 32 + 16 + r) * 64 + lane];
+        }
+        if (row < row_end) dst[row] = make_float2(x, y);
       }
     }
   }
@@ -922,16 +970,22 @@ hipError_t launch_synthesis(const SynthArgs& a, hipStream_t s, hipEvent_t* ev) {
 
 hipError_t launch_modal_multi(const void* P, const void* kg, const void* ab, const Task* tasks,
                               const void* task_dz32, int ntasks, int zt, int M, int L, int fz,
-                              int k0, int kcount, void* spec, hipStream_t s) {
+                              int k0, int kcount, void* W, void* spec, hipStream_t s) {
   if (zt < 1 || zt > 8 || 32 % zt != 0 || kcount < 1 || kcount * zt > 32)
     return hipErrorInvalidValue;
+  if (ntasks == 0) return hipSuccess;
+  const int n2p = multi_row_pitch(M);
+  multi_phase_kernel<<<blocks_for((long long)ntasks * 32 * n2p, 256), 256, 0, s>>>(
+      reinterpret_cast<const float2*>(kg), reinterpret_cast<const float2*>(ab), tasks,
+      reinterpret_cast<const float2*>(task_dz32), zt, M, L, n2p, k0, kcount, ntasks,
+      reinterpret_cast<float2*>(W));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   const int nb_xy = (2 * M + 31) / 32, nb_z = (M + 31) / 32;
   const long long nblocks = (long long)ntasks * (nb_xy + nb_z);
-  if (nblocks == 0) return hipSuccess;
-  modal_multi_kernel<<<(unsigned)nblocks, 128, 0, s>>>(
-      reinterpret_cast<const float4*>(P), reinterpret_cast<const float2*>(kg),
-      reinterpret_cast<const float2*>(ab), tasks, reinterpret_cast<const float2*>(task_dz32), zt,
-      M, L, fz, k0, kcount, nb_xy, nb_z, reinterpret_cast<float2*>(spec));
+  modal_multi_kernel<<<(unsigned)((nblocks + 7) / 8 * 8), 256, 0, s>>>(
+      reinterpret_cast<const float4*>(P), reinterpret_cast<const float4*>(W), tasks, zt, M, fz,
+      n2p, k0, kcount, ntasks, nb_xy, nb_z, reinterpret_cast<float2*>(spec));
   return hipGetLastError();
 }
 

@@ -137,6 +137,7 @@ struct Solution {
   DevBuf d_ab32;     // [K][2][L][2M] complex64: a, b of every illumination (K > 1)
   DevBuf d_ext;      // [K][3][3M] complex128: p_inc, p_ref, p_trn
   DevBuf d_spec_multi;  // [K][fz][3M] complex64: spectra of every illumination
+  DevBuf d_wmulti;      // phase table of one illumination group (matrix-core modal sum)
   DevBuf d_ksz;      // [2][M] complex128: k*sz_top, k*sz_bot
   Plan plan;
   Plan slice_plan;         // spectra of the planes of the last slice shape
@@ -381,10 +382,15 @@ hipError_t launch_synthesis_fp32(const SynthArgs& a, hipStream_t s, hipEvent_t* 
 // FP32 modal sum of illuminations k0 .. k0 + kcount - 1 on the matrix cores:
 // spec[k][plane][r] = sum_j P_l[r][j] W_k(sign(r))[plane][j] for every
 // interior plane, kcount * zt <= 32. kg: complex64 [L][2M] (k * gamma);
-// ab: complex64 [K][2][L][2M]; spec: complex64 [K][fz][3M].
+// ab: complex64 [K][2][L][2M]; W: workspace of multi_table_bytes(ntasks, M)
+// for the group's phase table; spec: complex64 [K][fz][3M].
+inline int multi_row_pitch(int M) { return (2 * M + 15) / 16 * 16; }
+inline size_t multi_table_bytes(int ntasks, int M) {
+  return (size_t)ntasks * 2 * 32 * multi_row_pitch(M) * 8;
+}
 hipError_t launch_modal_multi(const void* P, const void* kg, const void* ab, const Task* tasks,
                               const void* task_dz32, int ntasks, int zt, int M, int L, int fz,
-                              int k0, int kcount, void* spec, hipStream_t s);
+                              int k0, int kcount, void* W, void* spec, hipStream_t s);
 // A lateral slice from the per-plane spectra [fz][3M] (complex<T>): axis 0
 // sums over v with e^{2 pi i (v - V/2) frac} and runs u on the n samples with
 // tw = [2][n] (e^{2 pi i f/n}, e^{-2 pi i (U/2) f/n}); axis 1 the same with
