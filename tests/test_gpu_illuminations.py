@@ -4,8 +4,10 @@ oracle run once per illumination: each illumination is the problem of Sec. 2.3
 with that plane wave as its incident field, so the oracle needs no arithmetic
 of its own here. Cases: both boundary routes, more illuminations than one
 matrix-core launch group holds (a ragged last group), illumination 0 against
-the single-illumination path, linearity in the incident amplitudes, and the
-64x64x32 working sample at full size against separate single solves."""
+the single-illumination path, linearity in the incident amplitudes, a single
+illumination, a plain solution's own incident image, grids with no interior
+plane, and the 64x64x32 working sample at full size against separate single
+solves."""
 import dataclasses
 
 import numpy as np
@@ -157,3 +159,45 @@ def test_working_sample_against_single_solves(ctx):
         print("working sample, illumination %d vs its single solve: rel-L2 %.3e" % (k, err))
         assert err <= 1e-5
         single.free()
+
+
+def test_single_illumination_and_plain_solution(ctx):
+    """K = 1 (the single-illumination coefficient buffer) against the oracle,
+    and the illumination synthesis of a plain scw_solve solution (its own
+    incident image) against scw_synthesize."""
+    torch = _torch()
+    prob = problem(seed=4)
+    w = W.PlaneWave(-1, 2, 0.3 + 0.4j, -0.9)
+    grid = W.Grid(fx=10, fy=12, fz=8, z_begin=-0.2, z_end=prob.thickness + 0.2)
+    sol = ctx.solve(prob, waves=[w])
+    got = sol.synthesize_illuminations(grid).cpu().numpy()
+    torch.cuda.synchronize()
+    err = rel_l2(got[0], oracle_fields(prob, [w], grid)[0])
+    print("one illumination: rel-L2 %.3e" % err)
+    assert err <= TOL
+    rng = np.random.default_rng(8)
+    img = rng.standard_normal((6, 8)) + 1j * rng.standard_normal((6, 8))
+    plain = ctx.solve(dataclasses.replace(prob, inc_ex=img, inc_ey=0.5 * img))
+    E1 = plain.synthesize_illuminations(grid).cpu().numpy()
+    E0 = plain.synthesize(grid, "fp32").cpu().numpy()
+    torch.cuda.synchronize()
+    assert E1.shape == (1,) + E0.shape
+    assert rel_l2(E1[0], E0) <= 1e-5
+
+
+def test_exterior_only_grid(ctx):
+    """Planes only above and below the sample: no interior task."""
+    torch = _torch()
+    prob = problem(seed=6)
+    ws = waves(3, prob.U, prob.V, seed=6)
+    T = prob.thickness
+    sol = ctx.solve(prob, waves=ws)
+    for grid in (W.Grid(fx=8, fy=8, fz=5, z_begin=-0.6, z_end=-0.01),
+                 W.Grid(fx=8, fy=8, fz=5, z_begin=T + 0.01, z_end=T + 0.7)):
+        got = sol.synthesize_illuminations(grid).cpu().numpy()
+        torch.cuda.synchronize()
+        want = oracle_fields(prob, ws, grid)
+        errs = [rel_l2(got[k], want[k]) for k in range(len(ws))]
+        print("exterior-only grid [%.2f, %.2f]: max rel-L2 %.3e"
+              % (grid.z_begin, grid.z_end, max(errs)))
+        assert max(errs) <= TOL
