@@ -61,7 +61,13 @@ typedef enum {
     /* The paper's connection equations (Sec. 2.5.4, Eqs. 27-29): the product
        K of per-layer transfer matrices and a 6M x 6M solve. Loses accuracy
        when K contains large growing evanescent exponentials. */
-    SCW_ROUTE_CONNECTION = 1
+    SCW_ROUTE_CONNECTION = 1,
+    /* SCW_ROUTE_STABLE with its per-layer elimination on the GPU in FP64
+       (rocSOLVER LU with partial pivoting, rocBLAS complex GEMM); the 4M x 4M
+       top-surface system stays on the host. Same solution as
+       SCW_ROUTE_STABLE to rounding. Needs about 2 L (2M)^2 x 16 bytes of
+       device memory for the per-layer interface matrices. */
+    SCW_ROUTE_STABLE_DEVICE = 2
 } scw_route;
 
 typedef struct scw_ctx scw_ctx;
@@ -130,6 +136,7 @@ typedef struct {
     double setup_seconds;      /* wall time of scw_solve */
     double eig_seconds;        /* part spent in the eigensolves */
     double assembly_device_ms; /* GPU time of the band DFT + assembly kernels */
+    double boundary_seconds;   /* wall time of the boundary solve (route) */
 } scw_solution_info;
 
 /* Thread-local description of the last failure on the calling thread. */

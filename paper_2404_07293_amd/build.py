@@ -63,7 +63,7 @@ def build(jobs=8, verbose=False):
         objs = list(ex.map(compile_one, srcs))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs + [
-        "-ldl", "-lpthread"]
+        "-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-ldl", "-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed: %s\n%s\n%s" % (" ".join(cmd), r.stdout, r.stderr))

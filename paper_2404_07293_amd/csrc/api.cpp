@@ -354,6 +354,7 @@ static void profile_free(scw::Context& c);
 void scw_destroy(scw_ctx* ctx) {
   if (!ctx) return;
   profile_free(ctx->c);
+  release_blas(ctx->c);
   if (ctx->c.setup_stream) (void)hipStreamDestroy(ctx->c.setup_stream);
   delete ctx;
 }

@@ -197,7 +197,70 @@ __global__ void to_fp32(const double* __restrict__ in, float* __restrict__ out, 
 
 inline unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
+// Elementwise steps of the device elimination (column-major n x n blocks).
+__global__ void eye_kernel(z2* __restrict__ A, int n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long long)n * n) return;
+  A[i] = z2{i / n == i % n ? 1.0 : 0.0, 0.0};
+}
+
+// A1 <- (A1 + A2) / 2, A2 <- (A1 - A2) / 2
+__global__ void half_sum_diff(z2* __restrict__ A1, z2* __restrict__ A2, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const z2 a = A1[i], b = A2[i];
+  A1[i] = z2{0.5 * (a.x + b.x), 0.5 * (a.y + b.y)};
+  A2[i] = z2{0.5 * (a.x - b.x), 0.5 * (a.y - b.y)};
+}
+
+// P1 = I + E r E, P2 = I - E r E (E diagonal)
+__global__ void i_pm_ere(const z2* __restrict__ r, const z2* __restrict__ E, int n,
+                         z2* __restrict__ P1, z2* __restrict__ P2) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long long)n * n) return;
+  const int c = (int)(i / n), row = (int)(i % n);
+  const z2 x = zmul(zmul(E[row], r[i]), E[c]);
+  const double d = row == c ? 1.0 : 0.0;
+  P1[i] = z2{d + x.x, x.y};
+  P2[i] = z2{d - x.x, -x.y};
+}
+
+// out[c][j] = E[j] A[c][j] for n rows and k columns
+__global__ void scale_rows(const z2* __restrict__ E, const z2* __restrict__ A, int n, int k,
+                           z2* __restrict__ out) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long long)n * k) return;
+  out[i] = zmul(E[i % n], A[i]);
+}
+
 }  // namespace
+
+hipError_t launch_eye(double* A, int n, hipStream_t s) {
+  eye_kernel<<<blocks_for((long long)n * n, 256), 256, 0, s>>>(reinterpret_cast<z2*>(A), n);
+  return hipGetLastError();
+}
+
+hipError_t launch_half_sum_diff(double* A1, double* A2, long long n, hipStream_t s) {
+  half_sum_diff<<<blocks_for(n, 256), 256, 0, s>>>(reinterpret_cast<z2*>(A1),
+                                                   reinterpret_cast<z2*>(A2), n);
+  return hipGetLastError();
+}
+
+hipError_t launch_i_pm_ere(const double* r, const double* E, int n, double* P1, double* P2,
+                           hipStream_t s) {
+  i_pm_ere<<<blocks_for((long long)n * n, 256), 256, 0, s>>>(
+      reinterpret_cast<const z2*>(r), reinterpret_cast<const z2*>(E), n,
+      reinterpret_cast<z2*>(P1), reinterpret_cast<z2*>(P2));
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_rows(const double* E, const double* A, int n, int k, double* out,
+                             hipStream_t s) {
+  scale_rows<<<blocks_for((long long)n * k, 256), 256, 0, s>>>(
+      reinterpret_cast<const z2*>(E), reinterpret_cast<const z2*>(A), n, k,
+      reinterpret_cast<z2*>(out));
+  return hipGetLastError();
+}
 
 hipError_t launch_band_dft(const double* n, int L, int ny, int nx, int hu, int hv,
                            bool inverse_eps_too, bool square, double* rowbuf,

@@ -150,6 +150,7 @@ constexpr int kNumStages = 4;  // phase (FP64 path), modal sum, exterior, invers
 
 struct Context {
   int device = 0;
+  void* blas = nullptr;  // rocBLAS handle of the device elimination (created on first use)
   int host_threads = 1;
   hipStream_t setup_stream = nullptr;
   // profiling: (kNumStages + 1) events per recorded call
@@ -186,6 +187,16 @@ int synthesize_illuminations(Context& ctx, Solution& s, const scw_grid& g, void*
 // problem's own incident field is then ignored), sharing one setup.
 int solve_problem(Context& ctx, const scw_problem& prob, Solution& sol, int n_waves = 0,
                   const scw_plane_wave* waves = nullptr);
+void release_blas(Context& ctx);
+// Elementwise steps of the device elimination, column-major complex128
+// n x n blocks: A = I; A1, A2 <- (A1 + A2)/2, (A1 - A2)/2 over n entries;
+// P1, P2 = I +- E r E with E diagonal; out = diag(E) A for n x k A.
+hipError_t launch_eye(double* A, int n, hipStream_t s);
+hipError_t launch_half_sum_diff(double* A1, double* A2, long long n, hipStream_t s);
+hipError_t launch_i_pm_ere(const double* r, const double* E, int n, double* P1, double* P2,
+                           hipStream_t s);
+hipError_t launch_scale_rows(const double* E, const double* A, int n, int k, double* out,
+                             hipStream_t s);
 
 // ------------------------------------------------------------------ surrogate
 struct SurNet;

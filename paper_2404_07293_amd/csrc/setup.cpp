@@ -31,6 +31,9 @@
 #include <mutex>
 #include <thread>
 
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
 #include "lapack.h"
 #include "scw_internal.h"
 
@@ -197,6 +200,9 @@ int layer_eig(const Lin& lin, Solution& s, LayerHost& h) {
 }
 
 // ---------------------------------------------------------------- stable route
+int top_surface(const Lin& lin, Solution& s, const Mat& Fe, const Mat& Fh, std::vector<zc>& a1);
+void transmitted(Solution& s, int kk, const zc* a);
+
 int solve_stable(const Lin& lin, Solution& s, std::vector<LayerHost>& layers) {
   const int M = s.M, n2 = 2 * M, n4 = 4 * M, L = s.L;
   std::vector<Mat> t(L), r(L);
@@ -235,7 +241,49 @@ int solve_stable(const Lin& lin, Solution& s, std::vector<LayerHost>& layers) {
     lin.gemm('N', 'N', n2, n2, n2, 1.0, h.X.data(), n2, P1.data(), n2, 0.0, Fe.data(), n2);
     lin.gemm('N', 'N', n2, n2, n2, 1.0, h.Y.data(), n2, P2.data(), n2, 0.0, Fh.data(), n2);
   }
-  // top surface: F(-sz_top) rho - F_1 a_1 = -C_i p_inc
+  std::vector<zc> a1;
+  int rc = top_surface(lin, s, Fe, Fh, a1);
+  if (rc) return rc;
+  // back-substitution, one illumination at a time: b_l = r_l E a_l, a_{l+1} = t_l E a_l
+  const int K = s.K;
+  s.a.assign((size_t)K * L * n2, zc(0));
+  s.b.assign((size_t)K * L * n2, zc(0));
+  std::vector<zc> ea(n2), nxt(n2);
+  for (int kk = 0; kk < K; ++kk) {
+    std::vector<zc> a(a1.begin() + (size_t)kk * n2, a1.begin() + (size_t)(kk + 1) * n2);
+    zc* ak = s.a.data() + (size_t)kk * L * n2;
+    zc* bk = s.b.data() + (size_t)kk * L * n2;
+    for (int l = 0; l < L; ++l) {
+      std::copy(a.begin(), a.end(), ak + (size_t)l * n2);
+      for (int j = 0; j < n2; ++j) ea[j] = layers[l].E[j] * a[j];
+      lin.gemm('N', 'N', n2, 1, n2, 1.0, r[l].data(), n2, ea.data(), n2, 0.0,
+               bk + (size_t)l * n2, n2);
+      lin.gemm('N', 'N', n2, 1, n2, 1.0, t[l].data(), n2, ea.data(), n2, 0.0, nxt.data(), n2);
+      a = nxt;
+    }
+    transmitted(s, kk, a.data());
+  }
+  return SCW_OK;
+}
+
+// p_trn of illumination kk from the downward amplitudes below the last layer.
+void transmitted(Solution& s, int kk, const zc* a) {
+  const int M = s.M;
+  if (s.p_trn.size() != (size_t)s.K * 3 * M) s.p_trn.assign((size_t)s.K * 3 * M, zc(0));
+  zc* ptrn = s.p_trn.data() + (size_t)kk * 3 * M;
+  for (int m = 0; m < M; ++m) {
+    const zc px = a[m], py = a[M + m];
+    ptrn[m] = px;
+    ptrn[M + m] = py;
+    ptrn[2 * M + m] = -(s.sx[m] * px + s.sy[m] * py) / s.sz_bot[m];
+  }
+}
+
+// Top surface of the stable route: F(-sz_top) rho - F_1 a_1 = -C_i p_inc for
+// every illumination, with F_1 = [Fe; Fh]. Sets p_ref and returns a_1 as
+// n2 x K (column-major).
+int top_surface(const Lin& lin, Solution& s, const Mat& Fe, const Mat& Fh, std::vector<zc>& a1) {
+  const int M = s.M, n2 = 2 * M, n4 = 4 * M;
   std::vector<zc> msz(M);
   for (int m = 0; m < M; ++m) msz[m] = -s.sz_top[m];
   Mat Hr = half_space_h(s, msz);
@@ -252,13 +300,12 @@ int solve_stable(const Lin& lin, Solution& s, std::vector<LayerHost>& layers) {
   std::vector<int> piv;
   if (lin.lu(n4, S.data(), piv) != 0)
     return fail(SCW_EILLCOND, "singular top-surface system in the stable route");
-  // every illumination shares the factorisation and the t_l, r_l above
+  // every illumination shares the factorisation
   const int K = s.K;
   s.p_ref.assign((size_t)K * 3 * M, zc(0));
   s.p_trn.assign((size_t)K * 3 * M, zc(0));
-  s.a.assign((size_t)K * L * n2, zc(0));
-  s.b.assign((size_t)K * L * n2, zc(0));
-  std::vector<zc> rhs(n4), ea(n2), nxt(n2);
+  a1.assign((size_t)K * n2, zc(0));
+  std::vector<zc> rhs(n4);
   for (int kk = 0; kk < K; ++kk) {
     const zc* pin = s.p_inc.data() + (size_t)kk * 3 * M;
     std::fill(rhs.begin(), rhs.end(), zc(0));
@@ -272,27 +319,146 @@ int solve_stable(const Lin& lin, Solution& s, std::vector<LayerHost>& layers) {
       pref[M + m] = py;
       pref[2 * M + m] = (s.sx[m] * px + s.sy[m] * py) / s.sz_top[m];
     }
-    std::vector<zc> a(rhs.begin() + n2, rhs.end());
-    zc* ak = s.a.data() + (size_t)kk * L * n2;
-    zc* bk = s.b.data() + (size_t)kk * L * n2;
-    for (int l = 0; l < L; ++l) {
-      std::copy(a.begin(), a.end(), ak + (size_t)l * n2);
-      for (int j = 0; j < n2; ++j) ea[j] = layers[l].E[j] * a[j];
-      lin.gemm('N', 'N', n2, 1, n2, 1.0, r[l].data(), n2, ea.data(), n2, 0.0,
-               bk + (size_t)l * n2, n2);
-      lin.gemm('N', 'N', n2, 1, n2, 1.0, t[l].data(), n2, ea.data(), n2, 0.0, nxt.data(), n2);
-      a = nxt;
-    }
-    zc* ptrn = s.p_trn.data() + (size_t)kk * 3 * M;
-    for (int m = 0; m < M; ++m) {
-      const zc px = a[m], py = a[M + m];
-      ptrn[m] = px;
-      ptrn[M + m] = py;
-      ptrn[2 * M + m] = -(s.sx[m] * px + s.sy[m] * py) / s.sz_bot[m];
-    }
+    std::copy(rhs.begin() + n2, rhs.end(), a1.begin() + (size_t)kk * n2);
   }
   return SCW_OK;
 }
+
+// ---------------------------------------------------------------- stable route on the device
+// The same elimination in FP64 with rocSOLVER (LU with partial pivoting) and
+// rocBLAS (complex GEMM) on the setup stream: per layer, from the bottom up,
+// A1 = X^-1 Fe, A2 = Y^-1 Fh, G_t = (A1 + A2)/2, G_b = (A1 - A2)/2,
+// t = G_t^-1, r = G_b t, Fe = X (I + E r E), Fh = Y (I - E r E). The 4M x 4M
+// top-surface system is solved on the host (top_surface); the
+// back-substitution runs on the device for all illuminations at once.
+namespace {
+rocblas_double_complex* zp(const DevBuf& b, size_t off = 0) {
+  return reinterpret_cast<rocblas_double_complex*>(b.as<zc>() + off);
+}
+}  // namespace
+
+#define SCW_BLAS(call)                                                                   \
+  do {                                                                                   \
+    rocblas_status st_ = (call);                                                         \
+    if (st_ != rocblas_status_success)                                                   \
+      return fail(SCW_EHIP, std::string(#call) + ": " + rocblas_status_to_string(st_));  \
+  } while (0)
+
+int solve_stable_device(Context& ctx, const Lin& lin, Solution& s,
+                        std::vector<LayerHost>& layers) {
+  const int M = s.M, n2 = 2 * M, L = s.L, K = s.K;
+  const size_t nn = (size_t)n2 * n2;
+  hipStream_t st = ctx.setup_stream;
+  if (!ctx.blas) {
+    rocblas_handle h = nullptr;
+    SCW_BLAS(rocblas_create_handle(&h));
+    ctx.blas = h;
+  }
+  rocblas_handle h = static_cast<rocblas_handle>(ctx.blas);
+  SCW_BLAS(rocblas_set_stream(h, st));
+  DevBuf dX, dY, dXlu, dYlu, dFe, dFh, dA1, dA2, dP1, dP2, dT, dR, dE, dpiv, dinfo;
+  int rc;
+  if ((rc = dX.reserve(nn * 16)) || (rc = dY.reserve(nn * 16)) || (rc = dXlu.reserve(nn * 16)) ||
+      (rc = dYlu.reserve(nn * 16)) || (rc = dFe.reserve(nn * 16)) || (rc = dFh.reserve(nn * 16)) ||
+      (rc = dA1.reserve(nn * 16)) || (rc = dA2.reserve(nn * 16)) || (rc = dP1.reserve(nn * 16)) ||
+      (rc = dP2.reserve(nn * 16)) || (rc = dT.reserve(nn * 16 * L)) ||
+      (rc = dR.reserve(nn * 16 * L)) || (rc = dE.reserve((size_t)L * n2 * 16)) ||
+      (rc = dpiv.reserve((size_t)n2 * sizeof(rocblas_int))) ||
+      (rc = dinfo.reserve((size_t)3 * L * sizeof(rocblas_int))))
+    return rc;
+  for (int l = 0; l < L; ++l)
+    SCW_HIP(hipMemcpyAsync(dE.as<zc>() + (size_t)l * n2, layers[l].E.data(), n2 * 16,
+                           hipMemcpyHostToDevice, st));
+  SCW_HIP(launch_eye(dFe.as<double>(), n2, st));
+  const Mat Fh0 = half_space_h(s, s.sz_bot);
+  SCW_HIP(hipMemcpyAsync(dFh.p, Fh0.data(), nn * 16, hipMemcpyHostToDevice, st));
+  const rocblas_double_complex one = {1.0, 0.0}, zero = {0.0, 0.0};
+  rocblas_int* info = dinfo.as<rocblas_int>();
+  rocblas_int* piv = dpiv.as<rocblas_int>();
+  const rocblas_operation N = rocblas_operation_none;
+  for (int l = L - 1; l >= 0; --l) {
+    LayerHost& hl = layers[l];
+    SCW_HIP(hipMemcpyAsync(dX.p, hl.X.data(), nn * 16, hipMemcpyHostToDevice, st));
+    SCW_HIP(hipMemcpyAsync(dY.p, hl.Y.data(), nn * 16, hipMemcpyHostToDevice, st));
+    SCW_HIP(hipMemcpyAsync(dXlu.p, dX.p, nn * 16, hipMemcpyDeviceToDevice, st));
+    SCW_HIP(hipMemcpyAsync(dYlu.p, dY.p, nn * 16, hipMemcpyDeviceToDevice, st));
+    SCW_HIP(hipMemcpyAsync(dA1.p, dFe.p, nn * 16, hipMemcpyDeviceToDevice, st));
+    SCW_HIP(hipMemcpyAsync(dA2.p, dFh.p, nn * 16, hipMemcpyDeviceToDevice, st));
+    // A1 = X^-1 Fe, A2 = Y^-1 Fh
+    SCW_BLAS(rocsolver_zgetrf(h, n2, n2, zp(dXlu), n2, piv, info + 3 * l));
+    SCW_BLAS(rocsolver_zgetrs(h, N, n2, n2, zp(dXlu), n2, piv, zp(dA1), n2));
+    SCW_BLAS(rocsolver_zgetrf(h, n2, n2, zp(dYlu), n2, piv, info + 3 * l + 1));
+    SCW_BLAS(rocsolver_zgetrs(h, N, n2, n2, zp(dYlu), n2, piv, zp(dA2), n2));
+    // G_t, G_b in place; t = G_t^-1; r = G_b t
+    SCW_HIP(launch_half_sum_diff(dA1.as<double>(), dA2.as<double>(), (long long)nn, st));
+    zc* tl = dT.as<zc>() + (size_t)l * nn;
+    zc* rl = dR.as<zc>() + (size_t)l * nn;
+    SCW_HIP(launch_eye(reinterpret_cast<double*>(tl), n2, st));
+    SCW_BLAS(rocsolver_zgetrf(h, n2, n2, zp(dA1), n2, piv, info + 3 * l + 2));
+    SCW_BLAS(rocsolver_zgetrs(h, N, n2, n2, zp(dA1), n2, piv,
+                              reinterpret_cast<rocblas_double_complex*>(tl), n2));
+    SCW_BLAS(rocblas_zgemm(h, N, N, n2, n2, n2, &one, zp(dA2), n2,
+                           reinterpret_cast<rocblas_double_complex*>(tl), n2, &zero,
+                           reinterpret_cast<rocblas_double_complex*>(rl), n2));
+    // F_l = [X (I + E r E); Y (I - E r E)]
+    SCW_HIP(launch_i_pm_ere(reinterpret_cast<double*>(rl), dE.as<double>() + (size_t)l * n2 * 2,
+                            n2, dP1.as<double>(), dP2.as<double>(), st));
+    SCW_BLAS(rocblas_zgemm(h, N, N, n2, n2, n2, &one, zp(dX), n2, zp(dP1), n2, &zero, zp(dFe), n2));
+    SCW_BLAS(rocblas_zgemm(h, N, N, n2, n2, n2, &one, zp(dY), n2, zp(dP2), n2, &zero, zp(dFh), n2));
+  }
+  std::vector<rocblas_int> hinfo(3 * L);
+  Mat Fe(nn), Fh(nn);
+  SCW_HIP(hipMemcpyAsync(hinfo.data(), info, hinfo.size() * sizeof(rocblas_int),
+                         hipMemcpyDeviceToHost, st));
+  SCW_HIP(hipMemcpyAsync(Fe.data(), dFe.p, nn * 16, hipMemcpyDeviceToHost, st));
+  SCW_HIP(hipMemcpyAsync(Fh.data(), dFh.p, nn * 16, hipMemcpyDeviceToHost, st));
+  SCW_HIP(hipStreamSynchronize(st));
+  for (int i = 0; i < 3 * L; ++i)
+    if (hinfo[i] != 0)
+      return fail(i % 3 == 2 ? SCW_EILLCOND : SCW_EDEFECTIVE,
+                  "singular matrix in the device elimination (layer " + std::to_string(i / 3) + ")");
+  std::vector<zc> a1;
+  if ((rc = top_surface(lin, s, Fe, Fh, a1))) return rc;
+  // back-substitution of all illuminations: columns of n2 x K blocks
+  DevBuf dAc, dEA, dAs, dBs;
+  const size_t nk = (size_t)n2 * K;
+  if ((rc = dAc.reserve(nk * 16)) || (rc = dEA.reserve(nk * 16)) ||
+      (rc = dAs.reserve(nk * 16 * L)) || (rc = dBs.reserve(nk * 16 * L)))
+    return rc;
+  SCW_HIP(hipMemcpyAsync(dAc.p, a1.data(), nk * 16, hipMemcpyHostToDevice, st));
+  for (int l = 0; l < L; ++l) {
+    SCW_HIP(hipMemcpyAsync(dAs.as<zc>() + (size_t)l * nk, dAc.p, nk * 16, hipMemcpyDeviceToDevice,
+                           st));
+    SCW_HIP(launch_scale_rows(dE.as<double>() + (size_t)l * n2 * 2, dAc.as<double>(), n2, K,
+                              dEA.as<double>(), st));
+    SCW_BLAS(rocblas_zgemm(h, N, N, n2, K, n2, &one,
+                           reinterpret_cast<rocblas_double_complex*>(dR.as<zc>() + (size_t)l * nn),
+                           n2, zp(dEA), n2, &zero, zp(dBs, (size_t)l * nk), n2));
+    SCW_BLAS(rocblas_zgemm(h, N, N, n2, K, n2, &one,
+                           reinterpret_cast<rocblas_double_complex*>(dT.as<zc>() + (size_t)l * nn),
+                           n2, zp(dEA), n2, &zero, zp(dAc), n2));
+  }
+  std::vector<zc> As(nk * L), Bs(nk * L), last(nk);
+  SCW_HIP(hipMemcpyAsync(As.data(), dAs.p, As.size() * 16, hipMemcpyDeviceToHost, st));
+  SCW_HIP(hipMemcpyAsync(Bs.data(), dBs.p, Bs.size() * 16, hipMemcpyDeviceToHost, st));
+  SCW_HIP(hipMemcpyAsync(last.data(), dAc.p, nk * 16, hipMemcpyDeviceToHost, st));
+  SCW_HIP(hipStreamSynchronize(st));
+  // [L][K][n2] on the device -> [K][L][n2]
+  s.a.assign((size_t)K * L * n2, zc(0));
+  s.b.assign((size_t)K * L * n2, zc(0));
+  for (int l = 0; l < L; ++l)
+    for (int kk = 0; kk < K; ++kk) {
+      std::copy(As.begin() + (size_t)l * nk + (size_t)kk * n2,
+                As.begin() + (size_t)l * nk + (size_t)(kk + 1) * n2,
+                s.a.begin() + ((size_t)kk * L + l) * n2);
+      std::copy(Bs.begin() + (size_t)l * nk + (size_t)kk * n2,
+                Bs.begin() + (size_t)l * nk + (size_t)(kk + 1) * n2,
+                s.b.begin() + ((size_t)kk * L + l) * n2);
+    }
+  for (int kk = 0; kk < K; ++kk) transmitted(s, kk, last.data() + (size_t)kk * n2);
+  return SCW_OK;
+}
+#undef SCW_BLAS
 
 // ---------------------------------------------------------------- connection route
 int solve_connection(const Lin& lin, Solution& s, std::vector<LayerHost>& layers, int threads) {
@@ -407,6 +573,11 @@ int solve_connection(const Lin& lin, Solution& s, std::vector<LayerHost>& layers
 
 }  // namespace
 
+void release_blas(Context& ctx) {
+  if (ctx.blas) (void)rocblas_destroy_handle(static_cast<rocblas_handle>(ctx.blas));
+  ctx.blas = nullptr;
+}
+
 // ---------------------------------------------------------------- driver
 int solve_problem(Context& ctx, const scw_problem& p, Solution& s, int n_waves,
                   const scw_plane_wave* waves) {
@@ -420,7 +591,8 @@ int solve_problem(Context& ctx, const scw_problem& p, Solution& s, int n_waves,
   if (!(p.px > 0) || !(p.py > 0) || !(p.pz > 0) || !(p.lambda > 0))
     return fail(SCW_EINVAL, "pitches and wavelength must be positive");
   if (!(p.n_top > 0)) return fail(SCW_EINVAL, "n_top must be positive");
-  if (p.route != SCW_ROUTE_STABLE && p.route != SCW_ROUTE_CONNECTION)
+  if (p.route != SCW_ROUTE_STABLE && p.route != SCW_ROUTE_CONNECTION &&
+      p.route != SCW_ROUTE_STABLE_DEVICE)
     return fail(SCW_EINVAL, "unknown route");
   const bool image = !waves && (p.inc_ex || p.inc_ey);
   if (image && (p.inc_nx < 1 || p.inc_ny < 1))
@@ -614,8 +786,12 @@ int solve_problem(Context& ctx, const scw_problem& p, Solution& s, int n_waves,
 
   // ---- host: boundary solve (Sec. 2.5.4, Sec. 3.3-3.4)
   if (lp.set_threads) lp.set_threads(ctx.host_threads);
-  rc = stable ? solve_stable(lin, s, layers) : solve_connection(lin, s, layers, ctx.host_threads);
+  const double t_bnd = now_s();
+  rc = p.route == SCW_ROUTE_STABLE_DEVICE ? solve_stable_device(ctx, lin, s, layers)
+       : stable                           ? solve_stable(lin, s, layers)
+                                          : solve_connection(lin, s, layers, ctx.host_threads);
   if (rc) return rc;
+  s.info.boundary_seconds = now_s() - t_bnd;
 
   // ---- device: synthesis matrices P_l = [X; Psi (S_y Y_x - S_x Y_y)] (Sec. 4.1)
   const size_t pl = (size_t)3 * M * n2;

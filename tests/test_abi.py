@@ -43,6 +43,7 @@ int main(void) {
   F(scw_grid, fx) F(scw_grid, z_begin) F(scw_grid, z_end)
   F(scw_solution_info, M) F(scw_solution_info, min_abs_sz)
   F(scw_solution_info, connection_rcond) F(scw_solution_info, assembly_device_ms)
+  F(scw_solution_info, boundary_seconds)
   F(scw_synth_config, modal_rows) F(scw_synth_config, transform)
   F(scw_synth_config, fft_radix) F(scw_synth_config, tiles)
   F(scw_tune_report, n_candidates) F(scw_tune_report, default_ms) F(scw_tune_report, best_ms)
