@@ -321,16 +321,18 @@ def large_leg(ctx, torch, dev, stream, args):
     import workloads as W
     prob, grid = W.random_field_config("large")
     t0 = time.perf_counter()
-    sol = ctx.solve(prob)
+    sol = ctx.solve(prob, route="stable_device")
     t_setup = time.perf_counter() - t0
     info = sol.info()
-    log("large: setup %.1f s (eig %.1f s), growth exponent %.1f" % (
-        t_setup, info["eig_seconds"], info["growth_exponent"]))
+    log("large: setup %.1f s (eig %.1f s, boundary solve on the device %.2f s), "
+        "growth exponent %.1f" % (t_setup, info["eig_seconds"], info["boundary_seconds"],
+                                  info["growth_exponent"]))
     E = torch.empty((3, grid.fz, grid.fy, grid.fx), dtype=torch.complex64, device=dev)
     voxels = grid.fx * grid.fy * grid.fz
     rec = {"workload": "large: %dx%dx%d random-field sample, M=%d, %dx%dx%d grid" % (
         prob.nx, prob.ny, prob.nz, prob.U * prob.V, grid.fx, grid.fy, grid.fz),
         "voxels_per_step": voxels, "setup_s": t_setup, "eig_s": info["eig_seconds"],
+        "boundary_s": info["boundary_seconds"], "route": "stable_device",
         "growth_exponent": info["growth_exponent"]}
     steps = max(3, args.steps // 5)
     s0 = torch.cuda.Event(enable_timing=True)
@@ -607,6 +609,8 @@ def main(argv=None):
                     help="run the library's autotuner before timing (0: built-in defaults)")
     ap.add_argument("--illuminations", default="8,16",
                     help="illumination counts timed on the working sample ('' for none)")
+    ap.add_argument("--route-compare", type=int, default=1,
+                    help="also solve the workload with the boundary elimination on the device")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="also run N plain 256 MiB device copies (PMC scale reference)")
     args = ap.parse_args(argv)
@@ -626,8 +630,25 @@ def main(argv=None):
     t0 = time.perf_counter()
     sol = ctx.solve(prob)
     info = sol.info()
-    log("setup %.1f s (eig %.1f s), growth exponent %.1f" % (
-        time.perf_counter() - t0, info["eig_seconds"], info["growth_exponent"]))
+    log("setup %.1f s (eig %.1f s, boundary solve %.2f s), growth exponent %.1f" % (
+        time.perf_counter() - t0, info["eig_seconds"], info["boundary_seconds"],
+        info["growth_exponent"]))
+    routes = None
+    if args.route_compare:
+        # the same setup with the boundary elimination on the device
+        dsol = ctx.solve(prob, route="stable_device")
+        dinfo = dsol.info()
+        hx, dx = sol.exterior(), dsol.exterior()
+        diff = float(np.linalg.norm(dx[2] - hx[2]) / np.linalg.norm(hx[2]))
+        routes = {"stable": {"setup_s": info["setup_seconds"],
+                             "boundary_s": info["boundary_seconds"]},
+                  "stable_device": {"setup_s": dinfo["setup_seconds"],
+                                    "boundary_s": dinfo["boundary_seconds"]},
+                  "p_trn_rel_diff": diff}
+        log("boundary solve on the device: %.2f s (host %.2f s), setup %.1f s; p_trn "
+            "rel diff %.1e" % (dinfo["boundary_seconds"], info["boundary_seconds"],
+                               dinfo["setup_seconds"], diff))
+        dsol.free()
 
     dev = torch.device("cuda", 0)
     stream = torch.cuda.current_stream(dev)
@@ -731,6 +752,7 @@ def main(argv=None):
         "rel_l2_vs_oracle": err,
         "stages_ms": stages,
         "setup_s": info["setup_seconds"],
+        "setup_routes": routes,
         "assembly_device_ms": info["assembly_device_ms"],
         "roofline": roof,
         "roofline_by_stage": roof_stage,
