@@ -67,7 +67,12 @@ typedef enum {
        top-surface system stays on the host. Same solution as
        SCW_ROUTE_STABLE to rounding. Needs about 2 L (2M)^2 x 16 bytes of
        device memory for the per-layer interface matrices. */
-    SCW_ROUTE_STABLE_DEVICE = 2
+    SCW_ROUTE_STABLE_DEVICE = 2,
+    /* SCW_ROUTE_CONNECTION with the layer matrices, the product K and the
+       alpha recursion on the GPU in FP64 (rocSOLVER, rocBLAS); the 6M x 6M
+       system stays on the host. Needs about 2 L (4M)^2 x 16 bytes of device
+       memory. */
+    SCW_ROUTE_CONNECTION_DEVICE = 3
 } scw_route;
 
 typedef struct scw_ctx scw_ctx;

@@ -14,7 +14,7 @@ STATUS = {0: "SCW_OK", -1: "SCW_EINVAL", -2: "SCW_ENOMEM", -3: "SCW_EHIP",
           -4: "SCW_ELAPACK", -5: "SCW_EGRAZING", -6: "SCW_EDEFECTIVE",
           -7: "SCW_EILLCOND"}
 PRECISION = {"fp64": 0, "fp32": 1, "bf16x3": 2, "fp16x3": 3}
-ROUTE = {"stable": 0, "connection": 1, "stable_device": 2}
+ROUTE = {"stable": 0, "connection": 1, "stable_device": 2, "connection_device": 3}
 
 c_dp = ctypes.POINTER(ctypes.c_double)
 

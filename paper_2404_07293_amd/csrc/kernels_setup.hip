@@ -233,7 +233,33 @@ __global__ void scale_rows(const z2* __restrict__ E, const z2* __restrict__ A, i
   out[i] = zmul(E[i % n], A[i]);
 }
 
+// T_l = W diag(I, E) and B_l = W diag(E, I) of the connection route, with
+// W = [[X, X], [Y, -Y]] (forward columns first), column-major 4M x 4M.
+__global__ void build_tb(const z2* __restrict__ X, const z2* __restrict__ Y,
+                         const z2* __restrict__ E, int n2, z2* __restrict__ T,
+                         z2* __restrict__ B) {
+  const int n4 = 2 * n2;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long long)n4 * n4) return;
+  const int col = (int)(i / n4), row = (int)(i % n4);
+  const int c = col % n2, rr = row % n2;
+  const bool back = col >= n2, top = row < n2;
+  const z2 v = top ? X[(long long)c * n2 + rr] : Y[(long long)c * n2 + rr];
+  const z2 ve = zmul(v, E[c]);
+  const double sg = (back && !top) ? -1.0 : 1.0;  // the backward H part changes sign
+  T[i] = back ? z2{sg * ve.x, sg * ve.y} : v;
+  B[i] = back ? z2{sg * v.x, sg * v.y} : ve;
+}
+
 }  // namespace
+
+hipError_t launch_build_tb(const double* X, const double* Y, const double* E, int n2, double* T,
+                           double* B, hipStream_t s) {
+  build_tb<<<blocks_for(4LL * n2 * n2, 256), 256, 0, s>>>(
+      reinterpret_cast<const z2*>(X), reinterpret_cast<const z2*>(Y),
+      reinterpret_cast<const z2*>(E), n2, reinterpret_cast<z2*>(T), reinterpret_cast<z2*>(B));
+  return hipGetLastError();
+}
 
 hipError_t launch_eye(double* A, int n, hipStream_t s) {
   eye_kernel<<<blocks_for((long long)n * n, 256), 256, 0, s>>>(reinterpret_cast<z2*>(A), n);

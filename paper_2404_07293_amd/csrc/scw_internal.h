@@ -197,6 +197,9 @@ hipError_t launch_i_pm_ere(const double* r, const double* E, int n, double* P1, 
                            hipStream_t s);
 hipError_t launch_scale_rows(const double* E, const double* A, int n, int k, double* out,
                              hipStream_t s);
+// T = W diag(I, E), B = W diag(E, I) with W = [[X, X], [Y, -Y]] (4M x 4M).
+hipError_t launch_build_tb(const double* X, const double* Y, const double* E, int n2, double* T,
+                           double* B, hipStream_t s);
 
 // ------------------------------------------------------------------ surrogate
 struct SurNet;

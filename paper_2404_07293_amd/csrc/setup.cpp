@@ -324,6 +324,8 @@ int top_surface(const Lin& lin, Solution& s, const Mat& Fe, const Mat& Fh, std::
   return SCW_OK;
 }
 
+int connection_system(const Lin& lin, Solution& s, const Mat& K, std::vector<zc>& alpha1);
+
 // ---------------------------------------------------------------- stable route on the device
 // The same elimination in FP64 with rocSOLVER (LU with partial pivoting) and
 // rocBLAS (complex GEMM) on the setup stream: per layer, from the bottom up,
@@ -458,9 +460,101 @@ int solve_stable_device(Context& ctx, const Lin& lin, Solution& s,
   for (int kk = 0; kk < K; ++kk) transmitted(s, kk, last.data() + (size_t)kk * n2);
   return SCW_OK;
 }
+// The connection route with its per-layer work on the device: T_l and B_l
+// from X, Y, E, T_l = LU (kept per layer with its pivots), M_l = B_l T_l^-1,
+// K = M_L ... M_1; the 6M x 6M system on the host (connection_system); then
+// alpha_l = T_l^-1 B_{l-1} alpha_{l-1} for all illuminations on the device.
+int solve_connection_device(Context& ctx, const Lin& lin, Solution& s,
+                            std::vector<LayerHost>& layers) {
+  const int M = s.M, n2 = 2 * M, n4 = 4 * M, L = s.L, nk = s.K;
+  const size_t nn = (size_t)n2 * n2, nn4 = (size_t)n4 * n4;
+  hipStream_t st = ctx.setup_stream;
+  if (!ctx.blas) {
+    rocblas_handle h = nullptr;
+    SCW_BLAS(rocblas_create_handle(&h));
+    ctx.blas = h;
+  }
+  rocblas_handle h = static_cast<rocblas_handle>(ctx.blas);
+  SCW_BLAS(rocblas_set_stream(h, st));
+  DevBuf dX, dY, dE, dT, dB, dTi, dMk, dK, dK2, dpiv, dinfo;
+  int rc;
+  if ((rc = dX.reserve(nn * 16)) || (rc = dY.reserve(nn * 16)) ||
+      (rc = dE.reserve((size_t)L * n2 * 16)) || (rc = dT.reserve(nn4 * 16 * L)) ||
+      (rc = dB.reserve(nn4 * 16 * L)) || (rc = dTi.reserve(nn4 * 16)) ||
+      (rc = dMk.reserve(nn4 * 16)) || (rc = dK.reserve(nn4 * 16)) || (rc = dK2.reserve(nn4 * 16)) ||
+      (rc = dpiv.reserve((size_t)L * n4 * sizeof(rocblas_int))) ||
+      (rc = dinfo.reserve((size_t)L * sizeof(rocblas_int))))
+    return rc;
+  for (int l = 0; l < L; ++l)
+    SCW_HIP(hipMemcpyAsync(dE.as<zc>() + (size_t)l * n2, layers[l].E.data(), n2 * 16,
+                           hipMemcpyHostToDevice, st));
+  const rocblas_double_complex one = {1.0, 0.0}, zero = {0.0, 0.0};
+  const rocblas_operation N = rocblas_operation_none;
+  rocblas_int* info = dinfo.as<rocblas_int>();
+  auto piv = [&](int l) { return dpiv.as<rocblas_int>() + (size_t)l * n4; };
+  auto Tl = [&](int l) { return zp(dT, (size_t)l * nn4); };
+  auto Bl = [&](int l) { return zp(dB, (size_t)l * nn4); };
+  SCW_HIP(launch_eye(dK.as<double>(), n4, st));
+  for (int l = 0; l < L; ++l) {
+    SCW_HIP(hipMemcpyAsync(dX.p, layers[l].X.data(), nn * 16, hipMemcpyHostToDevice, st));
+    SCW_HIP(hipMemcpyAsync(dY.p, layers[l].Y.data(), nn * 16, hipMemcpyHostToDevice, st));
+    SCW_HIP(launch_build_tb(dX.as<double>(), dY.as<double>(), dE.as<double>() + (size_t)l * n2 * 2,
+                            n2, reinterpret_cast<double*>(Tl(l)),
+                            reinterpret_cast<double*>(Bl(l)), st));
+    SCW_BLAS(rocsolver_zgetrf(h, n4, n4, Tl(l), n4, piv(l), info + l));
+    SCW_HIP(launch_eye(dTi.as<double>(), n4, st));
+    SCW_BLAS(rocsolver_zgetrs(h, N, n4, n4, Tl(l), n4, piv(l), zp(dTi), n4));
+    SCW_BLAS(rocblas_zgemm(h, N, N, n4, n4, n4, &one, Bl(l), n4, zp(dTi), n4, &zero, zp(dMk), n4));
+    SCW_BLAS(rocblas_zgemm(h, N, N, n4, n4, n4, &one, zp(dMk), n4, zp(dK), n4, &zero, zp(dK2), n4));
+    std::swap(dK.p, dK2.p);
+  }
+  std::vector<rocblas_int> hinfo(L);
+  Mat K(nn4);
+  SCW_HIP(hipMemcpyAsync(hinfo.data(), info, L * sizeof(rocblas_int), hipMemcpyDeviceToHost, st));
+  SCW_HIP(hipMemcpyAsync(K.data(), dK.p, nn4 * 16, hipMemcpyDeviceToHost, st));
+  SCW_HIP(hipStreamSynchronize(st));
+  for (int l = 0; l < L; ++l)
+    if (hinfo[l] != 0)
+      return fail(SCW_EILLCOND, "singular layer matrix T in the connection route (layer " +
+                                    std::to_string(l) + ")");
+  std::vector<zc> alpha1;
+  if ((rc = connection_system(lin, s, K, alpha1))) return rc;
+  // alpha recursion of all illuminations: n4 x K blocks
+  DevBuf dAl, dTmp, dAs;
+  const size_t n4k = (size_t)n4 * nk;
+  if ((rc = dAl.reserve(n4k * 16)) || (rc = dTmp.reserve(n4k * 16)) ||
+      (rc = dAs.reserve(n4k * 16 * L)))
+    return rc;
+  SCW_HIP(hipMemcpyAsync(dAl.p, alpha1.data(), n4k * 16, hipMemcpyHostToDevice, st));
+  for (int l = 0; l < L; ++l) {
+    if (l > 0) {
+      SCW_BLAS(rocblas_zgemm(h, N, N, n4, nk, n4, &one, Bl(l - 1), n4, zp(dAl), n4, &zero,
+                             zp(dTmp), n4));
+      std::swap(dAl.p, dTmp.p);
+    }
+    SCW_BLAS(rocsolver_zgetrs(h, N, n4, nk, Tl(l), n4, piv(l), zp(dAl), n4));
+    SCW_HIP(hipMemcpyAsync(dAs.as<zc>() + (size_t)l * n4k, dAl.p, n4k * 16,
+                           hipMemcpyDeviceToDevice, st));
+  }
+  std::vector<zc> As(n4k * L);
+  SCW_HIP(hipMemcpyAsync(As.data(), dAs.p, As.size() * 16, hipMemcpyDeviceToHost, st));
+  SCW_HIP(hipStreamSynchronize(st));
+  s.a.assign((size_t)nk * L * n2, zc(0));
+  s.b.assign((size_t)nk * L * n2, zc(0));
+  for (int l = 0; l < L; ++l)
+    for (int kk = 0; kk < nk; ++kk) {
+      const zc* col = As.data() + (size_t)l * n4k + (size_t)kk * n4;
+      std::copy(col, col + n2, s.a.begin() + ((size_t)kk * L + l) * n2);
+      std::copy(col + n2, col + n4, s.b.begin() + ((size_t)kk * L + l) * n2);
+    }
+  return SCW_OK;
+}
+
 #undef SCW_BLAS
 
 // ---------------------------------------------------------------- connection route
+int connection_system(const Lin& lin, Solution& s, const Mat& K, std::vector<zc>& alpha1);
+
 int solve_connection(const Lin& lin, Solution& s, std::vector<LayerHost>& layers, int threads) {
   const int M = s.M, n2 = 2 * M, n4 = 4 * M, n6 = 6 * M, L = s.L;
   std::vector<Mat> Tlu(L), Bm(L), Mk(L);
@@ -500,6 +594,37 @@ int solve_connection(const Lin& lin, Solution& s, std::vector<LayerHost>& layers
     K.swap(tmp);
     Mat().swap(Mk[l]);
   }
+  std::vector<zc> alpha1;
+  if ((rc = connection_system(lin, s, K, alpha1))) return rc;
+  // alpha_l = T_l^-1 B_{l-1} alpha_{l-1}, one illumination at a time
+  const int nk = s.K;
+  s.a.assign((size_t)nk * L * n2, zc(0));
+  s.b.assign((size_t)nk * L * n2, zc(0));
+  std::vector<zc> nxt(n4);
+  for (int kk = 0; kk < nk; ++kk) {
+    std::vector<zc> alpha(alpha1.begin() + (size_t)kk * n4, alpha1.begin() + (size_t)(kk + 1) * n4);
+    zc* ak = s.a.data() + (size_t)kk * L * n2;
+    zc* bk = s.b.data() + (size_t)kk * L * n2;
+    for (int l = 0; l < L; ++l) {
+      if (l > 0) {
+        lin.gemm('N', 'N', n4, 1, n4, 1.0, Bm[l - 1].data(), n4, alpha.data(), n4, 0.0,
+                 nxt.data(), n4);
+        alpha = nxt;
+      }
+      lin.lu_solve(n4, 1, Tlu[l].data(), Tpiv[l], alpha.data());
+      std::copy(alpha.begin(), alpha.begin() + n2, ak + (size_t)l * n2);
+      std::copy(alpha.begin() + n2, alpha.end(), bk + (size_t)l * n2);
+    }
+  }
+  return SCW_OK;
+}
+
+// The 6M x 6M system of the connection route, C_t p_trn - K C_r p_ref =
+// K C_i p_inc plus the Gauss rows (Eq. 29), for every illumination. Sets
+// p_ref, p_trn and the reciprocal condition number, and returns
+// alpha_1 = C_i p_inc + C_r p_ref as n4 x K (column-major).
+int connection_system(const Lin& lin, Solution& s, const Mat& K, std::vector<zc>& alpha1) {
+  const int M = s.M, n4 = 4 * M, n6 = 6 * M;
   std::vector<zc> msz(M);
   for (int m = 0; m < M; ++m) msz[m] = -s.sz_top[m];
   Mat Ci = c_map(s, s.sz_top), Cr = c_map(s, msz), Ct = c_map(s, s.sz_bot);
@@ -533,13 +658,12 @@ int solve_connection(const Lin& lin, Solution& s, std::vector<LayerHost>& layers
   if (!(rcond > 1e-15))
     return fail(SCW_EILLCOND, "connection system is numerically singular (rcond " +
                                   std::to_string(rcond) + ")");
-  // every illumination shares the factorisation of A and the layer matrices
+  // every illumination shares the factorisation of A
   const int nk = s.K;
   s.p_ref.assign((size_t)nk * 3 * M, zc(0));
   s.p_trn.assign((size_t)nk * 3 * M, zc(0));
-  s.a.assign((size_t)nk * L * n2, zc(0));
-  s.b.assign((size_t)nk * L * n2, zc(0));
-  std::vector<zc> cip(n4), rhs(n6), nxt(n4);
+  alpha1.assign((size_t)nk * n4, zc(0));
+  std::vector<zc> cip(n4), rhs(n6);
   for (int kk = 0; kk < nk; ++kk) {
     const zc* pin = s.p_inc.data() + (size_t)kk * 3 * M;
     std::fill(cip.begin(), cip.end(), zc(0));
@@ -551,22 +675,11 @@ int solve_connection(const Lin& lin, Solution& s, std::vector<LayerHost>& layers
     zc* pref = s.p_ref.data() + (size_t)kk * 3 * M;
     std::copy(rhs.begin(), rhs.begin() + 3 * M, pref);
     std::copy(rhs.begin() + 3 * M, rhs.end(), s.p_trn.begin() + (size_t)kk * 3 * M);
-    // alpha_1 = T_1^-1 (C_i p_inc + C_r p_ref); alpha_l = T_l^-1 B_{l-1} alpha_{l-1}
-    std::vector<zc> alpha(cip);
+    // T_1 alpha_1 = C_i p_inc + C_r p_ref (the layer solves follow)
+    zc* al = alpha1.data() + (size_t)kk * n4;
+    std::copy(cip.begin(), cip.end(), al);
     for (int c = 0; c < 3 * M; ++c)
-      for (int rr = 0; rr < n4; ++rr) alpha[rr] += Cr[(size_t)c * n4 + rr] * pref[c];
-    zc* ak = s.a.data() + (size_t)kk * L * n2;
-    zc* bk = s.b.data() + (size_t)kk * L * n2;
-    for (int l = 0; l < L; ++l) {
-      if (l > 0) {
-        lin.gemm('N', 'N', n4, 1, n4, 1.0, Bm[l - 1].data(), n4, alpha.data(), n4, 0.0,
-                 nxt.data(), n4);
-        alpha = nxt;
-      }
-      lin.lu_solve(n4, 1, Tlu[l].data(), Tpiv[l], alpha.data());
-      std::copy(alpha.begin(), alpha.begin() + n2, ak + (size_t)l * n2);
-      std::copy(alpha.begin() + n2, alpha.end(), bk + (size_t)l * n2);
-    }
+      for (int rr = 0; rr < n4; ++rr) al[rr] += Cr[(size_t)c * n4 + rr] * pref[c];
   }
   return SCW_OK;
 }
@@ -591,8 +704,7 @@ int solve_problem(Context& ctx, const scw_problem& p, Solution& s, int n_waves,
   if (!(p.px > 0) || !(p.py > 0) || !(p.pz > 0) || !(p.lambda > 0))
     return fail(SCW_EINVAL, "pitches and wavelength must be positive");
   if (!(p.n_top > 0)) return fail(SCW_EINVAL, "n_top must be positive");
-  if (p.route != SCW_ROUTE_STABLE && p.route != SCW_ROUTE_CONNECTION &&
-      p.route != SCW_ROUTE_STABLE_DEVICE)
+  if (p.route < SCW_ROUTE_STABLE || p.route > SCW_ROUTE_CONNECTION_DEVICE)
     return fail(SCW_EINVAL, "unknown route");
   const bool image = !waves && (p.inc_ex || p.inc_ey);
   if (image && (p.inc_nx < 1 || p.inc_ny < 1))
@@ -787,9 +899,12 @@ int solve_problem(Context& ctx, const scw_problem& p, Solution& s, int n_waves,
   // ---- host: boundary solve (Sec. 2.5.4, Sec. 3.3-3.4)
   if (lp.set_threads) lp.set_threads(ctx.host_threads);
   const double t_bnd = now_s();
-  rc = p.route == SCW_ROUTE_STABLE_DEVICE ? solve_stable_device(ctx, lin, s, layers)
-       : stable                           ? solve_stable(lin, s, layers)
-                                          : solve_connection(lin, s, layers, ctx.host_threads);
+  switch (p.route) {
+    case SCW_ROUTE_STABLE: rc = solve_stable(lin, s, layers); break;
+    case SCW_ROUTE_STABLE_DEVICE: rc = solve_stable_device(ctx, lin, s, layers); break;
+    case SCW_ROUTE_CONNECTION_DEVICE: rc = solve_connection_device(ctx, lin, s, layers); break;
+    default: rc = solve_connection(lin, s, layers, ctx.host_threads); break;
+  }
   if (rc) return rc;
   s.info.boundary_seconds = now_s() - t_bnd;
 
