@@ -54,6 +54,9 @@ int main(void) {
   F(scw_plane_wave, u) F(scw_plane_wave, v) F(scw_plane_wave, ex) F(scw_plane_wave, ey)
   printf("size scw_plane_wave %zu\n", sizeof(scw_plane_wave));
   printf("size scw_slice %zu\n", sizeof(scw_slice));
+  printf("enum route stable %d\nenum route connection %d\n", SCW_ROUTE_STABLE, SCW_ROUTE_CONNECTION);
+  printf("enum route stable_device %d\nenum route connection_device %d\n",
+         SCW_ROUTE_STABLE_DEVICE, SCW_ROUTE_CONNECTION_DEVICE);
   printf("size scw_problem %zu\nsize scw_grid %zu\nsize scw_solution_info %zu\n",
          sizeof(scw_problem), sizeof(scw_grid), sizeof(scw_solution_info));
   printf("size scw_synth_config %zu\nsize scw_tune_report %zu\n",
@@ -78,6 +81,10 @@ def test_ctypes_structures_match_c_layout():
              "scw_plane_wave": N.ScwPlaneWave}
     for line in _c_layout():
         if not line:
+            continue
+        if line.startswith("enum route "):
+            _, _, name, value = line.split()
+            assert N.ROUTE[name] == int(value), line
             continue
         a, b, c = line.split()
         if a == "size":
