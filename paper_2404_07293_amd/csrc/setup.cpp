@@ -330,7 +330,9 @@ int connection_system(const Lin& lin, Solution& s, const Mat& K, std::vector<zc>
 // The same elimination in FP64 with rocSOLVER (LU with partial pivoting) and
 // rocBLAS (complex GEMM) on the setup stream: per layer, from the bottom up,
 // A1 = X^-1 Fe, A2 = Y^-1 Fh, G_t = (A1 + A2)/2, G_b = (A1 - A2)/2,
-// t = G_t^-1, r = G_b t, Fe = X (I + E r E), Fh = Y (I - E r E). The 4M x 4M
+// t = G_t^-1, r = G_b t, Fe = X (I + E r E), Fh = Y (I - E r E). The LU
+// factors of every layer's X and Y do not depend on the recursion and are
+// computed first, in one batched call over the 2L matrices. The 4M x 4M
 // top-surface system is solved on the host (top_surface); the
 // back-substitution runs on the device for all illuminations at once.
 namespace {
@@ -358,45 +360,53 @@ int solve_stable_device(Context& ctx, const Lin& lin, Solution& s,
   }
   rocblas_handle h = static_cast<rocblas_handle>(ctx.blas);
   SCW_BLAS(rocblas_set_stream(h, st));
-  DevBuf dX, dY, dXlu, dYlu, dFe, dFh, dA1, dA2, dP1, dP2, dT, dR, dE, dpiv, dinfo;
+  // XY: X_l, Y_l of every layer at 2l, 2l + 1; XYlu: their LU factors
+  DevBuf dXY, dXYlu, dFe, dFh, dA1, dA2, dP1, dP2, dT, dR, dE, dpiv, dxypiv, dinfo;
   int rc;
-  if ((rc = dX.reserve(nn * 16)) || (rc = dY.reserve(nn * 16)) || (rc = dXlu.reserve(nn * 16)) ||
-      (rc = dYlu.reserve(nn * 16)) || (rc = dFe.reserve(nn * 16)) || (rc = dFh.reserve(nn * 16)) ||
+  if ((rc = dXY.reserve(nn * 16 * 2 * L)) || (rc = dXYlu.reserve(nn * 16 * 2 * L)) ||
+      (rc = dFe.reserve(nn * 16)) || (rc = dFh.reserve(nn * 16)) ||
       (rc = dA1.reserve(nn * 16)) || (rc = dA2.reserve(nn * 16)) || (rc = dP1.reserve(nn * 16)) ||
       (rc = dP2.reserve(nn * 16)) || (rc = dT.reserve(nn * 16 * L)) ||
       (rc = dR.reserve(nn * 16 * L)) || (rc = dE.reserve((size_t)L * n2 * 16)) ||
       (rc = dpiv.reserve((size_t)n2 * sizeof(rocblas_int))) ||
+      (rc = dxypiv.reserve((size_t)2 * L * n2 * sizeof(rocblas_int))) ||
       (rc = dinfo.reserve((size_t)3 * L * sizeof(rocblas_int))))
     return rc;
-  for (int l = 0; l < L; ++l)
+  for (int l = 0; l < L; ++l) {
     SCW_HIP(hipMemcpyAsync(dE.as<zc>() + (size_t)l * n2, layers[l].E.data(), n2 * 16,
                            hipMemcpyHostToDevice, st));
+    SCW_HIP(hipMemcpyAsync(dXY.as<zc>() + (size_t)(2 * l) * nn, layers[l].X.data(), nn * 16,
+                           hipMemcpyHostToDevice, st));
+    SCW_HIP(hipMemcpyAsync(dXY.as<zc>() + (size_t)(2 * l + 1) * nn, layers[l].Y.data(), nn * 16,
+                           hipMemcpyHostToDevice, st));
+  }
+  SCW_HIP(hipMemcpyAsync(dXYlu.p, dXY.p, nn * 16 * 2 * L, hipMemcpyDeviceToDevice, st));
   SCW_HIP(launch_eye(dFe.as<double>(), n2, st));
   const Mat Fh0 = half_space_h(s, s.sz_bot);
   SCW_HIP(hipMemcpyAsync(dFh.p, Fh0.data(), nn * 16, hipMemcpyHostToDevice, st));
   const rocblas_double_complex one = {1.0, 0.0}, zero = {0.0, 0.0};
-  rocblas_int* info = dinfo.as<rocblas_int>();
+  rocblas_int* info = dinfo.as<rocblas_int>();  // [0, 2L): X, Y of each layer; [2L, 3L): G_t
   rocblas_int* piv = dpiv.as<rocblas_int>();
+  rocblas_int* xypiv = dxypiv.as<rocblas_int>();
   const rocblas_operation N = rocblas_operation_none;
+  SCW_BLAS(rocsolver_zgetrf_strided_batched(h, n2, n2, zp(dXYlu), n2, (rocblas_stride)nn, xypiv,
+                                            (rocblas_stride)n2, info, 2 * L));
   for (int l = L - 1; l >= 0; --l) {
-    LayerHost& hl = layers[l];
-    SCW_HIP(hipMemcpyAsync(dX.p, hl.X.data(), nn * 16, hipMemcpyHostToDevice, st));
-    SCW_HIP(hipMemcpyAsync(dY.p, hl.Y.data(), nn * 16, hipMemcpyHostToDevice, st));
-    SCW_HIP(hipMemcpyAsync(dXlu.p, dX.p, nn * 16, hipMemcpyDeviceToDevice, st));
-    SCW_HIP(hipMemcpyAsync(dYlu.p, dY.p, nn * 16, hipMemcpyDeviceToDevice, st));
+    rocblas_double_complex* Xl = zp(dXY, (size_t)(2 * l) * nn);
+    rocblas_double_complex* Yl = zp(dXY, (size_t)(2 * l + 1) * nn);
     SCW_HIP(hipMemcpyAsync(dA1.p, dFe.p, nn * 16, hipMemcpyDeviceToDevice, st));
     SCW_HIP(hipMemcpyAsync(dA2.p, dFh.p, nn * 16, hipMemcpyDeviceToDevice, st));
-    // A1 = X^-1 Fe, A2 = Y^-1 Fh
-    SCW_BLAS(rocsolver_zgetrf(h, n2, n2, zp(dXlu), n2, piv, info + 3 * l));
-    SCW_BLAS(rocsolver_zgetrs(h, N, n2, n2, zp(dXlu), n2, piv, zp(dA1), n2));
-    SCW_BLAS(rocsolver_zgetrf(h, n2, n2, zp(dYlu), n2, piv, info + 3 * l + 1));
-    SCW_BLAS(rocsolver_zgetrs(h, N, n2, n2, zp(dYlu), n2, piv, zp(dA2), n2));
+    // A1 = X^-1 Fe, A2 = Y^-1 Fh with the factors of the batched call
+    SCW_BLAS(rocsolver_zgetrs(h, N, n2, n2, zp(dXYlu, (size_t)(2 * l) * nn), n2,
+                              xypiv + (size_t)(2 * l) * n2, zp(dA1), n2));
+    SCW_BLAS(rocsolver_zgetrs(h, N, n2, n2, zp(dXYlu, (size_t)(2 * l + 1) * nn), n2,
+                              xypiv + (size_t)(2 * l + 1) * n2, zp(dA2), n2));
     // G_t, G_b in place; t = G_t^-1; r = G_b t
     SCW_HIP(launch_half_sum_diff(dA1.as<double>(), dA2.as<double>(), (long long)nn, st));
     zc* tl = dT.as<zc>() + (size_t)l * nn;
     zc* rl = dR.as<zc>() + (size_t)l * nn;
     SCW_HIP(launch_eye(reinterpret_cast<double*>(tl), n2, st));
-    SCW_BLAS(rocsolver_zgetrf(h, n2, n2, zp(dA1), n2, piv, info + 3 * l + 2));
+    SCW_BLAS(rocsolver_zgetrf(h, n2, n2, zp(dA1), n2, piv, info + 2 * L + l));
     SCW_BLAS(rocsolver_zgetrs(h, N, n2, n2, zp(dA1), n2, piv,
                               reinterpret_cast<rocblas_double_complex*>(tl), n2));
     SCW_BLAS(rocblas_zgemm(h, N, N, n2, n2, n2, &one, zp(dA2), n2,
@@ -405,8 +415,8 @@ int solve_stable_device(Context& ctx, const Lin& lin, Solution& s,
     // F_l = [X (I + E r E); Y (I - E r E)]
     SCW_HIP(launch_i_pm_ere(reinterpret_cast<double*>(rl), dE.as<double>() + (size_t)l * n2 * 2,
                             n2, dP1.as<double>(), dP2.as<double>(), st));
-    SCW_BLAS(rocblas_zgemm(h, N, N, n2, n2, n2, &one, zp(dX), n2, zp(dP1), n2, &zero, zp(dFe), n2));
-    SCW_BLAS(rocblas_zgemm(h, N, N, n2, n2, n2, &one, zp(dY), n2, zp(dP2), n2, &zero, zp(dFh), n2));
+    SCW_BLAS(rocblas_zgemm(h, N, N, n2, n2, n2, &one, Xl, n2, zp(dP1), n2, &zero, zp(dFe), n2));
+    SCW_BLAS(rocblas_zgemm(h, N, N, n2, n2, n2, &one, Yl, n2, zp(dP2), n2, &zero, zp(dFh), n2));
   }
   std::vector<rocblas_int> hinfo(3 * L);
   Mat Fe(nn), Fh(nn);
@@ -417,8 +427,11 @@ int solve_stable_device(Context& ctx, const Lin& lin, Solution& s,
   SCW_HIP(hipStreamSynchronize(st));
   for (int i = 0; i < 3 * L; ++i)
     if (hinfo[i] != 0)
-      return fail(i % 3 == 2 ? SCW_EILLCOND : SCW_EDEFECTIVE,
-                  "singular matrix in the device elimination (layer " + std::to_string(i / 3) + ")");
+      return fail(i >= 2 * L ? SCW_EILLCOND : SCW_EDEFECTIVE,
+                  i >= 2 * L ? "singular interface matrix in the device elimination (layer " +
+                                   std::to_string(i - 2 * L) + ")"
+                             : "eigenvector matrix is singular (layer " + std::to_string(i / 2) +
+                                   ")");
   std::vector<zc> a1;
   if ((rc = top_surface(lin, s, Fe, Fh, a1))) return rc;
   // back-substitution of all illuminations: columns of n2 x K blocks
