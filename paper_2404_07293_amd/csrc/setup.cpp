@@ -204,7 +204,7 @@ int top_surface(const Lin& lin, Solution& s, const Mat& Fe, const Mat& Fh, std::
 void transmitted(Solution& s, int kk, const zc* a);
 
 int solve_stable(const Lin& lin, Solution& s, std::vector<LayerHost>& layers) {
-  const int M = s.M, n2 = 2 * M, n4 = 4 * M, L = s.L;
+  const int M = s.M, n2 = 2 * M, L = s.L;
   std::vector<Mat> t(L), r(L);
   // F_{L+1}: transmitted waves
   Mat Fe = identity(n2);
@@ -569,7 +569,7 @@ int solve_connection_device(Context& ctx, const Lin& lin, Solution& s,
 int connection_system(const Lin& lin, Solution& s, const Mat& K, std::vector<zc>& alpha1);
 
 int solve_connection(const Lin& lin, Solution& s, std::vector<LayerHost>& layers, int threads) {
-  const int M = s.M, n2 = 2 * M, n4 = 4 * M, n6 = 6 * M, L = s.L;
+  const int M = s.M, n2 = 2 * M, n4 = 4 * M, L = s.L;
   std::vector<Mat> Tlu(L), Bm(L), Mk(L);
   std::vector<std::vector<int>> Tpiv(L);
   // T_l = W diag(I, E), B_l = W diag(E, I), M_l = B_l T_l^-1 (Eq. 27)
