@@ -42,8 +42,10 @@ typedef enum {
     SCW_ELAPACK = -4,     /* LAPACK returned info != 0, or no LAPACK found */
     SCW_EGRAZING = -5,    /* |s_z| < 1e-9 in a half-space (Eq. 2 at grazing) */
     SCW_EDEFECTIVE = -6,  /* |gamma| < 1e-9 max|gamma| in a layer: D defective */
-    SCW_EILLCOND = -7     /* connection route chosen explicitly and its system
-                             is numerically singular */
+    SCW_EILLCOND = -7     /* connection route chosen explicitly and either its
+                             growth exponent exceeds 25 or its 6M x 6M system
+                             has a reciprocal condition number below 1e-13
+                             (condition above 1e13) */
 } scw_status;
 
 typedef enum {
@@ -59,8 +61,10 @@ typedef enum {
        boundary-value system of Eqs. 24-26. */
     SCW_ROUTE_STABLE = 0,
     /* The paper's connection equations (Sec. 2.5.4, Eqs. 27-29): the product
-       K of per-layer transfer matrices and a 6M x 6M solve. Loses accuracy
-       when K contains large growing evanescent exponentials. */
+       K of per-layer transfer matrices and a 6M x 6M solve. K holds growing
+       evanescent exponentials up to exp(growth_exponent), so this route
+       fails with SCW_EILLCOND when the growth exponent exceeds 25 or the
+       system's reciprocal condition number is below 1e-13. */
     SCW_ROUTE_CONNECTION = 1,
     /* SCW_ROUTE_STABLE with its per-layer elimination on the GPU in FP64
        (rocSOLVER LU with partial pivoting, rocBLAS complex GEMM); the 4M x 4M
@@ -216,8 +220,14 @@ int scw_synthesize_illuminations(scw_ctx* ctx, scw_solution* sol, const scw_grid
  *   exp(i k s_m . r) on the grid by a separable inverse transform.
  * E_dev: caller-owned device buffer [3][fz][fy][fx], complex128 for SCW_FP64,
  * complex64 otherwise. `hip_stream` is a hipStream_t (NULL = default stream).
- * The call enqueues work and returns; the first call for a new grid or
- * precision builds a plan (device tables) synchronously. */
+ * The call enqueues work and returns; the first call for a new grid,
+ * precision or kernel configuration builds a plan (device tables and
+ * workspaces) synchronously. A plan is never rebuilt or freed before
+ * scw_solution_free, so work already enqueued, or captured in a HIP graph,
+ * stays valid while later calls use other grids, precisions or
+ * configurations (or scw_tune_synthesis runs). Calls that use the same plan
+ * share its workspaces: order them on one stream, or synchronise between
+ * streams, so that they do not overlap in time. */
 int scw_synthesize(scw_ctx* ctx, scw_solution* sol, const scw_grid* grid,
                    int precision, void* E_dev, void* hip_stream);
 

@@ -147,9 +147,10 @@ size_t fft_lds_bytes(const Solution& s, const scw_grid& g, int precision, int P)
   return ((size_t)s.U * s.V + 32 * 64 + 32 * (size_t)(g.fy / P)) * eb;
 }
 
-int build_plan(const Context& ctx, Solution& s, Plan& pl, const scw_grid& g, int precision,
-               bool direct_only) {
+int build_plan(Solution& s, Plan& pl, const scw_grid& g, int precision,
+               const scw_synth_config& cfg, bool direct_only) {
   pl.valid = false;
+  pl.direct_only = direct_only;
   pl.grid = g;
   pl.precision = precision;
   pl.planes.assign(g.fz, PlaneInfo{});
@@ -237,8 +238,6 @@ int build_plan(const Context& ctx, Solution& s, Plan& pl, const scw_grid& g, int
       return rc;
   }
   // kernel configuration: explicit, tuned, or the built-in default
-  scw_synth_config cfg = resolve_config(ctx, s, g, precision);
-  if (direct_only) cfg = scw_synth_config{cfg.modal_rows, SCW_XFORM_DIRECT, 0, 0};
   pl.cfg = cfg;
   const bool split = precision == SCW_BF16X3 || precision == SCW_FP16X3;
   if (cfg.transform < SCW_XFORM_AUTO || cfg.transform > SCW_XFORM_DIRECT)
@@ -434,28 +433,33 @@ std::string synth_key(const Solution& s, const scw_grid& g, int precision) {
   return buf;
 }
 
-int synthesize(Context& c, Solution& s, const scw_grid& g, int precision, void* E,
-               hipStream_t st, int stages, hipEvent_t* ev) {
-  return synthesize(c, s, s.plan, g, precision, E, st, stages, ev, false);
+static bool same_config(const scw_synth_config& a, const scw_synth_config& b) {
+  return a.modal_rows == b.modal_rows && a.transform == b.transform &&
+         a.fft_radix == b.fft_radix && a.tiles == b.tiles;
 }
 
-// The FP32 copy of P (first use) and the plan of (grid, precision).
-static int prepare(Context& c, Solution& s, Plan& pl, const scw_grid& g, int precision,
-                   hipStream_t st, bool direct_only) {
-  int rc;
+int get_plan(Context& c, Solution& s, const scw_grid& g, int precision, bool direct_only,
+             Plan** out) {
   if (s.device != c.device) return fail(SCW_EINVAL, "solution belongs to another device");
   SCW_HIP(hipSetDevice(c.device));
-  const size_t pl_elems = (size_t)s.L * 3 * s.M * 2 * s.M;
-  if (precision != SCW_FP64 && s.d_P32.bytes < pl_elems * 8) {
-    if ((rc = s.d_P32.reserve(pl_elems * 8))) return rc;
-    SCW_HIP(launch_p_to_fp32(s.d_P64.as<double>(), s.d_P32.as<float>(), pl_elems, st));
-  }
-  if (!pl.valid || pl.precision != precision || !same_grid(pl.grid, g) ||
-      pl.epoch != c.tune_epoch) {
-    SCW_HIP(hipStreamSynchronize(st));
-    if ((rc = build_plan(c, s, pl, g, precision, direct_only))) return rc;
-    pl.epoch = c.tune_epoch;
-  }
+  if (precision != SCW_FP64 && !s.d_P32.p)
+    return fail(SCW_EINVAL, "solution has no FP32 synthesis matrices");
+  scw_synth_config cfg = resolve_config(c, s, g, precision);
+  if (direct_only) cfg = scw_synth_config{cfg.modal_rows, SCW_XFORM_DIRECT, 0, 0};
+  for (auto& p : s.plans)
+    if (p->valid && p->precision == precision && p->direct_only == direct_only &&
+        same_grid(p->grid, g) && same_config(p->cfg, cfg)) {
+      *out = p.get();
+      return SCW_OK;
+    }
+  // A new plan: fresh buffers, so work in flight on older plans is untouched;
+  // its tables are uploaded synchronously before any kernel can read them.
+  std::unique_ptr<Plan> pl(new (std::nothrow) Plan());
+  if (!pl) return fail(SCW_ENOMEM, "plan allocation failed");
+  int rc = build_plan(s, *pl, g, precision, cfg, direct_only);
+  if (rc) return rc;
+  s.plans.push_back(std::move(pl));
+  *out = s.plans.back().get();
   return SCW_OK;
 }
 
@@ -502,11 +506,13 @@ static SynthArgs synth_args(const Solution& s, const Plan& pl, const scw_grid& g
   return a;
 }
 
-int synthesize(Context& c, Solution& s, Plan& pl, const scw_grid& g, int precision, void* E,
-               hipStream_t st, int stages, hipEvent_t* ev, bool direct_only) {
-  int rc = prepare(c, s, pl, g, precision, st, direct_only);
+int synthesize(Context& c, Solution& s, const scw_grid& g, int precision, void* E,
+               hipStream_t st, int stages, hipEvent_t* ev, bool direct_only, Plan** used) {
+  Plan* pl = nullptr;
+  int rc = get_plan(c, s, g, precision, direct_only, &pl);
   if (rc) return rc;
-  const SynthArgs a = synth_args(s, pl, g, precision, E, stages);
+  if (used) *used = pl;
+  const SynthArgs a = synth_args(s, *pl, g, precision, E, stages);
   SCW_HIP(precision == SCW_FP64 ? launch_synthesis_fp64(a, st, ev)
                                 : launch_synthesis_fp32(a, st, ev));
   return SCW_OK;
@@ -517,14 +523,15 @@ int synthesize(Context& c, Solution& s, Plan& pl, const scw_grid& g, int precisi
 // exterior planes and transform into its block of E.
 int synthesize_illuminations(Context& c, Solution& s, const scw_grid& g, void* E,
                              hipStream_t st) {
-  int rc = prepare(c, s, s.plan, g, SCW_FP32, st, false);
+  Plan* plp = nullptr;
+  int rc = get_plan(c, s, g, SCW_FP32, false, &plp);
   if (rc) return rc;
-  const Plan& pl = s.plan;
+  Plan& pl = *plp;
   const size_t per = (size_t)g.fz * 3 * s.M;
-  if (s.d_spec_multi.bytes < per * s.K * 8 && (rc = s.d_spec_multi.reserve(per * s.K * 8)))
-    return rc;
+  // sized once per plan (K is fixed for a solution): never reallocated
+  if (!pl.d_spec_multi.p && (rc = pl.d_spec_multi.reserve(per * s.K * 8))) return rc;
   const size_t wb = multi_table_bytes((int)pl.tasks.size(), s.M);
-  if (s.d_wmulti.bytes < wb && (rc = s.d_wmulti.reserve(wb))) return rc;
+  if (!pl.d_wmulti.p && (rc = pl.d_wmulti.reserve(wb))) return rc;
   const size_t lm = (size_t)s.L * 2 * s.M;  // complex per [L][2M] block
   // with one illumination, (a, b) are the last two blocks of k*gamma, a, b
   const void* ab = s.K > 1 ? s.d_ab32.p : (const void*)(s.d_kgab32.as<float>() + 2 * lm);
@@ -532,14 +539,14 @@ int synthesize_illuminations(Context& c, Solution& s, const scw_grid& g, void* E
   for (int k0 = 0; k0 < s.K && !pl.tasks.empty(); k0 += group)
     SCW_HIP(launch_modal_multi(s.d_P32.p, s.d_kgab32.p, ab, pl.d_tasks.as<Task>(),
                                pl.d_task_dz32.p, (int)pl.tasks.size(), pl.zt, s.M, s.L, g.fz,
-                               k0, std::min(group, s.K - k0), s.d_wmulti.p,
-                               s.d_spec_multi.p, st));
+                               k0, std::min(group, s.K - k0), pl.d_wmulti.p,
+                               pl.d_spec_multi.p, st));
   const size_t vol = (size_t)3 * g.fz * g.fy * g.fx;
   for (int k = 0; k < s.K; ++k) {
     SynthArgs a = synth_args(s, pl, g, SCW_FP32, static_cast<char*>(E) + k * vol * 8,
                              kStageExterior | kStageTransform);
     a.ext = s.d_ext.as<double>() + (size_t)k * 9 * s.M * 2;
-    a.spec = s.d_spec_multi.as<char>() + k * per * 8;
+    a.spec = pl.d_spec_multi.as<char>() + k * per * 8;
     SCW_HIP(launch_synthesis_fp32(a, st, nullptr));
   }
   return SCW_OK;
@@ -579,10 +586,11 @@ int scw_synthesize_slice(scw_ctx* ctx, scw_solution* sol, const scw_slice* slice
   if (rc) return rc;
   Solution& s = sol->s;
   const hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
-  if ((rc = synthesize(ctx->c, s, s.slice_plan, g, precision, nullptr, st,
-                       kStageModal | kStageExterior, nullptr, true)))
+  Plan* plp = nullptr;
+  if ((rc = synthesize(ctx->c, s, g, precision, nullptr, st, kStageModal | kStageExterior,
+                       nullptr, true, &plp)))
     return rc;
-  const Plan& pl = s.slice_plan;
+  const Plan& pl = *plp;
   SliceArgs a{};
   a.spec = pl.d_spec.p;
   a.tw = slice->axis == SCW_SLICE_XZ ? pl.d_twx.p : pl.d_twy.p;
@@ -601,7 +609,7 @@ int scw_synthesize_slice(scw_ctx* ctx, scw_solution* sol, const scw_slice* slice
 // is not null) the intensity.
 static int synthesize_with(scw_ctx* ctx, scw_solution* sol, const scw_grid* grid, int precision,
                            void* E_dev, void* I_dev, void* hip_stream,
-                           const std::function<hipError_t(Solution&, hipStream_t)>& op) {
+                           const std::function<hipError_t(Solution&, Plan&, hipStream_t)>& op) {
   if (!ctx || !sol || !E_dev) return fail(SCW_EINVAL, "null argument");
   int rc = check_grid(grid);
   if (rc) return rc;
@@ -612,9 +620,11 @@ static int synthesize_with(scw_ctx* ctx, scw_solution* sol, const scw_grid* grid
   Context& c = ctx->c;
   Solution& s = sol->s;
   const hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
-  if ((rc = synthesize(c, s, *grid, precision, E_dev, st, kStageModal | kStageExterior, nullptr)))
+  Plan* pl = nullptr;
+  if ((rc = synthesize(c, s, *grid, precision, E_dev, st, kStageModal | kStageExterior, nullptr,
+                       false, &pl)))
     return rc;
-  SCW_HIP(op(s, st));
+  SCW_HIP(op(s, *pl, st));
   if ((rc = synthesize(c, s, *grid, precision, E_dev, st, kStageTransform, nullptr))) return rc;
   if (I_dev)
     SCW_HIP(launch_intensity(E_dev, I_dev, (long long)grid->fz * grid->fy * grid->fx,
@@ -626,8 +636,8 @@ int scw_synthesize_image(scw_ctx* ctx, scw_solution* sol, const scw_grid* grid, 
                          double na, void* E_dev, void* I_dev, void* hip_stream) {
   if (!(na >= 0.0) || !std::isfinite(na)) return fail(SCW_EINVAL, "na must be finite and >= 0");
   return synthesize_with(ctx, sol, grid, precision, E_dev, I_dev, hip_stream,
-                         [&](Solution& s, hipStream_t st) {
-                           return launch_objective(s.plan.d_spec.p,
+                         [&](Solution& s, Plan& pl, hipStream_t st) {
+                           return launch_objective(pl.d_spec.p,
                                                    (long long)grid->fz * 3 * s.M, s.M, s.U, s.V,
                                                    s.lam / s.X, s.lam / s.Y, na,
                                                    precision == SCW_FP64, st);
@@ -638,8 +648,8 @@ int scw_synthesize_filtered(scw_ctx* ctx, scw_solution* sol, const scw_grid* gri
                             const void* H_dev, void* E_dev, void* I_dev, void* hip_stream) {
   if (!H_dev) return fail(SCW_EINVAL, "null transfer function");
   return synthesize_with(ctx, sol, grid, precision, E_dev, I_dev, hip_stream,
-                         [&](Solution& s, hipStream_t st) {
-                           return launch_transfer(s.plan.d_spec.p,
+                         [&](Solution& s, Plan& pl, hipStream_t st) {
+                           return launch_transfer(pl.d_spec.p,
                                                   (long long)grid->fz * 3 * s.M, s.M, H_dev,
                                                   precision == SCW_FP64, st);
                          });
@@ -648,8 +658,6 @@ int scw_synthesize_filtered(scw_ctx* ctx, scw_solution* sol, const scw_grid* gri
 int scw_synthesis_configure(scw_solution* sol, const scw_synth_config* cfg) {
   if (!sol) return fail(SCW_EINVAL, "null solution");
   sol->s.cfg = cfg ? *cfg : scw_synth_config{};
-  sol->s.plan.valid = false;
-  sol->s.slice_plan.valid = false;
   return SCW_OK;
 }
 

@@ -108,9 +108,11 @@ struct Plan {
   int modal_rw = 0;                 // rows per wave of the FP32 modal sum
   int tiles = 0;                    // DIRECT row tiles / MFMA plane-components per block
   scw_synth_config cfg{};           // the configuration the plan was built for
-  unsigned epoch = 0;               // context tuning epoch the plan was built in
+  bool direct_only = false;         // built for the direct-sum transform (slices)
   DevBuf d_twx;                     // [2][fx] complex<T>: e^{2 pi i f/fx}, e^{-2 pi i (U/2) f/fx}
   DevBuf d_twy;                     // [2][fy] complex<T>: same for g, V
+  DevBuf d_spec_multi;              // [K][fz][3M] complex64: spectra of every illumination
+  DevBuf d_wmulti;                  // phase table of one illumination group
   bool valid = false;
 };
 
@@ -130,17 +132,18 @@ struct Solution {
 
   // device copies
   DevBuf d_P64;      // [L][3M][2M] complex128, row-major
-  DevBuf d_P32;      // [L][3M][2M] complex64 (lazy)
+  DevBuf d_P32;      // [L][3M][2M] complex64
   DevBuf d_kg;       // [L][2M] complex128: k * gamma
   DevBuf d_a, d_b;   // [K][L][2M] complex128
   DevBuf d_kgab32;   // [3][L][2M] complex64: k*gamma, a, b of illumination 0
   DevBuf d_ab32;     // [K][2][L][2M] complex64: a, b of every illumination (K > 1)
   DevBuf d_ext;      // [K][3][3M] complex128: p_inc, p_ref, p_trn
-  DevBuf d_spec_multi;  // [K][fz][3M] complex64: spectra of every illumination
-  DevBuf d_wmulti;      // phase table of one illumination group (matrix-core modal sum)
   DevBuf d_ksz;      // [2][M] complex128: k*sz_top, k*sz_bot
-  Plan plan;
-  Plan slice_plan;         // spectra of the planes of the last slice shape
+  // Synthesis plans, one per (grid, precision, resolved configuration, slice
+  // or volume). A plan is never rebuilt in place and lives until the solution
+  // is freed, so work enqueued (or captured in a graph) with one plan stays
+  // valid when later calls use another grid, precision or configuration.
+  std::vector<std::unique_ptr<Plan>> plans;
   scw_synth_config cfg{};  // explicit kernel configuration (0 fields: library choice)
   int device = 0;
 };
@@ -163,20 +166,23 @@ struct Context {
     int P, blocks_per_cu, chunk;
   };
   std::map<std::string, BatchShape> tuned_batch;
-  unsigned tune_epoch = 0;  // bumped when tuned_synth changes
 };
 
 // Stages of one synthesis call, selectable for timing.
 enum StageMask { kStageModal = 1, kStageExterior = 2, kStageTransform = 4, kStageAll = 7 };
 
-// Plan (if needed) and enqueue one synthesis; `stages` selects kernels and
-// `ev` (nullable) receives kNumStages + 1 stage events.
+// The plan of (grid, precision, the configuration resolve_config gives, and
+// direct_only) for solution s: found among s.plans or built (synchronously)
+// and added. direct_only builds it for the direct-sum transform, which
+// accepts any lateral size (the slices use only its tables).
+int get_plan(Context& ctx, Solution& s, const scw_grid& g, int precision, bool direct_only,
+             Plan** out);
+// Plan (if needed) and enqueue one synthesis; `stages` selects kernels, `ev`
+// (nullable) receives kNumStages + 1 stage events and `used` (nullable) the
+// plan whose workspaces the kernels use.
 int synthesize(Context& ctx, Solution& s, const scw_grid& g, int precision, void* E,
-               hipStream_t st, int stages, hipEvent_t* ev);
-// The same with an explicit plan; direct_only builds it for the direct-sum
-// transform, which accepts any lateral size (the slices use only its tables).
-int synthesize(Context& ctx, Solution& s, Plan& pl, const scw_grid& g, int precision, void* E,
-               hipStream_t st, int stages, hipEvent_t* ev, bool direct_only);
+               hipStream_t st, int stages, hipEvent_t* ev, bool direct_only = false,
+               Plan** used = nullptr);
 std::string synth_key(const Solution& s, const scw_grid& g, int precision);
 // FP32 fields of every illumination, E: [K][3][fz][fy][fx] complex64.
 int synthesize_illuminations(Context& ctx, Solution& s, const scw_grid& g, void* E,

@@ -43,6 +43,11 @@ namespace {
 
 using Mat = std::vector<zc>;  // column-major
 
+// Limits of the connection route (Eqs. 27-29): reciprocal condition number of
+// its 6M x 6M system and growth exponent of K.
+constexpr double kConnectionMinRcond = 1e-13;
+constexpr double kConnectionMaxGrowth = 25.0;
+
 double now_s() {
   using namespace std::chrono;
   return duration<double>(steady_clock::now().time_since_epoch()).count();
@@ -668,9 +673,11 @@ int connection_system(const Lin& lin, Solution& s, const Mat& K, std::vector<zc>
   std::vector<zc> cw(2 * n6);
   lin.lp.zgecon(&one, &n6, A.data(), &n6, &anorm, &rcond, cw.data(), rw.data(), &info);
   s.info.connection_rcond = rcond;
-  if (!(rcond > 1e-15))
-    return fail(SCW_EILLCOND, "connection system is numerically singular (rcond " +
-                                  std::to_string(rcond) + ")");
+  // condition number above 1e13: FP64 keeps fewer than three digits of the
+  // coefficients, so the forced route reports it instead of answering
+  if (!(rcond >= kConnectionMinRcond))
+    return fail(SCW_EILLCOND, "connection system is ill-conditioned (rcond " +
+                                  std::to_string(rcond) + " < 1e-13)");
   // every illumination shares the factorisation of A
   const int nk = s.K;
   s.p_ref.assign((size_t)nk * 3 * M, zc(0));
@@ -910,6 +917,13 @@ int solve_problem(Context& ctx, const scw_problem& p, Solution& s, int n_waves,
   s.info.growth_exponent = growth;
 
   // ---- host: boundary solve (Sec. 2.5.4, Sec. 3.3-3.4)
+  // The connection product K holds exp(growth_exponent) next to O(1) terms;
+  // past e^25 (about 7e10) its system keeps fewer digits than the field needs,
+  // so a forced connection route fails instead of returning degraded values.
+  if ((p.route == SCW_ROUTE_CONNECTION || p.route == SCW_ROUTE_CONNECTION_DEVICE) &&
+      growth > kConnectionMaxGrowth)
+    return fail(SCW_EILLCOND, "connection route: growth exponent " + std::to_string(growth) +
+                                  " above 25 (use SCW_ROUTE_STABLE)");
   if (lp.set_threads) lp.set_threads(ctx.host_threads);
   const double t_bnd = now_s();
   switch (p.route) {
@@ -941,6 +955,10 @@ int solve_problem(Context& ctx, const scw_problem& p, Solution& s, int n_waves,
                            s.d_P64.as<double>() + (size_t)l0 * pl * 2, st));
     SCW_HIP(hipStreamSynchronize(st));
   }
+  // the complex64 copy every FP32 and split-precision synthesis streams
+  // (made here, once, so that no synthesis call has to create or wait for it)
+  if ((rc = s.d_P32.reserve(pl * 8 * L))) return rc;
+  SCW_HIP(launch_p_to_fp32(s.d_P64.as<double>(), s.d_P32.as<float>(), pl * L, st));
   // per-layer k*gamma, a, b and the exterior coefficients
   // (a, b and the exterior coefficients illumination-major: [K][L][2M], [K][3][3M])
   std::vector<zc> kg((size_t)L * n2), ext(9 * (size_t)M * s.K), ksz(2 * (size_t)M);

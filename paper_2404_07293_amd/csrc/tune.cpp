@@ -84,16 +84,19 @@ int sweep(int n, const std::function<int(int)>& prepare, const std::function<int
 
 }  // namespace
 
-// Restores a solution's explicit configuration when the tuner returns: the
-// tuner's result lives in the context, keyed by shape and precision.
+// Restores a solution's explicit configuration when the tuner returns (the
+// tuner's result lives in the context, keyed by shape and precision), and
+// frees the plans the candidates were built with: they were used only by the
+// tuner's own launches on its stream, which it has synchronised by then.
 struct ConfigGuard {
   Solution& s;
   scw_synth_config saved;
-  explicit ConfigGuard(Solution& sol) : s(sol), saved(sol.cfg) {}
-  ~ConfigGuard() {
-    s.cfg = saved;
-    s.plan.valid = false;
+  size_t n_plans;
+  explicit ConfigGuard(Solution& sol) : s(sol), saved(sol.cfg), n_plans(sol.plans.size()) {}
+  void drop_candidate_plans() {
+    if (s.plans.size() > n_plans) s.plans.resize(n_plans);
   }
+  ~ConfigGuard() { s.cfg = saved; }
 };
 
 int tune_synthesis(Context& c, Solution& s, const scw_grid& g, int precision, void* E,
@@ -101,15 +104,23 @@ int tune_synthesis(Context& c, Solution& s, const scw_grid& g, int precision, vo
   const std::string key = synth_key(s, g, precision);
   ConfigGuard guard(s);
   // candidates are timed without the context's tuned entry for this shape
+  auto prior = c.tuned_synth.find(key);
+  const bool had_prior = prior != c.tuned_synth.end();
+  const scw_synth_config prior_cfg = had_prior ? prior->second : scw_synth_config{};
   c.tuned_synth.erase(key);
-  ++c.tune_epoch;
-  auto use = [&](const scw_synth_config& cf) {
-    s.cfg = cf;
-    s.plan.valid = false;
+  auto use = [&](const scw_synth_config& cf) { s.cfg = cf; };
+  // on an error the stream is drained, the candidate plans freed and the
+  // context's earlier entry for this shape restored
+  auto bail = [&](int r) {
+    (void)hipStreamSynchronize(st);
+    guard.drop_candidate_plans();
+    if (had_prior) c.tuned_synth[key] = prior_cfg;
+    return r;
   };
+  Plan* last = nullptr;
   // builds the plan of the current configuration without launching kernels
   auto plan_only = [&]() {
-    int r = synthesize(c, s, g, precision, E, st, 0, nullptr);
+    int r = synthesize(c, s, g, precision, E, st, 0, nullptr, false, &last);
     if (r == SCW_EINVAL) set_error(SCW_OK, "");
     return r;
   };
@@ -125,18 +136,19 @@ int tune_synthesis(Context& c, Solution& s, const scw_grid& g, int precision, vo
     auto prep = [&](int i) {
       use(scw_synth_config{rows[i], 0, 0, 0});
       int r = plan_only();
-      if (r == SCW_OK && s.plan.modal_rw != rows[i]) r = SCW_EINVAL;  // capped: a duplicate
+      if (r == SCW_OK && last->modal_rw != rows[i]) r = SCW_EINVAL;  // capped: a duplicate
       return r;
     };
     const int b = sweep(4, prep, stage(kStageModal), st, reps, ms, &counted);
-    if (b < 0) return fail(SCW_EINVAL, "no modal-sum configuration ran");
+    if (b < -1) return bail(b);
+    if (b < 0) return bail(fail(SCW_EINVAL, "no modal-sum configuration ran"));
     best.modal_rows = rows[b];
   }
   // stage 2: the transform, on the spectra of one complete call
   {
     use(scw_synth_config{best.modal_rows, 0, 0, 0});
     int rc = synthesize(c, s, g, precision, E, st, kStageAll, nullptr);
-    if (rc) return rc;
+    if (rc) return bail(rc);
     const bool split = precision == SCW_BF16X3 || precision == SCW_FP16X3;
     std::vector<scw_synth_config> cands;
     if (!split)
@@ -151,7 +163,8 @@ int tune_synthesis(Context& c, Solution& s, const scw_grid& g, int precision, vo
       return plan_only();
     };
     const int b = sweep((int)cands.size(), prep, stage(kStageTransform), st, reps, ms, &counted);
-    if (b < 0) return fail(SCW_EINVAL, "no transform configuration ran");
+    if (b < -1) return bail(b);
+    if (b < 0) return bail(fail(SCW_EINVAL, "no transform configuration ran"));
     best = cands[b];
   }
   // the winner against the default as whole calls, alternately, twice each
@@ -160,22 +173,24 @@ int tune_synthesis(Context& c, Solution& s, const scw_grid& g, int precision, vo
     double t = 0;
     use(scw_synth_config{});
     int rc = time_calls(stage(kStageAll), st, reps, &t);
-    if (rc) return rc;
+    if (rc) return bail(rc);
     default_ms = std::min(default_ms, t);
     use(best);
-    if ((rc = time_calls(stage(kStageAll), st, reps, &t))) return rc;
+    if ((rc = time_calls(stage(kStageAll), st, reps, &t))) return bail(rc);
     best_ms = std::min(best_ms, t);
   }
   if (best_ms > default_ms) {  // the stage winners did not pay off as a whole
     best = scw_synth_config{};
     best_ms = default_ms;
   }
+  SCW_HIP(hipStreamSynchronize(st));
+  guard.drop_candidate_plans();
   c.tuned_synth[key] = best;
-  ++c.tune_epoch;
   // the field of the chosen configuration, as the caller's later calls
   // without an explicit configuration will compute it
   use(scw_synth_config{});
-  int rc = synthesize(c, s, g, precision, E, st, kStageAll, nullptr);
+  Plan* chosen = nullptr;
+  int rc = synthesize(c, s, g, precision, E, st, kStageAll, nullptr, false, &chosen);
   if (rc) return rc;
   SCW_HIP(hipStreamSynchronize(st));
   if (rep) {
@@ -183,7 +198,7 @@ int tune_synthesis(Context& c, Solution& s, const scw_grid& g, int precision, vo
     rep->n_candidates = counted;
     rep->default_ms = default_ms;
     rep->best_ms = best_ms;
-    const Plan& pl = s.plan;
+    const Plan& pl = *chosen;
     rep->config.modal_rows = precision == SCW_FP64 ? 0 : pl.modal_rw;
     rep->config.transform = pl.fft_p ? SCW_XFORM_FFT : (pl.mfma ? SCW_XFORM_MFMA : SCW_XFORM_DIRECT);
     rep->config.fft_radix = pl.fft_p;

@@ -12,7 +12,6 @@ import workloads as W
 
 pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "large_samples.npz")
-TOL = {"fp32": 1e-4, "bf16x3": 1e-4, "fp16x3": 1e-5}
 
 
 @pytest.fixture(scope="module")
@@ -43,20 +42,13 @@ def test_large_exterior_coefficients_match_oracle(solved):
 @pytest.mark.parametrize("precision", ["fp32", "bf16x3", "fp16x3"])
 def test_large_field_matches_oracle_samples(solved, precision):
     import torch
+    from parity_bounds import check
     ctx, sol, prob, grid = solved
-    tol = TOL[precision]
     g = np.load(GOLDEN, allow_pickle=False)
     E = sol.synthesize(grid, precision)
     torch.cuda.synchronize()
     idx = torch.as_tensor(np.stack([g["j"], g["g"], g["f"]]), device=E.device)
     got = E[:, idx[0], idx[1], idx[2]].cpu().numpy()
-    want = g["E"]
-    err = float(np.linalg.norm(got - want) / np.linalg.norm(want))
-    per = [float(np.linalg.norm(got[c] - want[c]) / np.linalg.norm(want[c])) for c in range(3)]
-    print("large %s rel-L2 at %d samples: %.3e per component %s" % (
-        precision, want.shape[1], err, ["%.2e" % x for x in per]))
-    assert err <= tol
-    for c in range(3):
-        assert per[c] <= 10 * tol
+    check(precision, got, g["E"], "large, %d samples:" % g["E"].shape[1])
     assert bool(torch.isfinite(torch.view_as_real(E)).all())
     del E

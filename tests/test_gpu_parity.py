@@ -324,3 +324,76 @@ def test_synthesis_replays_in_a_captured_graph(ctx):
         torch.cuda.synchronize()
         assert torch.equal(out, want), k
         del junk
+
+
+def _film_stack():
+    ns = [1.3, 1.7 + 0.02j, 1.5]
+    n = np.stack([np.full((4, 4), complex(x)) for x in ns])
+    return W.Problem(n=n, px=0.6, py=0.6, pz=0.25, lam=1.0, U=3, V=3, n_top=1.0,
+                     n_bot=1.2 + 0.01j, plane_wave=W.PlaneWave(1, 0, 1.0, 0.0))
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("fp32", FP32_TOL)])
+def test_planes_exactly_on_interfaces_match_oracle(ctx, precision, tol):
+    """One plane per interface, z_j = j d exactly (pitch 0.25, binary-exact):
+    z0 belongs to layer 1, z_l to layer l+1 and z_L to the lower half-space,
+    where E_z differs from the layer above by eps_above / eps_below."""
+    for prob in (W.sphere_config()[0], _film_stack()):
+        L, d = prob.nz, prob.pz
+        grid = W.Grid(fx=16, fy=8, fz=L + 1, z_begin=-d / 2, z_end=(L + 0.5) * d)
+        assert np.array_equal(grid.z_planes(), np.arange(L + 1) * d)
+        st = cwt.setup(prob)
+        sol_o = cwt.solve(st)
+        want = cwt.synthesize(st, sol_o, grid)
+        _, got = run(ctx, prob, grid, precision)
+        per = [rel_l2(got[c], want[c]) for c in range(3)]
+        print("interfaces %s per component %s" % (precision, ["%.2e" % x for x in per]))
+        assert max(per) <= tol
+        # the E_z of the layer above would be off by the index ratio
+        above = np.stack([cwt.plane_coefficients(st, sol_o, z - 1e-9)[2]
+                          for z in grid.z_planes()])
+        assert np.abs(above - np.stack([cwt.plane_coefficients(st, sol_o, z)[2]
+                                        for z in grid.z_planes()])).max() > 1e-3
+
+
+def test_defective_layer_is_rejected(ctx):
+    """A homogeneous layer with eps = s_x^2 on a lattice mode (n = 0.5, X = 2
+    lambda, u = 1): gamma = 0 exactly, D defective -> SCW_EDEFECTIVE."""
+    import paper_2404_07293_amd as P
+    n = np.full((2, 1, 4), 0.5 + 0j)
+    prob = W.Problem(n=n, px=0.5, py=0.5, pz=0.2, lam=1.0, U=3, V=1)
+    for route in ("stable", "connection", "stable_device"):
+        with pytest.raises(P.ScwError) as e:
+            ctx.solve(prob, route)
+        assert e.value.code == -6, route
+    prob.n = np.full((2, 1, 4), 0.6 + 0j)
+    ctx.solve(prob)
+
+
+def test_captured_synthesis_survives_other_grids_and_configurations(ctx):
+    """A graph captured with one grid keeps its plan: synthesizing other grids,
+    precisions and kernel configurations of the same solution, and tuning it,
+    builds new plans and leaves the captured one intact."""
+    torch = _torch()
+    prob = ragged_problem(seed=22, nx=8, ny=10, U=7, V=9)
+    grid_a = W.Grid(fx=48, fy=64, fz=10, z_begin=-0.3, z_end=1.0)
+    grid_b = W.Grid(fx=96, fy=128, fz=31, z_begin=-0.5, z_end=1.3)
+    sol = ctx.solve(prob)
+    want = sol.synthesize(grid_a, "fp32").clone()
+    torch.cuda.synchronize()
+    out = torch.zeros_like(want)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        sol.synthesize(grid_a, "fp32", out=out)
+    other = [lambda: sol.synthesize(grid_b, "fp32"),
+             lambda: sol.synthesize(grid_b, "bf16x3"),
+             lambda: sol.synthesize(grid_a, "fp64"),
+             lambda: (sol.configure(transform="direct"), sol.synthesize(grid_a, "fp32")),
+             lambda: (sol.configure(), sol.tune(grid_b, "fp32", reps=1))]
+    for k, fn in enumerate(other):
+        fn()
+        torch.cuda.synchronize()
+        out.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, want), k

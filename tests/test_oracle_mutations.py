@@ -121,3 +121,21 @@ _orig_sz = cwt.s_z
 def test_pins_catch_planted_mistake(monkeypatch, name, attr, repl):
     monkeypatch.setattr(cwt, attr, repl)
     assert _checks() != [], name
+
+
+def _interface_to_layer_above(st, z):
+    # a plane exactly on z_l assigned to the layer above it
+    zL = st.L * st.d
+    if z <= 0.0:
+        return -1
+    if z > zL:
+        return st.L
+    return min(int(np.ceil(z / st.d)) - 1, st.L - 1)
+
+
+def test_interface_pin_catches_the_layer_above_reading(monkeypatch):
+    import test_oracle_pins as pins
+    pins.test_plane_on_an_interface_takes_the_layer_below()
+    monkeypatch.setattr(cwt, "layer_of", _interface_to_layer_above)
+    with pytest.raises(AssertionError):
+        pins.test_plane_on_an_interface_takes_the_layer_below()

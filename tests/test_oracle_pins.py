@@ -370,3 +370,73 @@ def test_even_truncation_rejected():
     prob = _uniform_problem(1, 1.5, 1.0, 1.0, 4, 3, 2.3, 0.3, W.PlaneWave(0, 0, 1, 0))
     with pytest.raises(cwt.OracleError):
         cwt.setup(prob)
+
+
+# ---------------------------------------------------------------- interfaces (R14)
+def _film_stack():
+    """Three homogeneous layers of different index between two half-spaces,
+    lit by an oblique p-polarised lattice plane wave (E_z != 0). Pitch 0.25 so
+    that every interface z_l = l * 0.25 is exact in binary."""
+    ns = [1.3, 1.7 + 0.02j, 1.5]
+    n = np.stack([np.full((4, 4), complex(x)) for x in ns])
+    prob = W.Problem(n=n, px=0.6, py=0.6, pz=0.25, lam=1.0, U=3, V=3, n_top=1.0,
+                     n_bot=1.2 + 0.01j, plane_wave=W.PlaneWave(1, 0, 1.0, 0.0))
+    return prob, [prob.n_top] + ns + [prob.n_bot]
+
+
+def test_plane_on_an_interface_takes_the_layer_below():
+    """Across an interface tangential E is continuous and the normal D = eps E_z
+    is continuous (Gauss's law, no surface charge), so E_z jumps by
+    eps_above / eps_below. A plane exactly on z_l must give the tangential
+    field of both sides and the E_z of the region below it (including z0,
+    which belongs to layer 1, and z_L, which belongs to the lower
+    half-space)."""
+    prob, n_regions = _film_stack()
+    st = cwt.setup(prob)
+    sol = cwt.solve(st)
+    m = int(np.nonzero((st.u == 1) & (st.v == 0))[0][0])
+    delta = 1e-9
+    for ell in range(st.L + 1):
+        z = ell * st.d
+        at = cwt.plane_coefficients(st, sol, z)[:, m]
+        up = cwt.plane_coefficients(st, sol, z - delta)[:, m]
+        dn = cwt.plane_coefficients(st, sol, z + delta)[:, m]
+        scale = np.abs(at).max()
+        eps_up, eps_dn = complex(n_regions[ell]) ** 2, complex(n_regions[ell + 1]) ** 2
+        assert np.abs(at[:2] - up[:2]).max() < 1e-7 * scale, ell
+        assert np.abs(at[:2] - dn[:2]).max() < 1e-7 * scale, ell
+        assert abs(eps_up * up[2] - eps_dn * dn[2]) < 1e-7 * scale, ell
+        assert abs(up[2] - dn[2]) > 1e-2 * scale, ell      # E_z does jump here
+        assert abs(at[2] - dn[2]) < 1e-7 * scale, ell      # ... and z_l takes the side below
+    # a cell-centred grid from -d/2 with one plane per layer lands on every
+    # interface exactly; its synthesized planes are those coefficients
+    grid = W.Grid(fx=3, fy=3, fz=st.L + 1, z_begin=-st.d / 2, z_end=(st.L + 0.5) * st.d)
+    zs = grid.z_planes()
+    assert np.array_equal(zs, np.arange(st.L + 1) * st.d)
+    E = cwt.synthesize(st, sol, grid)
+    for ell in range(st.L + 1):
+        p = cwt.plane_coefficients(st, sol, ell * st.d)
+        np.testing.assert_allclose(E[:, ell, 0, 0], p.sum(axis=1), atol=1e-13)
+
+
+# ---------------------------------------------------------------- rejections
+def test_layer_modes_rejects_unpaired_and_near_defective_spectra():
+    # diagonal D: the eigenvalues are its entries, so the split is known
+    ok = cwt.layer_modes(np.diag([1.0, 0.5 + 0.1j, -1.0, -0.5 - 0.1j]).astype(complex))
+    assert ok.forward.tolist() == [True, True, False, False]
+    with pytest.raises(cwt.OracleError, match="forward mode count"):
+        cwt.layer_modes(np.diag([1.0, 2.0, 3.0, -1.0]).astype(complex))
+    with pytest.raises(cwt.OracleError, match="near-defective"):
+        cwt.layer_modes(np.diag([1.0, 1e-10, -1.0, -1e-10]).astype(complex))
+
+
+def test_grazing_mode_inside_a_layer_is_rejected():
+    """A homogeneous layer with eps = s_x^2 for a lattice mode (n = 0.5,
+    X = 2 lambda, u = 1) has gamma = sqrt(eps - s^2) = 0 exactly: D is
+    defective there and the layer cannot be expanded in its modes."""
+    n = np.full((2, 1, 4), 0.5 + 0j)
+    prob = W.Problem(n=n, px=0.5, py=0.5, pz=0.2, lam=1.0, U=3, V=1)
+    with pytest.raises(cwt.OracleError):
+        cwt.setup(prob)
+    n[:] = 0.6  # away from grazing the same layout solves
+    cwt.setup(prob)
