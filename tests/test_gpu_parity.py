@@ -346,8 +346,13 @@ def test_planes_exactly_on_interfaces_match_oracle(ctx, precision, tol):
         sol_o = cwt.solve(st)
         want = cwt.synthesize(st, sol_o, grid)
         _, got = run(ctx, prob, grid, precision)
-        per = [rel_l2(got[c], want[c]) for c in range(3)]
+        # each component's error against the whole field's norm: under TM
+        # incidence on the film stack E_y vanishes identically, so its own
+        # norm is rounding noise on both sides
+        norm = np.linalg.norm(want)
+        per = [float(np.linalg.norm(got[c] - want[c]) / norm) for c in range(3)]
         print("interfaces %s per component %s" % (precision, ["%.2e" % x for x in per]))
+        assert rel_l2(got, want) <= tol
         assert max(per) <= tol
         # the E_z of the layer above would be off by the index ratio
         above = np.stack([cwt.plane_coefficients(st, sol_o, z - 1e-9)[2]
