@@ -36,6 +36,10 @@ a closed-form test under tests/):
 * p_z inside a layer is +Psi (S_y b_x - S_x b_y) (Sec. 2.6.2, Eqs. 32-33).
 * Output planes that fall exactly on an interface belong to the layer below.
 
+The full boundary system is solved densely (solve_unreduced) or, for deep
+stacks at large M, by banded LU after a row reordering that makes it banded
+(solve_unreduced_banded); the two agree to rounding (tests/test_oracle_pins.py).
+
 Parity pinning of each function is listed in tests/test_oracle_*.py.
 """
 from dataclasses import dataclass
@@ -374,6 +378,57 @@ def solve_unreduced(st, dense_limit=6000):
     return Solution(p_ref=x[:3 * M], p_trn=x[pt0:], alpha=alpha)
 
 
+def solve_unreduced_banded(st):
+    """The same full system as solve_unreduced (Eqs. 24-26 and the Gauss rows
+    of Eq. 14), solved by banded LU with partial pivoting.
+
+    Only the row order differs: the reflected wave's Gauss rows come first and
+    the transmitted wave's last, so that every equation sits next to the
+    unknowns it touches. The matrix is then banded (lower bandwidth about 5M,
+    upper about 7M) and stored as bands only, which keeps a 16-layer stack at
+    M = 625 (43,750 unknowns) within a few GB.
+    """
+    M, L = st.M, st.L
+    C_i = half_space_map(st.sx, st.sy, st.sz_top)
+    C_r = half_space_map(st.sx, st.sy, -st.sz_top)
+    C_t = half_space_map(st.sx, st.sy, st.sz_bot)
+    G = _gauss_rows(st)
+    N = 4 * M * L + 6 * M
+    a0 = 3 * M
+    pt0 = 3 * M + 4 * M * L
+    blocks = []
+    rhs = np.zeros(N, dtype=np.complex128)
+    r = 0
+    blocks.append((r, 0, G[:M, :3 * M]))                 # reflected Gauss rows
+    r += M
+    blocks.append((r, a0, st.T[0]))                      # upper boundary (Eq. 24)
+    blocks.append((r, 0, -C_r))
+    rhs[r:r + 4 * M] = C_i @ st.p_inc
+    r += 4 * M
+    for layer in range(1, L):                            # middle boundaries (Eq. 25)
+        blocks.append((r, a0 + 4 * M * (layer - 1), st.B[layer - 1]))
+        blocks.append((r, a0 + 4 * M * layer, -st.T[layer]))
+        r += 4 * M
+    blocks.append((r, a0 + 4 * M * (L - 1), st.B[L - 1]))  # lower boundary (Eq. 26)
+    blocks.append((r, pt0, -C_t))
+    r += 4 * M
+    blocks.append((r, pt0, G[M:, 3 * M:]))               # transmitted Gauss rows
+    r += M
+    assert r == N
+    kl = max(r0 + b.shape[0] - 1 - c0 for r0, c0, b in blocks)
+    ku = max(c0 + b.shape[1] - 1 - r0 for r0, c0, b in blocks)
+    ab = np.zeros((kl + ku + 1, N), dtype=np.complex128)
+    for r0, c0, b in blocks:
+        h, w = b.shape
+        for jj in range(w):
+            j = c0 + jj
+            # ab[ku + i - j, j] = A[i, j] for rows i = r0 .. r0 + h - 1
+            ab[ku + r0 - j: ku + r0 + h - j, j] = b[:, jj]
+    x = sla.solve_banded((kl, ku), ab, rhs, overwrite_ab=True, check_finite=False)
+    alpha = [x[a0 + 4 * M * layer: a0 + 4 * M * (layer + 1)] for layer in range(L)]
+    return Solution(p_ref=x[:3 * M], p_trn=x[pt0:], alpha=alpha)
+
+
 def connection_matrix(st):
     """K = B_L T_L^-1 ... B_1 T_1^-1, the connection product of Eq. 27 in the
     top/bottom matrix reading."""
@@ -408,6 +463,8 @@ def solve_reduced(st):
 def solve(st, route="unreduced"):
     if route == "unreduced":
         return solve_unreduced(st)
+    if route == "banded":
+        return solve_unreduced_banded(st)
     if route == "reduced":
         return solve_reduced(st)
     raise ValueError(route)

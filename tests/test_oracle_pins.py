@@ -440,3 +440,20 @@ def test_grazing_mode_inside_a_layer_is_rejected():
         cwt.setup(prob)
     n[:] = 0.6  # away from grazing the same layout solves
     cwt.setup(prob)
+
+
+def test_banded_full_system_equals_dense_solve():
+    """The banded LU route of the full boundary system (rows reordered so
+    that the matrix is banded) gives the dense solve's coefficients and layer
+    amplitudes, on a lossy ragged stack with an oblique wave."""
+    rng = np.random.default_rng(12)
+    n = 1.3 + 0.3 * rng.random((4, 7, 9)) + 0.05j * rng.random((4, 7, 9))
+    prob = W.Problem(n=n.astype(complex), px=0.29, py=0.31, pz=0.17, lam=1.0, U=5, V=5,
+                     n_top=1.0, n_bot=1.35 + 0.02j, plane_wave=W.PlaneWave(1, 2, 0.6, -0.4j))
+    st = cwt.setup(prob)
+    dense = cwt.solve_unreduced(st)
+    band = cwt.solve_unreduced_banded(st)
+    assert np.abs(band.p_trn - dense.p_trn).max() <= 1e-12 * np.abs(dense.p_trn).max()
+    assert np.abs(band.p_ref - dense.p_ref).max() <= 1e-12 * np.abs(dense.p_ref).max()
+    for a, b in zip(band.alpha, dense.alpha):
+        assert np.abs(a - b).max() <= 1e-12 * np.abs(b).max()

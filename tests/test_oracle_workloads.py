@@ -114,6 +114,32 @@ def test_hard_sweep_golden_file_is_consistent():
     assert fi > 0 and fr >= 0 and ft > 0 and fi - fr - ft > 0
 
 
+def test_u25_sweep_golden_file_is_consistent():
+    """The widest sweep job (U = 25, band wrapped on the 32-voxel patch):
+    transversality of its stored waves and energy accounting of an absorbing
+    sample, as for the U = 21 job; the paper's reduced route is far off here."""
+    import os
+    g = np.load(os.path.join(os.path.dirname(__file__), "golden", "sweep_u25_job.npz"),
+                allow_pickle=False)
+    assert g["E"].shape == (3, 8, 64, 64) and int(g["U"]) == 25
+    assert np.all(np.isfinite(g["E"])) and np.abs(g["E"]).max() > 0
+    assert float(g["reduced_route_rel_l2"]) > 1e-2
+    prob, _ = W.sweep_problem(float(g["nu"]), int(g["patch"]), int(g["U"]), nz=1)
+    u, v = cwt.mode_indices(prob.U, prob.V)
+    sx, sy = cwt.spatial_frequencies(u, v, prob.X, prob.Y, prob.lam)
+    szb = cwt.s_z(1.0, sx, sy)
+    ptr = g["p_trn"].reshape(3, -1)
+    pre = g["p_ref"].reshape(3, -1)
+    assert np.abs(sx * ptr[0] + sy * ptr[1] + szb * ptr[2]).max() < 1e-10
+    assert np.abs(sx * pre[0] + sy * pre[1] - szb * pre[2]).max() < 1e-10
+    fr = -cwt.z_flux(pre, cwt.h_coefficients(pre, sx, sy, -szb))
+    ft = cwt.z_flux(ptr, cwt.h_coefficients(ptr, sx, sy, szb))
+    pin = np.zeros_like(ptr)
+    pin[0, (prob.V // 2) * prob.U + prob.U // 2] = 1.0
+    fi = cwt.z_flux(pin, cwt.h_coefficients(pin, sx, sy, szb))
+    assert fi > 0 and fr >= 0 and ft > 0 and fi - fr - ft > 0
+
+
 def test_sphere_golden_file_matches_the_oracle():
     import os
     g = np.load(os.path.join(os.path.dirname(__file__), "golden", "sphere_samples.npz"),
