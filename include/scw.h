@@ -79,6 +79,17 @@ typedef enum {
     SCW_ROUTE_CONNECTION_DEVICE = 3
 } scw_route;
 
+/* Where the per-layer eigendecompositions of A C run (Sec. 3.2, Sec. 4.2). */
+typedef enum {
+    /* LAPACK zgeev on the host, one layer per host thread (default). */
+    SCW_EIG_HOST = 0,
+    /* The library's batched FP64 eigensolver on the GPU (scw_eig_batched):
+       every layer at once; agrees with the host route to rounding. Needs
+       about 6 L (2M)^2 x 16 bytes of device memory during the solve and
+       2M <= SCW_EIG_MAX_N. */
+    SCW_EIG_DEVICE = 1
+} scw_eig_where;
+
 typedef struct scw_ctx scw_ctx;
 typedef struct scw_solution scw_solution;
 
@@ -104,6 +115,7 @@ typedef struct scw_solution scw_solution;
  *                lie inside the U x V band.
  *   pw_ex, pw_ey complex (re, im) transverse amplitudes of the plane wave.
  *   route        scw_route of the boundary solve.
+ *   eig          scw_eig_where of the eigendecompositions (0: host).
  */
 typedef struct {
     int nx, ny, nz;
@@ -120,6 +132,7 @@ typedef struct {
     double pw_ex[2];
     double pw_ey[2];
     int route;
+    int eig;
 } scw_problem;
 
 /* Output grid: fx*fy points per plane spanning one lateral period,
@@ -171,6 +184,25 @@ void scw_destroy(scw_ctx* ctx);
  *           convolution with psi.
  * Blocks until done. On success *out is a library-owned solution. */
 int scw_solve(scw_ctx* ctx, const scw_problem* prob, scw_solution** out);
+
+/* Batched FP64 eigendecomposition on the GPU (the step of Sec. 3.2 and
+ * Sec. 4.2 that the paper names its next bottleneck), as scw_solve runs it
+ * for SCW_EIG_DEVICE: count independent n x n complex matrices, each reduced
+ * to Hessenberg form by Householder reflections, to complex Schur form by the
+ * shifted QR algorithm, and its eigenvectors found by back-substitution on
+ * the Schur factor.
+ *   n          matrix order, 1 <= n <= SCW_EIG_MAX_N;
+ *   A_dev      device complex128 [count][n][n], column-major; overwritten;
+ *   w_dev      device complex128 [count][n]: the eigenvalues;
+ *   X_dev      device complex128 [count][n][n], column-major: column j is a
+ *              unit-norm eigenvector of eigenvalue j.
+ * Workspace (2 count n^2 x 16 bytes) is allocated and freed by the call,
+ * which blocks until the result is ready. Errors: SCW_EINVAL for a bad size
+ * or null pointer; SCW_ELAPACK when the QR iteration of a matrix does not
+ * converge (the message names the matrix); SCW_ENOMEM, SCW_EHIP. */
+#define SCW_EIG_MAX_N 2048
+int scw_eig_batched(scw_ctx* ctx, int n, int count, double* A_dev, double* w_dev,
+                    double* X_dev, void* hip_stream);
 void scw_solution_free(scw_solution* sol);
 int scw_solution_info_get(const scw_solution* sol, scw_solution_info* info);
 

@@ -15,6 +15,8 @@ STATUS = {0: "SCW_OK", -1: "SCW_EINVAL", -2: "SCW_ENOMEM", -3: "SCW_EHIP",
           -7: "SCW_EILLCOND"}
 PRECISION = {"fp64": 0, "fp32": 1, "bf16x3": 2, "fp16x3": 3}
 ROUTE = {"stable": 0, "connection": 1, "stable_device": 2, "connection_device": 3}
+EIG = {"host": 0, "device": 1}
+EIG_MAX_N = 2048
 
 c_dp = ctypes.POINTER(ctypes.c_double)
 
@@ -33,6 +35,7 @@ class ScwProblem(ctypes.Structure):
         ("pw_u", ctypes.c_int), ("pw_v", ctypes.c_int),
         ("pw_ex", ctypes.c_double * 2), ("pw_ey", ctypes.c_double * 2),
         ("route", ctypes.c_int),
+        ("eig", ctypes.c_int),
     ]
 
 
@@ -114,6 +117,9 @@ SIGNATURES = {
     "scw_synthesize_slice": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
                                             ctypes.POINTER(ScwSlice), ctypes.c_int,
                                             ctypes.c_void_p, ctypes.c_void_p]),
+    "scw_eig_batched": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_void_p]),
     "scw_synthesize": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ScwGrid),
                                       ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
     "scw_field": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ScwProblem),

@@ -25,6 +25,8 @@ SOURCES = [
     "kernels_batch.hip",
     "surrogate.cpp",
     "kernels_surrogate.hip",
+    "kernels_eig.hip",
+    "eig.cpp",
 ]
 
 ARCH = "gfx950"

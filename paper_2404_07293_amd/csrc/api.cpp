@@ -123,6 +123,8 @@ int build_amat(Solution& s, const scw_grid& g, int precision, Plan& pl) {
 // Plane classification, task grouping and device tables for one grid.
 // The configuration a plan is built with: the solution's explicit one, its
 // zero fields filled from the context's tuned entry for the same shape.
+}  // namespace
+
 scw_synth_config resolve_config(const Context& ctx, const Solution& s, const scw_grid& g,
                                 int precision) {
   scw_synth_config c = s.cfg;
@@ -139,6 +141,8 @@ scw_synth_config resolve_config(const Context& ctx, const Solution& s, const scw
   return c;
 }
 
+namespace {
+
 bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
 
 // LDS bytes of the factored transform block for radix P (64 columns).
@@ -147,6 +151,93 @@ size_t fft_lds_bytes(const Solution& s, const scw_grid& g, int precision, int P)
   return ((size_t)s.U * s.V + 32 * 64 + 32 * (size_t)(g.fy / P)) * eb;
 }
 
+}  // namespace
+
+PlaneInfo classify_plane(const scw_grid& g, int L, double d, int j) {
+  const double zL = L * d;
+  const double dz = (g.z_end - g.z_begin) / g.fz;
+  const double z = g.z_begin + (j + 0.5) * dz;
+  if (z < 0.0) return {0, -1, z, 0.0};
+  if (z >= zL) return {2, L, z - zL, 0.0};
+  const int l = std::min((int)std::floor(z / d), L - 1);
+  return {1, l, z - l * d, z - (l + 1) * d};
+}
+
+PlaneGroups plane_group_shape(const scw_grid& g, int L, double d) {
+  // Interior planes of one layer are consecutive (z grows with the index),
+  // so runs of equal layer are the per-layer plane counts.
+  PlaneGroups r{1, 0, 0};
+  int maxc = 0, run = 0, prev = -1;
+  for (int j = 0; j < g.fz; ++j) {
+    const PlaneInfo pi = classify_plane(g, L, d, j);
+    if (pi.kind != 1) {
+      ++r.n_ext;
+      run = 0;
+      prev = -1;
+      continue;
+    }
+    run = pi.layer == prev ? run + 1 : 1;
+    prev = pi.layer;
+    maxc = std::max(maxc, run);
+  }
+  while (r.zt < std::min(maxc, 8)) r.zt *= 2;
+  run = 0;
+  prev = -1;
+  for (int j = 0; j < g.fz; ++j) {
+    const PlaneInfo pi = classify_plane(g, L, d, j);
+    if (pi.kind != 1) {
+      prev = -1;
+      continue;
+    }
+    run = pi.layer == prev ? run + 1 : 0;
+    prev = pi.layer;
+    if (run % r.zt == 0) ++r.ntasks;
+  }
+  return r;
+}
+
+int choose_shape(const Solution& s, const scw_grid& g, int precision,
+                 const scw_synth_config& cfg, int zt, KernelShape* out) {
+  const bool split = precision == SCW_BF16X3 || precision == SCW_FP16X3;
+  if (cfg.transform < SCW_XFORM_AUTO || cfg.transform > SCW_XFORM_DIRECT)
+    return fail(SCW_EINVAL, "unknown transform kind " + std::to_string(cfg.transform));
+  if (cfg.modal_rows && !(is_pow2(cfg.modal_rows) && cfg.modal_rows >= 2 && cfg.modal_rows <= 16))
+    return fail(SCW_EINVAL, "modal_rows must be 2, 4, 8 or 16");
+  if (cfg.tiles < 0 || cfg.tiles > 4096) return fail(SCW_EINVAL, "tiles out of range");
+  // FP32 modal sum: rows per wave, so that rows x planes stays <= 32
+  int rw = cfg.modal_rows ? cfg.modal_rows : (zt >= 8 ? 4 : (zt == 4 ? 8 : 16));
+  while (rw > 2 && rw * zt > 32) rw /= 2;
+  out->modal_rw = rw;
+  out->tiles = cfg.tiles;
+  // factored y pass: fy = R * P, P <= 32 a power of two, spectra V <= 32 rows
+  const int p_default = std::min(32, std::max(2, g.fy / 16));
+  const int P = cfg.fft_radix ? cfg.fft_radix : p_default;
+  const bool fft_ok = !split && s.V <= 32 && g.fy >= 2 && is_pow2(g.fy) && is_pow2(P) &&
+                      P >= 2 && P <= 32 && P <= g.fy &&
+                      fft_lds_bytes(s, g, precision, P) <= 64 * 1024;
+  int kind = cfg.transform;
+  if (kind == SCW_XFORM_AUTO)
+    kind = split ? SCW_XFORM_MFMA
+                 : (fft_ok ? SCW_XFORM_FFT
+                           : (precision == SCW_FP32 && s.V <= 32 ? SCW_XFORM_MFMA
+                                                                 : SCW_XFORM_DIRECT));
+  if (split && kind != SCW_XFORM_MFMA)
+    return fail(SCW_EINVAL, "split-precision synthesis evaluates the transform on the matrix cores");
+  if (kind == SCW_XFORM_FFT && !fft_ok)
+    return fail(SCW_EINVAL, "factored transform needs FP64/FP32, V <= 32, fy a power of two and "
+                            "a radix P (2..32, power of two) whose tables fit in 64 KB of LDS");
+  if (kind == SCW_XFORM_FFT && cfg.tiles != 0 && cfg.tiles != 32 && cfg.tiles != 64)
+    return fail(SCW_EINVAL, "factored transform takes 32 or 64 columns per block (tiles)");
+  if (kind == SCW_XFORM_MFMA && (precision == SCW_FP64 || s.V > 32))
+    return fail(SCW_EINVAL, "matrix-core transform needs FP32 or split precision and V <= 32");
+  out->kind = kind;
+  out->fft_p = kind == SCW_XFORM_FFT ? P : 0;
+  out->fft_ok = fft_ok;
+  return SCW_OK;
+}
+
+namespace {
+
 int build_plan(Solution& s, Plan& pl, const scw_grid& g, int precision,
                const scw_synth_config& cfg, bool direct_only) {
   pl.valid = false;
@@ -154,29 +245,13 @@ int build_plan(Solution& s, Plan& pl, const scw_grid& g, int precision,
   pl.grid = g;
   pl.precision = precision;
   pl.planes.assign(g.fz, PlaneInfo{});
-  const double zL = s.L * s.d;
-  const double dz = (g.z_end - g.z_begin) / g.fz;
-  std::vector<int> per_layer(s.L, 0);
   std::vector<ExtPlane> ext;
   for (int j = 0; j < g.fz; ++j) {
-    const double z = g.z_begin + (j + 0.5) * dz;
     PlaneInfo& pi = pl.planes[j];
-    if (z < 0.0) {
-      pi = {0, -1, z, 0.0};
-      ext.push_back({j, 0, z});
-    } else if (z >= zL) {
-      pi = {2, s.L, z - zL, 0.0};
-      ext.push_back({j, 2, z - zL});
-    } else {
-      int l = std::min((int)std::floor(z / s.d), s.L - 1);
-      pi = {1, l, z - l * s.d, z - (l + 1) * s.d};
-      per_layer[l]++;
-    }
+    pi = classify_plane(g, s.L, s.d, j);
+    if (pi.kind != 1) ext.push_back({j, pi.kind, pi.dz_top});
   }
-  int maxc = 0;
-  for (int c : per_layer) maxc = std::max(maxc, c);
-  int zt = 1;
-  while (zt < std::min(maxc, 8)) zt *= 2;
+  const int zt = plane_group_shape(g, s.L, s.d).zt;
   pl.zt = zt;
   pl.tasks.clear();
   std::vector<double> tdz;
@@ -239,38 +314,11 @@ int build_plan(Solution& s, Plan& pl, const scw_grid& g, int precision,
   }
   // kernel configuration: explicit, tuned, or the built-in default
   pl.cfg = cfg;
-  const bool split = precision == SCW_BF16X3 || precision == SCW_FP16X3;
-  if (cfg.transform < SCW_XFORM_AUTO || cfg.transform > SCW_XFORM_DIRECT)
-    return fail(SCW_EINVAL, "unknown transform kind " + std::to_string(cfg.transform));
-  if (cfg.modal_rows && !(is_pow2(cfg.modal_rows) && cfg.modal_rows >= 2 && cfg.modal_rows <= 16))
-    return fail(SCW_EINVAL, "modal_rows must be 2, 4, 8 or 16");
-  if (cfg.tiles < 0 || cfg.tiles > 4096) return fail(SCW_EINVAL, "tiles out of range");
-  // FP32 modal sum: rows per wave, so that rows x planes stays <= 32
-  int rw = cfg.modal_rows ? cfg.modal_rows : (zt >= 8 ? 4 : (zt == 4 ? 8 : 16));
-  while (rw > 2 && rw * zt > 32) rw /= 2;
-  pl.modal_rw = rw;
-  pl.tiles = cfg.tiles;
-  // factored y pass: fy = R * P, P <= 32 a power of two, spectra V <= 32 rows
-  const int p_default = std::min(32, std::max(2, g.fy / 16));
-  const int P = cfg.fft_radix ? cfg.fft_radix : p_default;
-  const bool fft_ok = !split && s.V <= 32 && g.fy >= 2 && is_pow2(g.fy) && is_pow2(P) &&
-                      P >= 2 && P <= 32 && P <= g.fy &&
-                      fft_lds_bytes(s, g, precision, P) <= 64 * 1024;
-  int kind = cfg.transform;
-  if (kind == SCW_XFORM_AUTO)
-    kind = split ? SCW_XFORM_MFMA
-                 : (fft_ok ? SCW_XFORM_FFT
-                           : (precision == SCW_FP32 && s.V <= 32 ? SCW_XFORM_MFMA
-                                                                 : SCW_XFORM_DIRECT));
-  if (split && kind != SCW_XFORM_MFMA)
-    return fail(SCW_EINVAL, "split-precision synthesis evaluates the transform on the matrix cores");
-  if (kind == SCW_XFORM_FFT && !fft_ok)
-    return fail(SCW_EINVAL, "factored transform needs FP64/FP32, V <= 32, fy a power of two and "
-                            "a radix P (2..32, power of two) whose tables fit in 64 KB of LDS");
-  if (kind == SCW_XFORM_FFT && cfg.tiles != 0 && cfg.tiles != 32 && cfg.tiles != 64)
-    return fail(SCW_EINVAL, "factored transform takes 32 or 64 columns per block (tiles)");
-  if (kind == SCW_XFORM_MFMA && (precision == SCW_FP64 || s.V > 32))
-    return fail(SCW_EINVAL, "matrix-core transform needs FP32 or split precision and V <= 32");
+  KernelShape ks;
+  if ((rc = choose_shape(s, g, precision, cfg, pl.zt, &ks))) return rc;
+  pl.modal_rw = ks.modal_rw;
+  pl.tiles = ks.tiles;
+  const int kind = ks.kind, P = ks.fft_p;
   pl.fft_p = 0;
   pl.mfma = false;
   if (kind == SCW_XFORM_FFT) {
@@ -308,6 +356,9 @@ bool same_grid(const scw_grid& a, const scw_grid& b) {
          a.z_end == b.z_end;
 }
 
+
+}  // namespace
+
 int check_grid(const scw_grid* g) {
   if (!g) return fail(SCW_EINVAL, "grid is null");
   if (g->fx < 1 || g->fy < 1 || g->fz < 1)
@@ -318,7 +369,6 @@ int check_grid(const scw_grid* g) {
   return SCW_OK;
 }
 
-}  // namespace
 }  // namespace scw
 
 using namespace scw;

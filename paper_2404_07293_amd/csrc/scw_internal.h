@@ -184,6 +184,30 @@ int synthesize(Context& ctx, Solution& s, const scw_grid& g, int precision, void
                hipStream_t st, int stages, hipEvent_t* ev, bool direct_only = false,
                Plan** used = nullptr);
 std::string synth_key(const Solution& s, const scw_grid& g, int precision);
+// Plane j of grid g against a stack of L layers of thickness d: above the
+// sample, inside layer `layer`, or below it (a plane on an interface belongs
+// to the layer below).
+PlaneInfo classify_plane(const scw_grid& g, int L, double d, int j);
+// Interior planes are grouped per layer in tasks of zt (1, 2, 4 or 8) planes.
+struct PlaneGroups {
+  int zt, ntasks, n_ext;
+};
+PlaneGroups plane_group_shape(const scw_grid& g, int L, double d);
+// The configuration of a synthesis: the solution's explicit one with the
+// context's tuned entry filling its zero fields.
+scw_synth_config resolve_config(const Context& ctx, const Solution& s, const scw_grid& g,
+                                int precision);
+// Kernel shape from a configuration: modal-sum rows per wave, transform kind
+// (SCW_XFORM_*), factored-transform radix (0 unless kind is FFT), tiles, and
+// whether the factored transform applies to this grid at all.
+struct KernelShape {
+  int modal_rw, kind, fft_p, tiles;
+  bool fft_ok;
+};
+int choose_shape(const Solution& s, const scw_grid& g, int precision,
+                 const scw_synth_config& cfg, int zt, KernelShape* out);
+// SCW_OK for a grid every synthesis accepts, else SCW_EINVAL with a message.
+int check_grid(const scw_grid* g);
 // FP32 fields of every illumination, E: [K][3][fz][fy][fx] complex64.
 int synthesize_illuminations(Context& ctx, Solution& s, const scw_grid& g, void* E,
                              hipStream_t st);
@@ -206,6 +230,27 @@ hipError_t launch_scale_rows(const double* E, const double* A, int n, int k, dou
 // T = W diag(I, E), B = W diag(E, I) with W = [[X, X], [Y, -Y]] (4M x 4M).
 hipError_t launch_build_tb(const double* X, const double* Y, const double* E, int n2, double* T,
                            double* B, hipStream_t s);
+
+// ------------------------------------------------------------------ eigensolver
+// Batched FP64 eigendecomposition on the device (kernels_eig.hip, eig.cpp).
+constexpr int kEigMaxN = SCW_EIG_MAX_N;
+// count matrices n x n column-major complex128 (A overwritten): eigenvalues w
+// [count][n] and unit-norm eigenvectors X [count][n][n]. Blocks until done.
+int device_eig_batched(Context& ctx, int n, int count, double* A, double* w, double* X,
+                       hipStream_t st);
+// The context's rocBLAS handle (created on first use), bound to stream st.
+int blas_handle(Context& ctx, hipStream_t st, void** out);
+hipError_t launch_eig_hessenberg(int n, int count, double* A, double* Z, hipStream_t s);
+hipError_t launch_eig_schur(int n, int count, double* H, double* Z, double* w, int* info,
+                            hipStream_t s);
+// T (column-major Schur factors) -> Tt (row-major copies) -> Y (eigenvectors
+// of T, column-major; Y may be T).
+hipError_t launch_eig_vectors(int n, int count, const double* T, double* Tt, const double* w,
+                              double* Y, hipStream_t s);
+hipError_t launch_eig_normalize(int n, long long ncols, double* X, hipStream_t s);
+// X[:, j] *= f[j] over ncols columns of length n (f: complex128 [ncols]).
+hipError_t launch_eig_scale_cols(int n, long long ncols, const double* f, double* X,
+                                 hipStream_t s);
 
 // ------------------------------------------------------------------ surrogate
 struct SurNet;

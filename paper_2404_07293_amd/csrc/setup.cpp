@@ -162,6 +162,25 @@ struct LayerHost {
   std::vector<zc> E;       // exp(i k gamma d)
 };
 
+// Forward branch gamma_j = sqrt(lam_j) of the eigenvalues lam of A C, the
+// defectiveness check and E = exp(i k gamma d) of one layer.
+int layer_gamma(const Solution& s, const zc* lam, LayerHost& h) {
+  const int n2 = 2 * s.M;
+  double gmax = 0;
+  h.gamma.resize(n2);
+  for (int j = 0; j < n2; ++j) gmax = std::max(gmax, std::sqrt(std::abs(lam[j])));
+  // forward iff Im(gamma) > tol, or |Im| <= tol and Re > 0 (tol = 1e-12 max|gamma|)
+  for (int j = 0; j < n2; ++j) h.gamma[j] = principal_sqrt_branch(lam[j], 1e-12 * gmax);
+  double gmin = gmax;
+  for (int j = 0; j < n2; ++j) gmin = std::min(gmin, std::abs(h.gamma[j]));
+  if (gmin < 1e-9 * gmax)
+    return fail(SCW_EDEFECTIVE, "near-defective property matrix: |gamma| ~ 0");
+  h.E.resize(n2);
+  for (int j = 0; j < n2; ++j)
+    h.E[j] = std::exp(zc(0, 1) * s.k * h.gamma[j] * s.d);
+  return SCW_OK;
+}
+
 int layer_eig(const Lin& lin, Solution& s, LayerHost& h) {
   const int n2 = 2 * s.M;
   Mat AC((size_t)n2 * n2);
@@ -179,15 +198,8 @@ int layer_eig(const Lin& lin, Solution& s, LayerHost& h) {
   lin.lp.zgeev(&jl, &jr, &n2, AC.data(), &n2, lam.data(), &dummy, &one, h.X.data(), &n2,
                work.data(), &lwork, rwork.data(), &info);
   if (info != 0) return fail(SCW_ELAPACK, "zgeev info=" + std::to_string(info));
-  double gmax = 0;
-  h.gamma.resize(n2);
-  for (int j = 0; j < n2; ++j) gmax = std::max(gmax, std::sqrt(std::abs(lam[j])));
-  // forward iff Im(gamma) > tol, or |Im| <= tol and Re > 0 (tol = 1e-12 max|gamma|)
-  for (int j = 0; j < n2; ++j) h.gamma[j] = principal_sqrt_branch(lam[j], 1e-12 * gmax);
-  double gmin = gmax;
-  for (int j = 0; j < n2; ++j) gmin = std::min(gmin, std::abs(h.gamma[j]));
-  if (gmin < 1e-9 * gmax)
-    return fail(SCW_EDEFECTIVE, "near-defective property matrix: |gamma| ~ 0");
+  int rc = layer_gamma(s, lam.data(), h);
+  if (rc) return rc;
   // Y = C X diag(1/gamma)
   h.Y.assign((size_t)n2 * n2, zc(0));
   lin.gemm('N', 'N', n2, n2, n2, 1.0, h.C.data(), n2, h.X.data(), n2, 0.0, h.Y.data(), n2);
@@ -196,9 +208,6 @@ int layer_eig(const Lin& lin, Solution& s, LayerHost& h) {
     zc* col = h.Y.data() + (size_t)j * n2;
     for (int r = 0; r < n2; ++r) col[r] *= ig;
   }
-  h.E.resize(n2);
-  for (int j = 0; j < n2; ++j)
-    h.E[j] = std::exp(zc(0, 1) * s.k * h.gamma[j] * s.d);
   Mat().swap(h.A);
   Mat().swap(h.C);
   return SCW_OK;
@@ -568,7 +577,6 @@ int solve_connection_device(Context& ctx, const Lin& lin, Solution& s,
   return SCW_OK;
 }
 
-#undef SCW_BLAS
 
 // ---------------------------------------------------------------- connection route
 int connection_system(const Lin& lin, Solution& s, const Mat& K, std::vector<zc>& alpha1);
@@ -711,6 +719,58 @@ void release_blas(Context& ctx) {
   ctx.blas = nullptr;
 }
 
+// ---------------------------------------------------------------- device eigensolver
+// Every layer's A C (one strided-batched GEMM), its eigendecomposition by the
+// batched device eigensolver, gamma on the host, Y = C X diag(1/gamma) on the
+// device; X, Y, gamma and E of every layer end in `layers` as layer_eig
+// leaves them.
+static int device_layer_eig(Context& ctx, Solution& s, DevBuf& d_A, DevBuf& d_C,
+                            std::vector<LayerHost>& layers) {
+  const int n2 = 2 * s.M, L = s.L;
+  const size_t nn = (size_t)n2 * n2;
+  hipStream_t st = ctx.setup_stream;
+  DevBuf d_AC, d_X, d_w, d_f;
+  int rc;
+  if ((rc = d_AC.reserve(nn * 16 * L)) || (rc = d_X.reserve(nn * 16 * L)) ||
+      (rc = d_w.reserve((size_t)n2 * 16 * L)) || (rc = d_f.reserve((size_t)n2 * 16 * L)))
+    return rc;
+  void* hv = nullptr;
+  if ((rc = blas_handle(ctx, st, &hv))) return rc;
+  rocblas_handle h = static_cast<rocblas_handle>(hv);
+  const rocblas_double_complex one = {1.0, 0.0}, zero = {0.0, 0.0};
+  const rocblas_operation N = rocblas_operation_none;
+  SCW_BLAS(rocblas_zgemm_strided_batched(h, N, N, n2, n2, n2, &one, zp(d_A), n2,
+                                         (rocblas_stride)nn, zp(d_C), n2, (rocblas_stride)nn,
+                                         &zero, zp(d_AC), n2, (rocblas_stride)nn, L));
+  if ((rc = device_eig_batched(ctx, n2, L, d_AC.as<double>(), d_w.as<double>(),
+                               d_X.as<double>(), st)))
+    return rc;
+  std::vector<zc> lam((size_t)n2 * L), f((size_t)n2 * L);
+  SCW_HIP(hipMemcpyAsync(lam.data(), d_w.p, lam.size() * 16, hipMemcpyDeviceToHost, st));
+  SCW_HIP(hipStreamSynchronize(st));
+  for (int l = 0; l < L; ++l) {
+    if ((rc = layer_gamma(s, lam.data() + (size_t)l * n2, layers[l]))) return rc;
+    for (int j = 0; j < n2; ++j) f[(size_t)l * n2 + j] = 1.0 / layers[l].gamma[j];
+  }
+  SCW_HIP(hipMemcpyAsync(d_f.p, f.data(), f.size() * 16, hipMemcpyHostToDevice, st));
+  SCW_BLAS(rocblas_zgemm_strided_batched(h, N, N, n2, n2, n2, &one, zp(d_C), n2,
+                                         (rocblas_stride)nn, zp(d_X), n2, (rocblas_stride)nn,
+                                         &zero, zp(d_AC), n2, (rocblas_stride)nn, L));
+  SCW_HIP(launch_eig_scale_cols(n2, (long long)n2 * L, d_f.as<double>(), d_AC.as<double>(), st));
+  for (int l = 0; l < L; ++l) {
+    layers[l].X.resize(nn);
+    layers[l].Y.resize(nn);
+    SCW_HIP(hipMemcpyAsync(layers[l].X.data(), d_X.as<zc>() + (size_t)l * nn, nn * 16,
+                           hipMemcpyDeviceToHost, st));
+    SCW_HIP(hipMemcpyAsync(layers[l].Y.data(), d_AC.as<zc>() + (size_t)l * nn, nn * 16,
+                           hipMemcpyDeviceToHost, st));
+  }
+  SCW_HIP(hipStreamSynchronize(st));
+  return SCW_OK;
+}
+
+#undef SCW_BLAS
+
 // ---------------------------------------------------------------- driver
 int solve_problem(Context& ctx, const scw_problem& p, Solution& s, int n_waves,
                   const scw_plane_wave* waves) {
@@ -726,6 +786,10 @@ int solve_problem(Context& ctx, const scw_problem& p, Solution& s, int n_waves,
   if (!(p.n_top > 0)) return fail(SCW_EINVAL, "n_top must be positive");
   if (p.route < SCW_ROUTE_STABLE || p.route > SCW_ROUTE_CONNECTION_DEVICE)
     return fail(SCW_EINVAL, "unknown route");
+  if (p.eig != SCW_EIG_HOST && p.eig != SCW_EIG_DEVICE)
+    return fail(SCW_EINVAL, "unknown eigensolver placement");
+  if (p.eig == SCW_EIG_DEVICE && 2LL * p.U * p.V > kEigMaxN)
+    return fail(SCW_EINVAL, "device eigensolver needs 2 U V <= " + std::to_string(kEigMaxN));
   const bool image = !waves && (p.inc_ex || p.inc_ey);
   if (image && (p.inc_nx < 1 || p.inc_ny < 1))
     return fail(SCW_EINVAL, "incident image shape must be positive");
@@ -802,10 +866,14 @@ int solve_problem(Context& ctx, const scw_problem& p, Solution& s, int n_waves,
   SCW_HIP(launch_band_dft(d_n.as<double>(), L, p.ny, p.nx, U - 1, V - 1, true, true,
                           d_row.as<double>(), d_phi.as<double>(), d_psi.as<double>(), st));
 
-  // ---- device: property blocks A, C per layer chunk, copied to the host
+  // ---- device: property blocks A, C per layer chunk, copied to the host (or,
+  // for the device eigensolver, every layer kept on the device)
   std::vector<LayerHost> layers(L);
   const size_t blk = (size_t)n2 * n2;
-  const int chunk = (int)std::max<size_t>(1, std::min<size_t>(L, (size_t)(1u << 30) / (blk * 32)));
+  const bool dev_eig = p.eig == SCW_EIG_DEVICE;
+  const int chunk = dev_eig ? L
+                            : (int)std::max<size_t>(
+                                  1, std::min<size_t>(L, (size_t)(1u << 30) / (blk * 32)));
   DevBuf d_A, d_C;
   if ((rc = d_A.reserve(blk * 16 * chunk)) || (rc = d_C.reserve(blk * 16 * chunk))) return rc;
   float asm_ms = 0;
@@ -820,7 +888,7 @@ int solve_problem(Context& ctx, const scw_problem& p, Solution& s, int n_waves,
       SCW_HIP(hipEventSynchronize(ev1));
       SCW_HIP(hipEventElapsedTime(&asm_ms, ev0, ev1));
     }
-    for (int l = l0; l < l0 + nl; ++l) {
+    for (int l = l0; l < l0 + nl && !dev_eig; ++l) {
       layers[l].A.resize(blk);
       layers[l].C.resize(blk);
       SCW_HIP(hipMemcpyAsync(layers[l].A.data(), d_A.as<char>() + (size_t)(l - l0) * blk * 16,
@@ -831,8 +899,10 @@ int solve_problem(Context& ctx, const scw_problem& p, Solution& s, int n_waves,
     SCW_HIP(hipStreamSynchronize(st));
   }
   s.info.assembly_device_ms = asm_ms * ((double)L / std::min(chunk, L));
-  d_A.release();
-  d_C.release();
+  if (!dev_eig) {
+    d_A.release();
+    d_C.release();
+  }
 
   // ---- incident coefficients (Sec. 2.3): in-band DFT of the images / plane
   // wave, or one plane wave per illumination (illumination-major [K][3M])
@@ -882,12 +952,18 @@ int solve_problem(Context& ctx, const scw_problem& p, Solution& s, int n_waves,
       pin[2 * M + m] = -(s.sx[m] * pin[m] + s.sy[m] * pin[M + m]) / s.sz_top[m];
   }
 
-  // ---- host: eigendecompositions, one layer per worker (Sec. 3.2, Sec. 4.2)
+  // ---- eigendecompositions (Sec. 3.2, Sec. 4.2): on the host, one layer per
+  // worker, or every layer at once by the device eigensolver
   const double t_eig = now_s();
   const bool stable = p.route == SCW_ROUTE_STABLE;
+  if (dev_eig && (rc = device_layer_eig(ctx, s, d_A, d_C, layers))) return rc;
+  d_A.release();
+  d_C.release();
   rc = parallel_for(L, ctx.host_threads, [&](int l) -> int {
-    int r = layer_eig(lin, s, layers[l]);
-    if (r) return r;
+    if (!dev_eig) {
+      int r = layer_eig(lin, s, layers[l]);
+      if (r) return r;
+    }
     if (stable) {
       layers[l].Xlu = layers[l].X;
       layers[l].Ylu = layers[l].Y;

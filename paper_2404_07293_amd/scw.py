@@ -36,11 +36,34 @@ class Context:
         except Exception:
             pass
 
-    def solve(self, prob, route="stable", waves=None):
+    def eig_batched(self, A, stream=None):
+        """``scw_eig_batched`` on a CUDA complex128 tensor A [count, n, n]
+        (each matrix as numpy/torch row-major A[i, j]; passed transposed so
+        the library sees it column-major). Returns (w [count, n], X
+        [count, n, n]) with A[b] @ X[b][:, j] = w[b, j] X[b][:, j]; A is
+        left unchanged (the library works on a copy)."""
+        import torch
+        if A.dtype != torch.complex128 or A.dim() != 3 or A.shape[1] != A.shape[2]:
+            raise ValueError("A must be a complex128 tensor [count, n, n]")
+        count, n = int(A.shape[0]), int(A.shape[1])
+        work = A.transpose(1, 2).contiguous()          # column-major per matrix
+        w = torch.empty((count, n), dtype=torch.complex128, device=A.device)
+        Xc = torch.empty((count, n, n), dtype=torch.complex128, device=A.device)
+        if stream is None:
+            stream = torch.cuda.current_stream(A.device)
+        N.check(self.lib.scw_eig_batched(self.handle, n, count, ctypes.c_void_p(work.data_ptr()),
+                                         ctypes.c_void_p(w.data_ptr()),
+                                         ctypes.c_void_p(Xc.data_ptr()),
+                                         ctypes.c_void_p(stream.cuda_stream)))
+        return w, Xc.transpose(1, 2)
+
+    def solve(self, prob, route="stable", waves=None, eig="host"):
         """Run ``scw_solve`` on a ``workloads.Problem``; returns a Solution.
         With ``waves`` (a list of ``workloads.PlaneWave``) it runs
         ``scw_solve_illuminations`` instead: one illumination per wave, the
-        problem's own incident field ignored."""
+        problem's own incident field ignored. ``eig`` places the per-layer
+        eigendecompositions: "host" (LAPACK) or "device" (the library's
+        batched GPU eigensolver)."""
         n = np.ascontiguousarray(prob.n, dtype=np.complex128)
         keep = [n]
         p = N.ScwProblem()
@@ -67,6 +90,7 @@ class Context:
         p.pw_ex[0], p.pw_ex[1] = ex.real, ex.imag
         p.pw_ey[0], p.pw_ey[1] = ey.real, ey.imag
         p.route = N.ROUTE[route]
+        p.eig = N.EIG[eig]
         h = ctypes.c_void_p()
         if waves is None:
             N.check(self.lib.scw_solve(self.handle, ctypes.byref(p), ctypes.byref(h)))

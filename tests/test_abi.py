@@ -39,7 +39,7 @@ int main(void) {
   F(scw_problem, nx) F(scw_problem, px) F(scw_problem, n) F(scw_problem, lambda)
   F(scw_problem, n_top) F(scw_problem, n_bot_im) F(scw_problem, U) F(scw_problem, inc_ex)
   F(scw_problem, inc_ey) F(scw_problem, inc_nx) F(scw_problem, pw_u) F(scw_problem, pw_ex)
-  F(scw_problem, pw_ey) F(scw_problem, route)
+  F(scw_problem, pw_ey) F(scw_problem, route) F(scw_problem, eig)
   F(scw_grid, fx) F(scw_grid, z_begin) F(scw_grid, z_end)
   F(scw_solution_info, M) F(scw_solution_info, min_abs_sz)
   F(scw_solution_info, connection_rcond) F(scw_solution_info, assembly_device_ms)

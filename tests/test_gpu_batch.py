@@ -209,6 +209,39 @@ def test_high_growth_sweep_job_matches_full_system(ctx):
         assert e.value.code == -7  # SCW_EILLCOND
 
 
+def test_widest_sweep_job_matches_full_system(ctx):
+    """Patch 0 (U = 25, M = 625, 16 layers; the 49-wide band wraps on the
+    32-voxel patch) at 1000 cm^-1, growth exponent about 51: the oracle's full
+    boundary system (43,750 unknowns, banded LU; tests/golden/sweep_u25_job.npz)
+    against the library's default route, and the batched launch's field on it,
+    alone and next to a job of the smallest truncation."""
+    import os
+    torch = _torch()
+    g = np.load(os.path.join(os.path.dirname(__file__), "golden", "sweep_u25_job.npz"),
+                allow_pickle=False)
+    patch, U = int(g["patch"]), int(g["U"])
+    prob, grid = W.sweep_problem(float(g["nu"]), patch, U)
+    sol = ctx.solve(prob)
+    info = sol.info()
+    print("U=25 job: growth exponent %.1f, reduced route error in the oracle %.2e" % (
+        info["growth_exponent"], float(g["reduced_route_rel_l2"])))
+    assert info["growth_exponent"] > 40
+    p_trn = sol.exterior()[2].ravel()
+    assert rel_l2(p_trn, g["p_trn"]) <= 1e-8
+    want = g["E"]
+    e64 = sol.synthesize(grid, "fp64").cpu().numpy()
+    small = ctx.solve(small_job(9, 3, 3, 1.0))
+    eb = ctx.batch([small, sol, sol], grid).launch().cpu().numpy()
+    torch.cuda.synchronize()
+    print("rel-L2 fp64 %.3e, batched fp32 %.3e / %.3e" % (
+        rel_l2(e64, want), rel_l2(eb[1], want), rel_l2(eb[2], want)))
+    assert rel_l2(e64, want) <= 1e-8
+    assert rel_l2(eb[1], want) <= FP32_TOL
+    assert np.array_equal(eb[1], eb[2])
+    small.free()
+    sol.free()
+
+
 def test_batch_rejects_interior_grid(ctx):
     import paper_2404_07293_amd as P
     sol = ctx.solve(small_job(9, 3, 3, 1.0))

@@ -128,6 +128,41 @@ def test_gradients_match_reference(ctx):
         assert err <= 1e-4, name
 
 
+def test_bf16_gradients_match_reference(ctx):
+    """Matrix-core mode (bf16 operands, FP32 accumulation): every parameter
+    group's gradient against the exact FP64 gradient of the same network and
+    data (oracle/surrogate.py).
+
+    Bound, from the arithmetic: a bf16 operand carries a relative rounding of
+    up to 2^-9 (2e-3). Rounding the forward products alone moves the exact
+    backward's gradients by 1-7e-3 (the rounded reference,
+    forward(bf16=True) then the FP64 backward, measured per group below);
+    the library also rounds the operands of its backward products, which
+    adds about as much again (1.1e-2 measured on the deepest group, lift_w).
+    So each group must be within 2e-2 of the exact gradient and point the
+    same way (cosine above 0.9999): training in bf16 follows the true descent
+    direction. A wrong adjoint (a dropped term, a missing conjugate) is off by
+    O(1)."""
+    sur, p, x, tgt, xd, td = _net_and_data(ctx)
+    sur.set_compute(True)
+    loss, g = sur.loss_grad(xd, td)
+    sur.set_compute(False)
+    out, cache = S.forward(p, x, keep=True)
+    assert abs(loss - S.loss(out, tgt)) <= 1e-2 * S.loss(out, tgt)
+    gref = S.backward(p, cache, out, tgt)
+    outb, cacheb = S.forward(p, x, keep=True, bf16=True)
+    grnd = S.backward(p, cacheb, outb, tgt)
+    gg = S.unflatten(g.astype(np.float64))
+    for name, _, _ in S.param_shapes():
+        a, b, c = np.ravel(gg[name]), np.ravel(gref[name]), np.ravel(grnd[name])
+        err, err_rnd = rel(a, b), rel(c, b)
+        cos = float(np.real(np.vdot(b, a)) / (np.linalg.norm(a) * np.linalg.norm(b)))
+        print("bf16 grad %-7s rel-L2 %.3e (rounded reference %.3e) cosine %.7f"
+              % (name, err, err_rnd, cos))
+        assert err <= 2e-2, name
+        assert cos >= 0.9999, name
+
+
 def test_encode_matches_reference(ctx):
     torch = _torch()
     from paper_2404_07293_amd.surrogate import Surrogate
