@@ -263,6 +263,28 @@ int scw_synthesize_illuminations(scw_ctx* ctx, scw_solution* sol, const scw_grid
 int scw_synthesize(scw_ctx* ctx, scw_solution* sol, const scw_grid* grid,
                    int precision, void* E_dev, void* hip_stream);
 
+/* Allocation-free form of scw_synthesize, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, hosts
+ * that forbid hipMalloc. It computes the same field on the same kernels,
+ * with the plan's tables (plane tasks, exterior planes, twiddles) built on
+ * the device by a kernel and every workspace placed in one static device
+ * array of SCW_NOALLOC_SCRATCH_BYTES per GPU, held until the process ends.
+ * It allocates nothing, copies nothing from the host and never blocks: all
+ * work is enqueued on hip_stream.
+ *   precision  SCW_FP64 or SCW_FP32 (the split modes return SCW_EINVAL);
+ *   E_dev      caller-owned device buffer as for scw_synthesize.
+ * The transform is the one scw_synthesize would choose, except that a grid
+ * on which it would choose the matrix-core form gets the factored form when
+ * it applies and the direct sum otherwise. Every call on one GPU shares that
+ * GPU's array: calls that overlap in time (two streams, two contexts, two
+ * threads) race and give wrong fields; order them. Errors: SCW_EINVAL for a
+ * null argument, a bad grid or precision, or a problem and grid whose tables
+ * and workspaces need more than SCW_NOALLOC_SCRATCH_BYTES (the message gives
+ * the size); SCW_EHIP if the array could not be attached at scw_create. */
+#define SCW_NOALLOC_SCRATCH_BYTES (32u << 20)
+int scw_synthesize_noalloc(scw_ctx* ctx, scw_solution* sol, const scw_grid* grid,
+                           int precision, void* E_dev, void* hip_stream);
+
 /* Kernel configuration of scw_synthesize for one solution. Fields left 0
  * take the library's choice: a configuration found by scw_tune_synthesis for
  * the same shape on this context, else the built-in default.

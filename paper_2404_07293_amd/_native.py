@@ -122,6 +122,9 @@ SIGNATURES = {
                                        ctypes.c_void_p]),
     "scw_synthesize": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ScwGrid),
                                       ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
+    "scw_synthesize_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
+                                              ctypes.POINTER(ScwGrid), ctypes.c_int,
+                                              ctypes.c_void_p, ctypes.c_void_p]),
     "scw_field": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ScwProblem),
                                  ctypes.POINTER(ScwGrid), ctypes.c_int, ctypes.c_void_p,
                                  ctypes.c_void_p]),

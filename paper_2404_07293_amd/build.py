@@ -25,6 +25,7 @@ SOURCES = [
     "kernels_batch.hip",
     "surrogate.cpp",
     "kernels_surrogate.hip",
+    "noalloc.hip",
     "kernels_eig.hip",
     "eig.cpp",
 ]

@@ -394,6 +394,12 @@ int scw_create(scw_ctx** out, int hip_device, int host_threads) {
     delete c;
     return fail(SCW_EHIP, "could not create the setup stream");
   }
+  int rc = noalloc_attach(hip_device);  // the device's scratch array, with the device current
+  if (rc) {
+    (void)hipStreamDestroy(c->c.setup_stream);
+    delete c;
+    return rc;
+  }
   *out = c;
   return SCW_OK;
 }

@@ -208,6 +208,9 @@ int choose_shape(const Solution& s, const scw_grid& g, int precision,
                  const scw_synth_config& cfg, int zt, KernelShape* out);
 // SCW_OK for a grid every synthesis accepts, else SCW_EINVAL with a message.
 int check_grid(const scw_grid* g);
+// Allocation-free synthesis: attach the device's static scratch array (once
+// per device, from scw_create).
+int noalloc_attach(int device);
 // FP32 fields of every illumination, E: [K][3][fz][fy][fx] complex64.
 int synthesize_illuminations(Context& ctx, Solution& s, const scw_grid& g, void* E,
                              hipStream_t st);

@@ -183,6 +183,20 @@ class Solution:
                                         ctypes.c_void_p(stream.cuda_stream)))
         return out
 
+    def synthesize_noalloc(self, grid, out, precision="fp32", stream=None):
+        """Enqueue ``scw_synthesize_noalloc`` into the caller's ``out`` (a
+        CUDA tensor [3, fz, fy, fx]): the library allocates nothing, its
+        workspaces live in the device's static scratch array. Returns ``out``."""
+        if out is None:
+            raise ValueError("the allocation-free synthesis writes into a caller-owned out")
+        out, stream = self._out(grid, precision, out, stream)
+        N.check(self.lib.scw_synthesize_noalloc(self.ctx.handle, self.handle,
+                                                ctypes.byref(_grid(grid)),
+                                                N.PRECISION[precision],
+                                                ctypes.c_void_p(out.data_ptr()),
+                                                ctypes.c_void_p(stream.cuda_stream)))
+        return out
+
     def synthesize_illuminations(self, grid, out=None, stream=None):
         """Enqueue ``scw_synthesize_illuminations`` (FP32): the field of every
         illumination into ``out`` [K, 3, fz, fy, fx] complex64, allocated
