@@ -27,8 +27,8 @@
 namespace scw {
 namespace {
 
-constexpr int kThreads = 256;
 constexpr int kMaxSweepsPerEigenvalue = 300;
+constexpr int kEigWindow = 16;  // rotations per window of the QR sweep
 
 __device__ inline double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -72,20 +72,21 @@ __device__ inline double2 wave_sum(double2 v) {
   return v;
 }
 
+template <int TPB>
 __device__ double block_sum(double v, double* red) {
   const int tid = threadIdx.x;
   for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
   if ((tid & 63) == 0) red[tid >> 6] = v;
   __syncthreads();
   double s = 0.0;
-  for (int w = 0; w < kThreads / 64; ++w) s += red[w];
+  for (int w = 0; w < TPB / 64; ++w) s += red[w];
   __syncthreads();
   return s;
 }
 
 // M[:, k+1:n] -= tau (M[:, k+1:n] v) v^H on all n rows, one thread per row
 // (NR rows per thread).
-template <int NR>
+template <int TPB, int NR>
 __device__ void reflect_right(double2* __restrict__ Mx, int n, int k, const double2* v,
                               double2 tau) {
   const int tid = threadIdx.x, m = n - k - 1;
@@ -97,7 +98,7 @@ __device__ void reflect_right(double2* __restrict__ Mx, int n, int k, const doub
     const double2* col = Mx + (size_t)(k + 1 + i) * n;
 #pragma unroll
     for (int t = 0; t < NR; ++t) {
-      const int r = tid + t * kThreads;
+      const int r = tid + t * TPB;
       if (r < n) acc[t] = cadd(acc[t], cmul(col[r], vi));
     }
   }
@@ -108,33 +109,33 @@ __device__ void reflect_right(double2* __restrict__ Mx, int n, int k, const doub
     double2* col = Mx + (size_t)(k + 1 + i) * n;
 #pragma unroll
     for (int t = 0; t < NR; ++t) {
-      const int r = tid + t * kThreads;
+      const int r = tid + t * TPB;
       if (r < n) col[r] = csub(col[r], cmul(acc[t], vc));
     }
   }
 }
 
-// Step 1. One workgroup per matrix; n <= NR * 256 and the reflector vector
-// (n - 1 entries) in LDS.
-template <int NR>
-__global__ void __launch_bounds__(kThreads)
+// Step 1. One workgroup of TPB threads per matrix; n <= NR * TPB and the
+// reflector vector (n - 1 entries) in LDS.
+template <int TPB, int NR>
+__global__ void __launch_bounds__(TPB)
 eig_hessenberg_kernel(int n, double2* __restrict__ A, double2* __restrict__ Z) {
   extern __shared__ double2 v[];
-  __shared__ double red[kThreads / 64];
+  __shared__ double red[TPB / 64];
   __shared__ double2 s_tau, s_scale;
   __shared__ int s_skip;
   const size_t nn = (size_t)n * n;
   double2* H = A + blockIdx.x * nn;
   double2* Q = Z + blockIdx.x * nn;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (size_t e = tid; e < nn; e += kThreads)
+  for (size_t e = tid; e < nn; e += TPB)
     Q[e] = make_double2(e % (size_t)(n + 1) == 0 ? 1.0 : 0.0, 0.0);
   for (int k = 0; k + 2 < n; ++k) {
     const int m = n - k - 1;  // x = H[k+1 .. n-1, k]
     double2* x = H + (size_t)k * n + k + 1;
     double part = 0.0;
-    for (int i = 1 + tid; i < m; i += kThreads) part += x[i].x * x[i].x + x[i].y * x[i].y;
-    const double xnorm2 = block_sum(part, red);
+    for (int i = 1 + tid; i < m; i += TPB) part += x[i].x * x[i].x + x[i].y * x[i].y;
+    const double xnorm2 = block_sum<TPB>(part, red);
     if (tid == 0) {
       const double2 alpha = x[0];
       if (xnorm2 == 0.0 && alpha.y == 0.0) {
@@ -154,17 +155,17 @@ eig_hessenberg_kernel(int n, double2* __restrict__ A, double2* __restrict__ Z) {
     __syncthreads();
     if (s_skip) continue;
     const double2 tau = s_tau, scale = s_scale;
-    for (int i = 1 + tid; i < m; i += kThreads) {
+    for (int i = 1 + tid; i < m; i += TPB) {
       v[i] = cmul(x[i], scale);
       x[i] = make_double2(0.0, 0.0);
     }
     __syncthreads();
-    reflect_right<NR>(H, n, k, v, tau);
-    reflect_right<NR>(Q, n, k, v, tau);
+    reflect_right<TPB, NR>(H, n, k, v, tau);
+    reflect_right<TPB, NR>(Q, n, k, v, tau);
     __syncthreads();
     // left: H[k+1:, c] -= conj(tau) v (v^H H[k+1:, c]) for c > k, a wave per column
     const double2 ctau = cconj(tau);
-    for (int c = k + 1 + wave; c < n; c += kThreads / 64) {
+    for (int c = k + 1 + wave; c < n; c += TPB / 64) {
       double2* hc = H + (size_t)c * n + k + 1;
       double2 acc = make_double2(0.0, 0.0);
       for (int i = lane; i < m; i += 64) acc = cadd(acc, cmulcj(v[i], hc[i]));
@@ -199,13 +200,30 @@ __device__ inline void givens(double2 x, double2 y, double& c, double2& s, doubl
 
 __device__ inline double2& at(double2* M, int n, int i, int j) { return M[(size_t)j * n + i]; }
 
-// Step 2. One workgroup per matrix: H (upper Hessenberg, from step 1) becomes
-// the upper triangular Schur factor T, Z accumulates the rotations, w gets
-// the eigenvalues t_jj. info[b] = 0, or j + 1 when eigenvalue j did not
-// converge in kMaxSweepsPerEigenvalue sweeps.
-__global__ void __launch_bounds__(kThreads)
+// Step 2. One workgroup of TPB threads per matrix: H (upper Hessenberg, from
+// step 1) becomes the upper triangular Schur factor T, Z accumulates the
+// rotations, w gets the eigenvalues t_jj. info[b] = 0, or j + 1 when
+// eigenvalue j did not converge in kMaxSweepsPerEigenvalue sweeps.
+//
+// Each sweep runs in windows of W rotations (delayed updates): the diagonal
+// block the window's rotations touch (rows and columns b0 .. be, at most
+// W + 3) is chased in LDS, the rotations are kept, and then applied in one
+// pass to the three regions outside the block that they change: rows
+// k0 .. k1 right of the block (row rotations), columns k0 .. k1 above it and
+// in Z (column rotations). A thread takes one column or row of a region and
+// applies the whole window's rotations to its W + 1 values in registers, so a
+// window costs one read and one write of those regions and no barrier per
+// rotation outside the small block. Within a window the column entries a
+// rotation produces (its r and the zeroed bulge) are written by thread 0 one
+// rotation later, once every thread has read them.
+template <int TPB, int W>
+__global__ void __launch_bounds__(TPB)
 eig_schur_kernel(int n, double2* __restrict__ Hall, double2* __restrict__ Zall,
                  double2* __restrict__ wall, int* __restrict__ info) {
+  constexpr int LB = W + 3;  // leading dimension of the LDS block (column-major)
+  __shared__ double2 blk[LB * LB];
+  __shared__ double s_c[W];
+  __shared__ double2 s_s[W];
   __shared__ int s_l;
   const size_t nn = (size_t)n * n;
   double2* H = Hall + blockIdx.x * nn;
@@ -218,7 +236,7 @@ eig_schur_kernel(int n, double2* __restrict__ Hall, double2* __restrict__ Zall,
     // largest k in [1, ihi] with a negligible subdiagonal: the active block is [l, ihi]
     if (tid == 0) s_l = 0;
     __syncthreads();
-    for (int k = 1 + tid; k <= ihi; k += kThreads) {
+    for (int k = 1 + tid; k <= ihi; k += TPB) {
       const double sub = cabs1(at(H, n, k, k - 1));
       double tst = cabs1(at(H, n, k - 1, k - 1)) + cabs1(at(H, n, k, k));
       if (tst == 0.0) {
@@ -259,68 +277,111 @@ eig_schur_kernel(int n, double2* __restrict__ Hall, double2* __restrict__ Zall,
       const double2 den = cadd(x, y);
       mu = (den.x == 0.0 && den.y == 0.0) ? d : csub(d, cdiv(bc, den));
     }
-    // one implicit single-shift QR sweep over [l, ihi]
-    double2 r_prev = make_double2(0.0, 0.0);
-    for (int k = l; k < ihi; ++k) {
-      double2 x, y;
-      if (k == l) {
-        x = csub(at(H, n, l, l), mu);
-        y = at(H, n, l + 1, l);
-      } else {
-        x = at(H, n, k, k - 1);
-        y = at(H, n, k + 1, k - 1);
+    // one implicit single-shift QR sweep over [l, ihi], W rotations per window
+    for (int k0 = l; k0 < ihi; k0 += W) {
+      const int k1 = min(k0 + W, ihi);        // rotations k0 .. k1 - 1
+      const int b0 = k0 == l ? l : k0 - 1;    // block rows and columns b0 .. be
+      const int be = min(k1 + 1, ihi);
+      const int bn = be - b0 + 1;
+      for (int e = tid; e < bn * bn; e += TPB) {
+        const int r = e % bn, c = e / bn;
+        blk[c * LB + r] = at(H, n, b0 + r, b0 + c);
       }
-      double c;
-      double2 s, r;
-      givens(x, y, c, s, r);
-      const double2 ms = make_double2(-s.x, s.y);  // -conj(s)
-      const double2 cs = cconj(s);
-      if (tid == 0) {
-        // The previous rotation's column entries (its r and the zeroed bulge)
-        // are written one rotation late: every thread has read them by now.
-        if (k - 1 > l) {
-          at(H, n, k - 1, k - 2) = r_prev;
-          at(H, n, k, k - 2) = make_double2(0.0, 0.0);
+      __syncthreads();
+      double2 r_prev = make_double2(0.0, 0.0);
+      for (int k = k0; k < k1; ++k) {
+        const int kk = k - b0;
+        double2 x, y;
+        if (k == l) {
+          x = csub(blk[kk * LB + kk], mu);
+          y = blk[kk * LB + kk + 1];
+        } else {
+          x = blk[(kk - 1) * LB + kk];
+          y = blk[(kk - 1) * LB + kk + 1];
         }
-        // rows and columns k, k+1 meet in a 2 x 2 block: B <- G B G^H
-        const double2 b00 = at(H, n, k, k), b01 = at(H, n, k, k + 1);
-        const double2 b10 = at(H, n, k + 1, k), b11 = at(H, n, k + 1, k + 1);
-        const double2 t00 = cadd(cscale(b00, c), cmul(s, b10));
-        const double2 t01 = cadd(cscale(b01, c), cmul(s, b11));
-        const double2 t10 = cadd(cmul(ms, b00), cscale(b10, c));
-        const double2 t11 = cadd(cmul(ms, b01), cscale(b11, c));
-        at(H, n, k, k) = cadd(cscale(t00, c), cmul(cs, t01));
-        at(H, n, k, k + 1) = cadd(cmul(make_double2(-s.x, -s.y), t00), cscale(t01, c));
-        at(H, n, k + 1, k) = cadd(cscale(t10, c), cmul(cs, t11));
-        at(H, n, k + 1, k + 1) = cadd(cmul(make_double2(-s.x, -s.y), t10), cscale(t11, c));
+        double c;
+        double2 s, r;
+        givens(x, y, c, s, r);
+        const double2 ms = make_double2(-s.x, s.y);  // -conj(s)
+        const double2 cs = cconj(s);
+        if (tid == 0) {
+          if (k > k0 && k - 1 > l) {  // the previous rotation's column entries
+            blk[(kk - 2) * LB + kk - 1] = r_prev;
+            blk[(kk - 2) * LB + kk] = make_double2(0.0, 0.0);
+          }
+          s_c[k - k0] = c;
+          s_s[k - k0] = s;
+        }
+        r_prev = r;
+        for (int j = kk + tid; j < bn; j += TPB) {  // rows k, k+1: columns k .. be
+          const double2 t1 = blk[j * LB + kk], t2 = blk[j * LB + kk + 1];
+          blk[j * LB + kk] = cadd(cscale(t1, c), cmul(s, t2));
+          blk[j * LB + kk + 1] = cadd(cmul(ms, t1), cscale(t2, c));
+        }
+        __syncthreads();
+        const int iend = min(k + 2, be) - b0;
+        for (int i = tid; i <= iend; i += TPB) {  // columns k, k+1: rows b0 .. min(k+2, be)
+          const double2 t1 = blk[kk * LB + i], t2 = blk[(kk + 1) * LB + i];
+          blk[kk * LB + i] = cadd(cscale(t1, c), cmul(cs, t2));
+          blk[(kk + 1) * LB + i] = csub(cscale(t2, c), cmul(s, t1));
+        }
+        __syncthreads();
       }
-      r_prev = r;
-      // rows k, k+1 from the left, columns k+2 .. n-1
-      for (int j = k + 2 + tid; j < n; j += kThreads) {
-        const double2 t1 = at(H, n, k, j), t2 = at(H, n, k + 1, j);
-        at(H, n, k, j) = cadd(cscale(t1, c), cmul(s, t2));
-        at(H, n, k + 1, j) = cadd(cmul(ms, t1), cscale(t2, c));
+      if (tid == 0 && k1 - 1 > l) {  // the window's last pending entries
+        const int kk = k1 - 1 - b0;
+        blk[(kk - 1) * LB + kk] = r_prev;
+        blk[(kk - 1) * LB + kk + 1] = make_double2(0.0, 0.0);
       }
-      // columns k, k+1 from the right (G^H), rows 0 .. k-1 and k+2 (the bulge)
-      const int iend = min(k + 2, ihi);
-      for (int i = tid; i <= iend; i += kThreads) {
-        if (i == k || i == k + 1) continue;
-        const double2 t1 = at(H, n, i, k), t2 = at(H, n, i, k + 1);
-        at(H, n, i, k) = cadd(cscale(t1, c), cmul(cs, t2));
-        at(H, n, i, k + 1) = csub(cscale(t2, c), cmul(s, t1));
+      __syncthreads();
+      for (int e = tid; e < bn * bn; e += TPB) {
+        const int r = e % bn, c = e / bn;
+        at(H, n, b0 + r, b0 + c) = blk[c * LB + r];
       }
-      for (int i = tid; i < n; i += kThreads) {
-        const double2 t1 = at(Z, n, i, k), t2 = at(Z, n, i, k + 1);
-        at(Z, n, i, k) = cadd(cscale(t1, c), cmul(cs, t2));
-        at(Z, n, i, k + 1) = csub(cscale(t2, c), cmul(s, t1));
+      const int nq = k1 - k0;
+      // rows k0 .. k1 of the columns right of the block
+      for (int j = be + 1 + tid; j < n; j += TPB) {
+        double2 v[W + 1];
+#pragma unroll
+        for (int q = 0; q <= W; ++q)
+          if (q <= nq) v[q] = at(H, n, k0 + q, j);
+#pragma unroll
+        for (int q = 0; q < W; ++q) {
+          if (q < nq) {
+            const double c = s_c[q];
+            const double2 sq = s_s[q], msq = make_double2(-sq.x, sq.y);
+            const double2 t1 = v[q], t2 = v[q + 1];
+            v[q] = cadd(cscale(t1, c), cmul(sq, t2));
+            v[q + 1] = cadd(cmul(msq, t1), cscale(t2, c));
+          }
+        }
+#pragma unroll
+        for (int q = 0; q <= W; ++q)
+          if (q <= nq) at(H, n, k0 + q, j) = v[q];
+      }
+      // columns k0 .. k1 of the rows above the block, then of every row of Z
+      for (int i = tid; i < b0 + n; i += TPB) {
+        double2* Mx = i < b0 ? H : Z;
+        const int row = i < b0 ? i : i - b0;
+        double2 v[W + 1];
+#pragma unroll
+        for (int q = 0; q <= W; ++q)
+          if (q <= nq) v[q] = at(Mx, n, row, k0 + q);
+#pragma unroll
+        for (int q = 0; q < W; ++q) {
+          if (q < nq) {
+            const double c = s_c[q];
+            const double2 sq = s_s[q];
+            const double2 t1 = v[q], t2 = v[q + 1];
+            v[q] = cadd(cscale(t1, c), cmul(cconj(sq), t2));
+            v[q + 1] = csub(cscale(t2, c), cmul(sq, t1));
+          }
+        }
+#pragma unroll
+        for (int q = 0; q <= W; ++q)
+          if (q <= nq) at(Mx, n, row, k0 + q) = v[q];
       }
       __syncthreads();
     }
-    if (tid == 0 && ihi - 1 > l) {  // the last rotation's pending column entries
-      at(H, n, ihi - 1, ihi - 2) = r_prev;
-      at(H, n, ihi, ihi - 2) = make_double2(0.0, 0.0);
-    }
-    __syncthreads();
   }
   if (tid == 0) info[blockIdx.x] = status;
 }
@@ -422,20 +483,20 @@ hipError_t launch_eig_hessenberg(int n, int count, double* A, double* Z, hipStre
   const size_t lds = (size_t)n * sizeof(double2);
   double2* a = reinterpret_cast<double2*>(A);
   double2* z = reinterpret_cast<double2*>(Z);
-  const int nr = (n + kThreads - 1) / kThreads;
-  if (nr <= 1) eig_hessenberg_kernel<1><<<count, kThreads, lds, s>>>(n, a, z);
-  else if (nr <= 2) eig_hessenberg_kernel<2><<<count, kThreads, lds, s>>>(n, a, z);
-  else if (nr <= 4) eig_hessenberg_kernel<4><<<count, kThreads, lds, s>>>(n, a, z);
-  else eig_hessenberg_kernel<8><<<count, kThreads, lds, s>>>(n, a, z);
+  const int nr = (n + 255) / 256;
+  if (nr <= 1) eig_hessenberg_kernel<256, 1><<<count, 256, lds, s>>>(n, a, z);
+  else if (nr <= 2) eig_hessenberg_kernel<256, 2><<<count, 256, lds, s>>>(n, a, z);
+  else if (nr <= 4) eig_hessenberg_kernel<256, 4><<<count, 256, lds, s>>>(n, a, z);
+  else eig_hessenberg_kernel<256, 8><<<count, 256, lds, s>>>(n, a, z);
   return hipGetLastError();
 }
 
 hipError_t launch_eig_schur(int n, int count, double* H, double* Z, double* w, int* info,
                             hipStream_t s) {
   if (n < 1 || n > kEigMaxN || count < 1) return hipErrorInvalidValue;
-  eig_schur_kernel<<<count, kThreads, 0, s>>>(n, reinterpret_cast<double2*>(H),
-                                               reinterpret_cast<double2*>(Z),
-                                               reinterpret_cast<double2*>(w), info);
+  eig_schur_kernel<256, kEigWindow><<<count, 256, 0, s>>>(
+      n, reinterpret_cast<double2*>(H), reinterpret_cast<double2*>(Z),
+      reinterpret_cast<double2*>(w), info);
   return hipGetLastError();
 }
 
