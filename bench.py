@@ -680,6 +680,21 @@ def main(argv=None):
             "rel diff %.1e" % (dinfo["boundary_seconds"], info["boundary_seconds"],
                                dinfo["setup_seconds"], diff))
         dsol.free()
+        # the same setup with the eigendecompositions on the device
+        try:
+            esol = ctx.solve(prob, eig="device")
+            einfo = esol.info()
+            ediff = float(np.linalg.norm(esol.exterior()[2] - hx[2]) / np.linalg.norm(hx[2]))
+            routes["eig_device"] = {"setup_s": einfo["setup_seconds"],
+                                    "eig_s": einfo["eig_seconds"],
+                                    "eig_s_host": info["eig_seconds"],
+                                    "p_trn_rel_diff": ediff}
+            log("eigendecompositions on the device: %.2f s (host %.2f s); p_trn rel diff %.1e"
+                % (einfo["eig_seconds"], info["eig_seconds"], ediff))
+            esol.free()
+        except P.ScwError as e:
+            routes["eig_device"] = {"error": str(e)}
+            log("device eigensolver failed: %s" % e)
 
     dev = torch.device("cuda", 0)
     stream = torch.cuda.current_stream(dev)
