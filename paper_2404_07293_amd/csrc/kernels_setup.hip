@@ -261,6 +261,96 @@ hipError_t launch_build_tb(const double* X, const double* Y, const double* E, in
   return hipGetLastError();
 }
 
+// Top-surface system of the stable route, column-major n4 x n4 (n4 = 2 n2):
+// S = [[I, -Fe], [Hr, -Fh]] (incident + reflected = field at the top of layer 1).
+__global__ void top_system(const z2* __restrict__ Hr, const z2* __restrict__ Fe,
+                           const z2* __restrict__ Fh, int n2, z2* __restrict__ S) {
+  const int n4 = 2 * n2;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long long)n4 * n4) return;
+  const int col = (int)(i / n4), row = (int)(i % n4);
+  z2 v;
+  if (col < n2)
+    v = row < n2 ? z2{row == col ? 1.0 : 0.0, 0.0} : Hr[(long long)col * n2 + row - n2];
+  else {
+    const z2 f = row < n2 ? Fe[(long long)(col - n2) * n2 + row]
+                          : Fh[(long long)(col - n2) * n2 + row - n2];
+    v = z2{-f.x, -f.y};
+  }
+  S[i] = v;
+}
+
+// Connection system of Eq. 29, column-major n6 x n6 (n6 = 6M): rows 0 .. 4M-1
+// are [-K C_r | C_t], rows 4M .. 6M-1 the Gauss rows of the reflected and the
+// transmitted waves (Eq. 14). KCr, Ct: 4M x 3M column-major; szt, szb: s_z of
+// the two half-spaces.
+__global__ void connection_system_kernel(const z2* __restrict__ KCr, const z2* __restrict__ Ct,
+                                         const double* __restrict__ sx,
+                                         const double* __restrict__ sy,
+                                         const z2* __restrict__ szt, const z2* __restrict__ szb,
+                                         int M, z2* __restrict__ A) {
+  const int n4 = 4 * M, n6 = 6 * M;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long long)n6 * n6) return;
+  const int col = (int)(i / n6), row = (int)(i % n6);
+  z2 v{0.0, 0.0};
+  if (row < n4) {
+    if (col < 3 * M) {
+      const z2 k = KCr[(long long)col * n4 + row];
+      v = z2{-k.x, -k.y};
+    } else {
+      v = Ct[(long long)(col - 3 * M) * n4 + row];
+    }
+  } else if (row < n4 + M) {  // reflected wave: s_x p_x + s_y p_y - s_z p_z = 0
+    const int m = row - n4;
+    if (col == m) v = z2{sx[m], 0.0};
+    else if (col == M + m) v = z2{sy[m], 0.0};
+    else if (col == 2 * M + m) v = z2{-szt[m].x, -szt[m].y};
+  } else {  // transmitted wave: s_x p_x + s_y p_y + s_z p_z = 0
+    const int m = row - n4 - M;
+    if (col == 3 * M + m) v = z2{sx[m], 0.0};
+    else if (col == 4 * M + m) v = z2{sy[m], 0.0};
+    else if (col == 5 * M + m) v = szb[m];
+  }
+  A[i] = v;
+}
+
+// out[c] = sum_r |A[r][c]| over the n columns of a column-major n x n matrix
+// (one wave per column).
+__global__ void col_abs_sum(const z2* __restrict__ A, int n, double* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const long long c = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (c >= n) return;
+  const z2* col = A + c * n;
+  double acc = 0.0;
+  for (int r = lane; r < n; r += 64) acc += hypot(col[r].x, col[r].y);
+  for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 64);
+  if (lane == 0) out[c] = acc;
+}
+
+hipError_t launch_top_system(const double* Hr, const double* Fe, const double* Fh, int n2,
+                             double* S, hipStream_t s) {
+  top_system<<<blocks_for(4LL * n2 * n2, 256), 256, 0, s>>>(
+      reinterpret_cast<const z2*>(Hr), reinterpret_cast<const z2*>(Fe),
+      reinterpret_cast<const z2*>(Fh), n2, reinterpret_cast<z2*>(S));
+  return hipGetLastError();
+}
+
+hipError_t launch_connection_system(const double* KCr, const double* Ct, const double* sx,
+                                    const double* sy, const double* szt, const double* szb,
+                                    int M, double* A, hipStream_t s) {
+  connection_system_kernel<<<blocks_for(36LL * M * M, 256), 256, 0, s>>>(
+      reinterpret_cast<const z2*>(KCr), reinterpret_cast<const z2*>(Ct), sx, sy,
+      reinterpret_cast<const z2*>(szt), reinterpret_cast<const z2*>(szb), M,
+      reinterpret_cast<z2*>(A));
+  return hipGetLastError();
+}
+
+hipError_t launch_col_abs_sum(const double* A, int n, double* out, hipStream_t s) {
+  col_abs_sum<<<blocks_for(n, 4), 256, 0, s>>>(reinterpret_cast<const z2*>(A), n, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_eye(double* A, int n, hipStream_t s) {
   eye_kernel<<<blocks_for((long long)n * n, 256), 256, 0, s>>>(reinterpret_cast<z2*>(A), n);
   return hipGetLastError();

@@ -113,6 +113,7 @@ struct Plan {
   DevBuf d_twy;                     // [2][fy] complex<T>: same for g, V
   DevBuf d_spec_multi;              // [K][fz][3M] complex64: spectra of every illumination
   DevBuf d_wmulti;                  // phase table of one illumination group
+  DevBuf d_tile;                    // [3][fz][fy][fx]: one period, for tiled / composed fields
   bool valid = false;
 };
 
@@ -225,6 +226,16 @@ void release_blas(Context& ctx);
 // n x n blocks: A = I; A1, A2 <- (A1 + A2)/2, (A1 - A2)/2 over n entries;
 // P1, P2 = I +- E r E with E diagonal; out = diag(E) A for n x k A.
 hipError_t launch_eye(double* A, int n, hipStream_t s);
+// Top-surface system [[I, -Fe], [Hr, -Fh]] (4M x 4M) of the stable route.
+hipError_t launch_top_system(const double* Hr, const double* Fe, const double* Fh, int n2,
+                             double* S, hipStream_t s);
+// The 6M x 6M connection system of Eq. 29 from K C_r, C_t (4M x 3M) and the
+// Gauss rows (sx, sy real [M]; szt, szb complex [M]).
+hipError_t launch_connection_system(const double* KCr, const double* Ct, const double* sx,
+                                    const double* sy, const double* szt, const double* szb,
+                                    int M, double* A, hipStream_t s);
+// Column sums of |A| of a column-major n x n complex matrix (its 1-norm is the largest).
+hipError_t launch_col_abs_sum(const double* A, int n, double* out, hipStream_t s);
 hipError_t launch_half_sum_diff(double* A1, double* A2, long long n, hipStream_t s);
 hipError_t launch_i_pm_ere(const double* r, const double* E, int n, double* P1, double* P2,
                            hipStream_t s);
@@ -478,6 +489,10 @@ hipError_t launch_objective(void* spec, long long n, int M, int U, int V, double
 // spec[i] *= H[i mod M] over the spectra [n / M][M] (H: complex128 [M]).
 hipError_t launch_transfer(void* spec, long long n, int M, const void* H, bool fp64,
                            hipStream_t s);
+// dst[pc][oy + ty fy + g][ox + tx fx + f] = src[pc][g][f] for the 3 fz
+// plane-components, tx < rx, ty < ry (dst is [3 fz][dfy][dfx]).
+hipError_t launch_place(const void* src, int fx, int fy, int fz, void* dst, int dfx, int dfy,
+                        int ox, int oy, int rx, int ry, bool fp64, hipStream_t s);
 // I[i] = sum_c |E[c][i]|^2 over the three components of [3][npix].
 hipError_t launch_intensity(const void* E, void* I, long long npix, bool fp64, hipStream_t s);
 

@@ -215,6 +215,12 @@ int layer_eig(const Lin& lin, Solution& s, LayerHost& h) {
 
 // ---------------------------------------------------------------- stable route
 int top_surface(const Lin& lin, Solution& s, const Mat& Fe, const Mat& Fh, std::vector<zc>& a1);
+void top_surface_finish(Solution& s, const std::vector<zc>& x, std::vector<zc>& a1);
+std::vector<zc> top_surface_rhs(const Solution& s);
+Mat reflected_h(const Solution& s);
+std::vector<zc> incident_rhs(const Solution& s, const Mat& Ci);
+void connection_finish(Solution& s, const std::vector<zc>& x, const std::vector<zc>& cip,
+                       const Mat& Cr, std::vector<zc>& alpha1);
 void transmitted(Solution& s, int kk, const zc* a);
 
 int solve_stable(const Lin& lin, Solution& s, std::vector<LayerHost>& layers) {
@@ -296,11 +302,50 @@ void transmitted(Solution& s, int kk, const zc* a) {
 // Top surface of the stable route: F(-sz_top) rho - F_1 a_1 = -C_i p_inc for
 // every illumination, with F_1 = [Fe; Fh]. Sets p_ref and returns a_1 as
 // n2 x K (column-major).
+// p_ref and the top-layer amplitudes a_1 of every illumination from the
+// solution x = [p_ref,xy; a_1] (4M x K, column per illumination) of the
+// top-surface system; p_ref,z from Gauss's law (Eq. 14).
+void top_surface_finish(Solution& s, const std::vector<zc>& x, std::vector<zc>& a1) {
+  const int M = s.M, n2 = 2 * M, n4 = 4 * M, K = s.K;
+  s.p_ref.assign((size_t)K * 3 * M, zc(0));
+  s.p_trn.assign((size_t)K * 3 * M, zc(0));
+  a1.assign((size_t)K * n2, zc(0));
+  for (int kk = 0; kk < K; ++kk) {
+    const zc* rhs = x.data() + (size_t)kk * n4;
+    zc* pref = s.p_ref.data() + (size_t)kk * 3 * M;
+    for (int m = 0; m < M; ++m) {
+      const zc px = rhs[m], py = rhs[M + m];
+      pref[m] = px;
+      pref[M + m] = py;
+      pref[2 * M + m] = (s.sx[m] * px + s.sy[m] * py) / s.sz_top[m];
+    }
+    std::copy(rhs + n2, rhs + n4, a1.begin() + (size_t)kk * n2);
+  }
+}
+
+// Right-hand sides -C_i p_inc of the top-surface system, 4M x K.
+std::vector<zc> top_surface_rhs(const Solution& s) {
+  const int M = s.M, n4 = 4 * M, K = s.K;
+  Mat Ci = c_map(s, s.sz_top);
+  std::vector<zc> rhs((size_t)n4 * K, zc(0));
+  for (int kk = 0; kk < K; ++kk) {
+    const zc* pin = s.p_inc.data() + (size_t)kk * 3 * M;
+    zc* r = rhs.data() + (size_t)kk * n4;
+    for (int c = 0; c < 3 * M; ++c)
+      for (int rr = 0; rr < n4; ++rr) r[rr] -= Ci[(size_t)c * n4 + rr] * pin[c];
+  }
+  return rhs;
+}
+
+Mat reflected_h(const Solution& s) {
+  std::vector<zc> msz(s.M);
+  for (int m = 0; m < s.M; ++m) msz[m] = -s.sz_top[m];
+  return half_space_h(s, msz);
+}
+
 int top_surface(const Lin& lin, Solution& s, const Mat& Fe, const Mat& Fh, std::vector<zc>& a1) {
   const int M = s.M, n2 = 2 * M, n4 = 4 * M;
-  std::vector<zc> msz(M);
-  for (int m = 0; m < M; ++m) msz[m] = -s.sz_top[m];
-  Mat Hr = half_space_h(s, msz);
+  Mat Hr = reflected_h(s);
   Mat S((size_t)n4 * n4, zc(0));
   for (int c = 0; c < n2; ++c) {
     S[(size_t)c * n4 + c] = 1.0;
@@ -310,31 +355,13 @@ int top_surface(const Lin& lin, Solution& s, const Mat& Fe, const Mat& Fh, std::
       S[(size_t)(n2 + c) * n4 + n2 + rr] = -Fh[(size_t)c * n2 + rr];
     }
   }
-  Mat Ci = c_map(s, s.sz_top);
   std::vector<int> piv;
   if (lin.lu(n4, S.data(), piv) != 0)
     return fail(SCW_EILLCOND, "singular top-surface system in the stable route");
   // every illumination shares the factorisation
-  const int K = s.K;
-  s.p_ref.assign((size_t)K * 3 * M, zc(0));
-  s.p_trn.assign((size_t)K * 3 * M, zc(0));
-  a1.assign((size_t)K * n2, zc(0));
-  std::vector<zc> rhs(n4);
-  for (int kk = 0; kk < K; ++kk) {
-    const zc* pin = s.p_inc.data() + (size_t)kk * 3 * M;
-    std::fill(rhs.begin(), rhs.end(), zc(0));
-    for (int c = 0; c < 3 * M; ++c)
-      for (int rr = 0; rr < n4; ++rr) rhs[rr] -= Ci[(size_t)c * n4 + rr] * pin[c];
-    lin.lu_solve(n4, 1, S.data(), piv, rhs.data());
-    zc* pref = s.p_ref.data() + (size_t)kk * 3 * M;
-    for (int m = 0; m < M; ++m) {
-      const zc px = rhs[m], py = rhs[M + m];
-      pref[m] = px;
-      pref[M + m] = py;
-      pref[2 * M + m] = (s.sx[m] * px + s.sy[m] * py) / s.sz_top[m];
-    }
-    std::copy(rhs.begin() + n2, rhs.end(), a1.begin() + (size_t)kk * n2);
-  }
+  std::vector<zc> x = top_surface_rhs(s);
+  lin.lu_solve(n4, s.K, S.data(), piv, x.data());
+  top_surface_finish(s, x, a1);
   return SCW_OK;
 }
 
@@ -361,6 +388,116 @@ rocblas_double_complex* zp(const DevBuf& b, size_t off = 0) {
     if (st_ != rocblas_status_success)                                                   \
       return fail(SCW_EHIP, std::string(#call) + ": " + rocblas_status_to_string(st_));  \
   } while (0)
+
+// The stable route's 4M x 4M top-surface system on the device: assembled from
+// the device F_1 (Fe, Fh), LU-factored by rocSOLVER, solved for every
+// illumination; p_ref and a_1 as top_surface leaves them.
+int top_surface_device(Context& ctx, Solution& s, const DevBuf& dFe, const DevBuf& dFh,
+                       std::vector<zc>& a1) {
+  const int M = s.M, n2 = 2 * M, n4 = 4 * M, K = s.K;
+  hipStream_t st = ctx.setup_stream;
+  void* hv = nullptr;
+  int rc;
+  if ((rc = blas_handle(ctx, st, &hv))) return rc;
+  rocblas_handle h = static_cast<rocblas_handle>(hv);
+  const Mat Hr = reflected_h(s);
+  std::vector<zc> x = top_surface_rhs(s);
+  DevBuf dHr, dS, drhs, dpiv, dinfo;
+  if ((rc = dHr.reserve((size_t)n2 * n2 * 16)) || (rc = dS.reserve((size_t)n4 * n4 * 16)) ||
+      (rc = drhs.reserve(x.size() * 16)) || (rc = dpiv.reserve((size_t)n4 * sizeof(rocblas_int))) ||
+      (rc = dinfo.reserve(sizeof(rocblas_int))))
+    return rc;
+  SCW_HIP(hipMemcpyAsync(dHr.p, Hr.data(), Hr.size() * 16, hipMemcpyHostToDevice, st));
+  SCW_HIP(hipMemcpyAsync(drhs.p, x.data(), x.size() * 16, hipMemcpyHostToDevice, st));
+  SCW_HIP(launch_top_system(dHr.as<double>(), dFe.as<double>(), dFh.as<double>(), n2,
+                            dS.as<double>(), st));
+  SCW_BLAS(rocsolver_zgetrf(h, n4, n4, zp(dS), n4, dpiv.as<rocblas_int>(), dinfo.as<rocblas_int>()));
+  SCW_BLAS(rocsolver_zgetrs(h, rocblas_operation_none, n4, K, zp(dS), n4, dpiv.as<rocblas_int>(),
+                            zp(drhs), n4));
+  rocblas_int info = 0;
+  SCW_HIP(hipMemcpyAsync(&info, dinfo.p, sizeof(info), hipMemcpyDeviceToHost, st));
+  SCW_HIP(hipMemcpyAsync(x.data(), drhs.p, x.size() * 16, hipMemcpyDeviceToHost, st));
+  SCW_HIP(hipStreamSynchronize(st));
+  if (info != 0) return fail(SCW_EILLCOND, "singular top-surface system in the device elimination");
+  top_surface_finish(s, x, a1);
+  return SCW_OK;
+}
+
+// The connection route's 6M x 6M system (Eq. 29) on the device, from the
+// device product K: assembled, LU-factored and solved by rocSOLVER. Its
+// 1-norm condition number is computed exactly (the norm of the explicit
+// inverse, from the same factors) where the host route estimates it
+// (zgecon); the same 1e-13 limit on its reciprocal applies.
+int connection_system_device(Context& ctx, Solution& s, const DevBuf& dK,
+                             std::vector<zc>& alpha1) {
+  const int M = s.M, n4 = 4 * M, n6 = 6 * M, nk = s.K;
+  hipStream_t st = ctx.setup_stream;
+  void* hv = nullptr;
+  int rc;
+  if ((rc = blas_handle(ctx, st, &hv))) return rc;
+  rocblas_handle h = static_cast<rocblas_handle>(hv);
+  std::vector<zc> msz(M);
+  for (int m = 0; m < M; ++m) msz[m] = -s.sz_top[m];
+  const Mat Ci = c_map(s, s.sz_top), Cr = c_map(s, msz), Ct = c_map(s, s.sz_bot);
+  const std::vector<zc> cip = incident_rhs(s, Ci);
+  const size_t n43 = (size_t)n4 * 3 * M, nn6 = (size_t)n6 * n6;
+  DevBuf dCr, dCt, dKCr, dsx, dsy, dszt, dszb, dA, dInv, dnorm, dcip, drhs, dpiv, dinfo;
+  if ((rc = dCr.reserve(n43 * 16)) || (rc = dCt.reserve(n43 * 16)) ||
+      (rc = dKCr.reserve(n43 * 16)) || (rc = dsx.reserve((size_t)M * 8)) ||
+      (rc = dsy.reserve((size_t)M * 8)) || (rc = dszt.reserve((size_t)M * 16)) ||
+      (rc = dszb.reserve((size_t)M * 16)) || (rc = dA.reserve(nn6 * 16)) ||
+      (rc = dInv.reserve(nn6 * 16)) || (rc = dnorm.reserve((size_t)n6 * 8 * 2)) ||
+      (rc = dcip.reserve(cip.size() * 16)) || (rc = drhs.reserve((size_t)n6 * nk * 16)) ||
+      (rc = dpiv.reserve((size_t)n6 * sizeof(rocblas_int))) ||
+      (rc = dinfo.reserve(sizeof(rocblas_int))))
+    return rc;
+  SCW_HIP(hipMemcpyAsync(dCr.p, Cr.data(), n43 * 16, hipMemcpyHostToDevice, st));
+  SCW_HIP(hipMemcpyAsync(dCt.p, Ct.data(), n43 * 16, hipMemcpyHostToDevice, st));
+  SCW_HIP(hipMemcpyAsync(dsx.p, s.sx.data(), (size_t)M * 8, hipMemcpyHostToDevice, st));
+  SCW_HIP(hipMemcpyAsync(dsy.p, s.sy.data(), (size_t)M * 8, hipMemcpyHostToDevice, st));
+  SCW_HIP(hipMemcpyAsync(dszt.p, s.sz_top.data(), (size_t)M * 16, hipMemcpyHostToDevice, st));
+  SCW_HIP(hipMemcpyAsync(dszb.p, s.sz_bot.data(), (size_t)M * 16, hipMemcpyHostToDevice, st));
+  SCW_HIP(hipMemcpyAsync(dcip.p, cip.data(), cip.size() * 16, hipMemcpyHostToDevice, st));
+  const rocblas_double_complex one = {1.0, 0.0}, zero = {0.0, 0.0};
+  const rocblas_operation N = rocblas_operation_none;
+  SCW_BLAS(rocblas_zgemm(h, N, N, n4, 3 * M, n4, &one, zp(dK), n4, zp(dCr), n4, &zero, zp(dKCr),
+                         n4));
+  SCW_HIP(launch_connection_system(dKCr.as<double>(), dCt.as<double>(), dsx.as<double>(),
+                                   dsy.as<double>(), dszt.as<double>(), dszb.as<double>(), M,
+                                   dA.as<double>(), st));
+  double* colsum = dnorm.as<double>();
+  SCW_HIP(launch_col_abs_sum(dA.as<double>(), n6, colsum, st));
+  SCW_BLAS(rocsolver_zgetrf(h, n6, n6, zp(dA), n6, dpiv.as<rocblas_int>(), dinfo.as<rocblas_int>()));
+  SCW_HIP(launch_eye(dInv.as<double>(), n6, st));
+  SCW_BLAS(rocsolver_zgetrs(h, N, n6, n6, zp(dA), n6, dpiv.as<rocblas_int>(), zp(dInv), n6));
+  SCW_HIP(launch_col_abs_sum(dInv.as<double>(), n6, colsum + n6, st));
+  // rhs = [K C_i p_inc; 0], every illumination
+  SCW_HIP(hipMemsetAsync(drhs.p, 0, (size_t)n6 * nk * 16, st));
+  SCW_BLAS(rocblas_zgemm(h, N, N, n4, nk, n4, &one, zp(dK), n4, zp(dcip), n4, &zero, zp(drhs),
+                         n6));
+  SCW_BLAS(rocsolver_zgetrs(h, N, n6, nk, zp(dA), n6, dpiv.as<rocblas_int>(), zp(drhs), n6));
+  std::vector<double> sums(2 * (size_t)n6);
+  std::vector<zc> x((size_t)n6 * nk);
+  rocblas_int info = 0;
+  SCW_HIP(hipMemcpyAsync(&info, dinfo.p, sizeof(info), hipMemcpyDeviceToHost, st));
+  SCW_HIP(hipMemcpyAsync(sums.data(), dnorm.p, sums.size() * 8, hipMemcpyDeviceToHost, st));
+  SCW_HIP(hipMemcpyAsync(x.data(), drhs.p, x.size() * 16, hipMemcpyDeviceToHost, st));
+  SCW_HIP(hipStreamSynchronize(st));
+  if (info != 0) return fail(SCW_EILLCOND, "singular 6M x 6M connection system");
+  double anorm = 0, inorm = 0;
+  for (int c = 0; c < n6; ++c) {
+    anorm = std::max(anorm, sums[c]);
+    inorm = std::max(inorm, sums[n6 + c]);
+  }
+  const double rcond = (anorm > 0 && inorm > 0 && std::isfinite(inorm)) ? 1.0 / (anorm * inorm)
+                                                                          : 0.0;
+  s.info.connection_rcond = rcond;
+  if (!(rcond >= kConnectionMinRcond))
+    return fail(SCW_EILLCOND, "connection system is ill-conditioned (rcond " +
+                                  std::to_string(rcond) + " < 1e-13)");
+  connection_finish(s, x, cip, Cr, alpha1);
+  return SCW_OK;
+}
 
 int solve_stable_device(Context& ctx, const Lin& lin, Solution& s,
                         std::vector<LayerHost>& layers) {
@@ -433,11 +570,8 @@ int solve_stable_device(Context& ctx, const Lin& lin, Solution& s,
     SCW_BLAS(rocblas_zgemm(h, N, N, n2, n2, n2, &one, Yl, n2, zp(dP2), n2, &zero, zp(dFh), n2));
   }
   std::vector<rocblas_int> hinfo(3 * L);
-  Mat Fe(nn), Fh(nn);
   SCW_HIP(hipMemcpyAsync(hinfo.data(), info, hinfo.size() * sizeof(rocblas_int),
                          hipMemcpyDeviceToHost, st));
-  SCW_HIP(hipMemcpyAsync(Fe.data(), dFe.p, nn * 16, hipMemcpyDeviceToHost, st));
-  SCW_HIP(hipMemcpyAsync(Fh.data(), dFh.p, nn * 16, hipMemcpyDeviceToHost, st));
   SCW_HIP(hipStreamSynchronize(st));
   for (int i = 0; i < 3 * L; ++i)
     if (hinfo[i] != 0)
@@ -447,7 +581,7 @@ int solve_stable_device(Context& ctx, const Lin& lin, Solution& s,
                              : "eigenvector matrix is singular (layer " + std::to_string(i / 2) +
                                    ")");
   std::vector<zc> a1;
-  if ((rc = top_surface(lin, s, Fe, Fh, a1))) return rc;
+  if ((rc = top_surface_device(ctx, s, dFe, dFh, a1))) return rc;
   // back-substitution of all illuminations: columns of n2 x K blocks
   DevBuf dAc, dEA, dAs, dBs;
   const size_t nk = (size_t)n2 * K;
@@ -536,16 +670,14 @@ int solve_connection_device(Context& ctx, const Lin& lin, Solution& s,
     std::swap(dK.p, dK2.p);
   }
   std::vector<rocblas_int> hinfo(L);
-  Mat K(nn4);
   SCW_HIP(hipMemcpyAsync(hinfo.data(), info, L * sizeof(rocblas_int), hipMemcpyDeviceToHost, st));
-  SCW_HIP(hipMemcpyAsync(K.data(), dK.p, nn4 * 16, hipMemcpyDeviceToHost, st));
   SCW_HIP(hipStreamSynchronize(st));
   for (int l = 0; l < L; ++l)
     if (hinfo[l] != 0)
       return fail(SCW_EILLCOND, "singular layer matrix T in the connection route (layer " +
                                     std::to_string(l) + ")");
   std::vector<zc> alpha1;
-  if ((rc = connection_system(lin, s, K, alpha1))) return rc;
+  if ((rc = connection_system_device(ctx, s, dK, alpha1))) return rc;
   // alpha recursion of all illuminations: n4 x K blocks
   DevBuf dAl, dTmp, dAs;
   const size_t n4k = (size_t)n4 * nk;
@@ -649,6 +781,39 @@ int solve_connection(const Lin& lin, Solution& s, std::vector<LayerHost>& layers
 // K C_i p_inc plus the Gauss rows (Eq. 29), for every illumination. Sets
 // p_ref, p_trn and the reciprocal condition number, and returns
 // alpha_1 = C_i p_inc + C_r p_ref as n4 x K (column-major).
+// C_i p_inc of every illumination (4M x K).
+std::vector<zc> incident_rhs(const Solution& s, const Mat& Ci) {
+  const int M = s.M, n4 = 4 * M, K = s.K;
+  std::vector<zc> cip((size_t)n4 * K, zc(0));
+  for (int kk = 0; kk < K; ++kk) {
+    const zc* pin = s.p_inc.data() + (size_t)kk * 3 * M;
+    zc* r = cip.data() + (size_t)kk * n4;
+    for (int c = 0; c < 3 * M; ++c)
+      for (int rr = 0; rr < n4; ++rr) r[rr] += Ci[(size_t)c * n4 + rr] * pin[c];
+  }
+  return cip;
+}
+
+// p_ref, p_trn and alpha_1 = C_i p_inc + C_r p_ref (Sec. 2.5.4) from the
+// solution x = [p_ref; p_trn] (6M x K) of the connection system.
+void connection_finish(Solution& s, const std::vector<zc>& x, const std::vector<zc>& cip,
+                       const Mat& Cr, std::vector<zc>& alpha1) {
+  const int M = s.M, n4 = 4 * M, n6 = 6 * M, nk = s.K;
+  s.p_ref.assign((size_t)nk * 3 * M, zc(0));
+  s.p_trn.assign((size_t)nk * 3 * M, zc(0));
+  alpha1.assign((size_t)nk * n4, zc(0));
+  for (int kk = 0; kk < nk; ++kk) {
+    const zc* r = x.data() + (size_t)kk * n6;
+    zc* pref = s.p_ref.data() + (size_t)kk * 3 * M;
+    std::copy(r, r + 3 * M, pref);
+    std::copy(r + 3 * M, r + n6, s.p_trn.begin() + (size_t)kk * 3 * M);
+    zc* al = alpha1.data() + (size_t)kk * n4;
+    std::copy(cip.begin() + (size_t)kk * n4, cip.begin() + (size_t)(kk + 1) * n4, al);
+    for (int c = 0; c < 3 * M; ++c)
+      for (int rr = 0; rr < n4; ++rr) al[rr] += Cr[(size_t)c * n4 + rr] * pref[c];
+  }
+}
+
 int connection_system(const Lin& lin, Solution& s, const Mat& K, std::vector<zc>& alpha1) {
   const int M = s.M, n4 = 4 * M, n6 = 6 * M;
   std::vector<zc> msz(M);
@@ -686,29 +851,14 @@ int connection_system(const Lin& lin, Solution& s, const Mat& K, std::vector<zc>
   if (!(rcond >= kConnectionMinRcond))
     return fail(SCW_EILLCOND, "connection system is ill-conditioned (rcond " +
                                   std::to_string(rcond) + " < 1e-13)");
-  // every illumination shares the factorisation of A
+  // every illumination shares the factorisation of A: rhs = [K C_i p_inc; 0]
   const int nk = s.K;
-  s.p_ref.assign((size_t)nk * 3 * M, zc(0));
-  s.p_trn.assign((size_t)nk * 3 * M, zc(0));
-  alpha1.assign((size_t)nk * n4, zc(0));
-  std::vector<zc> cip(n4), rhs(n6);
-  for (int kk = 0; kk < nk; ++kk) {
-    const zc* pin = s.p_inc.data() + (size_t)kk * 3 * M;
-    std::fill(cip.begin(), cip.end(), zc(0));
-    std::fill(rhs.begin(), rhs.end(), zc(0));
-    for (int c = 0; c < 3 * M; ++c)
-      for (int rr = 0; rr < n4; ++rr) cip[rr] += Ci[(size_t)c * n4 + rr] * pin[c];
-    lin.gemm('N', 'N', n4, 1, n4, 1.0, K.data(), n4, cip.data(), n4, 0.0, rhs.data(), n6);
-    lin.lu_solve(n6, 1, A.data(), piv, rhs.data());
-    zc* pref = s.p_ref.data() + (size_t)kk * 3 * M;
-    std::copy(rhs.begin(), rhs.begin() + 3 * M, pref);
-    std::copy(rhs.begin() + 3 * M, rhs.end(), s.p_trn.begin() + (size_t)kk * 3 * M);
-    // T_1 alpha_1 = C_i p_inc + C_r p_ref (the layer solves follow)
-    zc* al = alpha1.data() + (size_t)kk * n4;
-    std::copy(cip.begin(), cip.end(), al);
-    for (int c = 0; c < 3 * M; ++c)
-      for (int rr = 0; rr < n4; ++rr) al[rr] += Cr[(size_t)c * n4 + rr] * pref[c];
-  }
+  std::vector<zc> cip = incident_rhs(s, Ci), x((size_t)n6 * nk, zc(0));
+  for (int kk = 0; kk < nk; ++kk)
+    lin.gemm('N', 'N', n4, 1, n4, 1.0, K.data(), n4, cip.data() + (size_t)kk * n4, n4, 0.0,
+             x.data() + (size_t)kk * n6, n6);
+  lin.lu_solve(n6, nk, A.data(), piv, x.data());
+  connection_finish(s, x, cip, Cr, alpha1);
   return SCW_OK;
 }
 

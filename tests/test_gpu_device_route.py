@@ -109,3 +109,22 @@ def test_device_route_agrees_with_host_route_at_working_size(ctx, working_host, 
     dev.free()
     assert e[0] <= 1e-9 and e[1] <= 1e-9
     assert ef <= 1e-6
+
+
+def test_device_connection_route_reports_its_condition(ctx):
+    """The device connection route computes the 1-norm condition of its 6M x 6M
+    system exactly (norm of the explicit inverse); the host route estimates it
+    with zgecon, whose estimate of the inverse's norm is a lower bound that is
+    usually within a small factor. Both must describe the same system."""
+    prob = problem(3, U=7, V=5)
+    host = ctx.solve(prob, route="connection")
+    dev = ctx.solve(prob, route="connection_device")
+    rh, rd = host.info()["connection_rcond"], dev.info()["connection_rcond"]
+    hx, dx = host.exterior(), dev.exterior()
+    err = rel_l2(dx[2].ravel(), hx[2].ravel())
+    print("connection rcond: host estimate %.3e, device exact %.3e; p_trn rel diff %.2e"
+          % (rh, rd, err))
+    assert 0 < rd <= rh * (1 + 1e-6) and rd >= rh / 10
+    assert err <= 1e-12
+    host.free()
+    dev.free()
