@@ -434,15 +434,85 @@ def batched_sweep(ctx, torch, dev, stream, args):
     bytes_out = voxels * 3 * 8
     log("batched sweep: %d jobs, %.3f ms/launch, %.3e voxels/s, rel-L2 %s (setup %.1f s)" % (
         len(jobs), ms, voxels / (ms * 1e-3), err, t_setup))
+    distinct = distinct_sweep(ctx, torch, dev, stream, args, jobs, grid, tune)
     rec = {"value": voxels / (ms * 1e-3), "ms_per_step": ms, "jobs": len(jobs),
            "voxels_per_step": voxels, "rel_l2_vs_oracle": err,
            "hbm_write_gbps": bytes_out / (ms * 1e-3) / 1e9,
            "roofline": roof_batch(jobs, grid, ms),
            "solved_jobs": len(solved), "setup_s": t_setup, "tuning": tune,
-           "note": "one solve per patch; all 256 wavenumbers of a patch reuse it"}
+           "note": "one solve per patch; all 256 wavenumbers of a patch reuse it",
+           "distinct": distinct}
     del Eb
     b.free()
     for sol in solved.values():
+        sol.free()
+    return rec
+
+
+def distinct_sweep(ctx, torch, dev, stream, args, jobs, grid, tune):
+    """Every wavenumber of the two U = 9 patches (8 and 13) solved on its own:
+    512 distinct jobs. Their fields in one batched launch (the shape the
+    4096-job tuner chose), against the same jobs as 512 separate
+    scw_synthesize calls (the plain GPU form), both FP32; the stored oracle job
+    (patch 8 at the 129th wavenumber) is one of them and gives the error of
+    both forms."""
+    import workloads as W
+    pats = (8, 13)
+    djobs = [(nu, p, u) for nu, p, u in jobs if p in pats]
+    nus = sorted(set(j[0] for j in jobs))
+    t0 = time.perf_counter()
+    sols = [ctx.solve(W.sweep_problem(nu, p, u)[0]) for nu, p, u in djobs]
+    t_setup = time.perf_counter() - t0
+    b = ctx.batch(sols, grid)
+    if tune:
+        b.configure(tune["radix"], tune["blocks_per_cu"], tune["chunk"])
+    Eb = torch.empty((len(djobs), 3, grid.fz, grid.fy, grid.fx), dtype=torch.complex64,
+                     device=dev)
+    Ep = torch.empty_like(Eb)
+    for _ in range(max(2, args.warmup)):
+        b.launch(out=Eb, stream=stream)
+    for i, sol in enumerate(sols):  # plans of the plain form, built before timing
+        sol.synthesize(grid, "fp32", out=Ep[i], stream=stream)
+    torch.cuda.synchronize()
+    s0 = torch.cuda.Event(enable_timing=True)
+    s1 = torch.cuda.Event(enable_timing=True)
+    s0.record(stream)
+    for _ in range(args.steps):
+        b.launch(out=Eb, stream=stream)
+    s1.record(stream)
+    torch.cuda.synchronize()
+    ms_b = s0.elapsed_time(s1) / args.steps
+    reps = max(2, args.steps // 5)
+    s0.record(stream)
+    for _ in range(reps):
+        for i, sol in enumerate(sols):
+            sol.synthesize(grid, "fp32", out=Ep[i], stream=stream)
+    s1.record(stream)
+    torch.cuda.synchronize()
+    ms_p = s0.elapsed_time(s1) / reps
+    voxels = len(djobs) * grid.fz * grid.fy * grid.fx
+    err_b = err_p = None
+    if os.path.exists(SWEEP_GOLDEN):
+        g = np.load(SWEEP_GOLDEN, allow_pickle=False)
+        key = (nus[int(g["nu_index"])], int(g["patch"]))
+        idx = [i for i, (nu, p, _) in enumerate(djobs) if (nu, p) == key]
+        if idx:
+            want = g["E"]
+            err_b = float(np.linalg.norm(Eb[idx[0]].cpu().numpy() - want) / np.linalg.norm(want))
+            err_p = float(np.linalg.norm(Ep[idx[0]].cpu().numpy() - want) / np.linalg.norm(want))
+    same = float(torch.linalg.vector_norm(Eb - Ep) / torch.linalg.vector_norm(Ep))
+    log("distinct sweep jobs: %d solved in %.1f s; batched %.3f ms (%.3e voxels/s), plain "
+        "per-job synthesis %.3f ms (%.3e voxels/s); rel-L2 vs oracle batched %s plain %s; "
+        "batched vs plain %.1e" % (len(djobs), t_setup, ms_b, voxels / (ms_b * 1e-3), ms_p,
+                                   voxels / (ms_p * 1e-3), err_b, err_p, same))
+    rec = {"jobs": len(djobs), "patches": list(pats), "U": 9, "setup_s": t_setup,
+           "batched": {"ms": ms_b, "value": voxels / (ms_b * 1e-3), "rel_l2_vs_oracle": err_b},
+           "plain": {"ms": ms_p, "value": voxels / (ms_p * 1e-3), "rel_l2_vs_oracle": err_p,
+                     "calls": len(djobs)},
+           "batched_over_plain": ms_p / ms_b, "batched_vs_plain_rel_l2": same}
+    del Eb, Ep
+    b.free()
+    for sol in sols:
         sol.free()
     return rec
 

@@ -185,6 +185,17 @@ void scw_destroy(scw_ctx* ctx);
  * Blocks until done. On success *out is a library-owned solution. */
 int scw_solve(scw_ctx* ctx, const scw_problem* prob, scw_solution** out);
 
+/* n problems solved together (Sec. 3; the setup of a spectral sweep or of a
+ * training set). Each is solved as scw_solve would solve it; the device
+ * eigendecompositions (eig = SCW_EIG_DEVICE) of all problems with the same
+ * truncation U*V share one batched launch of the eigensolver, in rounds of
+ * up to about 24 GB of device workspace. On success out[i] (caller-provided
+ * array of n pointers) receives problem i's solution, each freed by
+ * scw_solution_free. On failure every out[i] is NULL and the message names
+ * the problem. The solutions' eig_seconds all report the shared batch time
+ * of their round (plus any host part). */
+int scw_solve_batch(scw_ctx* ctx, const scw_problem* probs, int n, scw_solution** out);
+
 /* Batched FP64 eigendecomposition on the GPU (the step of Sec. 3.2 and
  * Sec. 4.2 that the paper names its next bottleneck), as scw_solve runs it
  * for SCW_EIG_DEVICE: count independent n x n complex matrices, each reduced
@@ -284,6 +295,33 @@ int scw_synthesize(scw_ctx* ctx, scw_solution* sol, const scw_grid* grid,
 #define SCW_NOALLOC_SCRATCH_BYTES (32u << 20)
 int scw_synthesize_noalloc(scw_ctx* ctx, scw_solution* sol, const scw_grid* grid,
                            int precision, void* E_dev, void* hip_stream);
+
+/* Periodic display (Sec. 4.6: the field of one unit cell applied to the
+ * whole periodic pattern): the field over tx x ty lateral periods. Every
+ * plane wave of Eq. 10 has a lattice frequency, so the field repeats with the
+ * period; one period is synthesised on `grid` and copied tx x ty times.
+ * E_dev: caller-owned device buffer [3][fz][ty*fy][tx*fx] (complex128 for
+ * SCW_FP64, complex64 otherwise); column tx'*fx + f of a row lies at
+ * x = tx'*X + f*X/fx. Work is enqueued on hip_stream; the period is held in a
+ * workspace of the solution's plan for this grid and precision, so calls on
+ * one solution must be ordered. Errors: as scw_synthesize, and SCW_EINVAL
+ * for tx or ty below 1. */
+int scw_synthesize_tiled(scw_ctx* ctx, scw_solution* sol, const scw_grid* grid, int tx,
+                         int ty, int precision, void* E_dev, void* hip_stream);
+
+/* A large sample composed of small patches in two dimensions (Sec. 1): px x
+ * py solutions, patches[j*px + i] for the patch at lateral position (i, j),
+ * each solved as its own periodic unit cell, each synthesised on `grid` over
+ * its own period and written side by side: patch (i, j) fills columns
+ * i*fx .. (i+1)*fx - 1 and rows j*fy .. (j+1)*fy - 1 of E_dev
+ * [3][fz][py*fy][px*fx]. Coupling across patch borders is not modelled (each
+ * patch sees its own periodic continuation); identical patches give exactly
+ * the tiled field of one. Patches may differ in truncation and lateral
+ * period. Errors: as scw_synthesize, SCW_EINVAL for a null patch or counts
+ * below 1. */
+int scw_synthesize_composed(scw_ctx* ctx, scw_solution* const* patches, int px, int py,
+                            const scw_grid* grid, int precision, void* E_dev,
+                            void* hip_stream);
 
 /* Kernel configuration of scw_synthesize for one solution. Fields left 0
  * take the library's choice: a configuration found by scw_tune_synthesis for

@@ -556,6 +556,33 @@ def field_at_points(st, sol, x, y, z):
 
 
 # --------------------------------------------------------------------------
+# Large samples (Sec. 1: a large sample composed of small patches in two
+# dimensions; Sec. 4.6: the field of one unit cell applied to the whole
+# periodic pattern).
+# --------------------------------------------------------------------------
+def tiled(st, sol, grid, tx, ty):
+    """The field over tx x ty lateral periods, [3, fz, ty*fy, tx*fx]: every
+    plane wave of Eq. 10 has a lattice frequency (s_x = lam u / X), so the
+    sum repeats with the period; the grid of each period is grid's."""
+    return np.tile(synthesize(st, sol, grid), (1, 1, ty, tx))
+
+
+def compose(parts, px, py, grid):
+    """A large sample of px x py patches, each solved as its own periodic
+    unit cell: parts[j * px + i] = (setup, solution) of the patch at lateral
+    position (i, j); its field on grid (one period of that patch) fills
+    columns i*fx .. (i+1)*fx - 1 and rows j*fy .. (j+1)*fy - 1 of the result
+    [3, fz, py*fy, px*fx]. Coupling across patch borders is not modelled."""
+    out = np.zeros((3, grid.fz, py * grid.fy, px * grid.fx), dtype=np.complex128)
+    for j in range(py):
+        for i in range(px):
+            st, sol = parts[j * px + i]
+            out[:, :, j * grid.fy:(j + 1) * grid.fy, i * grid.fx:(i + 1) * grid.fx] = \
+                synthesize(st, sol, grid)
+    return out
+
+
+# --------------------------------------------------------------------------
 # Optics: an ideal objective acting on the plane-wave spectrum (Sec. 1: the
 # Fourier representation lets an optical system be applied directly to the
 # field's spectrum).

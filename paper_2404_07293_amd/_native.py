@@ -117,9 +117,18 @@ SIGNATURES = {
     "scw_synthesize_slice": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
                                             ctypes.POINTER(ScwSlice), ctypes.c_int,
                                             ctypes.c_void_p, ctypes.c_void_p]),
+    "scw_solve_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ScwProblem),
+                                       ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)]),
     "scw_eig_batched": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_void_p]),
+    "scw_synthesize_tiled": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.POINTER(ScwGrid), ctypes.c_int, ctypes.c_int,
+                                            ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
+    "scw_synthesize_composed": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
+                                               ctypes.c_int, ctypes.c_int,
+                                               ctypes.POINTER(ScwGrid), ctypes.c_int,
+                                               ctypes.c_void_p, ctypes.c_void_p]),
     "scw_synthesize": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ScwGrid),
                                       ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
     "scw_synthesize_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,

@@ -440,6 +440,28 @@ int scw_solve(scw_ctx* ctx, const scw_problem* prob, scw_solution** out) {
   return solve_into(ctx, prob, 0, nullptr, out);
 }
 
+int scw_solve_batch(scw_ctx* ctx, const scw_problem* probs, int n, scw_solution** out) {
+  if (!ctx || !probs || !out || n < 1) return fail(SCW_EINVAL, "null argument or n < 1");
+  for (int i = 0; i < n; ++i) out[i] = nullptr;
+  std::vector<scw_solution*> made(n, nullptr);
+  std::vector<Solution*> sols(n, nullptr);
+  for (int i = 0; i < n; ++i) {
+    made[i] = new (std::nothrow) scw_solution();
+    if (!made[i]) {
+      for (scw_solution* m : made) delete m;
+      return fail(SCW_ENOMEM, "solution allocation failed");
+    }
+    sols[i] = &made[i]->s;
+  }
+  const int rc = solve_problems(ctx->c, probs, n, sols.data());
+  if (rc) {
+    for (scw_solution* m : made) delete m;
+    return rc;
+  }
+  for (int i = 0; i < n; ++i) out[i] = made[i];
+  return SCW_OK;
+}
+
 int scw_solve_illuminations(scw_ctx* ctx, const scw_problem* prob, int n_waves,
                             const scw_plane_wave* waves, scw_solution** out) {
   if (n_waves < 1 || n_waves > 4096 || !waves)
@@ -626,6 +648,57 @@ int scw_synthesize(scw_ctx* ctx, scw_solution* sol, const scw_grid* grid, int pr
   if (c.prof_used < c.prof_max) ev = c.prof_events.data() + (size_t)c.prof_used++ * (kNumStages + 1);
   return synthesize(c, sol->s, *grid, precision, E_dev, reinterpret_cast<hipStream_t>(hip_stream),
                     kStageAll, ev);
+}
+
+// One period of sol's field into its plan's tile workspace, then placed.
+static int synthesize_placed(Context& c, Solution& s, const scw_grid& g, int precision, void* E,
+                             int dfx, int dfy, int ox, int oy, int rx, int ry, hipStream_t st) {
+  Plan* pl = nullptr;
+  int rc = get_plan(c, s, g, precision, false, &pl);
+  if (rc) return rc;
+  const size_t eb = precision == SCW_FP64 ? 16 : 8;
+  const size_t bytes = (size_t)3 * g.fz * g.fy * g.fx * eb;
+  if (pl->d_tile.bytes < bytes && (rc = pl->d_tile.reserve(bytes))) return rc;
+  if ((rc = synthesize(c, s, g, precision, pl->d_tile.p, st, kStageAll, nullptr))) return rc;
+  SCW_HIP(launch_place(pl->d_tile.p, g.fx, g.fy, g.fz, E, dfx, dfy, ox, oy, rx, ry,
+                       precision == SCW_FP64, st));
+  return SCW_OK;
+}
+
+int scw_synthesize_tiled(scw_ctx* ctx, scw_solution* sol, const scw_grid* grid, int tx, int ty,
+                         int precision, void* E_dev, void* hip_stream) {
+  if (!ctx || !sol || !E_dev) return fail(SCW_EINVAL, "null argument");
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  if (precision < SCW_FP64 || precision > SCW_FP16X3)
+    return fail(SCW_EINVAL, "unknown precision " + std::to_string(precision));
+  if (tx < 1 || ty < 1 || (long long)tx * grid->fx > (1LL << 30) ||
+      (long long)ty * grid->fy > (1LL << 30))
+    return fail(SCW_EINVAL, "tile counts must be positive");
+  return synthesize_placed(ctx->c, sol->s, *grid, precision, E_dev, tx * grid->fx,
+                           ty * grid->fy, 0, 0, tx, ty, reinterpret_cast<hipStream_t>(hip_stream));
+}
+
+int scw_synthesize_composed(scw_ctx* ctx, scw_solution* const* patches, int px, int py,
+                            const scw_grid* grid, int precision, void* E_dev, void* hip_stream) {
+  if (!ctx || !patches || !E_dev) return fail(SCW_EINVAL, "null argument");
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  if (precision < SCW_FP64 || precision > SCW_FP16X3)
+    return fail(SCW_EINVAL, "unknown precision " + std::to_string(precision));
+  if (px < 1 || py < 1 || (long long)px * grid->fx > (1LL << 30) ||
+      (long long)py * grid->fy > (1LL << 30))
+    return fail(SCW_EINVAL, "patch counts must be positive");
+  for (int i = 0; i < px * py; ++i)
+    if (!patches[i]) return fail(SCW_EINVAL, "null patch " + std::to_string(i));
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  for (int j = 0; j < py; ++j)
+    for (int i = 0; i < px; ++i)
+      if ((rc = synthesize_placed(ctx->c, patches[j * px + i]->s, *grid, precision, E_dev,
+                                  px * grid->fx, py * grid->fy, i * grid->fx, j * grid->fy, 1, 1,
+                                  st)))
+        return rc;
+  return SCW_OK;
 }
 
 int scw_synthesize_slice(scw_ctx* ctx, scw_solution* sol, const scw_slice* slice, int precision,

@@ -1043,6 +1043,41 @@ hipError_t launch_slice(const SliceArgs& a, bool fp64, hipStream_t s) {
   return fp64 ? go(double{}) : go(float{});
 }
 
+// Copies a field [np][fy][fx] (np = 3 fz plane-components) into the window
+// at (ox, oy) of a wider field [np][dfy][dfx], rx x ry times side by side.
+template <typename T>
+__global__ void place_kernel(const cx<T>* __restrict__ src, int fx, int fy, long long total,
+                             cx<T>* __restrict__ dst, int dfx, int dfy, int ox, int oy, int rx,
+                             int ry) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const int f = (int)(i % fx);
+  const long long q = i / fx;
+  const int g = (int)(q % fy);
+  const long long pc = q / fy;
+  const cx<T> v = src[i];
+  for (int ty = 0; ty < ry; ++ty) {
+    cx<T>* row = dst + (pc * dfy + oy + (long long)ty * fy + g) * dfx + ox + f;
+    for (int tx = 0; tx < rx; ++tx) row[(long long)tx * fx] = v;
+  }
+}
+
+hipError_t launch_place(const void* src, int fx, int fy, int fz, void* dst, int dfx, int dfy,
+                        int ox, int oy, int rx, int ry, bool fp64, hipStream_t s) {
+  const long long total = 3LL * fz * fy * fx;
+  if (total <= 0) return hipSuccess;
+  const unsigned nb = blocks_for(total, 256);
+  if (fp64)
+    place_kernel<double><<<nb, 256, 0, s>>>(reinterpret_cast<const cx<double>*>(src), fx, fy,
+                                            total, reinterpret_cast<cx<double>*>(dst), dfx, dfy,
+                                            ox, oy, rx, ry);
+  else
+    place_kernel<float><<<nb, 256, 0, s>>>(reinterpret_cast<const cx<float>*>(src), fx, fy,
+                                           total, reinterpret_cast<cx<float>*>(dst), dfx, dfy,
+                                           ox, oy, rx, ry);
+  return hipGetLastError();
+}
+
 hipError_t launch_synthesis_fp32(const SynthArgs& a, hipStream_t s, hipEvent_t* ev) {
   return launch_synthesis<float>(a, s, ev);
 }

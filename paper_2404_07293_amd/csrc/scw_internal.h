@@ -221,6 +221,10 @@ int synthesize_illuminations(Context& ctx, Solution& s, const scw_grid& g, void*
 // problem's own incident field is then ignored), sharing one setup.
 int solve_problem(Context& ctx, const scw_problem& prob, Solution& sol, int n_waves = 0,
                   const scw_plane_wave* waves = nullptr);
+// n problems solved together: their device eigendecompositions
+// (SCW_EIG_DEVICE) of equal truncation share launches; each other step runs
+// per problem as in solve_problem. sols[i] receives problem i.
+int solve_problems(Context& ctx, const scw_problem* probs, int n, Solution** sols);
 void release_blas(Context& ctx);
 // Elementwise steps of the device elimination, column-major complex128
 // n x n blocks: A = I; A1, A2 <- (A1 + A2)/2, (A1 - A2)/2 over n entries;

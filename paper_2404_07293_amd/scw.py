@@ -15,6 +15,39 @@ def _ptr(a):
     return a.ctypes.data_as(N.c_dp) if a is not None else None
 
 
+def _problem(prob, route, eig, keep):
+    """A ctypes scw_problem for a ``workloads.Problem``; arrays it points to
+    are appended to ``keep`` (the caller holds them through the call)."""
+    n = np.ascontiguousarray(prob.n, dtype=np.complex128)
+    keep.append(n)
+    p = N.ScwProblem()
+    p.nz, p.ny, p.nx = n.shape
+    p.px, p.py, p.pz = float(prob.px), float(prob.py), float(prob.pz)
+    p.n = _ptr(n)
+    p.lam = float(prob.lam)
+    p.n_top = float(prob.n_top)
+    nb = complex(prob.n_bot)
+    p.n_bot_re, p.n_bot_im = nb.real, nb.imag
+    p.U, p.V = int(prob.U), int(prob.V)
+    if prob.inc_ex is not None or prob.inc_ey is not None:
+        ref = prob.inc_ex if prob.inc_ex is not None else prob.inc_ey
+        p.inc_ny, p.inc_nx = ref.shape
+        for name in ("inc_ex", "inc_ey"):
+            img = getattr(prob, name)
+            if img is not None:
+                img = np.ascontiguousarray(img, dtype=np.complex128)
+                keep.append(img)
+                setattr(p, name, _ptr(img))
+    pw = prob.plane_wave
+    p.pw_u, p.pw_v = int(pw.u), int(pw.v)
+    ex, ey = complex(pw.ex), complex(pw.ey)
+    p.pw_ex[0], p.pw_ex[1] = ex.real, ex.imag
+    p.pw_ey[0], p.pw_ey[1] = ey.real, ey.imag
+    p.route = N.ROUTE[route]
+    p.eig = N.EIG[eig]
+    return p
+
+
 class Context:
     """A library context on one HIP device (``scw_create``)."""
 
@@ -57,6 +90,43 @@ class Context:
                                          ctypes.c_void_p(stream.cuda_stream)))
         return w, Xc.transpose(1, 2)
 
+    def synthesize_composed(self, patches, px, py, grid, precision="fp32", out=None,
+                            stream=None):
+        """``scw_synthesize_composed``: the solutions ``patches`` (row-major,
+        px x py) side by side, each over its own period, into ``out``
+        [3, fz, py*fy, px*fx] (allocated when None)."""
+        import torch
+        if len(patches) != px * py:
+            raise ValueError("need px * py patches")
+        dt = torch.complex128 if precision == "fp64" else torch.complex64
+        dev = torch.device("cuda", self.device)
+        shape = (3, int(grid.fz), int(py) * int(grid.fy), int(px) * int(grid.fx))
+        if out is None:
+            out = torch.empty(shape, dtype=dt, device=dev)
+        if tuple(out.shape) != shape or out.dtype != dt or not out.is_contiguous():
+            raise ValueError("out must be a contiguous %s tensor of shape %s" % (dt, shape))
+        if stream is None:
+            stream = torch.cuda.current_stream(dev)
+        arr = (ctypes.c_void_p * len(patches))(*[p.handle for p in patches])
+        N.check(self.lib.scw_synthesize_composed(self.handle, arr, int(px), int(py),
+                                                 ctypes.byref(_grid(grid)),
+                                                 N.PRECISION[precision],
+                                                 ctypes.c_void_p(out.data_ptr()),
+                                                 ctypes.c_void_p(stream.cuda_stream)))
+        return out
+
+    def solve_batch(self, probs, route="stable", eig="device"):
+        """``scw_solve_batch``: solve the ``workloads.Problem`` list together
+        (the device eigendecompositions of equal truncation share launches);
+        returns one Solution per problem."""
+        keep = []
+        arr = (N.ScwProblem * len(probs))()
+        for i, pr in enumerate(probs):
+            arr[i] = _problem(pr, route, eig, keep)
+        hs = (ctypes.c_void_p * len(probs))()
+        N.check(self.lib.scw_solve_batch(self.handle, arr, len(probs), hs))
+        return [Solution(self, ctypes.c_void_p(hs[i]), pr) for i, pr in enumerate(probs)]
+
     def solve(self, prob, route="stable", waves=None, eig="host"):
         """Run ``scw_solve`` on a ``workloads.Problem``; returns a Solution.
         With ``waves`` (a list of ``workloads.PlaneWave``) it runs
@@ -64,33 +134,8 @@ class Context:
         problem's own incident field ignored. ``eig`` places the per-layer
         eigendecompositions: "host" (LAPACK) or "device" (the library's
         batched GPU eigensolver)."""
-        n = np.ascontiguousarray(prob.n, dtype=np.complex128)
-        keep = [n]
-        p = N.ScwProblem()
-        p.nz, p.ny, p.nx = n.shape
-        p.px, p.py, p.pz = float(prob.px), float(prob.py), float(prob.pz)
-        p.n = _ptr(n)
-        p.lam = float(prob.lam)
-        p.n_top = float(prob.n_top)
-        nb = complex(prob.n_bot)
-        p.n_bot_re, p.n_bot_im = nb.real, nb.imag
-        p.U, p.V = int(prob.U), int(prob.V)
-        if prob.inc_ex is not None or prob.inc_ey is not None:
-            ref = prob.inc_ex if prob.inc_ex is not None else prob.inc_ey
-            p.inc_ny, p.inc_nx = ref.shape
-            for name in ("inc_ex", "inc_ey"):
-                img = getattr(prob, name)
-                if img is not None:
-                    img = np.ascontiguousarray(img, dtype=np.complex128)
-                    keep.append(img)
-                    setattr(p, name, _ptr(img))
-        pw = prob.plane_wave
-        p.pw_u, p.pw_v = int(pw.u), int(pw.v)
-        ex, ey = complex(pw.ex), complex(pw.ey)
-        p.pw_ex[0], p.pw_ex[1] = ex.real, ex.imag
-        p.pw_ey[0], p.pw_ey[1] = ey.real, ey.imag
-        p.route = N.ROUTE[route]
-        p.eig = N.EIG[eig]
+        keep = []
+        p = _problem(prob, route, eig, keep)
         h = ctypes.c_void_p()
         if waves is None:
             N.check(self.lib.scw_solve(self.handle, ctypes.byref(p), ctypes.byref(h)))
@@ -181,6 +226,26 @@ class Solution:
                                         ctypes.byref(_grid(grid)), N.PRECISION[precision],
                                         ctypes.c_void_p(out.data_ptr()),
                                         ctypes.c_void_p(stream.cuda_stream)))
+        return out
+
+    def synthesize_tiled(self, grid, tx, ty, precision="fp32", out=None, stream=None):
+        """Enqueue ``scw_synthesize_tiled``: the field over tx x ty lateral
+        periods into ``out`` [3, fz, ty*fy, tx*fx] (allocated when None)."""
+        import torch
+        dt = torch.complex128 if precision == "fp64" else torch.complex64
+        dev = torch.device("cuda", self.ctx.device)
+        shape = (3, int(grid.fz), int(ty) * int(grid.fy), int(tx) * int(grid.fx))
+        if out is None:
+            out = torch.empty(shape, dtype=dt, device=dev)
+        if tuple(out.shape) != shape or out.dtype != dt or not out.is_contiguous():
+            raise ValueError("out must be a contiguous %s tensor of shape %s" % (dt, shape))
+        if stream is None:
+            stream = torch.cuda.current_stream(dev)
+        N.check(self.lib.scw_synthesize_tiled(self.ctx.handle, self.handle,
+                                              ctypes.byref(_grid(grid)), int(tx), int(ty),
+                                              N.PRECISION[precision],
+                                              ctypes.c_void_p(out.data_ptr()),
+                                              ctypes.c_void_p(stream.cuda_stream)))
         return out
 
     def synthesize_noalloc(self, grid, out, precision="fp32", stream=None):
