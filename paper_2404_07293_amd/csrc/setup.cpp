@@ -869,62 +869,116 @@ void release_blas(Context& ctx) {
   ctx.blas = nullptr;
 }
 
+// ---------------------------------------------------------------- phases of a solve
+// What a solve keeps between its steps, so that the device eigendecompositions
+// of many problems can share launches (solve_problems).
+struct PendingSolve {
+  double t_start = 0;
+  bool dev_eig = false;
+  double device_eig_seconds = 0;
+  std::vector<LayerHost> layers;
+  DevBuf d_A, d_C;  // property blocks of every layer (device eigensolver only)
+  DevBuf d_psi, d_u, d_v, d_sx, d_sy;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  PendingSolve() = default;
+  PendingSolve(const PendingSolve&) = delete;
+  PendingSolve& operator=(const PendingSolve&) = delete;
+  ~PendingSolve() {
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+  }
+};
+
 // ---------------------------------------------------------------- device eigensolver
-// Every layer's A C (one strided-batched GEMM), its eigendecomposition by the
-// batched device eigensolver, gamma on the host, Y = C X diag(1/gamma) on the
-// device; X, Y, gamma and E of every layer end in `layers` as layer_eig
-// leaves them.
-static int device_layer_eig(Context& ctx, Solution& s, DevBuf& d_A, DevBuf& d_C,
-                            std::vector<LayerHost>& layers) {
-  const int n2 = 2 * s.M, L = s.L;
+// The layers of n problems of one truncation (2M x 2M products): every A C
+// by one strided-batched GEMM, all of them eigendecomposed by the batched
+// device eigensolver at once, gamma on the host, Y = C X diag(1/gamma) on the
+// device; X, Y, gamma and E of every layer end in each problem's `layers` as
+// layer_eig leaves them.
+static int device_eig_group(Context& ctx, Solution** sols, PendingSolve** ps, int n) {
+  const int n2 = 2 * sols[0]->M;
   const size_t nn = (size_t)n2 * n2;
+  int total = 0;
+  for (int i = 0; i < n; ++i) total += sols[i]->L;
   hipStream_t st = ctx.setup_stream;
-  DevBuf d_AC, d_X, d_w, d_f;
+  const double t0 = now_s();
+  DevBuf cat_A, cat_C, d_AC, d_X, d_w, d_f;
   int rc;
-  if ((rc = d_AC.reserve(nn * 16 * L)) || (rc = d_X.reserve(nn * 16 * L)) ||
-      (rc = d_w.reserve((size_t)n2 * 16 * L)) || (rc = d_f.reserve((size_t)n2 * 16 * L)))
+  const DevBuf* A = &ps[0]->d_A;
+  const DevBuf* C = &ps[0]->d_C;
+  if (n > 1) {  // one contiguous batch
+    if ((rc = cat_A.reserve(nn * 16 * total)) || (rc = cat_C.reserve(nn * 16 * total))) return rc;
+    size_t off = 0;
+    for (int i = 0; i < n; ++i) {
+      const size_t b = nn * 16 * sols[i]->L;
+      SCW_HIP(hipMemcpyAsync(cat_A.as<char>() + off, ps[i]->d_A.p, b, hipMemcpyDeviceToDevice, st));
+      SCW_HIP(hipMemcpyAsync(cat_C.as<char>() + off, ps[i]->d_C.p, b, hipMemcpyDeviceToDevice, st));
+      off += b;
+    }
+    A = &cat_A;
+    C = &cat_C;
+  }
+  if ((rc = d_AC.reserve(nn * 16 * total)) || (rc = d_X.reserve(nn * 16 * total)) ||
+      (rc = d_w.reserve((size_t)n2 * 16 * total)) || (rc = d_f.reserve((size_t)n2 * 16 * total)))
     return rc;
   void* hv = nullptr;
   if ((rc = blas_handle(ctx, st, &hv))) return rc;
   rocblas_handle h = static_cast<rocblas_handle>(hv);
   const rocblas_double_complex one = {1.0, 0.0}, zero = {0.0, 0.0};
   const rocblas_operation N = rocblas_operation_none;
-  SCW_BLAS(rocblas_zgemm_strided_batched(h, N, N, n2, n2, n2, &one, zp(d_A), n2,
-                                         (rocblas_stride)nn, zp(d_C), n2, (rocblas_stride)nn,
-                                         &zero, zp(d_AC), n2, (rocblas_stride)nn, L));
-  if ((rc = device_eig_batched(ctx, n2, L, d_AC.as<double>(), d_w.as<double>(),
+  SCW_BLAS(rocblas_zgemm_strided_batched(h, N, N, n2, n2, n2, &one, zp(*A), n2,
+                                         (rocblas_stride)nn, zp(*C), n2, (rocblas_stride)nn,
+                                         &zero, zp(d_AC), n2, (rocblas_stride)nn, total));
+  if ((rc = device_eig_batched(ctx, n2, total, d_AC.as<double>(), d_w.as<double>(),
                                d_X.as<double>(), st)))
     return rc;
-  std::vector<zc> lam((size_t)n2 * L), f((size_t)n2 * L);
+  std::vector<zc> lam((size_t)n2 * total), f((size_t)n2 * total);
   SCW_HIP(hipMemcpyAsync(lam.data(), d_w.p, lam.size() * 16, hipMemcpyDeviceToHost, st));
   SCW_HIP(hipStreamSynchronize(st));
-  for (int l = 0; l < L; ++l) {
-    if ((rc = layer_gamma(s, lam.data() + (size_t)l * n2, layers[l]))) return rc;
-    for (int j = 0; j < n2; ++j) f[(size_t)l * n2 + j] = 1.0 / layers[l].gamma[j];
-  }
+  size_t g = 0;  // global layer index
+  for (int i = 0; i < n; ++i)
+    for (int l = 0; l < sols[i]->L; ++l, ++g) {
+      LayerHost& lh = ps[i]->layers[l];
+      if ((rc = layer_gamma(*sols[i], lam.data() + g * n2, lh))) return rc;
+      for (int j = 0; j < n2; ++j) f[g * n2 + j] = 1.0 / lh.gamma[j];
+    }
   SCW_HIP(hipMemcpyAsync(d_f.p, f.data(), f.size() * 16, hipMemcpyHostToDevice, st));
-  SCW_BLAS(rocblas_zgemm_strided_batched(h, N, N, n2, n2, n2, &one, zp(d_C), n2,
+  SCW_BLAS(rocblas_zgemm_strided_batched(h, N, N, n2, n2, n2, &one, zp(*C), n2,
                                          (rocblas_stride)nn, zp(d_X), n2, (rocblas_stride)nn,
-                                         &zero, zp(d_AC), n2, (rocblas_stride)nn, L));
-  SCW_HIP(launch_eig_scale_cols(n2, (long long)n2 * L, d_f.as<double>(), d_AC.as<double>(), st));
-  for (int l = 0; l < L; ++l) {
-    layers[l].X.resize(nn);
-    layers[l].Y.resize(nn);
-    SCW_HIP(hipMemcpyAsync(layers[l].X.data(), d_X.as<zc>() + (size_t)l * nn, nn * 16,
-                           hipMemcpyDeviceToHost, st));
-    SCW_HIP(hipMemcpyAsync(layers[l].Y.data(), d_AC.as<zc>() + (size_t)l * nn, nn * 16,
-                           hipMemcpyDeviceToHost, st));
-  }
+                                         &zero, zp(d_AC), n2, (rocblas_stride)nn, total));
+  SCW_HIP(launch_eig_scale_cols(n2, (long long)n2 * total, d_f.as<double>(), d_AC.as<double>(),
+                                st));
+  g = 0;
+  for (int i = 0; i < n; ++i)
+    for (int l = 0; l < sols[i]->L; ++l, ++g) {
+      LayerHost& lh = ps[i]->layers[l];
+      lh.X.resize(nn);
+      lh.Y.resize(nn);
+      SCW_HIP(hipMemcpyAsync(lh.X.data(), d_X.as<zc>() + g * nn, nn * 16, hipMemcpyDeviceToHost,
+                             st));
+      SCW_HIP(hipMemcpyAsync(lh.Y.data(), d_AC.as<zc>() + g * nn, nn * 16, hipMemcpyDeviceToHost,
+                             st));
+    }
   SCW_HIP(hipStreamSynchronize(st));
+  const double dt = now_s() - t0;
+  for (int i = 0; i < n; ++i) {
+    ps[i]->d_A.release();
+    ps[i]->d_C.release();
+    ps[i]->device_eig_seconds = dt;
+  }
   return SCW_OK;
 }
 
 #undef SCW_BLAS
 
 // ---------------------------------------------------------------- driver
-int solve_problem(Context& ctx, const scw_problem& p, Solution& s, int n_waves,
-                  const scw_plane_wave* waves) {
-  const double t_start = now_s();
+// Steps of a solve up to the eigendecompositions: validation, mode table,
+// band coefficients and property blocks on the device (kept there for the
+// device eigensolver, copied to `layers` for the host one), incident
+// coefficients. `ps` keeps what the later steps need.
+int solve_begin(Context& ctx, const scw_problem& p, Solution& s, int n_waves,
+                const scw_plane_wave* waves, PendingSolve& ps) {
+  ps.t_start = now_s();
   if (n_waves < 0 || (n_waves > 0 && !waves) || n_waves > 4096)
     return fail(SCW_EINVAL, "illumination count must be 0..4096 with a non-null list");
   if (p.nx < 1 || p.ny < 1 || p.nz < 1 || !p.n)
@@ -946,7 +1000,6 @@ int solve_problem(Context& ctx, const scw_problem& p, Solution& s, int n_waves,
   if ((long long)p.U * p.V > 8192) return fail(SCW_EINVAL, "U*V above 8192");
   const Lapack& lp = lapack();
   if (!lp.ok) return fail(SCW_ELAPACK, "LAPACK unavailable: " + lp.error);
-  const Lin lin{lp};
 
   s.U = p.U;
   s.V = p.V;
@@ -991,14 +1044,15 @@ int solve_problem(Context& ctx, const scw_problem& p, Solution& s, int n_waves,
 
   SCW_HIP(hipSetDevice(ctx.device));
   hipStream_t st = ctx.setup_stream;
-  hipEvent_t ev0, ev1;
-  SCW_HIP(hipEventCreate(&ev0));
-  SCW_HIP(hipEventCreate(&ev1));
+  SCW_HIP(hipEventCreate(&ps.ev0));
+  SCW_HIP(hipEventCreate(&ps.ev1));
+  hipEvent_t ev0 = ps.ev0, ev1 = ps.ev1;
 
   // ---- device: band coefficients of n^2 and 1/n^2 (Eqs. 11-12)
   const int nbu = 2 * U - 1, nbv = 2 * V - 1;
   const size_t nvox = (size_t)p.nx * p.ny * p.nz;
-  DevBuf d_n, d_row, d_phi, d_psi, d_u, d_v, d_sx, d_sy;
+  DevBuf d_n, d_row, d_phi;
+  DevBuf &d_psi = ps.d_psi, &d_u = ps.d_u, &d_v = ps.d_v, &d_sx = ps.d_sx, &d_sy = ps.d_sy;
   int rc;
   if ((rc = d_n.reserve(nvox * 16))) return rc;
   if ((rc = d_row.reserve((size_t)2 * L * p.ny * nbu * 16))) return rc;
@@ -1018,13 +1072,15 @@ int solve_problem(Context& ctx, const scw_problem& p, Solution& s, int n_waves,
 
   // ---- device: property blocks A, C per layer chunk, copied to the host (or,
   // for the device eigensolver, every layer kept on the device)
-  std::vector<LayerHost> layers(L);
+  std::vector<LayerHost>& layers = ps.layers;
+  layers.assign(L, LayerHost{});
   const size_t blk = (size_t)n2 * n2;
   const bool dev_eig = p.eig == SCW_EIG_DEVICE;
   const int chunk = dev_eig ? L
                             : (int)std::max<size_t>(
                                   1, std::min<size_t>(L, (size_t)(1u << 30) / (blk * 32)));
-  DevBuf d_A, d_C;
+  ps.dev_eig = dev_eig;
+  DevBuf &d_A = ps.d_A, &d_C = ps.d_C;
   if ((rc = d_A.reserve(blk * 16 * chunk)) || (rc = d_C.reserve(blk * 16 * chunk))) return rc;
   float asm_ms = 0;
   for (int l0 = 0; l0 < L; l0 += chunk) {
@@ -1101,14 +1157,29 @@ int solve_problem(Context& ctx, const scw_problem& p, Solution& s, int n_waves,
     for (int m = 0; m < M; ++m)
       pin[2 * M + m] = -(s.sx[m] * pin[m] + s.sy[m] * pin[M + m]) / s.sz_top[m];
   }
+  return SCW_OK;
+}
 
+// Steps after the eigendecompositions' device part: host eigendecompositions
+// (SCW_EIG_HOST), LU of the eigenvector blocks for the host stable route,
+// growth exponent, boundary solve, synthesis matrices and device uploads.
+int solve_finish(Context& ctx, const scw_problem& p, Solution& s, PendingSolve& ps) {
+  const Lapack& lp = lapack();
+  const Lin lin{lp};
+  const int M = s.M, n2 = 2 * M, L = s.L, U = s.U, V = s.V;
+  const int nbu = 2 * U - 1, nbv = 2 * V - 1;
+  const size_t blk = (size_t)n2 * n2;
+  const bool dev_eig = ps.dev_eig;
+  std::vector<LayerHost>& layers = ps.layers;
+  DevBuf &d_psi = ps.d_psi, &d_u = ps.d_u, &d_v = ps.d_v, &d_sx = ps.d_sx, &d_sy = ps.d_sy;
+  hipStream_t st = ctx.setup_stream;
+  int rc;
   // ---- eigendecompositions (Sec. 3.2, Sec. 4.2): on the host, one layer per
   // worker, or every layer at once by the device eigensolver
   const double t_eig = now_s();
   const bool stable = p.route == SCW_ROUTE_STABLE;
-  if (dev_eig && (rc = device_layer_eig(ctx, s, d_A, d_C, layers))) return rc;
-  d_A.release();
-  d_C.release();
+  ps.d_A.release();
+  ps.d_C.release();
   rc = parallel_for(L, ctx.host_threads, [&](int l) -> int {
     if (!dev_eig) {
       int r = layer_eig(lin, s, layers[l]);
@@ -1124,7 +1195,7 @@ int solve_problem(Context& ctx, const scw_problem& p, Solution& s, int n_waves,
     return 0;
   });
   if (rc) return rc;
-  s.info.eig_seconds = now_s() - t_eig;
+  s.info.eig_seconds = (now_s() - t_eig) + ps.device_eig_seconds;
   double gmin_rel = 1e300, growth = 0;
   s.gamma.resize((size_t)L * n2);
   for (int l = 0; l < L; ++l) {
@@ -1235,10 +1306,71 @@ int solve_problem(Context& ctx, const scw_problem& p, Solution& s, int n_waves,
   SCW_HIP(hipMemcpyAsync(s.d_ext.p, ext.data(), ext.size() * 16, hipMemcpyHostToDevice, st));
   SCW_HIP(hipMemcpyAsync(s.d_ksz.p, ksz.data(), ksz.size() * 16, hipMemcpyHostToDevice, st));
   SCW_HIP(hipStreamSynchronize(st));
-  (void)hipEventDestroy(ev0);
-  (void)hipEventDestroy(ev1);
   s.device = ctx.device;
-  s.info.setup_seconds = now_s() - t_start;
+  s.info.setup_seconds = now_s() - ps.t_start;
+  return SCW_OK;
+}
+
+int solve_problem(Context& ctx, const scw_problem& p, Solution& s, int n_waves,
+                  const scw_plane_wave* waves) {
+  PendingSolve ps;
+  int rc = solve_begin(ctx, p, s, n_waves, waves, ps);
+  if (rc) return rc;
+  if (ps.dev_eig) {
+    PendingSolve* one[1] = {&ps};
+    Solution* sol[1] = {&s};
+    if ((rc = device_eig_group(ctx, sol, one, 1))) return rc;
+  }
+  return solve_finish(ctx, p, s, ps);
+}
+
+int solve_problems(Context& ctx, const scw_problem* probs, int n, Solution** sols) {
+  // in rounds of problems whose device eigendecompositions share launches:
+  // problems of one round with the same matrix order form one batch
+  const size_t kRoundBytes = (size_t)24 << 30;  // device A, C and eigensolver workspace
+  int i0 = 0;
+  while (i0 < n) {
+    std::vector<std::unique_ptr<PendingSolve>> ps;
+    size_t bytes = 0;
+    int i1 = i0;
+    while (i1 < n) {
+      const size_t nn = 4 * (size_t)probs[i1].U * probs[i1].V * probs[i1].U * probs[i1].V;
+      const size_t need = nn * 16 * 6 * (size_t)std::max(1, probs[i1].nz);
+      if (i1 > i0 && bytes + need > kRoundBytes) break;
+      bytes += need;
+      ++i1;
+    }
+    for (int i = i0; i < i1; ++i) ps.emplace_back(new PendingSolve());
+    int rc;
+    for (int i = i0; i < i1; ++i)
+      if ((rc = solve_begin(ctx, probs[i], *sols[i], 0, nullptr, *ps[i - i0]))) {
+        set_error(rc, "problem " + std::to_string(i) + ": " + scw_last_error());
+        return rc;
+      }
+    // device eigendecompositions: one batch per matrix order
+    std::vector<char> done(i1 - i0, 0);
+    for (int i = i0; i < i1; ++i) {
+      if (done[i - i0] || !ps[i - i0]->dev_eig) continue;
+      std::vector<PendingSolve*> grp;
+      std::vector<Solution*> gs;
+      for (int j = i; j < i1; ++j)
+        if (!done[j - i0] && ps[j - i0]->dev_eig && sols[j]->M == sols[i]->M) {
+          grp.push_back(ps[j - i0].get());
+          gs.push_back(sols[j]);
+          done[j - i0] = 1;
+        }
+      if ((rc = device_eig_group(ctx, gs.data(), grp.data(), (int)grp.size()))) {
+        set_error(rc, "problems from " + std::to_string(i) + ": " + scw_last_error());
+        return rc;
+      }
+    }
+    for (int i = i0; i < i1; ++i)
+      if ((rc = solve_finish(ctx, probs[i], *sols[i], *ps[i - i0]))) {
+        set_error(rc, "problem " + std::to_string(i) + ": " + scw_last_error());
+        return rc;
+      }
+    i0 = i1;
+  }
   return SCW_OK;
 }
 

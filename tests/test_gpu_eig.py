@@ -230,3 +230,35 @@ def test_device_eigensolver_rejects_oversized_problem(ctx):
     with pytest.raises(P.ScwError) as e:
         ctx.solve(prob, eig="device")
     assert e.value.code == -1
+
+
+def test_solve_batch_matches_single_solves(ctx):
+    """scw_solve_batch: seven problems of three truncations (their device
+    eigendecompositions share one launch per truncation), one with the host
+    eigensolver, against the same problems solved one by one on the host
+    route, field by field, and one of them against the oracle."""
+    torch = _torch()
+    rng = np.random.default_rng(31)
+    probs = []
+    for i, (U, V, nz) in enumerate([(5, 3, 3), (3, 3, 2), (5, 3, 4), (5, 5, 2), (3, 3, 3),
+                                     (5, 3, 2), (5, 5, 3)]):
+        n = 1.3 + 0.3 * rng.random((nz, 6, 8)) + 0.04j * rng.random((nz, 6, 8))
+        probs.append(W.Problem(n=n.astype(complex), px=0.31, py=0.27, pz=0.19, lam=1.0, U=U,
+                               V=V, n_top=1.0, n_bot=1.45 + 0.01j,
+                               plane_wave=W.PlaneWave(1, 0, 0.8, 0.3j)))
+    sols = ctx.solve_batch(probs)
+    for i, (pr, sol) in enumerate(zip(probs, sols)):
+        grid = W.Grid(fx=16, fy=12, fz=2 * pr.nz + 2, z_begin=-0.1, z_end=pr.thickness + 0.1)
+        got = sol.synthesize(grid, "fp64").cpu().numpy()
+        ref = ctx.solve(pr)
+        want = ref.synthesize(grid, "fp64").cpu().numpy()
+        torch.cuda.synchronize()
+        err = rel_l2(got, want)
+        print("batch problem %d (U=%d V=%d L=%d): rel-L2 vs single host solve %.2e"
+              % (i, pr.U, pr.V, pr.nz, err))
+        assert err <= 1e-10
+        if i == 0:
+            _, _, oracle = cwt.simulate(pr, grid)
+            assert rel_l2(got, oracle) <= 1e-10
+        ref.free()
+        sol.free()
