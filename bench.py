@@ -532,36 +532,42 @@ def surrogate_flops_per_patch():
     return lift + 4 * layer + head
 
 
-def surrogate_bytes_per_patch():
-    """Activation traffic one inference cannot avoid (FP32 activations of 32 x
-    32 x 32 per patch): the lift reads its 16 input channels and writes h; each
-    Fourier layer reads h and writes the next h (its spectra can stay on
-    chip); the head reads h and writes 15 x 15 x 3 complex64 outputs."""
+def surrogate_bytes_per_patch(elem=4):
+    """Activation traffic one inference cannot avoid (activations of 32 x 32 x
+    32 per patch, elem bytes each: 4 for FP32 storage, 2 for bf16): the lift
+    reads its 16 FP32 input channels and writes h; each Fourier layer reads h
+    and writes the next h (its spectra can stay on chip); the head reads h and
+    writes 15 x 15 x 3 complex64 outputs."""
     n, w, cin, hk = 32, 32, 16, 15
-    act = w * n * n * 4
+    act = w * n * n * elem
     return cin * n * n * 4 + act + 4 * (2 * act) + act + hk * hk * 3 * 8
 
 
 def cwt_equal_accuracy(ctx, patches, targets, err_goal):
     """Plain CWT on the surrogate's patches at truncation U = 1, 3, 5, ...:
     rel-L2 of its transmitted coefficients (zero outside its band) against the
-    15 x 15 reference, and its patches/s. Returns the first U whose error is at
-    most err_goal, with the sweep."""
+    15 x 15 reference, and its patches/s on its fastest route (the patches
+    solved together by scw_solve_batch: device eigensolver, device
+    elimination). Returns the first U whose error is at most err_goal, with
+    the sweep."""
     import workloads as W
     sweep = []
     for U in range(1, 16, 2):
         got = np.zeros(targets.shape, np.complex128)
         lo = 7 - U // 2
-        t0 = time.perf_counter()
-        for i, n in enumerate(patches):
+        probs = []
+        for n in patches:
             prob = W.surrogate_problem(n)
-            prob = W.Problem(n=prob.n, px=prob.px, py=prob.py, pz=prob.pz, lam=prob.lam, U=U,
-                             V=U, n_top=prob.n_top, n_bot=prob.n_bot,
-                             plane_wave=prob.plane_wave)
-            sol = ctx.solve(prob)
+            probs.append(W.Problem(n=prob.n, px=prob.px, py=prob.py, pz=prob.pz, lam=prob.lam,
+                                   U=U, V=U, n_top=prob.n_top, n_bot=prob.n_bot,
+                                   plane_wave=prob.plane_wave))
+        t0 = time.perf_counter()
+        sols = ctx.solve_batch(probs, route="stable_device", eig="device")
+        for i, sol in enumerate(sols):
             got[i, :, lo:lo + U, lo:lo + U] = sol.exterior()[2].reshape(3, U, U)
-            sol.free()
         rate = len(patches) / (time.perf_counter() - t0)
+        for sol in sols:
+            sol.free()
         err = float(np.linalg.norm(got - targets) / np.linalg.norm(targets))
         sweep.append({"U": U, "rel_l2": err, "patches_per_s": rate})
         if err <= err_goal:
@@ -569,11 +575,17 @@ def cwt_equal_accuracy(ctx, patches, targets, err_goal):
     return {"U": None, "sweep": sweep}
 
 
+SUR_WEIGHTS = os.path.join(ROOT, "paper_2404_07293_amd", "data", "surrogate_weights.npz")
+
+
 def surrogate_leg(ctx, torch, dev, stream, args):
-    """Train the spectral-convolution surrogate on CWT-generated pairs, then
-    time inference at batch 4096 and compare with plain CWT."""
+    """The spectral-convolution surrogate: the trained network when its
+    weights file is present (else a short training on the committed pairs),
+    validation rel-L2 on 128 held-out CWT pairs, inference at batch 4096 in
+    both product arithmetics, checked inference, and plain CWT at equal
+    accuracy."""
     import workloads as W
-    from paper_2404_07293_amd.surrogate import Surrogate, cwt_targets
+    from paper_2404_07293_amd.surrogate import Surrogate
     d = np.load(SUR_DATA, allow_pickle=False)
     seeds, targets = d["seeds"], d["targets"]
     n_val = 128
@@ -584,21 +596,31 @@ def surrogate_leg(ctx, torch, dev, stream, args):
     t_all = torch.as_tensor(targets).to(dev)
     n_tr = len(seeds) - n_val
     xtr, ttr, xva, tva = x_all[:n_tr], t_all[:n_tr], x_all[n_tr:], t_all[n_tr:]
-    rng = np.random.Generator(np.random.PCG64(3))
-    bs, epochs, lr0 = args.sur_batch, args.sur_epochs, args.sur_lr
-    steps = epochs * (n_tr // bs)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    k = 0
-    for ep in range(epochs):
-        perm = torch.as_tensor(rng.permutation(n_tr), device=dev)
-        for i in range(n_tr // bs):
-            idx = perm[i * bs:(i + 1) * bs]
-            lr = 0.5 * lr0 * (1 + np.cos(np.pi * k / steps))   # cosine decay
-            sur.train_step(xtr[idx].contiguous(), ttr[idx].contiguous(), lr=lr, want_loss=False)
-            k += 1
-    torch.cuda.synchronize()
-    t_train = time.perf_counter() - t0
+    trained = None
+    if args.sur_weights and os.path.exists(args.sur_weights):
+        w = np.load(args.sur_weights, allow_pickle=False)
+        sur.set_params(w["params"])
+        trained = {k: (w[k].item() if w[k].ndim == 0 else None) for k in w.files if k != "params"}
+        train_pairs, steps, t_train = int(w["seed_count"]), int(w["steps"]), float(
+            w["train_seconds"])
+    else:
+        rng = np.random.Generator(np.random.PCG64(3))
+        bs, epochs, lr0 = args.sur_batch, args.sur_epochs, args.sur_lr
+        steps = epochs * (n_tr // bs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        k = 0
+        for ep in range(epochs):
+            perm = torch.as_tensor(rng.permutation(n_tr), device=dev)
+            for i in range(n_tr // bs):
+                idx = perm[i * bs:(i + 1) * bs]
+                lr = 0.5 * lr0 * (1 + np.cos(np.pi * k / steps))   # cosine decay
+                sur.train_step(xtr[idx].contiguous(), ttr[idx].contiguous(), lr=lr,
+                               want_loss=False)
+                k += 1
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t0
+        train_pairs = n_tr
 
     def err_on(x, t):
         out = sur.forward(x.contiguous())
@@ -606,73 +628,75 @@ def surrogate_leg(ctx, torch, dev, stream, args):
         o, w = out.cpu().numpy(), t.cpu().numpy()
         return float(np.linalg.norm(o - w) / np.linalg.norm(w))
 
-    train_err, val_err = err_on(xtr[:512], ttr[:512]), err_on(xva, tva)
+    val_err = err_on(xva, tva)
     # inference throughput at batch 4096 (inputs encoded and resident)
     reps = (4096 + len(seeds) - 1) // len(seeds)
     xb = x_all.repeat(reps, 1, 1, 1)[:4096].contiguous()
     out = torch.empty((4096, 3, 15, 15), dtype=torch.complex64, device=dev)
-    for _ in range(2):
-        sur.forward(xb, out=out)
-    torch.cuda.synchronize()
     s0 = torch.cuda.Event(enable_timing=True)
     s1 = torch.cuda.Event(enable_timing=True)
-    n_inf = max(3, args.steps // 5)
-    s0.record(stream)
-    for _ in range(n_inf):
-        sur.forward(xb, out=out)
-    s1.record(stream)
-    torch.cuda.synchronize()
-    ms_inf = s0.elapsed_time(s1) / n_inf
-    # the same trained parameters with the other arithmetic of the products
+    n_inf = max(5, args.steps // 5)
+
+    def time_inference():
+        for _ in range(3):
+            sur.forward(xb, out=out)
+        torch.cuda.synchronize()
+        s0.record(stream)
+        for _ in range(n_inf):
+            sur.forward(xb, out=out)
+        s1.record(stream)
+        torch.cuda.synchronize()
+        return s0.elapsed_time(s1) / n_inf
+
+    ms_inf = time_inference()
+    # the same parameters with the other arithmetic of the products
     sur.set_compute(not args.sur_bf16)
     other_err = err_on(xva, tva)
-    for _ in range(2):
-        sur.forward(xb, out=out)
-    torch.cuda.synchronize()
-    s0.record(stream)
-    for _ in range(n_inf):
-        sur.forward(xb, out=out)
-    s1.record(stream)
-    torch.cuda.synchronize()
-    ms_other = s0.elapsed_time(s1) / n_inf
+    ms_other = time_inference()
     sur.set_compute(bool(args.sur_bf16))
-    # plain CWT on a few validation patches (host FP64 setup + synthesis of p_trn)
-    t1 = time.perf_counter()
-    ncwt = 8
-    cwt_targets(ctx, patches[n_tr:n_tr + ncwt])
-    cwt_rate = ncwt / (time.perf_counter() - t1)
     # plain CWT at equal accuracy: the smallest truncation whose transmitted
     # coefficients are as close to the 15 x 15 reference as the surrogate's
-    equal = cwt_equal_accuracy(ctx, patches[n_tr:n_tr + 8], targets[n_tr:n_tr + 8], val_err)
+    nq = args.sur_cwt_patches
+    equal = cwt_equal_accuracy(ctx, patches[n_tr:n_tr + nq], targets[n_tr:n_tr + nq], val_err)
+    full = (equal["sweep"][-1] if equal["sweep"] and equal["sweep"][-1]["U"] == 15 else None)
     # checked inference with the CWT fallback on 64 validation patches
     t2 = time.perf_counter()
-    _, fell, chk = sur.infer_checked(patches[n_tr:n_tr + 64], n_check=8, seed=5, tol=1e-2)
+    _, fell, chk = sur.infer_checked(patches[n_tr:n_tr + 64], n_check=32, seed=5, tol=1e-2)
     t_checked = time.perf_counter() - t2
     rate = 4096 / (ms_inf * 1e-3)
-    log("surrogate: train %.1f s (%d steps), rel-L2 train %.3e val %.3e; %.0f patches/s "
-        "vs CWT %.2f patches/s; checked batch rel-L2 %.3e fallback %s" % (
-            t_train, steps, train_err, val_err, rate, cwt_rate, chk, fell))
     mode, other = ("bf16", "fp32") if args.sur_bf16 else ("fp32", "bf16")
-    log("surrogate %s products: val rel-L2 %.3e, %.2f ms per 4096; %s products with the same "
-        "parameters: val rel-L2 %.3e, %.2f ms" % (mode, val_err, ms_inf, other, other_err,
-                                                   ms_other))
-    rec = {"products": mode, "train_pairs": n_tr, "val_pairs": n_val, "train_steps": steps,
-           "train_seconds": t_train, "rel_l2_train": train_err, "rel_l2_val": val_err,
+    log("surrogate (%s, %d training pairs): val rel-L2 %.3e; %.2f ms per 4096 = %.0f patches/s; "
+        "%s products: val rel-L2 %.3e, %.2f ms" % (
+            "trained weights" if trained else "short training", train_pairs, val_err, ms_inf,
+            rate, other, other_err, ms_other))
+    if equal.get("U"):
+        log("plain CWT reaches rel-L2 %.3e at U = %d: %.2f patches/s (batched device solve); "
+            "surrogate gain at equal accuracy %.0fx" % (
+                equal["rel_l2"], equal["U"], equal["patches_per_s"],
+                rate / equal["patches_per_s"]))
+    log("checked inference, 64 patches, 32 solved by CWT: rel-L2 %.3e, fallback %s, %.1f s" % (
+        chk, fell, t_checked))
+    bpp = surrogate_bytes_per_patch(2 if args.sur_bf16 else 4)
+    rec = {"products": mode, "storage": "bf16" if args.sur_bf16 else "fp32",
+           "weights": os.path.relpath(args.sur_weights, ROOT) if trained else None,
+           "train_pairs": train_pairs, "val_pairs": n_val, "train_steps": steps,
+           "train_seconds": t_train, "training": trained, "rel_l2_val": val_err,
            "infer_batch": 4096, "infer_ms": ms_inf, "patches_per_s": rate,
-           "cwt_patches_per_s": cwt_rate, "speedup_vs_cwt": rate / cwt_rate,
            "roofline": {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK / 1e9,
-                        "achieved": surrogate_bytes_per_patch() * rate / 1e9,
-                        "frac": surrogate_bytes_per_patch() * rate / HBM_PEAK,
-                        "algorithmic_bytes_per_patch": surrogate_bytes_per_patch(),
+                        "achieved": bpp * rate / 1e9, "frac": bpp * rate / HBM_PEAK,
+                        "algorithmic_bytes_per_patch": bpp,
                         "direct_dft_flops_per_patch": surrogate_flops_per_patch(),
                         "direct_dft_tflops": surrogate_flops_per_patch() * rate / 1e12},
-           "checked_batch": 64, "check_rel_l2": chk, "fallback_fired": fell,
+           "checked_batch": 64, "n_check": 32, "check_rel_l2": chk, "fallback_fired": fell,
            "checked_seconds": t_checked, "cwt_equal_accuracy": equal,
+           "cwt_patches_per_s_full_band": full["patches_per_s"] if full else None,
            "other_products": {"products": other, "rel_l2_val": other_err, "infer_ms": ms_other,
                               "patches_per_s": 4096 / (ms_other * 1e-3)},
            "speedup_vs_cwt_equal_accuracy": (rate / equal["patches_per_s"]
-                                             if equal and equal.get("patches_per_s") else None),
-           "note": "fallback threshold 1e-2 rel-L2 on 8 CWT-solved patches of the batch"}
+                                             if equal.get("U") else None),
+           "note": "CWT rates: patches solved together by scw_solve_batch (device eigensolver, "
+                   "device elimination), setup included; fallback threshold 1e-2 rel-L2 on 32 "
+                   "CWT-solved patches of the batch"}
     sur.free()
     return rec
 
@@ -691,8 +715,13 @@ def main(argv=None):
     ap.add_argument("--sur-epochs", type=int, default=400)
     ap.add_argument("--sur-batch", type=int, default=32)
     ap.add_argument("--sur-lr", type=float, default=2e-3)
-    ap.add_argument("--sur-bf16", type=int, default=0,
-                    help="surrogate matrix products in bf16 on the matrix cores (1) or FP32 (0)")
+    ap.add_argument("--sur-bf16", type=int, default=1,
+                    help="surrogate matrix products in bf16 on the matrix cores with bf16 "
+                         "storage (1, deployed) or FP32 (0)")
+    ap.add_argument("--sur-weights", default=SUR_WEIGHTS,
+                    help="trained surrogate weights (train_surrogate.py); '' trains briefly")
+    ap.add_argument("--sur-cwt-patches", type=int, default=32,
+                    help="validation patches solved by plain CWT for the equal-accuracy sweep")
     ap.add_argument("--batched", type=int, default=1,
                     help="also time the batched spectral sweep (4096 jobs, one launch)")
     ap.add_argument("--large", type=int, default=1,

@@ -489,7 +489,11 @@ int scw_sur_set_params(scw_sur* sur, const float* host);  /* also resets Adam st
 /* Arithmetic of the network's matrix products: bf16 = 0 (default) computes
  * them in FP32 on the vector units; bf16 = 1 rounds both operands of every
  * product to bf16 and runs it on the matrix cores with FP32 accumulation
- * (activations, parameters, Adam state and the elementwise steps stay FP32). */
+ * (parameters, Adam state and the elementwise steps stay FP32). In that mode
+ * inference (scw_sur_forward, scw_sur_infer_checked) also stores the
+ * activations and spectra between its kernels in bf16: each is used only as
+ * a rounded operand, so the outputs are those of the FP32-storage kernels up
+ * to the order of the FP32 sums; training keeps FP32 storage. */
 int scw_sur_set_compute(scw_sur* sur, int bf16);
 int scw_sur_encode(scw_sur* sur, const void* n_dev, int batch, void* x_dev, void* stream);
 int scw_sur_forward(scw_sur* sur, const void* x_dev, int batch, void* out_dev, void* stream);
@@ -501,8 +505,9 @@ int scw_sur_loss_grad(scw_sur* sur, const void* x_dev, const void* target_dev, i
 int scw_sur_train_step(scw_sur* sur, const void* x_dev, const void* target_dev, int batch,
                        float lr, double* loss, void* stream);
 /* Surrogate inference of host patches (complex128 [B][8][32][32]) with a CWT
- * check on n_check seeded patches solved by scw_solve. When their rel-L2
- * exceeds tol, every patch is solved by CWT instead and *fell_back = 1.
+ * check on n_check seeded patches, solved together by scw_solve_batch (device
+ * eigensolver, SCW_ROUTE_STABLE_DEVICE). When their rel-L2 exceeds tol,
+ * every patch is solved by CWT the same way instead and *fell_back = 1.
  * out_host receives complex128 [B][3][15][15]. Synchronous. */
 int scw_sur_infer_checked(scw_ctx* ctx, scw_sur* sur, const double* n_host, int batch,
                           int n_check, unsigned long long seed, double tol, double* out_host,

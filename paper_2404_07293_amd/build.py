@@ -27,6 +27,7 @@ SOURCES = [
     "kernels_surrogate.hip",
     "noalloc.hip",
     "kernels_eig.hip",
+    "kernels_surrogate_bf16.hip",
     "eig.cpp",
 ]
 

@@ -1,0 +1,652 @@
+// Inference of the spectral-convolution surrogate in its matrix-core mode,
+// with every activation and spectrum stored in bf16.
+//
+// In this mode both operands of every matrix product are rounded to bf16
+// (nearest even) and the sums stay FP32. Each stored tensor is used only as
+// an operand of such products: the activations h (forward transform and
+// pointwise map of the next layer, the head), the spectra H (mixing) and the
+// mixed spectra G (inverse transform). Storing them already rounded therefore
+// gives the same operands, bit for bit, at half the memory traffic of FP32.
+// The products run on v_mfma_f32_32x32x16_bf16. Only the order of the FP32
+// sums differs from the vector-unit kernels that the training path uses.
+//
+// Storage: h[b][c][y][x] (bf16); spectra and mixed spectra as packed complex
+// bf16 (one 32-bit word: real part in the low half), H[m][b][c] mode-major
+// and G[b][m][o]. The layer modes are ky in [-8, 8] (17 rows of the table) x
+// kx in [0, 8]; the head's are ky, kx in [-7, 7]; m = ky * KX + kx.
+//
+// MFMA lane layout (one wave, 32 x 32 x 16): lane l holds A[l % 32][8 (l / 32)
+// + 0..7] and B[8 (l / 32) + 0..7][l % 32]; accumulator r of lane l is
+// D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32]. Within a K step the eight values
+// of a lane may stand for any eight indices of the contraction, provided the A
+// and B lanes of the same half agree; the kernels use that freedom to read
+// packed complex values and to spread LDS accesses over the banks.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "scw_internal.h"
+
+namespace scw {
+namespace {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned short bf_t;
+
+struct cf {
+  float x, y;
+};
+
+constexpr int N = 32, C = 32;          // image side, channels
+constexpr int LKY = 17, LKX = 9;       // a layer's modes
+constexpr int LNM = LKY * LKX;         // 153
+constexpr int HK = 15, HNM = HK * HK;  // the head's modes
+
+// Rounding to bf16, nearest even: the hardware conversion (v_cvt_pk_bf16_f32
+// on gfx950), two values per instruction; pk packs (lo, hi) into one word.
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ unsigned pk(float a, float b) {
+  const bf16x2 v = {(__bf16)a, (__bf16)b};
+  return __builtin_bit_cast(unsigned, v);
+}
+__device__ __forceinline__ float lo(unsigned w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float hi(unsigned w) { return __uint_as_float(w & 0xFFFF0000u); }
+__device__ __forceinline__ float rb(float x) { return (float)(__bf16)x; }
+
+__device__ __forceinline__ floatx16 mma(u32x4 a, u32x4 b, floatx16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
+                                                 __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+
+// GELU(z) = z (1 + erf(z / sqrt 2)) / 2 with erf from Abramowitz and Stegun
+// 7.1.26 (absolute error at most 1.5e-7), as in the FP32 kernels.
+__device__ __forceinline__ float gelu(float z) {
+  const float x = fabsf(z) * 0.70710678118654752f;
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, x, 1.f));
+  float q = fmaf(1.061405429f, t, -1.453152027f);
+  q = fmaf(q, t, 1.421413741f);
+  q = fmaf(q, t, -0.284496736f);
+  q = fmaf(q, t, 0.254829592f);
+  const float pe = q * t * __expf(-x * x);
+  return 0.5f * z * (z >= 0.f ? 2.f - pe : pe);
+}
+
+// ---------------------------------------------------------------------------
+// Lift: h[b][o][p] = sum_c lw[c][o] x[b][c][p] + lb[o] (16 -> 32 channels),
+// operands rounded, the sum in the order of the FP32 kernel, then stored
+// rounded. One patch per block, 4 pixels per thread.
+__global__ void __launch_bounds__(256) lift_bf16(const float* __restrict__ x,
+                                                 const float* __restrict__ lw,
+                                                 const float* __restrict__ lb,
+                                                 bf_t* __restrict__ h) {
+  constexpr int CI = 16;
+  __shared__ float lws[CI * C], lbs[C];
+  const int t = threadIdx.x, b = blockIdx.x;
+  for (int i = t; i < CI * C; i += 256) lws[i] = rb(lw[i]);
+  if (t < C) lbs[t] = lb[t];
+  float xr[CI][4];
+  const float* xb = x + (long long)b * CI * N * N;
+#pragma unroll
+  for (int c = 0; c < CI; ++c) {
+    const float4 v = reinterpret_cast<const float4*>(xb + c * N * N)[t];
+    xr[c][0] = rb(v.x);
+    xr[c][1] = rb(v.y);
+    xr[c][2] = rb(v.z);
+    xr[c][3] = rb(v.w);
+  }
+  __syncthreads();
+  bf_t* hb = h + (long long)b * C * N * N + 4 * t;
+#pragma unroll 4
+  for (int o = 0; o < C; ++o) {
+    float a[4] = {lbs[o], lbs[o], lbs[o], lbs[o]};
+#pragma unroll
+    for (int c = 0; c < CI; ++c) {
+      const float w = lws[c * C + o];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) a[j] = fmaf(w, xr[c][j], a[j]);
+    }
+    *reinterpret_cast<uint2*>(hb + o * N * N) = make_uint2(pk(a[0], a[1]), pk(a[2], a[3]));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Truncated forward DFT, 4 waves per block, the block's patches taken in turn
+// (patch blockIdx.x, then every gridDim.x-th):
+//   H[ky][kx][c] = sum_y fy[ky][y] sum_x h[c][y][x] fx[x][kx]
+// Row transform, per channel: D[y][n] = sum_x h[c][y][x] T[x][n] with the
+// twiddle columns n < KX the real parts of fx[.][n], KX <= n < 2 KX the
+// imaginary parts (the input is real). A lane's K values are the 16
+// consecutive pixels x = 16 (l / 32) .. + 15 of its row, read straight from
+// memory; once a channel's registers are used they are refilled with the same
+// rows of the next patch, so its loads are in flight during the rest of this
+// one. The rounded results go to LDS as planes [n][c][y], the four 16-byte
+// chunks of y of channel c placed at chunk ^ ((c / 2) % 4), so that 8 lanes
+// reading one chunk each of 8 channels hit distinct banks.
+// Column transform, per kx: D[ky][c] over K = 64 = (part, y): the real output
+// takes (Re fy, -Im fy) against (Re, Im) of the row-transformed values, the
+// imaginary output (Im fy, Re fy). Rows ky >= KY of the twiddle operand are
+// zero. Output: packed complex, mode-major out[m][b][c]: 32 channels of one
+// (mode, patch), one 128-byte line per half-wave.
+constexpr int FW_PS = C * N + 8;  // bf16 per plane: 32 channels x 32 y + pad
+__device__ __forceinline__ int fw_at(int c, int chunk) {
+  return c * N + 8 * (chunk ^ ((c >> 1) & 3));
+}
+template <int KY, int KX>
+__global__ void __launch_bounds__(256) fwd_bf16(const bf_t* __restrict__ h,
+                                                const cf* __restrict__ fy,
+                                                const cf* __restrict__ fx,
+                                                unsigned* __restrict__ out, int B) {
+  static_assert(2 * KX <= 32 && KY <= 32, "mode band exceeds one tile");
+  __shared__ __attribute__((aligned(16))) bf_t hxl[2 * KX * FW_PS];
+  const int t = threadIdx.x, w = __builtin_amdgcn_readfirstlane(t >> 6), l = t & 63,
+            li = l & 31, hh = l >> 5;
+  int b = blockIdx.x;
+  if (b >= B) return;  // uniform over the block, before any barrier
+  // this wave's 8 channels: 32 rows of 32 pixels each, 2 x 16 bytes per lane
+  const long long row_off = (long long)8 * w * N * N + li * N + 16 * hh;
+  auto rows = [&](int bb, int c) {
+    return reinterpret_cast<const u32x4*>(h + (long long)bb * C * N * N + row_off + c * N * N);
+  };
+  u32x4 a[8][2];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    a[c][0] = rows(b, c)[0];
+    a[c][1] = rows(b, c)[1];
+  }
+  // row-transform twiddles: lane (n = li, hh), K step s, slot j: x = 16 hh + 8 s + j
+  u32x4 tb[2];
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    unsigned v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      float e[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int xx = 16 * hh + 8 * s + 2 * q + u;
+        e[u] = li < KX ? fx[xx * KX + li].x : li < 2 * KX ? fx[xx * KX + li - KX].y : 0.f;
+      }
+      v[q] = pk(e[0], e[1]);
+    }
+    tb[s] = u32x4{v[0], v[1], v[2], v[3]};
+  }
+  // column-transform twiddles: lane (ky = li, hh), K step s: part s / 2,
+  // y = 16 (s % 2) + 8 hh + j
+  u32x4 are[4], aim[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    unsigned vr[4], vi[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      float er[2], ei[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int yy = 16 * (s & 1) + 8 * hh + 2 * q + u;
+        const cf f = li < KY ? fy[li * N + yy] : cf{0.f, 0.f};
+        er[u] = s < 2 ? f.x : -f.y;
+        ei[u] = s < 2 ? f.y : f.x;
+      }
+      vr[q] = pk(er[0], er[1]);
+      vi[q] = pk(ei[0], ei[1]);
+    }
+    are[s] = u32x4{vr[0], vr[1], vr[2], vr[3]};
+    aim[s] = u32x4{vi[0], vi[1], vi[2], vi[3]};
+  }
+  for (;;) {
+    const int bn = b + gridDim.x;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      floatx16 d = {0};
+      d = mma(a[c][0], tb[0], d);
+      d = mma(a[c][1], tb[1], d);
+      if (bn < B) {
+        a[c][0] = rows(bn, c)[0];
+        a[c][1] = rows(bn, c)[1];
+      }
+      if (li < 2 * KX) {
+        bf_t* dst = hxl + li * FW_PS + 4 * hh;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          *reinterpret_cast<uint2*>(dst + fw_at(8 * w + c, q)) =
+              make_uint2(pk(d[4 * q], d[4 * q + 1]), pk(d[4 * q + 2], d[4 * q + 3]));
+      }
+    }
+    __syncthreads();
+    for (int kx = w; kx < KX; kx += 4) {
+      floatx16 dr = {0}, di = {0};
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int plane = kx + (s >> 1) * KX;
+        const u32x4 bv = *reinterpret_cast<const u32x4*>(hxl + plane * FW_PS +
+                                                         fw_at(li, 2 * (s & 1) + hh));
+        dr = mma(are[s], bv, dr);
+        di = mma(aim[s], bv, di);
+      }
+      unsigned* ob = out + (long long)b * C + li;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int ky = 8 * (r / 4) + 4 * hh + (r % 4);
+        if (ky < KY) ob[(long long)(ky * KX + kx) * B * C] = pk(dr[r], di[r]);
+      }
+    }
+    if (bn >= B) break;
+    __syncthreads();  // the planes are read before the next patch overwrites them
+    b = bn;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Mixing weights as B operands: Wb[k][m][part][s][hh][o] holds 8 bf16 for the
+// lane (o, hh) of K step s: for j = 0..7, channel i = 8 s + 4 hh + j / 2 and
+// (j even) Re W, -Im W for the real output (part 0), Im W, Re W for the
+// imaginary output (part 1), W = W_k[i][o][m].
+__global__ void mix_weights_bf16(const cf* __restrict__ W, long long layer_stride, int nmode,
+                                 u32x4* __restrict__ Wb) {
+  const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long per = (long long)nmode * 2 * 4 * 2 * C;
+  if (q >= per) return;
+  const int k = blockIdx.y;
+  const int o = (int)(q % C), hh = (int)((q / C) % 2), s = (int)((q / (2 * C)) % 4);
+  const int part = (int)((q / (8 * C)) % 2), m = (int)(q / (16 * C));
+  unsigned v[4];
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    const int i = 8 * s + 4 * hh + p;
+    const cf wv = W[k * layer_stride + ((long long)i * C + o) * nmode + m];
+    v[p] = part == 0 ? pk(wv.x, -wv.y) : pk(wv.y, wv.x);
+  }
+  Wb[(long long)k * per + q] = u32x4{v[0], v[1], v[2], v[3]};
+}
+
+// Per-mode mixing: G[b][m][o] = sum_i H[m][b][i] W[m][i][o] (complex, 32 x
+// 32) as D[b][o] over K = 64: a lane's 8 values are 4 consecutive channels as
+// (Re, Im) pairs, read as one 16-byte word of the packed spectra. One wave per
+// mode keeps its 8 weight words and walks MIX_TT tiles of 32 patches.
+constexpr int MIX_TT = 4;
+__global__ void __launch_bounds__(256) mix_bf16(const unsigned* __restrict__ H,
+                                                const u32x4* __restrict__ Wb, int nmode, int B,
+                                                unsigned* __restrict__ G) {
+  const int t = threadIdx.x, w = __builtin_amdgcn_readfirstlane(t >> 6), l = t & 63,
+            li = l & 31, hh = l >> 5;
+  const int m = blockIdx.x * 4 + w;
+  if (m >= nmode) return;  // no barrier in this kernel
+  const u32x4* wm = Wb + (long long)m * 16 * C + hh * C + li;
+  u32x4 wr[4], wi[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    wr[s] = wm[s * 2 * C];
+    wi[s] = wm[8 * C + s * 2 * C];
+  }
+  const int b_first = blockIdx.y * MIX_TT * 32;
+  for (int tt = 0; tt < MIX_TT; ++tt) {
+    const int b0 = b_first + 32 * tt;
+    if (b0 >= B) break;
+    u32x4 av[4];
+    const int ba = b0 + li;
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+      av[s] = ba < B ? *reinterpret_cast<const u32x4*>(H + ((long long)m * B + ba) * C + 8 * s +
+                                                       4 * hh)
+                     : u32x4{0u, 0u, 0u, 0u};
+    floatx16 dr = {0}, di = {0};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      dr = mma(av[s], wr[s], dr);
+      di = mma(av[s], wi[s], di);
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int bb = b0 + 8 * (r / 4) + 4 * hh + (r % 4);
+      if (bb < B) G[((long long)bb * nmode + m) * C + li] = pk(dr[r], di[r]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Inverse half of a Fourier layer, 4 waves per block, the block's patches
+// taken in turn:
+//   gy[o][y][kx] = sum_ky iy[y][ky] G[ky][kx][o]                  (column)
+//   z[o][y][x]   = sum_i pw[i][o] h[i][y][x]
+//                + sum_kx (Re gy Re ix[kx][x] - Im gy Im ix[kx][x]) + pb[o]
+//   h'[o][y][x]  = GELU(z) (or z after the last layer: GELU false), stored rounded.
+// Column transform on the matrix cores, per kx: D[y][o] over the 17 (up to
+// 24) complex ky as (Re, Im) pairs: (Re iy, -Im iy) for the real part, (Im iy,
+// Re iy) for the imaginary part, against G staged in LDS as [kx][o][ky]. Wave
+// w keeps rows y = 8 w .. 8 w + 7 of it (accumulators 4 w .. 4 w + 3) as
+// packed (Re, Im) words per kx: lane (o, hh) holds rows 8 w + 4 hh + j.
+// Output tile per row y: D[x][o] over K = 64: the pointwise part (K step s,
+// slot j of half hh: channel 16 s + 2 j + hh, so that the two halves read
+// neighbouring channel rows of the staged pixels, 64 bytes apart, on distinct
+// LDS banks) and the row transform (slots 2 kx, 2 kx + 1 = Re, Im; kx < 9).
+// The gy operand of a row lives in one half of the wave: a row pair (8 w + j,
+// 8 w + 4 + j) trades the missing words across the halves with five shuffles.
+// Each wave stages its own pixel rows, so only wave-level ordering is needed
+// there; the next row pair's pixels, and the next patch's G and first row
+// pair, are loaded while the current rows are computed.
+constexpr int IV_GS = 28;  // packed words per (kx, o) record of staged G: 17 ky + pad
+constexpr int IV_GQ = (LNM * C / 4 + 255) / 256;  // 16-byte chunks of G per thread
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+template <bool GELU>
+__global__ void __launch_bounds__(256) inv_bf16(const unsigned* __restrict__ G,
+                                                const bf_t* __restrict__ h,
+                                                const cf* __restrict__ iy,
+                                                const cf* __restrict__ ix,
+                                                const float* __restrict__ pw,
+                                                const float* __restrict__ pb,
+                                                bf_t* __restrict__ h_out, int B) {
+  __shared__ __attribute__((aligned(16))) unsigned gs[LKX * C * IV_GS];
+  __shared__ __attribute__((aligned(16))) bf_t hst[4][2][C * N];  // [wave][row][i][x]
+  const int t = threadIdx.x, w = __builtin_amdgcn_readfirstlane(t >> 6), l = t & 63,
+            li = l & 31, hh = l >> 5;
+  int b = blockIdx.x;
+  if (b >= B) return;  // uniform over the block, before any barrier
+  auto load_rows = [&](int bb, int j, u32x4* pf) {
+    const bf_t* hb = h + (long long)bb * C * N * N;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int q = 64 * u + l, row = q >> 7, i = (q & 127) >> 2, xq = q & 3;
+      const int y = 8 * w + 4 * row + j;
+      pf[u] = *reinterpret_cast<const u32x4*>(hb + (i * N + y) * N + 8 * xq);
+    }
+  };
+  auto load_g = [&](int bb, u32x4* gp) {
+    const u32x4* gb = reinterpret_cast<const u32x4*>(G + (long long)bb * LNM * C);
+#pragma unroll
+    for (int u = 0; u < IV_GQ; ++u) {
+      const int q = t + 256 * u;
+      if (q < LNM * C / 4) gp[u] = gb[q];
+    }
+  };
+  u32x4 gpf[IV_GQ], pf[4];
+  load_g(b, gpf);
+  load_rows(b, 0, pf);
+  // ky 17 .. 23 of every staged record stay zero
+  for (int q = t; q < LKX * C * 7; q += 256) gs[(q / 7) * IV_GS + LKY + q % 7] = 0u;
+  // column-transform twiddles: lane (y = li, hh), K step s: ky = 8 s + 4 hh + p
+  u32x4 are[3], aim[3];
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    unsigned vr[4], vi[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      const int ky = 8 * s + 4 * hh + p;
+      const cf f = ky < LKY ? iy[li * LKY + ky] : cf{0.f, 0.f};
+      vr[p] = pk(f.x, -f.y);
+      vi[p] = pk(f.y, f.x);
+    }
+    are[s] = u32x4{vr[0], vr[1], vr[2], vr[3]};
+    aim[s] = u32x4{vi[0], vi[1], vi[2], vi[3]};
+  }
+  // row-transform twiddles (A operand, lane (x = li, hh)): K step 0 holds kx
+  // 4 hh .. 4 hh + 3, step 1 kx 8 in the lower half; (Re ix, -Im ix) words
+  u32x4 ta0, ta1;
+  {
+    unsigned v[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      const cf f = ix[(4 * hh + p) * N + li];
+      v[p] = pk(f.x, -f.y);
+    }
+    ta0 = u32x4{v[0], v[1], v[2], v[3]};
+    const cf f8 = ix[8 * N + li];
+    ta1 = u32x4{hh == 0 ? pk(f8.x, -f8.y) : 0u, 0u, 0u, 0u};
+  }
+  // pointwise weights (B operand, lane (o = li, hh)): channel 16 s + 2 p + hh
+  u32x4 pwb[2];
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    unsigned v[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+      v[p] = pk(pw[(16 * s + 4 * p + hh) * C + li], pw[(16 * s + 4 * p + 2 + hh) * C + li]);
+    pwb[s] = u32x4{v[0], v[1], v[2], v[3]};
+  }
+  const float bias = pb[li];
+  bf_t* hs = &hst[w][0][0];
+  for (;;) {
+    // stage G[m][o] -> gs[kx][o][ky]
+#pragma unroll
+    for (int u = 0; u < IV_GQ; ++u) {
+      const int q = t + 256 * u;
+      if (q < LNM * C / 4) {
+        const int m = q >> 3, o0 = (q & 7) * 4, ky = m / LKX, kx = m % LKX;
+        unsigned* d = gs + (kx * C + o0) * IV_GS + ky;
+        d[0] = gpf[u][0];
+        d[IV_GS] = gpf[u][1];
+        d[2 * IV_GS] = gpf[u][2];
+        d[3 * IV_GS] = gpf[u][3];
+      }
+    }
+    __syncthreads();
+    // column transform; keep this wave's rows as gv[j][kx]
+    unsigned gv[4][LKX];
+#pragma unroll
+    for (int kx = 0; kx < LKX; ++kx) {
+      floatx16 dr = {0}, di = {0};
+#pragma unroll
+      for (int s = 0; s < 3; ++s) {
+        const u32x4 bv =
+            *reinterpret_cast<const u32x4*>(gs + (kx * C + li) * IV_GS + 8 * s + 4 * hh);
+        dr = mma(are[s], bv, dr);
+        di = mma(aim[s], bv, di);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (q == w) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) gv[j][kx] = pk(dr[4 * q + j], di[4 * q + j]);
+        }
+    }
+    __syncthreads();  // every wave is done with gs
+    const int bn = b + gridDim.x;
+    if (bn < B) load_g(bn, gpf);
+    bf_t* ob = h_out + (long long)b * C * N * N + li * N * N;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      // stage the pixels of rows 8 w + j and 8 w + 4 + j
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int q = 64 * u + l, row = q >> 7, i = (q & 127) >> 2, xq = q & 3;
+        *reinterpret_cast<u32x4*>(hs + row * C * N + i * N + 8 * xq) = pf[u];
+      }
+      wave_sync();
+      if (j + 1 < 4) load_rows(b, j + 1, pf);
+      else if (bn < B) load_rows(bn, 0, pf);
+      // trade gy words across the halves (lower half owns row 8 w + j, upper 8 w + 4 + j)
+      unsigned rv[5];
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+        rv[p] = (unsigned)__shfl_xor((int)(hh ? gv[j][p] : gv[j][4 + p]), 32);
+      rv[4] = (unsigned)__shfl_xor((int)gv[j][8], 32);
+#pragma unroll
+      for (int row = 0; row < 2; ++row) {
+        const int y = 8 * w + 4 * row + j;
+        // pointwise A operand: pixels x = li of channels 16 s + 2 p + hh (+ 2)
+        const bf_t* src = hs + row * C * N + li;
+        u32x4 pa[2];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+          unsigned v[4];
+#pragma unroll
+          for (int p = 0; p < 4; ++p)
+            v[p] = (unsigned)src[(16 * s + 4 * p + hh) * N] |
+                   ((unsigned)src[(16 * s + 4 * p + 2 + hh) * N] << 16);
+          pa[s] = u32x4{v[0], v[1], v[2], v[3]};
+        }
+        u32x4 g0, g1;
+        if (row == 0) {
+          g0 = hh ? u32x4{rv[0], rv[1], rv[2], rv[3]}
+                  : u32x4{gv[j][0], gv[j][1], gv[j][2], gv[j][3]};
+          g1 = u32x4{hh ? 0u : gv[j][8], 0u, 0u, 0u};
+        } else {
+          g0 = hh ? u32x4{gv[j][4], gv[j][5], gv[j][6], gv[j][7]}
+                  : u32x4{rv[0], rv[1], rv[2], rv[3]};
+          g1 = u32x4{hh ? 0u : rv[4], 0u, 0u, 0u};
+        }
+        floatx16 d = {0};
+        d = mma(pa[0], pwb[0], d);
+        d = mma(pa[1], pwb[1], d);
+        d = mma(ta0, g0, d);
+        d = mma(ta1, g1, d);
+        bf_t* orow = ob + y * N + 4 * hh;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          float z[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            z[e] = d[4 * q + e] + bias;
+            if (GELU) z[e] = gelu(z[e]);
+          }
+          *reinterpret_cast<uint2*>(orow + 8 * q) = make_uint2(pk(z[0], z[1]), pk(z[2], z[3]));
+        }
+      }
+      wave_sync();  // this row pair's pixels are read before the next are staged
+    }
+    if (bn >= B) break;
+    b = bn;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The head's mixing: out[b][o][m] = sum_i F[m][b][i] W[i][o][m] for the 3
+// outputs, FP32 on the vector units (operands rounded as read or staged).
+// Block: 32 modes x 32 patches. Thread (patch bi = t % 32, group g = t / 32)
+// takes modes g, g + 8, g + 16, g + 24 of the block in turn: a half-wave reads
+// 32 consecutive (mode, patch) records of 32 packed channels, 4 KB in one
+// run, and the mode's weights, staged in LDS, are the same for all its lanes.
+// The outputs are gathered in LDS and written as runs of 32 modes.
+constexpr int HM_B = 32;
+__global__ void __launch_bounds__(256) head_mix_bf16(const unsigned* __restrict__ F,
+                                                     const cf* __restrict__ Wt, int B,
+                                                     cf* __restrict__ out) {
+  __shared__ cf wl[32][C * 3 + 1];         // [mode][i * 3 + o], rows 97 apart
+  __shared__ cf ol[HM_B][3][33];           // [patch][o][mode]
+  const int t = threadIdx.x, bi = t & 31, g = t >> 5;
+  const int m0 = blockIdx.x * 32, b0 = blockIdx.y * HM_B, bb = b0 + bi;
+  for (int q = t; q < 32 * C * 3; q += 256) {
+    const int mm = q & 31, io = q >> 5;  // io = i * 3 + o
+    const cf v = m0 + mm < HNM ? Wt[(long long)io * HNM + m0 + mm] : cf{0.f, 0.f};
+    wl[mm][io] = cf{rb(v.x), rb(v.y)};
+  }
+  auto load = [&](int mm, u32x4* r) {
+    const int m = m0 + mm;
+    const u32x4* p = reinterpret_cast<const u32x4*>(F + ((long long)m * B + bb) * C);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) r[q] = (m < HNM && bb < B) ? p[q] : u32x4{0u, 0u, 0u, 0u};
+  };
+  u32x4 cur[8], nxt[8];
+  load(g, cur);
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int mm = g + 8 * k;
+    if (k < 3) load(mm + 8, nxt);
+    const cf* wm = wl[mm];
+    cf acc[3] = {{0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}};
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const float vr = lo(cur[q][e]), vi = hi(cur[q][e]);
+        const int i = 4 * q + e;
+#pragma unroll
+        for (int o = 0; o < 3; ++o) {
+          const cf c = wm[i * 3 + o];
+          acc[o].x = fmaf(vr, c.x, fmaf(-vi, c.y, acc[o].x));
+          acc[o].y = fmaf(vr, c.y, fmaf(vi, c.x, acc[o].y));
+        }
+      }
+    }
+#pragma unroll
+    for (int o = 0; o < 3; ++o) ol[bi][o][mm] = acc[o];
+    if (k < 3)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) cur[q] = nxt[q];
+  }
+  __syncthreads();
+  // write: 3 x 32 patches rows of 32 modes
+  for (int q = t; q < HM_B * 3 * 32; q += 256) {
+    const int mm = q & 31, o = (q >> 5) % 3, pb_ = q / 96;
+    if (b0 + pb_ < B && m0 + mm < HNM)
+      out[((long long)(b0 + pb_) * 3 + o) * HNM + m0 + mm] = ol[pb_][o][mm];
+  }
+}
+
+// Blocks that are resident at once for a kernel of 256 threads (the grid of
+// the kernels that take their patches in turn); at least 1.
+template <typename K>
+int resident_blocks(K kern) {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, 256, 0) != hipSuccess)
+    return 256;
+  return std::max(1, cus * per);
+}
+
+}  // namespace
+
+hipError_t sur_lift_bf16(const float* x, const float* lw, const float* lb, void* h, int B,
+                         hipStream_t s) {
+  lift_bf16<<<B, 256, 0, s>>>(x, lw, lb, reinterpret_cast<bf_t*>(h));
+  return hipGetLastError();
+}
+hipError_t sur_fwd_bf16(const void* h, const float* fy, const float* fx, void* H, int B,
+                        bool head, hipStream_t s) {
+  const bf_t* hp = reinterpret_cast<const bf_t*>(h);
+  const cf* y = reinterpret_cast<const cf*>(fy);
+  const cf* x = reinterpret_cast<const cf*>(fx);
+  unsigned* o = reinterpret_cast<unsigned*>(H);
+  auto go = [&](auto kern) {
+    static const int slots = resident_blocks(kern);
+    kern<<<std::min(B, slots), 256, 0, s>>>(hp, y, x, o, B);
+  };
+  if (head) go(fwd_bf16<HK, HK>);
+  else go(fwd_bf16<LKY, LKX>);
+  return hipGetLastError();
+}
+hipError_t sur_mix_weights_bf16(const float* W, long long layer_stride_floats, int layers,
+                                void* Wb, hipStream_t s) {
+  if (layer_stride_floats % 2 != 0) return hipErrorInvalidValue;
+  const long long per = (long long)LNM * 2 * 4 * 2 * C;
+  dim3 grid((unsigned)((per + 255) / 256), layers);
+  mix_weights_bf16<<<grid, 256, 0, s>>>(reinterpret_cast<const cf*>(W), layer_stride_floats / 2,
+                                        LNM, reinterpret_cast<u32x4*>(Wb));
+  return hipGetLastError();
+}
+size_t sur_mix_weights_bf16_bytes(int layers) { return (size_t)layers * LNM * 16 * C * 16; }
+hipError_t sur_mix_bf16(const void* H, const void* Wb_layer, int B, void* G, hipStream_t s) {
+  dim3 grid((LNM + 3) / 4, (B + MIX_TT * 32 - 1) / (MIX_TT * 32));
+  mix_bf16<<<grid, 256, 0, s>>>(reinterpret_cast<const unsigned*>(H),
+                                reinterpret_cast<const u32x4*>(Wb_layer), LNM, B,
+                                reinterpret_cast<unsigned*>(G));
+  return hipGetLastError();
+}
+hipError_t sur_inv_bf16(const void* G, const void* h, const float* iy, const float* ix,
+                        const float* pw, const float* pb, void* h_out, bool gelu_on, int B,
+                        hipStream_t s) {
+  auto go = [&](auto kern) {
+    static const int slots = resident_blocks(kern);
+    kern<<<std::min(B, slots), 256, 0, s>>>(
+        reinterpret_cast<const unsigned*>(G), reinterpret_cast<const bf_t*>(h),
+        reinterpret_cast<const cf*>(iy), reinterpret_cast<const cf*>(ix), pw, pb,
+        reinterpret_cast<bf_t*>(h_out), B);
+  };
+  if (gelu_on) go(inv_bf16<true>);
+  else go(inv_bf16<false>);
+  return hipGetLastError();
+}
+hipError_t sur_head_mix_bf16(const void* F, const float* W, int B, float* out, hipStream_t s) {
+  dim3 grid((HNM + 31) / 32, (B + HM_B - 1) / HM_B);
+  head_mix_bf16<<<grid, 256, 0, s>>>(reinterpret_cast<const unsigned*>(F),
+                                     reinterpret_cast<const cf*>(W), B,
+                                     reinterpret_cast<cf*>(out));
+  return hipGetLastError();
+}
+
+}  // namespace scw

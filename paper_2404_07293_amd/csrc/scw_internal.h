@@ -458,6 +458,24 @@ hipError_t sur_lift(const float* x, const float* lw, const float* lb, float* h, 
 hipError_t sur_fused_dft_inv(const float* G, const float* h, const float* iy, const float* ix,
                              const float* pw, const float* pb, float* z_out, float* h_out,
                              bool gelu, int B, bool bf16, hipStream_t s);
+// Matrix-core inference with bf16 storage (kernels_surrogate_bf16.hip):
+// activations h bf16 [b][c][32][32]; spectra packed complex bf16 words,
+// mode-major H[m][b][c] (the layer's 153 modes, or the head's 225 with head)
+// and G[b][m][o]; Wb the mixing weights as matrix-core operands,
+// sur_mix_weights_bf16_bytes(layers) bytes built from the parameters by
+// sur_mix_weights_bf16; out the head's FP32 complex [b][3][225].
+hipError_t sur_lift_bf16(const float* x, const float* lw, const float* lb, void* h, int B,
+                         hipStream_t s);
+hipError_t sur_fwd_bf16(const void* h, const float* fy, const float* fx, void* H, int B,
+                        bool head, hipStream_t s);
+hipError_t sur_mix_weights_bf16(const float* W, long long layer_stride_floats, int layers,
+                                void* Wb, hipStream_t s);
+size_t sur_mix_weights_bf16_bytes(int layers);
+hipError_t sur_mix_bf16(const void* H, const void* Wb_layer, int B, void* G, hipStream_t s);
+hipError_t sur_inv_bf16(const void* G, const void* h, const float* iy, const float* ix,
+                        const float* pw, const float* pb, void* h_out, bool gelu_on, int B,
+                        hipStream_t s);
+hipError_t sur_head_mix_bf16(const void* F, const float* W, int B, float* out, hipStream_t s);
 hipError_t launch_idft_mfma(const MfmaArgs& a, int precision, hipStream_t s);
 // `ev`, when non-null, holds kNumStages + 1 events recorded around the stages.
 hipError_t launch_synthesis_fp64(const SynthArgs& a, hipStream_t s, hipEvent_t* ev);

@@ -21,6 +21,7 @@
 #include <memory>
 #include <new>
 #include <random>
+#include <utility>
 #include <vector>
 
 #include "scw_internal.h"
@@ -59,6 +60,7 @@ struct SurNet {
   long long o_fy, o_fx, o_iy, o_ix, o_hy, o_hx;
   DevBuf x, h[NL + 1], z[NL], Hk[NL], G, Wm, F, out, gout, gF, T1, gh, gh2, T2, gG, gH,
       tmp, sums, enc_in;
+  DevBuf Wb;  // mixing weights as bf16 matrix-core operands (inference)
 };
 
 namespace {
@@ -181,6 +183,33 @@ int forward(SurNet& n, const float* x, int B, hipStream_t s, bool keep) {
   return SCW_OK;
 }
 
+// Inference in the matrix-core mode with bf16 storage: the same network and
+// the same rounded operands as forward() with n.bf16, every activation and
+// spectrum kept in bf16 (h ping-pongs between the memory of h[0] and h[1]).
+int forward_bf16(SurNet& n, const float* x, int B, hipStream_t s) {
+  const Off o;
+  const float* P = n.params.as<float>();
+  SUR_HIP(sur_mix_weights_bf16(P + o.spec(0), SZ_LAYER, NL, n.Wb.p, s));
+  void* ha = n.h[0].p;
+  void* hb = n.h[1].p;
+  SUR_HIP(sur_lift_bf16(x, P + o.lw, P + o.lb, ha, B, s));
+  const size_t wl = sur_mix_weights_bf16_bytes(1);
+  for (int k = 0; k < NL; ++k) {
+    SUR_HIP(sur_fwd_bf16(ha, cx(n, n.o_fy), cx(n, n.o_fx), n.Hk[0].p, B, false, s));
+    SUR_HIP(sur_mix_bf16(n.Hk[0].p, static_cast<char*>(n.Wb.p) + k * wl, B, n.G.p, s));
+    SUR_HIP(sur_inv_bf16(n.G.p, ha, cx(n, n.o_iy), cx(n, n.o_ix), P + o.pw(k), P + o.pb(k), hb,
+                         k < NL - 1, B, s));
+    std::swap(ha, hb);
+  }
+  SUR_HIP(sur_fwd_bf16(ha, cx(n, n.o_hy), cx(n, n.o_hx), n.F.p, B, true, s));
+  SUR_HIP(sur_head_mix_bf16(n.F.p, P + o.head(), B, n.out.as<float>(), s));
+  return SCW_OK;
+}
+
+int infer(SurNet& n, const float* x, int B, hipStream_t s) {
+  return n.bf16 ? forward_bf16(n, x, B, s) : forward(n, x, B, s, false);
+}
+
 // Backward pass from gout (= dL/dout) into grads.
 int backward(SurNet& n, int B, hipStream_t s) {
   const Off o;
@@ -270,7 +299,8 @@ int sur_create(Context& ctx, int max_batch, unsigned long long seed, SurNet** ou
       (rc = alloc(n->T1, B * W * 32 * HN * 2)) || (rc = alloc(n->gh, act)) ||
       (rc = alloc(n->gh2, act)) || (rc = alloc(n->T2, B * W * 32 * KXN * 2)) ||
       (rc = alloc(n->gG, B * W * NM * 2)) || (rc = alloc(n->gH, B * W * NM * 2)) ||
-      (rc = alloc(n->tmp, B * W * W)) || (rc = alloc(n->sums, 16)))
+      (rc = alloc(n->tmp, B * W * W)) || (rc = alloc(n->sums, 16)) ||
+      (rc = n->Wb.reserve(sur_mix_weights_bf16_bytes(NL))))
     return rc;
   for (int k = 0; k <= NL; ++k)
     if ((rc = alloc(n->h[k], act))) return rc;
@@ -330,7 +360,7 @@ int sur_encode(SurNet& n, const void* n_dev, int B, void* x_dev, hipStream_t s) 
 int sur_forward(SurNet& n, const void* x_dev, int B, void* out_dev, hipStream_t s) {
   int rc = check_batch(n, B);
   if (rc) return rc;
-  if ((rc = forward(n, reinterpret_cast<const float*>(x_dev), B, s, false))) return rc;
+  if ((rc = infer(n, reinterpret_cast<const float*>(x_dev), B, s))) return rc;
   SCW_HIP(hipMemcpyAsync(out_dev, n.out.p, (size_t)B * OUT * HM * 8, hipMemcpyDeviceToDevice, s));
   return SCW_OK;
 }
@@ -368,9 +398,9 @@ int sur_train_step(SurNet& n, const void* x_dev, const void* tgt_dev, int B, flo
 }
 
 // Inference with a sampled CWT check: the surrogate runs on the whole batch;
-// n_check seeded patches are also solved by plain CWT (scw_solve); if the
-// rel-L2 of the surrogate on them exceeds tol, every patch of the batch is
-// solved by CWT and those results are returned instead.
+// n_check seeded patches are also solved by plain CWT (scw_solve_batch); if
+// the rel-L2 of the surrogate on them exceeds tol, every patch of the batch
+// is solved by CWT and those results are returned instead.
 int sur_infer_checked(Context& ctx, SurNet& n, const double* n_host, int B, int n_check,
                       unsigned long long seed, double tol, double* out_host, int* fell_back,
                       double* check_err) {
@@ -382,7 +412,7 @@ int sur_infer_checked(Context& ctx, SurNet& n, const double* n_host, int B, int 
   for (size_t i = 0; i < f.size(); ++i) f[i] = (float)n_host[i];
   SCW_HIP(hipMemcpy(n.enc_in.p, f.data(), f.size() * 4, hipMemcpyHostToDevice));
   SCW_HIP(sur_encode(n.enc_in.as<float>(), n.x.as<float>(), B, nullptr));
-  if ((rc = forward(n, n.x.as<float>(), B, nullptr, false))) return rc;
+  if ((rc = infer(n, n.x.as<float>(), B, nullptr))) return rc;
   std::vector<float> o((size_t)B * OUT * HM * 2);
   SCW_HIP(hipMemcpy(o.data(), n.out.p, o.size() * 4, hipMemcpyDeviceToHost));
   for (size_t i = 0; i < o.size(); ++i) out_host[i] = o[i];
@@ -391,45 +421,59 @@ int sur_infer_checked(Context& ctx, SurNet& n, const double* n_host, int B, int 
   std::mt19937_64 rng(seed);
   std::shuffle(idx.begin(), idx.end(), rng);
   idx.resize(std::min(n_check, B));
-  auto solve_patch = [&](int b, std::vector<double>& ptrn) -> int {
-    scw_problem pr{};
-    pr.nx = pr.ny = 32;
-    pr.nz = 8;
-    pr.px = pr.py = pr.pz = 0.25;
-    pr.n = n_host + (size_t)b * nvox * 2;
-    pr.lambda = 1.0;
-    pr.n_top = 1.0;
-    pr.n_bot_re = 1.0;
-    pr.U = pr.V = HN;
-    pr.pw_ex[0] = 1.0;
-    pr.route = SCW_ROUTE_STABLE;
-    scw_solution* sol = nullptr;
-    int r = scw_solve(reinterpret_cast<scw_ctx*>(&ctx), &pr, &sol);
-    if (r) return r;
-    ptrn.assign((size_t)OUT * HM * 2, 0.0);
-    r = scw_solution_exterior(sol, nullptr, nullptr, ptrn.data());
-    scw_solution_free(sol);
-    return r;
-  };
-  double num = 0, den = 0;
-  std::vector<double> ref;
-  for (int b : idx) {
-    if ((rc = solve_patch(b, ref))) return rc;
-    for (size_t i = 0; i < ref.size(); ++i) {
-      const double d = out_host[(size_t)b * ref.size() + i] - ref[i];
-      num += d * d;
-      den += ref[i] * ref[i];
+  // plain CWT of a set of patches: scw_solve_batch with the device eigensolver
+  // and the device elimination, in groups of at most 128 problems
+  const size_t per = (size_t)OUT * HM * 2;
+  auto solve_set = [&](const std::vector<int>& set, std::vector<double>& res) -> int {
+    res.assign(set.size() * per, 0.0);
+    constexpr int group = 128;
+    for (size_t g0 = 0; g0 < set.size(); g0 += group) {
+      const int cnt = (int)std::min<size_t>(group, set.size() - g0);
+      std::vector<scw_problem> probs(cnt);
+      for (int i = 0; i < cnt; ++i) {
+        scw_problem& pr = probs[i];
+        pr = scw_problem{};
+        pr.nx = pr.ny = 32;
+        pr.nz = 8;
+        pr.px = pr.py = pr.pz = 0.25;
+        pr.n = n_host + (size_t)set[g0 + i] * nvox * 2;
+        pr.lambda = 1.0;
+        pr.n_top = 1.0;
+        pr.n_bot_re = 1.0;
+        pr.U = pr.V = HN;
+        pr.pw_ex[0] = 1.0;
+        pr.route = SCW_ROUTE_STABLE_DEVICE;
+        pr.eig = SCW_EIG_DEVICE;
+      }
+      std::vector<scw_solution*> sols(cnt, nullptr);
+      int r = scw_solve_batch(reinterpret_cast<scw_ctx*>(&ctx), probs.data(), cnt, sols.data());
+      for (int i = 0; i < cnt && r == SCW_OK; ++i)
+        r = scw_solution_exterior(sols[i], nullptr, nullptr, res.data() + (g0 + i) * per);
+      for (scw_solution* so : sols)
+        if (so) scw_solution_free(so);
+      if (r) return r;
     }
-  }
+    return SCW_OK;
+  };
+  std::vector<double> ref;
+  if ((rc = solve_set(idx, ref))) return rc;
+  double num = 0, den = 0;
+  for (size_t k = 0; k < idx.size(); ++k)
+    for (size_t i = 0; i < per; ++i) {
+      const double r = ref[k * per + i];
+      const double d = out_host[(size_t)idx[k] * per + i] - r;
+      num += d * d;
+      den += r * r;
+    }
   const double err = den > 0 ? std::sqrt(num / den) : 0.0;
   if (check_err) *check_err = err;
   const bool fb = !idx.empty() && err > tol;
   if (fell_back) *fell_back = fb ? 1 : 0;
   if (fb) {
-    for (int b = 0; b < B; ++b) {
-      if ((rc = solve_patch(b, ref))) return rc;
-      std::copy(ref.begin(), ref.end(), out_host + (size_t)b * ref.size());
-    }
+    std::vector<int> all(B);
+    for (int b = 0; b < B; ++b) all[b] = b;
+    if ((rc = solve_set(all, ref))) return rc;
+    std::copy(ref.begin(), ref.end(), out_host);
   }
   return SCW_OK;
 }

@@ -107,11 +107,21 @@ class Surrogate:
         return out, bool(fb.value), err.value
 
 
-def cwt_targets(ctx, patches):
-    """Transmitted coefficients [B][3][15][15] of each patch by plain CWT
-    (``scw_solve``), for training data and checks."""
+def cwt_targets(ctx, patches, eig="host", chunk=256, route="stable"):
+    """Transmitted coefficients [B][3][15][15] of each patch by plain CWT, for
+    training data and checks: one ``scw_solve`` per patch with the host
+    eigensolver, or, with eig="device", ``scw_solve_batch`` over chunks of
+    patches whose eigendecompositions share the device eigensolver's launches
+    (route "stable_device" also keeps the boundary systems on the device)."""
     import workloads as W
     out = np.empty((len(patches),) + OUT_SHAPE, np.complex128)
+    if eig == "device":
+        for c0 in range(0, len(patches), chunk):
+            probs = [W.surrogate_problem(n) for n in patches[c0:c0 + chunk]]
+            for i, sol in enumerate(ctx.solve_batch(probs, route=route, eig="device")):
+                out[c0 + i] = sol.exterior()[2].reshape(OUT_SHAPE)
+                sol.free()
+        return out
     for i, n in enumerate(patches):
         prob = W.surrogate_problem(n)
         sol = ctx.solve(prob)

@@ -1,11 +1,14 @@
 """GPU parity of the HIP library against the FP64 oracle, through the C ABI.
 
-Tolerances (relative L2 over all voxels and components):
-  FP64 synthesis  <= 1e-10  (both sides are FP64; the setups differ in
-                             formulation: 2M product eigenproblem and stable
-                             elimination vs. 4M geev and the full system)
-  FP32 synthesis  <= 1e-4   (complex64 storage of P and outputs; expected error
-                             ~1e-6, sum lengths up to 2M terms)
+Tolerances, checked by `field_check` on every synthesised field:
+  FP64 synthesis  rel-L2 <= 1e-10 (both sides are FP64; the setups differ in
+                  formulation: 2M product eigenproblem and stable elimination
+                  vs. 4M geev and the full system)
+  FP32 and the split forms: the bounds of SMALL_BOUNDS below, a few times the
+                  errors these problems measure, far under the 1e-4 target:
+                  total rel-L2, each component's error against the field's
+                  norm (a component can vanish, e.g. E_y under TM incidence),
+                  and the largest element error against the largest element.
 """
 import numpy as np
 import pytest
@@ -17,7 +20,36 @@ from paper_2404_07293_amd._native import ScwError
 pytestmark = pytest.mark.gpu
 
 FP64_TOL = 1e-10
-FP32_TOL = 1e-4
+FP32_TOL = 5e-6
+
+# (total rel-L2, per component against the field's norm, largest element) for
+# the small problems of this file. FP32: complex64 storage of the coefficients
+# and of P (unit roundoff 6e-8) and sums of up to 2M + U + V terms give about
+# 1e-7 to 1e-6; the split forms add the lo * lo term and the rounding of lo
+# (2^-16 of the operands for bf16, 2^-22 for fp16) over the K <= 2V terms of
+# the transform.
+SMALL_BOUNDS = {
+    "fp64": (1e-10, 1e-10, 1e-10),
+    "fp32": (5e-6, 5e-6, 2e-5),
+    "bf16x3": (2e-5, 2e-5, 6e-5),
+    "fp16x3": (5e-6, 5e-6, 2e-5),
+}
+
+
+def field_check(precision, got, want, label=""):
+    """Assert the bounds of SMALL_BOUNDS; returns (total, per component,
+    element) and prints them."""
+    norm = np.linalg.norm(want)
+    total = float(np.linalg.norm(got - want) / norm)
+    per = [float(np.linalg.norm(got[c] - want[c]) / norm) for c in range(got.shape[0])]
+    elem = float(np.abs(got - want).max() / np.abs(want).max())
+    print("%s %s rel-L2 %.3e per component %s max-element %.3e" % (
+        label, precision, total, ["%.2e" % x for x in per], elem), flush=True)
+    bt, bc, be = SMALL_BOUNDS[precision]
+    assert total <= bt, (label, precision, total)
+    assert max(per) <= bc, (label, precision, per)
+    assert elem <= be, (label, precision, elem)
+    return total, per, elem
 
 
 def _torch():
@@ -61,9 +93,7 @@ def test_sphere_fp64_matches_oracle(ctx):
     _, _, want = cwt.simulate(prob, grid)
     _, got = run(ctx, prob, grid, "fp64")
     assert got.shape == want.shape
-    err = rel_l2(got, want)
-    print("sphere fp64 rel-L2 %.3e" % err)
-    assert err <= FP64_TOL
+    field_check("fp64", got, want, "sphere")
     for c in range(3):
         assert rel_l2(got[c], want[c]) <= 10 * FP64_TOL
 
@@ -72,9 +102,7 @@ def test_sphere_fp32_matches_oracle(ctx):
     prob, grid = W.sphere_config()
     _, _, want = cwt.simulate(prob, grid)
     _, got = run(ctx, prob, grid, "fp32")
-    err = rel_l2(got, want)
-    print("sphere fp32 rel-L2 %.3e" % err)
-    assert err <= FP32_TOL
+    field_check("fp32", got, want, "sphere")
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("fp32", FP32_TOL)])
@@ -84,9 +112,7 @@ def test_planes_above_inside_below_ragged_grid(ctx, precision, tol):
     grid = W.Grid(fx=13, fy=7, fz=11, z_begin=-0.4, z_end=T + 0.4)
     _, _, want = cwt.simulate(prob, grid)
     _, got = run(ctx, prob, grid, precision)
-    err = rel_l2(got, want)
-    print("ragged %s rel-L2 %.3e" % (precision, err))
-    assert err <= tol
+    field_check(precision, got, want, "ragged")
 
 
 def test_connection_route_matches_oracle(ctx):
@@ -127,9 +153,9 @@ def test_many_planes_per_layer(ctx):
     prob = ragged_problem(seed=5, nz=2)
     grid = W.Grid(fx=8, fy=8, fz=23, z_begin=0.0, z_end=prob.thickness)
     _, _, want = cwt.simulate(prob, grid)
-    for precision, tol in (("fp64", FP64_TOL), ("fp32", FP32_TOL)):
+    for precision in ("fp64", "fp32"):
         _, got = run(ctx, prob, grid, precision)
-        assert rel_l2(got, want) <= tol
+        field_check(precision, got, want, "23 planes")
 
 
 def test_single_frequency(ctx):
@@ -187,8 +213,8 @@ def test_error_codes(ctx):
 # term and the rounding of lo leave a relative error per product of about
 # 2^-16 (bf16) or 2^-22 (fp16) of the operand magnitudes. Over the K <= 2V
 # terms of one output and the spread of magnitudes in a field, the bounds are:
-BF16X3_TOL = 1e-4
-FP16X3_TOL = 1e-5
+BF16X3_TOL = SMALL_BOUNDS["bf16x3"][0]
+FP16X3_TOL = SMALL_BOUNDS["fp16x3"][0]
 
 
 @pytest.mark.parametrize("precision,tol", [("bf16x3", BF16X3_TOL), ("fp16x3", FP16X3_TOL),
@@ -199,11 +225,7 @@ def test_split_precision_matches_oracle(ctx, precision, tol):
                         W.Grid(fx=13, fy=7, fz=9, z_begin=-0.3, z_end=0.9))):
         _, _, want = cwt.simulate(prob, grid)
         _, got = run(ctx, prob, grid, precision)
-        err = rel_l2(got, want)
-        per = [rel_l2(got[c], want[c]) for c in range(3)]
-        print("%s rel-L2 %.3e per component %s" % (precision, err,
-                                                   ["%.2e" % x for x in per]))
-        assert err <= tol
+        field_check(precision, got, want, "split form")
 
 
 # every kernel configuration the FP32 and FP64 paths can take: the three
@@ -242,9 +264,7 @@ def test_kernel_configurations_match_oracle(ctx, precision, cfg):
             continue
         _, _, want = cwt.simulate(prob, grid)
         got = sol.synthesize(grid, precision).cpu().numpy()
-        err = rel_l2(got, want)
-        print("%s %s fy=%d rel-L2 %.3e" % (precision, cfg, grid.fy, err))
-        assert err <= tol
+        field_check(precision, got, want, "%s fy=%d" % (cfg, grid.fy))
 
 
 def test_unsupported_configurations_are_rejected(ctx):
@@ -283,7 +303,7 @@ def test_autotuner_keeps_a_correct_and_no_slower_configuration(ctx, precision):
     print(precision, rep)
     assert rep["n_candidates"] >= 2
     assert 0 < rep["best_ms"] <= rep["default_ms"]
-    assert rel_l2(out.cpu().numpy(), want) <= tol
+    field_check(precision, out.cpu().numpy(), want, "tuned")
     if precision == "bf16x3":
         assert rep["transform"] == "mfma"
     # a second solution of the same shape takes the tuned configuration and

@@ -100,6 +100,27 @@ def test_bf16_forward_matches_rounded_reference(ctx):
     assert rel(back, exact) <= 1e-5
 
 
+def test_bf16_forward_over_several_tiles(ctx):
+    """Matrix-core inference with bf16 storage on 37 patches: the mixing's
+    second tile of 32 patches and the head's second group are ragged. Every
+    patch meets the bound of the rounded reference on its own."""
+    torch = _torch()
+    sur, p, x, tgt, xd, td = _net_and_data(ctx, B=37, seed=9)
+    sur.set_compute(True)
+    got = sur.forward(xd).cpu().numpy()
+    torch.cuda.synchronize()
+    want = S.forward(p, x, bf16=True)
+    exact = S.forward(p, x)
+    errs = [rel(got[i], want[i]) for i in range(len(x))]
+    refs = [rel(want[i], exact[i]) for i in range(len(x))]
+    dists = [rel(got[i], exact[i]) for i in range(len(x))]
+    print("bf16 forward, 37 patches: max rel-L2 %.3e vs rounded reference (max reference "
+          "distance %.3e)" % (max(errs), max(refs)))
+    for i in range(len(x)):
+        assert errs[i] <= 1.5 * refs[i], i
+        assert dists[i] <= 2.5 * refs[i], i
+
+
 def test_bf16_training_reduces_loss(ctx, small_set):
     torch = _torch()
     from paper_2404_07293_amd.surrogate import Surrogate
