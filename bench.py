@@ -657,12 +657,15 @@ def surrogate_leg(ctx, torch, dev, stream, args):
     # plain CWT at equal accuracy: the smallest truncation whose transmitted
     # coefficients are as close to the 15 x 15 reference as the surrogate's
     nq = args.sur_cwt_patches
-    equal = cwt_equal_accuracy(ctx, patches[n_tr:n_tr + nq], targets[n_tr:n_tr + nq], val_err)
+    equal = (cwt_equal_accuracy(ctx, patches[n_tr:n_tr + nq], targets[n_tr:n_tr + nq], val_err)
+             if nq > 0 else {"U": None, "sweep": []})
     full = (equal["sweep"][-1] if equal["sweep"] and equal["sweep"][-1]["U"] == 15 else None)
     # checked inference with the CWT fallback on 64 validation patches
-    t2 = time.perf_counter()
-    _, fell, chk = sur.infer_checked(patches[n_tr:n_tr + 64], n_check=32, seed=5, tol=1e-2)
-    t_checked = time.perf_counter() - t2
+    fell, chk, t_checked = None, None, None
+    if args.sur_check:
+        t2 = time.perf_counter()
+        _, fell, chk = sur.infer_checked(patches[n_tr:n_tr + 64], n_check=32, seed=5, tol=1e-2)
+        t_checked = time.perf_counter() - t2
     rate = 4096 / (ms_inf * 1e-3)
     mode, other = ("bf16", "fp32") if args.sur_bf16 else ("fp32", "bf16")
     log("surrogate (%s, %d training pairs): val rel-L2 %.3e; %.2f ms per 4096 = %.0f patches/s; "
@@ -674,8 +677,9 @@ def surrogate_leg(ctx, torch, dev, stream, args):
             "surrogate gain at equal accuracy %.0fx" % (
                 equal["rel_l2"], equal["U"], equal["patches_per_s"],
                 rate / equal["patches_per_s"]))
-    log("checked inference, 64 patches, 32 solved by CWT: rel-L2 %.3e, fallback %s, %.1f s" % (
-        chk, fell, t_checked))
+    if args.sur_check:
+        log("checked inference, 64 patches, 32 solved by CWT: rel-L2 %.3e, fallback %s, "
+            "%.1f s" % (chk, fell, t_checked))
     bpp = surrogate_bytes_per_patch(2 if args.sur_bf16 else 4)
     rec = {"products": mode, "storage": "bf16" if args.sur_bf16 else "fp32",
            "weights": os.path.relpath(args.sur_weights, ROOT) if trained else None,
@@ -721,7 +725,10 @@ def main(argv=None):
     ap.add_argument("--sur-weights", default=SUR_WEIGHTS,
                     help="trained surrogate weights (train_surrogate.py); '' trains briefly")
     ap.add_argument("--sur-cwt-patches", type=int, default=32,
-                    help="validation patches solved by plain CWT for the equal-accuracy sweep")
+                    help="validation patches solved by plain CWT for the equal-accuracy sweep "
+                         "(0 skips it)")
+    ap.add_argument("--sur-check", type=int, default=1,
+                    help="run the checked inference (32 CWT samples of 64 patches)")
     ap.add_argument("--batched", type=int, default=1,
                     help="also time the batched spectral sweep (4096 jobs, one launch)")
     ap.add_argument("--large", type=int, default=1,

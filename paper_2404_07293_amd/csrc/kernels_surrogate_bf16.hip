@@ -367,21 +367,6 @@ __global__ void __launch_bounds__(256) inv_bf16(const unsigned* __restrict__ G,
   load_rows(b, 0, pf);
   // ky 17 .. 23 of every staged record stay zero
   for (int q = t; q < LKX * C * 7; q += 256) gs[(q / 7) * IV_GS + LKY + q % 7] = 0u;
-  // column-transform twiddles: lane (y = li, hh), K step s: ky = 8 s + 4 hh + p
-  u32x4 are[3], aim[3];
-#pragma unroll
-  for (int s = 0; s < 3; ++s) {
-    unsigned vr[4], vi[4];
-#pragma unroll
-    for (int p = 0; p < 4; ++p) {
-      const int ky = 8 * s + 4 * hh + p;
-      const cf f = ky < LKY ? iy[li * LKY + ky] : cf{0.f, 0.f};
-      vr[p] = pk(f.x, -f.y);
-      vi[p] = pk(f.y, f.x);
-    }
-    are[s] = u32x4{vr[0], vr[1], vr[2], vr[3]};
-    aim[s] = u32x4{vi[0], vi[1], vi[2], vi[3]};
-  }
   // row-transform twiddles (A operand, lane (x = li, hh)): K step 0 holds kx
   // 4 hh .. 4 hh + 3, step 1 kx 8 in the lower half; (Re ix, -Im ix) words
   u32x4 ta0, ta1;
@@ -421,6 +406,22 @@ __global__ void __launch_bounds__(256) inv_bf16(const unsigned* __restrict__ G,
         d[2 * IV_GS] = gpf[u][2];
         d[3 * IV_GS] = gpf[u][3];
       }
+    }
+    // column-transform twiddles: lane (y = li, hh), K step s: ky = 8 s + 4 hh + p
+    // (rebuilt per patch from the cached table: they are not live in the rows)
+    u32x4 are[3], aim[3];
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+      unsigned vr[4], vi[4];
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        const int ky = 8 * s + 4 * hh + p;
+        const cf f = ky < LKY ? iy[li * LKY + ky] : cf{0.f, 0.f};
+        vr[p] = pk(f.x, -f.y);
+        vi[p] = pk(f.y, f.x);
+      }
+      are[s] = u32x4{vr[0], vr[1], vr[2], vr[3]};
+      aim[s] = u32x4{vi[0], vi[1], vi[2], vi[3]};
     }
     __syncthreads();
     // column transform; keep this wave's rows as gv[j][kx]

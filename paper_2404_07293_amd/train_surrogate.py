@@ -94,9 +94,10 @@ def train(a):
     sur = Surrogate(ctx, max_batch=max(a.batch, 512), seed=11)
     sur.set_compute(True)
     x_tr = torch.empty((n, 16, 32, 32), dtype=torch.float32, device=dev)
-    for c0 in range(0, n, 1024):
-        x_tr[c0:c0 + 1024] = sur.encode(np.stack([W.surrogate_patch(int(s))
-                                                  for s in seeds[c0:c0 + 1024]]))
+    step = sur.max_batch
+    for c0 in range(0, n, step):
+        x_tr[c0:c0 + step] = sur.encode(np.stack([W.surrogate_patch(int(s))
+                                                  for s in seeds[c0:c0 + step]]))
     t_tr = torch.as_tensor(targets).to(dev)
     d = np.load(VAL_DATA, allow_pickle=False)
     vseeds, vtargets = d["seeds"][-N_VAL:], d["targets"][-N_VAL:]
