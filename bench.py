@@ -89,6 +89,27 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
+def surrogate_source_hash():
+    h = hashlib.sha256()
+    for f in ("kernels_surrogate_bf16.hip", "surrogate.cpp"):
+        p = os.path.join(ROOT, "paper_2404_07293_amd", "csrc", f)
+        if os.path.exists(p):
+            h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_surrogate_traffic():
+    """HBM bytes of one bf16 inference at batch 4096 from the committed PMC
+    summary, if it was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic_surrogate_bf16_4096.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("source_hash") != surrogate_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_inference")
+
+
 def measured_traffic(kernel_stage, precision, workload):
     """HBM bytes per launch from the committed PMC summary, if it was taken on
     the current kernel sources."""
@@ -688,6 +709,10 @@ def surrogate_leg(ctx, torch, dev, stream, args):
            "infer_batch": 4096, "infer_ms": ms_inf, "patches_per_s": rate,
            "roofline": {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK / 1e9,
                         "achieved": bpp * rate / 1e9, "frac": bpp * rate / HBM_PEAK,
+                        "traffic": (measured_surrogate_traffic() if args.sur_bf16 else None),
+                        "measured_gbps": ((measured_surrogate_traffic() or 0) / (ms_inf * 1e-3)
+                                          / 1e9 if args.sur_bf16 and measured_surrogate_traffic()
+                                          else None),
                         "algorithmic_bytes_per_patch": bpp,
                         "direct_dft_flops_per_patch": surrogate_flops_per_patch(),
                         "direct_dft_tflops": surrogate_flops_per_patch() * rate / 1e12},
