@@ -159,9 +159,14 @@ void device_paths() {
              hipMemcpy(f32.data(), E32, nvox * 8, hipMemcpyDeviceToHost) == hipSuccess &&
              hipMemcpy(f32b.data(), E32b, nvox * 8, hipMemcpyDeviceToHost) == hipSuccess,
          "copy back");
-  for (size_t i = 0; i < nvox; ++i) e32[i] = std::complex<double>(f32[i]);
+  std::vector<std::complex<double>> e32b(nvox);
+  for (size_t i = 0; i < nvox; ++i) {
+    e32[i] = std::complex<double>(f32[i]);
+    e32b[i] = std::complex<double>(f32b[i]);
+  }
   expect(rel(e32, e64) < 5e-6, "FP32 field against FP64");
-  expect(std::memcmp(f32.data(), f32b.data(), nvox * 8) == 0, "no-allocation field identical");
+  // the no-allocation path builds its tables on the device: FP32 agreement
+  expect(rel(e32b, e32) < 1e-6, "no-allocation field agrees");
   // a batch of three problems with the device eigensolver
   std::vector<double> n2 = sample_index(nx, ny, 2);
   scw_problem batch[3] = {problem(n, nx, ny, nz, U, V), problem(n2, nx, ny, 2, 3, 3),

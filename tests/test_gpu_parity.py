@@ -20,7 +20,7 @@ from paper_2404_07293_amd._native import ScwError
 pytestmark = pytest.mark.gpu
 
 FP64_TOL = 1e-10
-FP32_TOL = 5e-6
+FP32_TOL = 1e-6
 
 # (total rel-L2, per component against the field's norm, largest element) for
 # the small problems of this file. FP32: complex64 storage of the coefficients
@@ -28,11 +28,13 @@ FP32_TOL = 5e-6
 # 1e-7 to 1e-6; the split forms add the lo * lo term and the rounding of lo
 # (2^-16 of the operands for bf16, 2^-22 for fp16) over the K <= 2V terms of
 # the transform.
+# Measured on these problems: FP32 at most 2.2e-7 total and 4.6e-7 largest
+# element; BF16x3 4.0e-6 and 1.1e-5; FP16x3 1.8e-7 and 4.4e-7; FP64 2e-14.
 SMALL_BOUNDS = {
     "fp64": (1e-10, 1e-10, 1e-10),
-    "fp32": (5e-6, 5e-6, 2e-5),
+    "fp32": (1e-6, 1e-6, 2e-6),
     "bf16x3": (2e-5, 2e-5, 6e-5),
-    "fp16x3": (5e-6, 5e-6, 2e-5),
+    "fp16x3": (1e-6, 1e-6, 2e-6),
 }
 
 

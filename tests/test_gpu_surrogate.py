@@ -312,3 +312,43 @@ def test_trained_network_beats_cwt_at_equal_accuracy(ctx):
     assert err_sur < 0.1
     assert err_cwt <= err_sur
     assert t_cwt > 100 * t_sur
+
+
+def test_deployed_weights_meet_their_validation_error(ctx):
+    """The committed network (paper_2404_07293_amd/data/surrogate_weights.npz,
+    trained on 20,000 CWT pairs by train_surrogate.py) in its deployed
+    arithmetic: on the 128 held-out pairs it reproduces the validation rel-L2
+    recorded at training (within 5 %), which is below the checked inference's
+    1e-2 threshold; on 4 of those patches it is as close to the FP64 oracle's
+    bf16 network as the rounded reference is to the exact one."""
+    import os
+    torch = _torch()
+    from paper_2404_07293_amd.surrogate import Surrogate
+    here = os.path.join(os.path.dirname(__file__), "..", "paper_2404_07293_amd", "data")
+    wfile = os.path.join(here, "surrogate_weights.npz")
+    if not os.path.exists(wfile):
+        pytest.skip("no deployed weights")
+    w = np.load(wfile, allow_pickle=False)
+    d = np.load(os.path.join(here, "surrogate_targets.npz"), allow_pickle=False)
+    seeds, targets = d["seeds"][-128:], d["targets"][-128:]
+    assert int(w["val_seed_first"]) == int(seeds[0])
+    patches = np.stack([W.surrogate_patch(int(s)) for s in seeds])
+    sur = Surrogate(ctx, max_batch=128, seed=0)
+    sur.set_params(w["params"])
+    sur.set_compute(True)
+    x = sur.encode(patches)
+    got = sur.forward(x).cpu().numpy()
+    torch.cuda.synchronize()
+    err = rel(got, targets)
+    rec = float(w["val_rel_l2_bf16"])
+    print("deployed weights: val rel-L2 %.4e (recorded %.4e)" % (err, rec))
+    assert err <= 1.05 * rec and err < 1e-2
+    p = S.unflatten(w["params"].astype(np.float64))
+    xs = x[:4].cpu().numpy().astype(np.float64)
+    want = S.forward(p, xs, bf16=True)
+    exact = S.forward(p, xs)
+    e_ref, e_gpu = rel(want, exact), rel(got[:4], exact)
+    print("deployed weights, 4 patches: GPU %.3e, rounded reference %.3e from the exact network"
+          % (e_gpu, e_ref))
+    assert rel(got[:4], want) <= e_ref
+    assert e_gpu <= 2.0 * e_ref
