@@ -320,8 +320,10 @@ __global__ void __launch_bounds__(256) mix_bf16(const unsigned* __restrict__ H,
 // slot j of half hh: channel 16 s + 2 j + hh, so that the two halves read
 // neighbouring channel rows of the staged pixels, 64 bytes apart, on distinct
 // LDS banks) and the row transform (slots 2 kx, 2 kx + 1 = Re, Im; kx < 9).
-// The gy operand of a row lives in one half of the wave: a row pair (8 w + j,
-// 8 w + 4 + j) trades the missing words across the halves with five shuffles.
+// The gy operand of a row lives in one half of the wave (rows 8 w + 4 hh + j
+// in half hh); the other half receives the words of its K slots by shuffles.
+// Rows go in adjacent pairs (8 w + 2 jj, + 1): a channel's two rows are one
+// 128-byte line of h and of h', loaded and stored whole in one iteration.
 // Each wave stages its own pixel rows, so only wave-level ordering is needed
 // there; the next row pair's pixels, and the next patch's G and first row
 // pair, are loaded while the current rows are computed.
@@ -350,7 +352,7 @@ __global__ void __launch_bounds__(256) inv_bf16(const unsigned* __restrict__ G,
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int q = 64 * u + l, row = q >> 7, i = (q & 127) >> 2, xq = q & 3;
-      const int y = 8 * w + 4 * row + j;
+      const int y = 8 * w + 2 * j + row;
       pf[u] = *reinterpret_cast<const u32x4*>(hb + (i * N + y) * N + 8 * xq);
     }
   };
@@ -448,25 +450,29 @@ __global__ void __launch_bounds__(256) inv_bf16(const unsigned* __restrict__ G,
     if (bn < B) load_g(bn, gpf);
     bf_t* ob = h_out + (long long)b * C * N * N + li * N * N;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      // stage the pixels of rows 8 w + j and 8 w + 4 + j
+    for (int jj = 0; jj < 4; ++jj) {
+      // stage the pixels of rows 8 w + 2 jj and 8 w + 2 jj + 1 (each channel's
+      // two rows are one 128-byte line, loaded and stored whole)
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int q = 64 * u + l, row = q >> 7, i = (q & 127) >> 2, xq = q & 3;
         *reinterpret_cast<u32x4*>(hs + row * C * N + i * N + 8 * xq) = pf[u];
       }
       wave_sync();
-      if (j + 1 < 4) load_rows(b, j + 1, pf);
+      if (jj + 1 < 4) load_rows(b, jj + 1, pf);
       else if (bn < B) load_rows(bn, 0, pf);
-      // trade gy words across the halves (lower half owns row 8 w + j, upper 8 w + 4 + j)
-      unsigned rv[5];
-#pragma unroll
-      for (int p = 0; p < 4; ++p)
-        rv[p] = (unsigned)__shfl_xor((int)(hh ? gv[j][p] : gv[j][4 + p]), 32);
-      rv[4] = (unsigned)__shfl_xor((int)gv[j][8], 32);
+      // both rows belong to half own = jj / 2 of the wave (its gv[j], j = row
+      // index mod 4); the other half receives the words of its K slots
+      const int own = jj >> 1;
+      unsigned zw[2][8];  // packed outputs of both rows: x = 8 q + 4 hh + 2 e2, + 1
 #pragma unroll
       for (int row = 0; row < 2; ++row) {
-        const int y = 8 * w + 4 * row + j;
+        const int j = (2 * jj + row) & 3;
+        unsigned rv[5];
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+          rv[p] = (unsigned)__shfl_xor((int)(own ? gv[j][p] : gv[j][4 + p]), 32);
+        rv[4] = own ? (unsigned)__shfl_xor((int)gv[j][8], 32) : 0u;
         // pointwise A operand: pixels x = li of channels 16 s + 2 p + hh (+ 2)
         const bf_t* src = hs + row * C * N + li;
         u32x4 pa[2];
@@ -480,7 +486,7 @@ __global__ void __launch_bounds__(256) inv_bf16(const unsigned* __restrict__ G,
           pa[s] = u32x4{v[0], v[1], v[2], v[3]};
         }
         u32x4 g0, g1;
-        if (row == 0) {
+        if (own == 0) {
           g0 = hh ? u32x4{rv[0], rv[1], rv[2], rv[3]}
                   : u32x4{gv[j][0], gv[j][1], gv[j][2], gv[j][3]};
           g1 = u32x4{hh ? 0u : gv[j][8], 0u, 0u, 0u};
@@ -494,7 +500,6 @@ __global__ void __launch_bounds__(256) inv_bf16(const unsigned* __restrict__ G,
         d = mma(pa[1], pwb[1], d);
         d = mma(ta0, g0, d);
         d = mma(ta1, g1, d);
-        bf_t* orow = ob + y * N + 4 * hh;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           float z[4];
@@ -503,8 +508,22 @@ __global__ void __launch_bounds__(256) inv_bf16(const unsigned* __restrict__ G,
             z[e] = d[4 * q + e] + bias;
             if (GELU) z[e] = gelu(z[e]);
           }
-          *reinterpret_cast<uint2*>(orow + 8 * q) = make_uint2(pk(z[0], z[1]), pk(z[2], z[3]));
+          zw[row][2 * q] = pk(z[0], z[1]);
+          zw[row][2 * q + 1] = pk(z[2], z[3]);
         }
+      }
+      // the lower half keeps row 8 w + 2 jj, the upper half row 8 w + 2 jj + 1:
+      // each lane gives its partner the other row's words and stores one whole
+      // 64-byte row, so a channel's 128-byte line is written at once
+      unsigned xw[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) xw[k] = (unsigned)__shfl_xor((int)(hh ? zw[0][k] : zw[1][k]), 32);
+      bf_t* orow = ob + (8 * w + 2 * jj + hh) * N;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const u32x4 v = hh ? u32x4{xw[2 * q], xw[2 * q + 1], zw[1][2 * q], zw[1][2 * q + 1]}
+                           : u32x4{zw[0][2 * q], zw[0][2 * q + 1], xw[2 * q], xw[2 * q + 1]};
+        *reinterpret_cast<u32x4*>(orow + 8 * q) = v;
       }
       wave_sync();  // this row pair's pixels are read before the next are staged
     }
