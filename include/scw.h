@@ -513,6 +513,25 @@ int scw_sur_infer_checked(scw_ctx* ctx, scw_sur* sur, const double* n_host, int 
                           int n_check, unsigned long long seed, double tol, double* out_host,
                           int* fell_back, double* check_err);
 
+/* The stages of scw_synthesize (Eq. 10 per plane after Eqs. 30-34 / Eq. 9),
+ * selectable for timing single stages and for callers that keep one plane
+ * spectrum and transform it more than once. */
+enum scw_stage_mask {
+    SCW_STAGE_MODAL = 1,      /* per-layer modal sum into the plan's spectra */
+    SCW_STAGE_EXTERIOR = 2,   /* plane-wave spectra of planes outside the sample */
+    SCW_STAGE_TRANSFORM = 4,  /* inverse transform of the plan's spectra into E */
+    SCW_STAGE_ALL = 7
+};
+/* scw_synthesize restricted to the stages in `stages` (a non-zero mask of
+ * scw_stage_mask). The spectra live in the workspace of the (solution, grid,
+ * precision) plan, which the first call builds: a call without
+ * SCW_STAGE_MODAL / SCW_STAGE_EXTERIOR transforms whatever the last call that
+ * ran them left there (undefined before any). E_dev as for scw_synthesize;
+ * it is written only with SCW_STAGE_TRANSFORM. SCW_STAGE_ALL is exactly
+ * scw_synthesize. SCW_EINVAL for a mask outside 1..7. */
+int scw_synthesize_stages(scw_ctx* ctx, scw_solution* sol, const scw_grid* grid, int precision,
+                          int stages, void* E_dev, void* hip_stream);
+
 /* Per-stage timing of scw_synthesize with HIP events recorded on the
  * synthesis stream between its kernels. scw_profile_begin enables recording
  * for up to `max_calls` following scw_synthesize calls on this context;

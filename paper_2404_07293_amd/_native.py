@@ -16,6 +16,7 @@ STATUS = {0: "SCW_OK", -1: "SCW_EINVAL", -2: "SCW_ENOMEM", -3: "SCW_EHIP",
 PRECISION = {"fp64": 0, "fp32": 1, "bf16x3": 2, "fp16x3": 3}
 ROUTE = {"stable": 0, "connection": 1, "stable_device": 2, "connection_device": 3}
 EIG = {"host": 0, "device": 1}
+STAGE = {"modal": 1, "exterior": 2, "transform": 4, "all": 7}
 EIG_MAX_N = 2048
 
 c_dp = ctypes.POINTER(ctypes.c_double)
@@ -134,6 +135,9 @@ SIGNATURES = {
     "scw_synthesize_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
                                               ctypes.POINTER(ScwGrid), ctypes.c_int,
                                               ctypes.c_void_p, ctypes.c_void_p]),
+    "scw_synthesize_stages": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.POINTER(ScwGrid), ctypes.c_int, ctypes.c_int,
+                                             ctypes.c_void_p, ctypes.c_void_p]),
     "scw_field": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ScwProblem),
                                  ctypes.POINTER(ScwGrid), ctypes.c_int, ctypes.c_void_p,
                                  ctypes.c_void_p]),

@@ -650,6 +650,25 @@ int scw_synthesize(scw_ctx* ctx, scw_solution* sol, const scw_grid* grid, int pr
                     kStageAll, ev);
 }
 
+int scw_synthesize_stages(scw_ctx* ctx, scw_solution* sol, const scw_grid* grid, int precision,
+                          int stages, void* E_dev, void* hip_stream) {
+  if (!ctx || !sol) return fail(SCW_EINVAL, "null argument");
+  if (stages < 1 || stages > SCW_STAGE_ALL)
+    return fail(SCW_EINVAL, "stage mask must be in 1..7");
+  if ((stages & SCW_STAGE_TRANSFORM) && !E_dev) return fail(SCW_EINVAL, "null output");
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  if (precision < SCW_FP64 || precision > SCW_FP16X3)
+    return fail(SCW_EINVAL, "unknown precision " + std::to_string(precision));
+  if ((precision == SCW_BF16X3 || precision == SCW_FP16X3) && sol->s.V > 32)
+    return fail(SCW_EINVAL, "split-precision transform needs V <= 32");
+  static_assert(SCW_STAGE_MODAL == kStageModal && SCW_STAGE_EXTERIOR == kStageExterior &&
+                    SCW_STAGE_TRANSFORM == kStageTransform && SCW_STAGE_ALL == kStageAll,
+                "public and internal stage masks agree");
+  return synthesize(ctx->c, sol->s, *grid, precision, E_dev,
+                    reinterpret_cast<hipStream_t>(hip_stream), stages, nullptr);
+}
+
 // One period of sol's field into its plan's tile workspace, then placed.
 static int synthesize_placed(Context& c, Solution& s, const scw_grid& g, int precision, void* E,
                              int dfx, int dfy, int ox, int oy, int rx, int ry, hipStream_t st) {

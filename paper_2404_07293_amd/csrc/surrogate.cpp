@@ -61,6 +61,9 @@ struct SurNet {
   DevBuf x, h[NL + 1], z[NL], Hk[NL], G, Wm, F, out, gout, gF, T1, gh, gh2, T2, gG, gH,
       tmp, sums, enc_in;
   DevBuf Wb;  // mixing weights as bf16 matrix-core operands (inference)
+  // the parameters change only in sur_set_params and Adam steps; Wb is rebuilt
+  // when its version lags behind theirs
+  unsigned long long params_version = 1, wb_version = 0;
 };
 
 namespace {
@@ -189,7 +192,10 @@ int forward(SurNet& n, const float* x, int B, hipStream_t s, bool keep) {
 int forward_bf16(SurNet& n, const float* x, int B, hipStream_t s) {
   const Off o;
   const float* P = n.params.as<float>();
-  SUR_HIP(sur_mix_weights_bf16(P + o.spec(0), SZ_LAYER, NL, n.Wb.p, s));
+  if (n.wb_version != n.params_version) {
+    SUR_HIP(sur_mix_weights_bf16(P + o.spec(0), SZ_LAYER, NL, n.Wb.p, s));
+    n.wb_version = n.params_version;
+  }
   void* ha = n.h[0].p;
   void* hb = n.h[1].p;
   SUR_HIP(sur_lift_bf16(x, P + o.lw, P + o.lb, ha, B, s));
@@ -333,6 +339,7 @@ void sur_free(SurNet* n) { delete n; }
 
 int sur_set_params(SurNet& n, const float* host) {
   SCW_HIP(hipMemcpy(n.params.p, host, N_PARAMS * 4, hipMemcpyHostToDevice));
+  n.params_version++;
   SCW_HIP(hipMemset(n.adam_m.p, 0, N_PARAMS * 4));
   SCW_HIP(hipMemset(n.adam_v.p, 0, N_PARAMS * 4));
   n.step = 0;
@@ -392,6 +399,7 @@ int sur_train_step(SurNet& n, const void* x_dev, const void* tgt_dev, int B, flo
   int rc = sur_loss_grad(n, x_dev, tgt_dev, B, loss, nullptr, s);
   if (rc) return rc;
   n.step++;
+  n.params_version++;
   SCW_HIP(sur_adam(n.params.as<float>(), n.grads.as<float>(), n.adam_m.as<float>(),
                    n.adam_v.as<float>(), N_PARAMS, lr, n.step, s));
   return SCW_OK;

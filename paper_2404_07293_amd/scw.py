@@ -262,6 +262,24 @@ class Solution:
                                                 ctypes.c_void_p(stream.cuda_stream)))
         return out
 
+    def synthesize_stages(self, grid, stages, out=None, precision="fp32", stream=None):
+        """Enqueue ``scw_synthesize_stages``: only the named stages ("modal",
+        "exterior", "transform", or a list of them) of the synthesis. The
+        spectra stay in the plan's workspace between calls; ``out`` (allocated
+        when None) is written only by the transform. Returns ``out``."""
+        if isinstance(stages, str):
+            stages = [stages]
+        mask = 0
+        for st in stages:
+            mask |= N.STAGE[st]
+        out, stream = self._out(grid, precision, out, stream)
+        N.check(self.lib.scw_synthesize_stages(self.ctx.handle, self.handle,
+                                               ctypes.byref(_grid(grid)),
+                                               N.PRECISION[precision], mask,
+                                               ctypes.c_void_p(out.data_ptr()),
+                                               ctypes.c_void_p(stream.cuda_stream)))
+        return out
+
     def synthesize_illuminations(self, grid, out=None, stream=None):
         """Enqueue ``scw_synthesize_illuminations`` (FP32): the field of every
         illumination into ``out`` [K, 3, fz, fy, fx] complex64, allocated

@@ -424,3 +424,28 @@ def test_captured_synthesis_survives_other_grids_and_configurations(ctx):
         g.replay()
         torch.cuda.synchronize()
         assert torch.equal(out, want), k
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_synthesis_stages_compose_to_the_full_synthesis(ctx, precision):
+    """scw_synthesize_stages: the modal sum, the exterior spectra and the
+    transform run as separate calls (in any grouping) give the field of one
+    scw_synthesize call bit for bit, and a transform-only call repeats it."""
+    torch = _torch()
+    prob = ragged_problem(seed=23)
+    grid = W.Grid(fx=13, fy=16, fz=9, z_begin=-0.3, z_end=prob.thickness + 0.3)
+    sol = ctx.solve(prob)
+    full = sol.synthesize(grid, precision).clone()
+    a = sol.synthesize_stages(grid, ["modal", "exterior"], precision=precision)
+    a = sol.synthesize_stages(grid, "transform", out=a, precision=precision)
+    torch.cuda.synchronize()
+    assert torch.equal(a, full)
+    sol.synthesize_stages(grid, "modal", precision=precision)
+    sol.synthesize_stages(grid, "exterior", precision=precision)
+    b = sol.synthesize_stages(grid, "transform", precision=precision)
+    c = sol.synthesize_stages(grid, "transform", precision=precision)
+    torch.cuda.synchronize()
+    assert torch.equal(b, full) and torch.equal(c, full)
+    with pytest.raises(ScwError) as e:
+        sol.synthesize_stages(grid, [], precision=precision)
+    assert e.value.code == -1

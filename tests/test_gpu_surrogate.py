@@ -352,3 +352,39 @@ def test_deployed_weights_meet_their_validation_error(ctx):
           % (e_gpu, e_ref))
     assert rel(got[:4], want) <= e_ref
     assert e_gpu <= 2.0 * e_ref
+
+
+def test_bf16_inference_is_per_patch_at_large_batch(ctx):
+    """1100 patches: the persistent inference kernels then take several patches
+    per block, with the next patch's loads in flight. Every patch's output is
+    bit for bit the one it gets in a batch of its own 100 (one patch per
+    block), and sampled patches meet the rounded reference's bound."""
+    torch = _torch()
+    from paper_2404_07293_amd.surrogate import Surrogate
+    sur = Surrogate(ctx, max_batch=1100, seed=1)
+    p = S.init_params(4)
+    for k in range(S.N_LAYERS):
+        p["spec%d" % k] *= 4.0
+    flat = S.flatten(p).astype(np.float32)
+    sur.set_params(flat)
+    sur.set_compute(True)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(7)
+    x = torch.randn((1100, 16, 32, 32), device="cuda", generator=g)
+    big = sur.forward(x).clone()
+    part = sur.forward(x[1000:].contiguous())
+    first = sur.forward(x[:3].contiguous())
+    torch.cuda.synchronize()
+    assert torch.equal(big[1000:], part)
+    assert torch.equal(big[:3], first)
+    p32 = S.unflatten(flat.astype(np.float64))
+    idx = [0, 517, 1099]
+    xs = x[idx].cpu().numpy().astype(np.float64)
+    want = S.forward(p32, xs, bf16=True)
+    exact = S.forward(p32, xs)
+    got = big[idx].cpu().numpy()
+    err, ref = rel(got, want), rel(want, exact)
+    print("bf16 inference, 1100 patches: sampled rel-L2 %.3e vs rounded reference (%.3e)"
+          % (err, ref))
+    assert err <= ref
+    assert rel(got, exact) <= 2.0 * ref
