@@ -151,7 +151,7 @@ def main(argv=None):
     g.add_argument("--out", required=True)
     t = sub.add_parser("train", help="train on generated pairs and save the network")
     t.add_argument("--pairs", nargs="+", required=True, help="pair files (globs allowed)")
-    t.add_argument("--epochs", type=int, default=60)
+    t.add_argument("--epochs", type=int, default=500)
     t.add_argument("--batch", type=int, default=64)
     t.add_argument("--lr", type=float, default=2e-3)
     t.add_argument("--out", required=True)
