@@ -61,16 +61,24 @@ __device__ __forceinline__ floatx16 mma(u32x4 a, u32x4 b, floatx16 c) {
 }
 
 // GELU(z) = z (1 + erf(z / sqrt 2)) / 2 with erf from Abramowitz and Stegun
-// 7.1.26 (absolute error at most 1.5e-7), as in the FP32 kernels.
+// 7.1.26 (absolute error at most 1.5e-7), the formula of the FP32 kernels
+// rearranged for fewer operations: with x = |z| / sqrt 2, t = 1 / (1 + p x)
+// and E = t P(t) exp(-x^2) / 2 (so erf x = 1 - 2 E), GELU(z) = max(z, 0) -
+// |z| E for either sign of z. The halves and 1 / sqrt 2 are folded into the
+// constants and exp(-x^2) = 2^(-z^2 log2(e) / 2): 11 vector operations and
+// two transcendentals per value.
 __device__ __forceinline__ float gelu(float z) {
-  const float x = fabsf(z) * 0.70710678118654752f;
-  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, x, 1.f));
-  float q = fmaf(1.061405429f, t, -1.453152027f);
-  q = fmaf(q, t, 1.421413741f);
-  q = fmaf(q, t, -0.284496736f);
-  q = fmaf(q, t, 0.254829592f);
-  const float pe = q * t * __expf(-x * x);
-  return 0.5f * z * (z >= 0.f ? 2.f - pe : pe);
+  const float az = fabsf(z);
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.231641888f, az, 1.f));  // p / sqrt 2
+  const float e = __builtin_amdgcn_exp2f(-(z * 0.72134752f) * z);       // log2(e) / 2
+  float q = fmaf(0.5307027145f, t, -0.7265760135f);
+  q = fmaf(q, t, 0.7107068705f);
+  q = fmaf(q, t, -0.142248368f);
+  q = fmaf(q, t, 0.127414796f);
+  // max(z, 0) as an integer maximum of the bits: the float maximum would first
+  // quiet a signalling NaN, one more operation
+  const float zp = __int_as_float(max(__float_as_int(z), 0));
+  return fmaf(-az, q * t * e, zp);
 }
 
 // ---------------------------------------------------------------------------
@@ -313,22 +321,32 @@ __global__ void __launch_bounds__(256) mix_bf16(const unsigned* __restrict__ H,
 //   h'[o][y][x]  = GELU(z) (or z after the last layer: GELU false), stored rounded.
 // Column transform on the matrix cores, per kx: D[y][o] over the 17 (up to
 // 24) complex ky as (Re, Im) pairs: (Re iy, -Im iy) for the real part, (Im iy,
-// Re iy) for the imaginary part, against G staged in LDS as [kx][o][ky]. Wave
-// w keeps rows y = 8 w .. 8 w + 7 of it (accumulators 4 w .. 4 w + 3) as
-// packed (Re, Im) words per kx: lane (o, hh) holds rows 8 w + 4 hh + j.
+// Re iy) for the imaginary part, against G staged in LDS as rows [kx][ky] of
+// 32 channels (40 words apart, so that the two halves of a wave, 4 rows apart,
+// read distinct banks); the K slots of ky >= 17 take zeros from registers.
+// Wave w transforms kx = w, w + 4 (and 8 for wave 0) for all 32 rows y; the
+// packed results replace the staged G in LDS as gy[y][o][kx] (kx < 8, the two
+// 16-byte halves of a record swapped for o / 8 odd so that 16 lanes reading
+// one half each hit distinct banks) and gy8[y][o] (kx = 8).
 // Output tile per row y: D[x][o] over K = 64: the pointwise part (K step s,
 // slot j of half hh: channel 16 s + 2 j + hh, so that the two halves read
 // neighbouring channel rows of the staged pixels, 64 bytes apart, on distinct
-// LDS banks) and the row transform (slots 2 kx, 2 kx + 1 = Re, Im; kx < 9).
-// The gy operand of a row lives in one half of the wave (rows 8 w + 4 hh + j
-// in half hh); the other half receives the words of its K slots by shuffles.
+// LDS banks), the row transform (slots 2 kx, 2 kx + 1 = Re, Im; kx < 9, read
+// from gy as one 16-byte word per half plus gy8) and the bias (slots 18 .. 20:
+// its three bf16 terms against ones).
 // Rows go in adjacent pairs (8 w + 2 jj, + 1): a channel's two rows are one
 // 128-byte line of h and of h', loaded and stored whole in one iteration.
 // Each wave stages its own pixel rows, so only wave-level ordering is needed
-// there; the next row pair's pixels, and the next patch's G and first row
-// pair, are loaded while the current rows are computed.
-constexpr int IV_GS = 28;  // packed words per (kx, o) record of staged G: 17 ky + pad
+// there. Pixels are fetched one row pair ahead (the last pair fetches the
+// next patch's first) and the next patch's G during the rows. Every load and
+// store of h and h' moves whole 128-byte lines, eight lanes to a line: the
+// pixels are regrouped for the products, and the outputs for the stores,
+// through the wave's stage.
+constexpr int IV_GR = 40;                   // words per staged G row: 32 channels + pad
+constexpr int IV_GY8 = C * N * 8;           // offset of gy8 in the shared words
+constexpr int IV_WORDS = C * N * 8 + C * N; // gy and gy8 (9216 words, 36 KB)
 constexpr int IV_GQ = (LNM * C / 4 + 255) / 256;  // 16-byte chunks of G per thread
+static_assert(LKX * LKY * IV_GR <= IV_WORDS, "staged G exceeds the shared words");
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -341,20 +359,23 @@ __global__ void __launch_bounds__(256) inv_bf16(const unsigned* __restrict__ G,
                                                 const float* __restrict__ pw,
                                                 const float* __restrict__ pb,
                                                 bf_t* __restrict__ h_out, int B) {
-  __shared__ __attribute__((aligned(16))) unsigned gs[LKX * C * IV_GS];
-  __shared__ __attribute__((aligned(16))) bf_t hst[4][2][C * N];  // [wave][row][i][x]
+  // staged G, then (after every wave has read it) gy and gy8
+  __shared__ __attribute__((aligned(16))) unsigned gsh[IV_WORDS];
+  // per wave: a row pair as [i][row][x] (the 32 lines, in order), then the
+  // outputs as [o][row][x] with the 16-byte chunks of line o at c ^ (o % 8)
+  __shared__ __attribute__((aligned(16))) bf_t hst[4][2 * C * N];
   const int t = threadIdx.x, w = __builtin_amdgcn_readfirstlane(t >> 6), l = t & 63,
             li = l & 31, hh = l >> 5;
   int b = blockIdx.x;
   if (b >= B) return;  // uniform over the block, before any barrier
+  // a row pair of all channels is 32 lines of 128 bytes (channel i: rows y,
+  // y + 1); load u takes lines 8 u .. 8 u + 7, eight lanes to a line (chunk
+  // l % 8), so that every load reads whole lines
+  const int lane_px = (l >> 3) * N * N + (l & 7) * 8 + 8 * w * N;
   auto load_rows = [&](int bb, int j, u32x4* pf) {
-    const bf_t* hb = h + (long long)bb * C * N * N;
+    const bf_t* hb = h + (long long)bb * C * N * N + lane_px + 2 * j * N;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int q = 64 * u + l, row = q >> 7, i = (q & 127) >> 2, xq = q & 3;
-      const int y = 8 * w + 2 * j + row;
-      pf[u] = *reinterpret_cast<const u32x4*>(hb + (i * N + y) * N + 8 * xq);
-    }
+    for (int u = 0; u < 4; ++u) pf[u] = *reinterpret_cast<const u32x4*>(hb + 8 * u * N * N);
   };
   auto load_g = [&](int bb, u32x4* gp) {
     const u32x4* gb = reinterpret_cast<const u32x4*>(G + (long long)bb * LNM * C);
@@ -364,11 +385,10 @@ __global__ void __launch_bounds__(256) inv_bf16(const unsigned* __restrict__ G,
       if (q < LNM * C / 4) gp[u] = gb[q];
     }
   };
-  u32x4 gpf[IV_GQ], pf[4];
+  // pixel rows are fetched one row pair ahead
+  u32x4 gpf[IV_GQ], pf[1][4];
   load_g(b, gpf);
-  load_rows(b, 0, pf);
-  // ky 17 .. 23 of every staged record stay zero
-  for (int q = t; q < LKX * C * 7; q += 256) gs[(q / 7) * IV_GS + LKY + q % 7] = 0u;
+  load_rows(b, 0, pf[0]);
   // row-transform twiddles (A operand, lane (x = li, hh)): K step 0 holds kx
   // 4 hh .. 4 hh + 3, step 1 kx 8 in the lower half; (Re ix, -Im ix) words
   u32x4 ta0, ta1;
@@ -380,8 +400,9 @@ __global__ void __launch_bounds__(256) inv_bf16(const unsigned* __restrict__ G,
       v[p] = pk(f.x, -f.y);
     }
     ta0 = u32x4{v[0], v[1], v[2], v[3]};
+    // slots 2 .. 4 of the lower half multiply the bias terms of g1 by one
     const cf f8 = ix[8 * N + li];
-    ta1 = u32x4{hh == 0 ? pk(f8.x, -f8.y) : 0u, 0u, 0u, 0u};
+    ta1 = hh == 0 ? u32x4{pk(f8.x, -f8.y), pk(1.f, 1.f), pk(1.f, 0.f), 0u} : u32x4{0u, 0u, 0u, 0u};
   }
   // pointwise weights (B operand, lane (o = li, hh)): channel 16 s + 2 p + hh
   u32x4 pwb[2];
@@ -393,20 +414,27 @@ __global__ void __launch_bounds__(256) inv_bf16(const unsigned* __restrict__ G,
       v[p] = pk(pw[(16 * s + 4 * p + hh) * C + li], pw[(16 * s + 4 * p + 2 + hh) * C + li]);
     pwb[s] = u32x4{v[0], v[1], v[2], v[3]};
   }
-  const float bias = pb[li];
-  bf_t* hs = &hst[w][0][0];
+  // the bias of output channel o = li as three bf16 terms whose sum is exactly
+  // the FP32 value (each takes the next 8 significant bits of the remainder),
+  // added by the row-transform product through K slots 2 .. 4 of the lower half
+  unsigned bw1, bw2;
+  {
+    const float b0 = pb[li], bh = rb(b0), bm = rb(b0 - bh), bl = rb(b0 - bh - bm);
+    bw1 = hh == 0 ? pk(bh, bm) : 0u;
+    bw2 = hh == 0 ? pk(bl, 0.f) : 0u;
+  }
+  bf_t* hs = &hst[w][0];
+  const bf_t* hs_lane = hs + hh * 2 * N + li;
+  // this lane's gy word: record (y, o = li), half hh of the 8 kx < 8
+  const int gy_lane = li * 8 + 4 * (hh ^ ((li >> 3) & 1));
   for (;;) {
-    // stage G[m][o] -> gs[kx][o][ky]
+    // stage G[m][o] -> rows [kx][ky] of 32 channels
 #pragma unroll
     for (int u = 0; u < IV_GQ; ++u) {
       const int q = t + 256 * u;
       if (q < LNM * C / 4) {
         const int m = q >> 3, o0 = (q & 7) * 4, ky = m / LKX, kx = m % LKX;
-        unsigned* d = gs + (kx * C + o0) * IV_GS + ky;
-        d[0] = gpf[u][0];
-        d[IV_GS] = gpf[u][1];
-        d[2 * IV_GS] = gpf[u][2];
-        d[3 * IV_GS] = gpf[u][3];
+        *reinterpret_cast<u32x4*>(gsh + (kx * LKY + ky) * IV_GR + o0) = gpf[u];
       }
     }
     // column-transform twiddles: lane (y = li, hh), K step s: ky = 8 s + 4 hh + p
@@ -425,76 +453,86 @@ __global__ void __launch_bounds__(256) inv_bf16(const unsigned* __restrict__ G,
       are[s] = u32x4{vr[0], vr[1], vr[2], vr[3]};
       aim[s] = u32x4{vi[0], vi[1], vi[2], vi[3]};
     }
-    __syncthreads();
-    // column transform; keep this wave's rows as gv[j][kx]
-    unsigned gv[4][LKX];
-#pragma unroll
-    for (int kx = 0; kx < LKX; ++kx) {
+    __syncthreads();  // G staged
+    // column transform of kx = w + 4 n (n = 0, 1) and, in wave 0, of kx = 8;
+    // packed rows y = 8 (r / 4) + 4 hh + r % 4 of channel o = li
+    auto column = [&](int kx, unsigned* res) {
+      const unsigned* gk = gsh + kx * LKY * IV_GR + li + 4 * hh * IV_GR;
       floatx16 dr = {0}, di = {0};
 #pragma unroll
       for (int s = 0; s < 3; ++s) {
-        const u32x4 bv =
-            *reinterpret_cast<const u32x4*>(gs + (kx * C + li) * IV_GS + 8 * s + 4 * hh);
+        u32x4 bv;
+        if (s < 2) {
+#pragma unroll
+          for (int p = 0; p < 4; ++p) bv[p] = gk[(8 * s + p) * IV_GR];
+        } else {  // ky 16 in slot 0 of the lower half; ky 17 .. 23 are zero
+          const unsigned v16 = gk[(LKY - 1 - 4 * hh) * IV_GR];
+          bv = u32x4{hh ? 0u : v16, 0u, 0u, 0u};
+        }
         dr = mma(are[s], bv, dr);
         di = mma(aim[s], bv, di);
       }
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        if (q == w) {
+      for (int r = 0; r < 16; ++r) res[r] = pk(dr[r], di[r]);
+    };
+    // one column at a time: overlapping them would hold three accumulator pairs
+    unsigned res0[16], res1[16], res8[16];
+    column(w, res0);
+    __builtin_amdgcn_sched_barrier(0);
+    column(w + 4, res1);
+    __builtin_amdgcn_sched_barrier(0);
+    if (w == 0) column(8, res8);
+    __syncthreads();  // every wave is done with the staged G
+    {
+      // row y = 8 (r / 4) + 4 hh + r % 4: lane base at row 4 hh
+      const int sw = (li >> 3) & 1;
+      unsigned* gq0 = gsh + (4 * hh * C + li) * 8 + w + 4 * sw;
+      unsigned* gq1 = gsh + (4 * hh * C + li) * 8 + w + 4 * (sw ^ 1);
 #pragma unroll
-          for (int j = 0; j < 4; ++j) gv[j][kx] = pk(dr[4 * q + j], di[4 * q + j]);
-        }
+      for (int r = 0; r < 16; ++r) {
+        const int y0 = 8 * (r / 4) + (r % 4);
+        gq0[y0 * C * 8] = res0[r];
+        gq1[y0 * C * 8] = res1[r];
+      }
+      if (w == 0) {
+        unsigned* g8 = gsh + IV_GY8 + 4 * hh * C + li;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) g8[(8 * (r / 4) + (r % 4)) * C] = res8[r];
+      }
     }
-    __syncthreads();  // every wave is done with gs
+    __syncthreads();  // gy complete
     const int bn = b + gridDim.x;
     if (bn < B) load_g(bn, gpf);
-    bf_t* ob = h_out + (long long)b * C * N * N + li * N * N;
 #pragma unroll
     for (int jj = 0; jj < 4; ++jj) {
       // stage the pixels of rows 8 w + 2 jj and 8 w + 2 jj + 1 (each channel's
       // two rows are one 128-byte line, loaded and stored whole)
+      // load u, lane l holds chunk l % 8 of line 8 u + l / 8: [i][row][x]
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int q = 64 * u + l, row = q >> 7, i = (q & 127) >> 2, xq = q & 3;
-        *reinterpret_cast<u32x4*>(hs + row * C * N + i * N + 8 * xq) = pf[u];
-      }
+      for (int u = 0; u < 4; ++u)
+        *reinterpret_cast<u32x4*>(hs + (64 * u + l) * 8) = pf[0][u];
       wave_sync();
-      if (jj + 1 < 4) load_rows(b, jj + 1, pf);
-      else if (bn < B) load_rows(bn, 0, pf);
-      // both rows belong to half own = jj / 2 of the wave (its gv[j], j = row
-      // index mod 4); the other half receives the words of its K slots
-      const int own = jj >> 1;
+      if (jj + 1 < 4) load_rows(b, jj + 1, pf[0]);
+      else if (bn < B) load_rows(bn, 0, pf[0]);
       unsigned zw[2][8];  // packed outputs of both rows: x = 8 q + 4 hh + 2 e2, + 1
 #pragma unroll
       for (int row = 0; row < 2; ++row) {
-        const int j = (2 * jj + row) & 3;
-        unsigned rv[5];
-#pragma unroll
-        for (int p = 0; p < 4; ++p)
-          rv[p] = (unsigned)__shfl_xor((int)(own ? gv[j][p] : gv[j][4 + p]), 32);
-        rv[4] = own ? (unsigned)__shfl_xor((int)gv[j][8], 32) : 0u;
-        // pointwise A operand: pixels x = li of channels 16 s + 2 p + hh (+ 2)
-        const bf_t* src = hs + row * C * N + li;
+        const int y = 8 * w + 2 * jj + row;
+        // pointwise A operand: pixels x = li of channels 16 s + 4 p + hh (+ 2)
+        const bf_t* src = hs_lane + row * N;
         u32x4 pa[2];
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
           unsigned v[4];
 #pragma unroll
           for (int p = 0; p < 4; ++p)
-            v[p] = (unsigned)src[(16 * s + 4 * p + hh) * N] |
-                   ((unsigned)src[(16 * s + 4 * p + 2 + hh) * N] << 16);
+            v[p] = (unsigned)src[(16 * s + 4 * p) * 2 * N] |
+                   ((unsigned)src[(16 * s + 4 * p + 2) * 2 * N] << 16);
           pa[s] = u32x4{v[0], v[1], v[2], v[3]};
         }
-        u32x4 g0, g1;
-        if (own == 0) {
-          g0 = hh ? u32x4{rv[0], rv[1], rv[2], rv[3]}
-                  : u32x4{gv[j][0], gv[j][1], gv[j][2], gv[j][3]};
-          g1 = u32x4{hh ? 0u : gv[j][8], 0u, 0u, 0u};
-        } else {
-          g0 = hh ? u32x4{gv[j][4], gv[j][5], gv[j][6], gv[j][7]}
-                  : u32x4{rv[0], rv[1], rv[2], rv[3]};
-          g1 = u32x4{hh ? 0u : rv[4], 0u, 0u, 0u};
-        }
+        const u32x4 g0 = *reinterpret_cast<const u32x4*>(gsh + y * C * 8 + gy_lane);
+        const unsigned g8 = gsh[IV_GY8 + y * C + li];
+        const u32x4 g1 = u32x4{hh ? 0u : g8, bw1, bw2, 0u};
         floatx16 d = {0};
         d = mma(pa[0], pwb[0], d);
         d = mma(pa[1], pwb[1], d);
@@ -505,29 +543,39 @@ __global__ void __launch_bounds__(256) inv_bf16(const unsigned* __restrict__ G,
           float z[4];
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
-            z[e] = d[4 * q + e] + bias;
-            if (GELU) z[e] = gelu(z[e]);
+            z[e] = GELU ? gelu(d[4 * q + e]) : d[4 * q + e];
           }
           zw[row][2 * q] = pk(z[0], z[1]);
           zw[row][2 * q + 1] = pk(z[2], z[3]);
         }
       }
-      // the lower half keeps row 8 w + 2 jj, the upper half row 8 w + 2 jj + 1:
-      // each lane gives its partner the other row's words and stores one whole
-      // 64-byte row, so a channel's 128-byte line is written at once
-      unsigned xw[8];
+      // outputs through the wave's stage: lane (o, hh) holds, per row, pixels
+      // 8 q + 4 hh .. + 3 (8 bytes) of channel o; as [o][row][x] they form the
+      // 32 output lines, whose 16-byte chunk c sits at c ^ (o % 8) to spread
+      // the writes over the banks. The pixels are all read by now (the
+      // products that used them are done), so the stage is free.
 #pragma unroll
-      for (int k = 0; k < 8; ++k) xw[k] = (unsigned)__shfl_xor((int)(hh ? zw[0][k] : zw[1][k]), 32);
-      bf_t* orow = ob + (8 * w + 2 * jj + hh) * N;
+      for (int row = 0; row < 2; ++row)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const u32x4 v = hh ? u32x4{xw[2 * q], xw[2 * q + 1], zw[1][2 * q], zw[1][2 * q + 1]}
-                           : u32x4{zw[0][2 * q], zw[0][2 * q + 1], xw[2 * q], xw[2 * q + 1]};
-        *reinterpret_cast<u32x4*>(orow + 8 * q) = v;
+        for (int q = 0; q < 4; ++q)
+          *reinterpret_cast<uint2*>(hs + li * 2 * N + (((4 * row + q) ^ (li & 7)) * 8) + 4 * hh) =
+              make_uint2(zw[row][2 * q], zw[row][2 * q + 1]);
+      wave_sync();
+      // store u: lines 8 u .. 8 u + 7, eight lanes to a line, whole lines
+      {
+        bf_t* orow = h_out + (long long)b * C * N * N + (8 * w + 2 * jj) * N + (l & 7) * 8;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int o = 8 * u + (l >> 3);
+          const u32x4 v =
+              *reinterpret_cast<const u32x4*>(hs + o * 2 * N + (((l & 7) ^ (o & 7)) * 8));
+          *reinterpret_cast<u32x4*>(orow + (long long)o * N * N) = v;
+        }
       }
       wave_sync();  // this row pair's pixels are read before the next are staged
     }
     if (bn >= B) break;
+    __syncthreads();  // every wave is done with gy before the next G is staged
     b = bn;
   }
 }
