@@ -582,59 +582,72 @@ __global__ void __launch_bounds__(256) inv_bf16(const unsigned* __restrict__ G,
 
 // ---------------------------------------------------------------------------
 // The head's mixing: out[b][o][m] = sum_i F[m][b][i] W[i][o][m] for the 3
-// outputs, FP32 on the vector units (operands rounded as read or staged).
-// Block: 32 modes x 32 patches. Thread (patch bi = t % 32, group g = t / 32)
-// takes modes g, g + 8, g + 16, g + 24 of the block in turn: a half-wave reads
-// 32 consecutive (mode, patch) records of 32 packed channels, 4 KB in one
-// run, and the mode's weights, staged in LDS, are the same for all its lanes.
-// The outputs are gathered in LDS and written as runs of 32 modes.
+// outputs, on the matrix cores. Per mode, D[b][n] over K = 64 = (channel,
+// part) for 32 patches: a lane's 8 K values are 4 consecutive channels as
+// (Re, Im), one 16-byte chunk of the patch's packed record; column n = 2 o
+// takes (Re W, -Im W) for the real part of output o, n = 2 o + 1 takes
+// (Im W, Re W) for its imaginary part, and columns n >= 6 are zero. The
+// weights are staged in LDS as packed bf16 words (12 KB with the 25 KB output
+// stage: four blocks per CU, so that a batch of 4096 is one round of blocks),
+// and each mode's operand is built from them. Block: 32 modes x 32 patches, wave w takes modes 8 w .. 8 w + 7
+// with the next mode's records loaded during the current one. The outputs
+// are gathered in LDS and written as runs of 32 modes.
 constexpr int HM_B = 32;
 __global__ void __launch_bounds__(256) head_mix_bf16(const unsigned* __restrict__ F,
                                                      const cf* __restrict__ Wt, int B,
                                                      cf* __restrict__ out) {
-  __shared__ cf wl[32][C * 3 + 1];         // [mode][i * 3 + o], rows 97 apart
+  // weights as packed bf16 (Re, Im) words: 12 KB, so that 4 blocks fit a CU
+  __shared__ unsigned wl[32][C * 3 + 1];   // [mode][i * 3 + o], rows 97 apart
   __shared__ cf ol[HM_B][3][33];           // [patch][o][mode]
-  const int t = threadIdx.x, bi = t & 31, g = t >> 5;
-  const int m0 = blockIdx.x * 32, b0 = blockIdx.y * HM_B, bb = b0 + bi;
+  const int t = threadIdx.x, w = __builtin_amdgcn_readfirstlane(t >> 6), l = t & 63,
+            li = l & 31, hh = l >> 5;
+  const int m0 = blockIdx.x * 32, b0 = blockIdx.y * HM_B, bb = b0 + li;
   for (int q = t; q < 32 * C * 3; q += 256) {
     const int mm = q & 31, io = q >> 5;  // io = i * 3 + o
     const cf v = m0 + mm < HNM ? Wt[(long long)io * HNM + m0 + mm] : cf{0.f, 0.f};
-    wl[mm][io] = cf{rb(v.x), rb(v.y)};
+    wl[mm][io] = pk(v.x, v.y);
   }
-  auto load = [&](int mm, u32x4* r) {
+  // A operand of K step s: chunk 2 s + hh of record (m, bb), channels 8 s + 4 hh .. + 3
+  auto load = [&](int mm, u32x4* a) {
     const int m = m0 + mm;
-    const u32x4* p = reinterpret_cast<const u32x4*>(F + ((long long)m * B + bb) * C);
+    const u32x4* p = reinterpret_cast<const u32x4*>(F + ((long long)m * B + bb) * C) + hh;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) r[q] = (m < HNM && bb < B) ? p[q] : u32x4{0u, 0u, 0u, 0u};
+    for (int s = 0; s < 4; ++s) a[s] = (m < HNM && bb < B) ? p[2 * s] : u32x4{0u, 0u, 0u, 0u};
   };
-  u32x4 cur[8], nxt[8];
-  load(g, cur);
-  __syncthreads();
+  u32x4 cur[4], nxt[4];
+  load(8 * w, cur);
+  __syncthreads();  // weights staged
+  const bool nlive = li < 6;
+  const int on = nlive ? li >> 1 : 0, part = li & 1;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int mm = g + 8 * k;
-    if (k < 3) load(mm + 8, nxt);
-    const cf* wm = wl[mm];
-    cf acc[3] = {{0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}};
+  for (int k = 0; k < 8; ++k) {
+    const int mm = 8 * w + k;
+    if (k < 7) load(mm + 1, nxt);
+    const unsigned* wm = wl[mm];
+    floatx16 d = {0};
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
+    for (int s = 0; s < 4; ++s) {
+      unsigned v[4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const float vr = lo(cur[q][e]), vi = hi(cur[q][e]);
-        const int i = 4 * q + e;
+      for (int p = 0; p < 4; ++p) {
+        // (Im, Re): the halves swapped; (Re, -Im): the upper sign flipped
+        const unsigned c = wm[(8 * s + 4 * hh + p) * 3 + on];
+        v[p] = !nlive ? 0u : (part ? __builtin_amdgcn_alignbit(c, c, 16) : c ^ 0x80000000u);
+      }
+      d = mma(cur[s], u32x4{v[0], v[1], v[2], v[3]}, d);
+    }
+    // lane (n, hh) holds patches 8 (r / 4) + 4 hh + r % 4 of column n
+    if (nlive) {
 #pragma unroll
-        for (int o = 0; o < 3; ++o) {
-          const cf c = wm[i * 3 + o];
-          acc[o].x = fmaf(vr, c.x, fmaf(-vi, c.y, acc[o].x));
-          acc[o].y = fmaf(vr, c.y, fmaf(vi, c.x, acc[o].y));
-        }
+      for (int r = 0; r < 16; ++r) {
+        cf* dst = &ol[8 * (r / 4) + 4 * hh + (r % 4)][on][mm];
+        if (part) dst->y = d[r];
+        else dst->x = d[r];
       }
     }
+    if (k < 7)
 #pragma unroll
-    for (int o = 0; o < 3; ++o) ol[bi][o][mm] = acc[o];
-    if (k < 3)
-#pragma unroll
-      for (int q = 0; q < 8; ++q) cur[q] = nxt[q];
+      for (int s = 0; s < 4; ++s) cur[s] = nxt[s];
   }
   __syncthreads();
   // write: 3 x 32 patches rows of 32 modes
