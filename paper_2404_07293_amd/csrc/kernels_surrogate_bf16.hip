@@ -163,7 +163,14 @@ __global__ void __launch_bounds__(256) fwd_bf16(const bf_t* __restrict__ h,
     a[c][0] = rows(b, c)[0];
     a[c][1] = rows(b, c)[1];
   }
-  // row-transform twiddles: lane (n = li, hh), K step s, slot j: x = 16 hh + 8 s + j
+  // row-transform twiddles: lane (n = li, hh), K step s, slot j: x = 16 hh + 8 s + j.
+  // The table reads are unconditional (clamped index, the unwanted parts
+  // multiplied by zero): a load under a lane condition becomes a branch that
+  // waits for every load in flight, the first patch's rows included.
+  const int tcol = li < KX ? li : (li < 2 * KX ? li - KX : 0);
+  const int trow = li < KY ? li : 0;
+  const float sx = li < KX ? 1.f : 0.f, sy = (li >= KX && li < 2 * KX) ? 1.f : 0.f;
+  const float sr = li < KY ? 1.f : 0.f;
   u32x4 tb[2];
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
@@ -174,7 +181,8 @@ __global__ void __launch_bounds__(256) fwd_bf16(const bf_t* __restrict__ h,
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
         const int xx = 16 * hh + 8 * s + 2 * q + u;
-        e[u] = li < KX ? fx[xx * KX + li].x : li < 2 * KX ? fx[xx * KX + li - KX].y : 0.f;
+        const cf f = fx[xx * KX + tcol];
+        e[u] = fmaf(sx, f.x, sy * f.y);
       }
       v[q] = pk(e[0], e[1]);
     }
@@ -192,7 +200,8 @@ __global__ void __launch_bounds__(256) fwd_bf16(const bf_t* __restrict__ h,
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
         const int yy = 16 * (s & 1) + 8 * hh + 2 * q + u;
-        const cf f = li < KY ? fy[li * N + yy] : cf{0.f, 0.f};
+        const cf f0 = fy[trow * N + yy];
+        const cf f = {f0.x * sr, f0.y * sr};
         er[u] = s < 2 ? f.x : -f.y;
         ei[u] = s < 2 ? f.y : f.x;
       }
@@ -204,15 +213,17 @@ __global__ void __launch_bounds__(256) fwd_bf16(const bf_t* __restrict__ h,
   }
   for (;;) {
     const int bn = b + gridDim.x;
+    // every pass loads a patch (the last one reloads its own), so that the
+    // count of loads in flight is the same on every path and the waits
+    // before each channel's products stay exact
+    const int bl = bn < B ? bn : b;
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
       floatx16 d = {0};
       d = mma(a[c][0], tb[0], d);
       d = mma(a[c][1], tb[1], d);
-      if (bn < B) {
-        a[c][0] = rows(bn, c)[0];
-        a[c][1] = rows(bn, c)[1];
-      }
+      a[c][0] = rows(bl, c)[0];
+      a[c][1] = rows(bl, c)[1];
       if (li < 2 * KX) {
         bf_t* dst = hxl + li * FW_PS + 4 * hh;
 #pragma unroll
@@ -222,7 +233,8 @@ __global__ void __launch_bounds__(256) fwd_bf16(const bf_t* __restrict__ h,
       }
     }
     __syncthreads();
-    for (int kx = w; kx < KX; kx += 4) {
+    // column transform of kx; `mine` is the lane's share of the stores
+    auto column = [&](int kx, bool mine) {
       floatx16 dr = {0}, di = {0};
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
@@ -236,9 +248,18 @@ __global__ void __launch_bounds__(256) fwd_bf16(const bf_t* __restrict__ h,
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int ky = 8 * (r / 4) + 4 * hh + (r % 4);
-        if (ky < KY) ob[(long long)(ky * KX + kx) * B * C] = pk(dr[r], di[r]);
+        if (ky < KY && mine) ob[(long long)(ky * KX + kx) * B * C] = pk(dr[r], di[r]);
       }
-    }
+    };
+    // every wave issues the same stores on every path (the waits before the
+    // next patch's products then count them exactly): wave w takes kx = w +
+    // 4 i, and the KX % 4 last kx are transformed by all four waves, each
+    // storing channels 8 w .. 8 w + 7
+    constexpr int KS = KX / 4, KR = KX % 4;
+#pragma unroll
+    for (int i = 0; i < KS; ++i) column(w + 4 * i, true);
+#pragma unroll
+    for (int k = 0; k < KR; ++k) column(4 * KS + k, (li >> 3) == w);
     if (bn >= B) break;
     __syncthreads();  // the planes are read before the next patch overwrites them
     b = bn;
@@ -364,6 +385,7 @@ __global__ void __launch_bounds__(256) inv_bf16(const unsigned* __restrict__ G,
   // per wave: a row pair as [i][row][x] (the 32 lines, in order), then the
   // outputs as [o][row][x] with the 16-byte chunks of line o at c ^ (o % 8)
   __shared__ __attribute__((aligned(16))) bf_t hst[4][2 * C * N];
+  __shared__ u32x4 twl[2][3][64];  // column twiddles (Re, Im outputs) per K step and lane
   const int t = threadIdx.x, w = __builtin_amdgcn_readfirstlane(t >> 6), l = t & 63,
             li = l & 31, hh = l >> 5;
   int b = blockIdx.x;
@@ -423,6 +445,26 @@ __global__ void __launch_bounds__(256) inv_bf16(const unsigned* __restrict__ G,
     bw1 = hh == 0 ? pk(bh, bm) : 0u;
     bw2 = hh == 0 ? pk(bl, 0.f) : 0u;
   }
+  // column-transform twiddles (A operand, lane (y = li, hh), K step s: ky = 8 s
+  // + 4 hh + p), built once per block into LDS by wave 0 with unconditional
+  // table reads; read only after the first barrier of the patch loop
+  if (w == 0) {
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+      unsigned vr[4], vi[4];
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        const int ky = 8 * s + 4 * hh + p;
+        const cf f0 = iy[li * LKY + min(ky, LKY - 1)];
+        const float m = ky < LKY ? 1.f : 0.f;  // unconditional read, zero past the band
+        const cf f = {f0.x * m, f0.y * m};
+        vr[p] = pk(f.x, -f.y);
+        vi[p] = pk(f.y, f.x);
+      }
+      twl[0][s][l] = u32x4{vr[0], vr[1], vr[2], vr[3]};
+      twl[1][s][l] = u32x4{vi[0], vi[1], vi[2], vi[3]};
+    }
+  }
   bf_t* hs = &hst[w][0];
   const bf_t* hs_lane = hs + hh * 2 * N + li;
   // this lane's gy word: record (y, o = li), half hh of the 8 kx < 8
@@ -437,23 +479,15 @@ __global__ void __launch_bounds__(256) inv_bf16(const unsigned* __restrict__ G,
         *reinterpret_cast<u32x4*>(gsh + (kx * LKY + ky) * IV_GR + o0) = gpf[u];
       }
     }
-    // column-transform twiddles: lane (y = li, hh), K step s: ky = 8 s + 4 hh + p
-    // (rebuilt per patch from the cached table: they are not live in the rows)
+    __syncthreads();  // G staged (and, before the first patch, the twiddle table)
+    // column-transform twiddles from the block's LDS table (not held in
+    // registers through the rows)
     u32x4 are[3], aim[3];
 #pragma unroll
     for (int s = 0; s < 3; ++s) {
-      unsigned vr[4], vi[4];
-#pragma unroll
-      for (int p = 0; p < 4; ++p) {
-        const int ky = 8 * s + 4 * hh + p;
-        const cf f = ky < LKY ? iy[li * LKY + ky] : cf{0.f, 0.f};
-        vr[p] = pk(f.x, -f.y);
-        vi[p] = pk(f.y, f.x);
-      }
-      are[s] = u32x4{vr[0], vr[1], vr[2], vr[3]};
-      aim[s] = u32x4{vi[0], vi[1], vi[2], vi[3]};
+      are[s] = twl[0][s][l];
+      aim[s] = twl[1][s][l];
     }
-    __syncthreads();  // G staged
     // column transform of kx = w + 4 n (n = 0, 1) and, in wave 0, of kx = 8;
     // packed rows y = 8 (r / 4) + 4 hh + r % 4 of channel o = li
     auto column = [&](int kx, unsigned* res) {
