@@ -213,17 +213,19 @@ __global__ void __launch_bounds__(256) fwd_bf16(const bf_t* __restrict__ h,
   }
   for (;;) {
     const int bn = b + gridDim.x;
-    // every pass loads a patch (the last one reloads its own), so that the
-    // count of loads in flight is the same on every path and the waits
-    // before each channel's products stay exact
-    const int bl = bn < B ? bn : b;
+    // every pass issues the next patch's loads (the last one, loads of the
+    // first line of each of its own channel planes by every lane, with no
+    // use), so that the count of loads in flight is the same on every path
+    // and the waits before each channel's products stay exact
+    const bool more = bn < B;
+    const bf_t* nb = h + (long long)(more ? bn : b) * C * N * N + (more ? row_off : 8 * w * N * N);
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
       floatx16 d = {0};
       d = mma(a[c][0], tb[0], d);
       d = mma(a[c][1], tb[1], d);
-      a[c][0] = rows(bl, c)[0];
-      a[c][1] = rows(bl, c)[1];
+      a[c][0] = reinterpret_cast<const u32x4*>(nb + c * N * N)[0];
+      a[c][1] = reinterpret_cast<const u32x4*>(nb + c * N * N)[1];
       if (li < 2 * KX) {
         bf_t* dst = hxl + li * FW_PS + 4 * hh;
 #pragma unroll
@@ -244,21 +246,29 @@ __global__ void __launch_bounds__(256) fwd_bf16(const bf_t* __restrict__ h,
         dr = mma(are[s], bv, dr);
         di = mma(aim[s], bv, di);
       }
-      unsigned* ob = out + (long long)b * C + li;
+      // the index as a part uniform over the wave (patch, ky block, kx) and
+      // one 32-bit lane offset (channel, ky half), so that the stores share
+      // one address register (the spectra hold fewer than 2^31 words)
+      unsigned* ob = out + (long long)b * C;
+      const unsigned bc = (unsigned)B * C;
+      const unsigned lane_off = (unsigned)li + (unsigned)(4 * hh * KX) * bc;
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int ky = 8 * (r / 4) + 4 * hh + (r % 4);
-        if (ky < KY && mine) ob[(long long)(ky * KX + kx) * B * C] = pk(dr[r], di[r]);
+        const unsigned uni = (unsigned)((8 * (r / 4) + (r % 4)) * KX + kx) * bc;
+        if (ky < KY && mine) ob[uni + lane_off] = pk(dr[r], di[r]);
       }
     };
     // every wave issues the same stores on every path (the waits before the
     // next patch's products then count them exactly): wave w takes kx = w +
     // 4 i, and the KX % 4 last kx are transformed by all four waves, each
     // storing channels 8 w .. 8 w + 7
+    // (loops kept rolled: unrolled, the columns' operands and accumulators
+    // overlap and cost a wave per SIMD)
     constexpr int KS = KX / 4, KR = KX % 4;
-#pragma unroll
+#pragma unroll 1
     for (int i = 0; i < KS; ++i) column(w + 4 * i, true);
-#pragma unroll
+#pragma unroll 1
     for (int k = 0; k < KR; ++k) column(4 * KS + k, (li >> 3) == w);
     if (bn >= B) break;
     __syncthreads();  // the planes are read before the next patch overwrites them
