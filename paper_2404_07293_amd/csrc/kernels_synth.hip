@@ -223,58 +223,76 @@ __global__ void __launch_bounds__(256) modal_f32_kernel(
 #pragma unroll
   for (int i = 0; i < NV; ++i) acc[i] = 0.f;
 
-  // The first rows' loads are issued before the phase table is built, and
-  // each iteration prefetches the next one, so every wave keeps two sets of
-  // RW 16-byte loads in flight.
-  const int qn_first = min(jc, n2) / 2;
-  float4 cur[RW];
+  // The phase table holds jq float4 per plane, jq = jc / 2 rounded up to a
+  // multiple of 64, with zeros past the chunk. Every lane then runs the same
+  // ceil(qn / 64) steps: a lane past the chunk reads a valid element of its
+  // row (the index clamped to the row) and adds its product with a zero
+  // weight, which leaves its sums unchanged. Each step first issues its RW
+  // loads for the next step unconditionally, into the other of two register
+  // sets, so the wait before its products leaves those loads in flight.
+  const int jq = (jc / 2 + 63) / 64 * 64;
+  float4 pa[RW], pb[RW];
 #pragma unroll
-  for (int r = 0; r < RW; ++r) cur[r] = lane < qn_first ? prow[r][lane] : make_float4(0, 0, 0, 0);
+  for (int r = 0; r < RW; ++r) pa[r] = prow[r][min(lane, h2 - 1)];
+  auto step = [&](const float4 (&cur)[RW], float4 (&nxt)[RW], int q, int qg) {
+#pragma unroll
+    for (int r = 0; r < RW; ++r) nxt[r] = prow[r][qg];
+    // keep the loads ahead of this step's products (the scheduler would
+    // otherwise sink them to the end of the step)
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int p = 0; p < ZT; ++p) {
+      const float4 w = sw4[p * jq + q];
+#pragma unroll
+      for (int r = 0; r < RW; ++r) {
+        float& re = acc[(r * ZT + p) * 2];
+        float& im = acc[(r * ZT + p) * 2 + 1];
+        re = fmaf(cur[r].x, w.x, re);
+        re = fmaf(-cur[r].y, w.y, re);
+        im = fmaf(cur[r].x, w.y, im);
+        im = fmaf(cur[r].y, w.x, im);
+        re = fmaf(cur[r].z, w.z, re);
+        re = fmaf(-cur[r].w, w.w, re);
+        im = fmaf(cur[r].z, w.w, im);
+        im = fmaf(cur[r].w, w.z, im);
+      }
+    }
+  };
   for (int j0 = 0; j0 < n2; j0 += jc) {
     const int jn = min(jc, n2 - j0);
     __syncthreads();
-    for (int jj = threadIdx.x; jj < jn; jj += 256) {
-      const float2 g = kg[j0 + jj], a = av[j0 + jj], b = bv[j0 + jj];
+    for (int jj = threadIdx.x; jj < 2 * jq; jj += 256) {
+      if (jj < jn) {
+        const float2 g = kg[j0 + jj], a = av[j0 + jj], b = bv[j0 + jj];
 #pragma unroll
-      for (int p = 0; p < ZT; ++p) {
-        const float2 gf = cexpi_f(g.x * dzp[p].x, g.y * dzp[p].x);
-        const float2 gb = cexpi_f(-g.x * dzp[p].y, -g.y * dzp[p].y);
-        const float fx = a.x * gf.x - a.y * gf.y, fy = a.x * gf.y + a.y * gf.x;
-        const float bx = b.x * gb.x - b.y * gb.y, by = b.x * gb.y + b.y * gb.x;
-        sw[p * jc + jj] = make_float2(fx + sgn * bx, fy + sgn * by);
+        for (int p = 0; p < ZT; ++p) {
+          const float2 gf = cexpi_f(g.x * dzp[p].x, g.y * dzp[p].x);
+          const float2 gb = cexpi_f(-g.x * dzp[p].y, -g.y * dzp[p].y);
+          const float fx = a.x * gf.x - a.y * gf.y, fy = a.x * gf.y + a.y * gf.x;
+          const float bx = b.x * gb.x - b.y * gb.y, by = b.x * gb.y + b.y * gb.x;
+          sw[p * 2 * jq + jj] = make_float2(fx + sgn * bx, fy + sgn * by);
+        }
+      } else {
+#pragma unroll
+        for (int p = 0; p < ZT; ++p) sw[p * 2 * jq + jj] = make_float2(0.f, 0.f);
       }
     }
     __syncthreads();
-    const int q0 = j0 / 2, qn = jn / 2;
-    const int nq_next = (j0 + jc < n2) ? min(jc, n2 - j0 - jc) / 2 : 0;
-    for (int q = lane; q < qn; q += 64) {
-      // prefetch the next iteration (or the first of the next chunk)
-      float4 nxt[RW];
-      const int qa = q + 64;
-      const bool in_chunk = qa < qn;
-      const int qg = in_chunk ? q0 + qa : q0 + qn + (qa - qn);
-      const bool have = in_chunk || (qa - qn) < nq_next;
+    // step i covers q = lane + 64 i of the chunk and loads element q + 64 of
+    // the rows: the next step's, or for the last step the first of the next
+    // chunk (chunks before the last hold a multiple of 64 float4)
+    const int q0 = j0 / 2, ns = (jn / 2 + 63) / 64;
+    int i = 0;
+    for (; i + 2 <= ns; i += 2) {
+      const int q = lane + 64 * i;
+      step(pa, pb, q, min(q0 + q + 64, h2 - 1));
+      step(pb, pa, q + 64, min(q0 + q + 128, h2 - 1));
+    }
+    if (i < ns) {
+      const int q = lane + 64 * i;
+      step(pa, pb, q, min(q0 + q + 64, h2 - 1));
 #pragma unroll
-      for (int r = 0; r < RW; ++r) nxt[r] = have ? prow[r][qg] : make_float4(0, 0, 0, 0);
-#pragma unroll
-      for (int p = 0; p < ZT; ++p) {
-        const float4 w = sw4[p * (jc / 2) + q];
-#pragma unroll
-        for (int r = 0; r < RW; ++r) {
-          float& re = acc[(r * ZT + p) * 2];
-          float& im = acc[(r * ZT + p) * 2 + 1];
-          re = fmaf(cur[r].x, w.x, re);
-          re = fmaf(-cur[r].y, w.y, re);
-          im = fmaf(cur[r].x, w.y, im);
-          im = fmaf(cur[r].y, w.x, im);
-          re = fmaf(cur[r].z, w.z, re);
-          re = fmaf(-cur[r].w, w.w, re);
-          im = fmaf(cur[r].z, w.w, im);
-          im = fmaf(cur[r].w, w.z, im);
-        }
-      }
-#pragma unroll
-      for (int r = 0; r < RW; ++r) cur[r] = nxt[r];
+      for (int r = 0; r < RW; ++r) pa[r] = pb[r];
     }
   }
   halve<NV>(acc, lane);
@@ -297,7 +315,8 @@ hipError_t launch_modal_f32_rw(const SynthArgs& a, hipStream_t s) {
   const size_t max_lds = 64 * 1024;
   int jc = (int)(max_lds / (ZT * sizeof(float2)));
   jc = jc >= n2 ? n2 : (jc / 128) * 128;
-  const size_t lds = (size_t)ZT * jc * sizeof(float2);
+  // per plane jc / 2 float4 of phases, padded with zeros to a multiple of 64
+  const size_t lds = (size_t)ZT * ((jc / 2 + 63) / 64 * 64) * sizeof(float4);
   const long long nblocks = (long long)a.ntasks * (nb_xy + nb_z);
   if (nblocks == 0) return hipSuccess;
   modal_f32_kernel<ZT, RW><<<(unsigned)nblocks, 256, lds, s>>>(
