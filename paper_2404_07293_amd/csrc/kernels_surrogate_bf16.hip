@@ -651,18 +651,28 @@ __global__ void __launch_bounds__(256) head_mix_bf16(const unsigned* __restrict_
     const cf v = m0 + mm < HNM ? Wt[(long long)io * HNM + m0 + mm] : cf{0.f, 0.f};
     wl[mm][io] = pk(v.x, v.y);
   }
-  // A operand of K step s: chunk 2 s + hh of record (m, bb), channels 8 s + 4 hh .. + 3
+  // A operand of K step s: chunk 2 s + hh of record (m, bb), channels 8 s + 4 hh .. + 3.
+  // The loads are unconditional, the record clamped to the last mode and
+  // patch: the products of records past the end are computed and not
+  // written, so every path issues the same loads and the waits stay exact.
+  const int bc = min(bb, B - 1);
   auto load = [&](int mm, u32x4* a) {
-    const int m = m0 + mm;
-    const u32x4* p = reinterpret_cast<const u32x4*>(F + ((long long)m * B + bb) * C) + hh;
+    const int m = min(m0 + mm, HNM - 1);
+    const u32x4* p = reinterpret_cast<const u32x4*>(F + ((long long)m * B + bc) * C) + hh;
 #pragma unroll
-    for (int s = 0; s < 4; ++s) a[s] = (m < HNM && bb < B) ? p[2 * s] : u32x4{0u, 0u, 0u, 0u};
+    for (int s = 0; s < 4; ++s) a[s] = p[2 * s];
   };
   u32x4 cur[4], nxt[4];
   load(8 * w, cur);
   __syncthreads();  // weights staged
   const bool nlive = li < 6;
   const int on = nlive ? li >> 1 : 0, part = li & 1;
+  // One formula for every lane, so that the weight words are not read under
+  // a lane condition (a branch and a wait per word): (Im, Re) is the word
+  // rotated by 16 bits, (Re, -Im) the word with its upper sign bit flipped,
+  // and lanes past column 5 mask it to zero.
+  const unsigned rot = part ? 16u : 0u, flip = part ? 0u : 0x80000000u;
+  const unsigned live_mask = nlive ? 0xffffffffu : 0u;
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     const int mm = 8 * w + k;
@@ -674,20 +684,17 @@ __global__ void __launch_bounds__(256) head_mix_bf16(const unsigned* __restrict_
       unsigned v[4];
 #pragma unroll
       for (int p = 0; p < 4; ++p) {
-        // (Im, Re): the halves swapped; (Re, -Im): the upper sign flipped
         const unsigned c = wm[(8 * s + 4 * hh + p) * 3 + on];
-        v[p] = !nlive ? 0u : (part ? __builtin_amdgcn_alignbit(c, c, 16) : c ^ 0x80000000u);
+        v[p] = (__builtin_amdgcn_alignbit(c, c, rot) ^ flip) & live_mask;
       }
       d = mma(cur[s], u32x4{v[0], v[1], v[2], v[3]}, d);
     }
-    // lane (n, hh) holds patches 8 (r / 4) + 4 hh + r % 4 of column n
+    // lane (n, hh) holds patches 8 (r / 4) + 4 hh + r % 4 of column n, the
+    // real part of output n in even lanes and the imaginary part in odd ones
     if (nlive) {
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        cf* dst = &ol[8 * (r / 4) + 4 * hh + (r % 4)][on][mm];
-        if (part) dst->y = d[r];
-        else dst->x = d[r];
-      }
+      for (int r = 0; r < 16; ++r)
+        reinterpret_cast<float*>(&ol[8 * (r / 4) + 4 * hh + (r % 4)][on][mm])[part] = d[r];
     }
     if (k < 7)
 #pragma unroll
